@@ -1,0 +1,547 @@
+/*
+ * ASCI determinant-search oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct CPU implementation of what the ASCI
+ * determinant search computes.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product library never
+ * links, calls or includes it, and it shares no code with that library.
+ *
+ * What it follows (paper: Williams-Young et al., "A Parallel, Distributed Memory
+ * Implementation of the Adaptive Sampling Configuration Interaction Method"):
+ *   - Eq. (1): a candidate a outside the wave function gets the partial scores
+ *     H_ai C_i / (E0 - H_aa) from every core determinant i; the score is their
+ *     sum.  (The paper writes the denominator as H_aa - E0; this library
+ *     uses E0 - H_aa, so every score is the negative of the paper's S_a.  The
+ *     selection uses |score| and is unaffected.)
+ *   - Sec. II.A: only determinants singly or doubly connected to a core
+ *     determinant can receive a non-zero score; candidates exclude every input
+ *     determinant.
+ *   - Alg. 2 (ASCI search): core set = the N_cdets input determinants of
+ *     largest |C|; one pass over the cores generates (target, partial score)
+ *     pairs; pairs are sorted on the target bitstring and summed per target;
+ *     the N_tdets targets of largest |score| are kept.
+ *   - Alg. 2's threshold: with eps > 0 a pair is kept only when its partial
+ *     score exceeds eps in magnitude.
+ *
+ * Conventions (the paper fixes none; they are part of this library's ABI):
+ *   - a determinant is (alpha, beta), two 64-bit strings, bit p = spatial
+ *     orbital p;
+ *   - spin orbitals are ordered alpha first then beta, each ascending, and a
+ *     determinant is the product of creators in that order acting on vacuum,
+ *     so a^+_q a_p acting on a determinant has sign (-1)^(number of occupied
+ *     orbitals of that spin strictly between p and q);
+ *   - h is n x n, eri is (pq|rs) in chemists' notation, n^4 row-major, real,
+ *     with the 8-fold permutational symmetry;
+ *   - sums are evaluated left to right in the order written below, with no
+ *     fused multiply-add (build with -ffp-contract=off).
+ *
+ * Slater-Condon rules used by oracle_helem (textbook, written out here):
+ *   diagonal: H_aa = ecore + sum_{p in alpha} h_pp + sum_{p in beta} h_pp
+ *                   + sum_{p<q in alpha} (J_pq - K_pq) + sum_{p<q in beta} (J_pq - K_pq)
+ *                   + sum_{p in alpha, q in beta} J_pq,
+ *             with J_pq = (pp|qq), K_pq = (pq|qp); every sum ascending in p, then q.
+ *   single p -> q of spin s (i has p, a has q):
+ *             H_ai = sign * ( h_qp + sum_{r in occ_s(i), r != p} [(qp|rr) - (qr|rp)]
+ *                                  + sum_{r in occ_other(i)} (qp|rr) ), r ascending.
+ *   same-spin double, holes p < r of i, particles q < s of a:
+ *             H_ai = sign(p->q on i) * sign(r->s on i') * [(qp|sr) - (qr|sp)],
+ *             i' = i with p replaced by q.
+ *   opposite-spin double, alpha p -> q, beta r -> s:
+ *             H_ai = sign_alpha(p->q) * sign_beta(r->s) * (qp|sr).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+
+typedef struct {
+    int n;
+    const double *h;
+    const double *eri;
+    double ecore;
+} ham_t;
+
+static double H1(const ham_t *H, int p, int q) { return H->h[(size_t)p * H->n + q]; }
+
+static double V(const ham_t *H, int p, int q, int r, int s)
+{
+    size_t n = (size_t)H->n;
+    return H->eri[((p * n + q) * n + r) * n + s];
+}
+
+static int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+/* (-1)^(number of set bits of occ strictly between orbitals p and q) */
+static int between_sign(uint64_t occ, int p, int q)
+{
+    int lo = p < q ? p : q, hi = p < q ? q : p;
+    int cnt = 0;
+    for (int t = lo + 1; t < hi; ++t)
+        if ((occ >> t) & 1ull)
+            ++cnt;
+    return (cnt & 1) ? -1 : 1;
+}
+
+/* lowest set bit index; x must be non-zero */
+static int first_bit(uint64_t x)
+{
+    for (int t = 0; t < 64; ++t)
+        if ((x >> t) & 1ull)
+            return t;
+    return -1;
+}
+
+double oracle_hdiag(const double *h, const double *eri, int n, double ecore,
+                    uint64_t alpha, uint64_t beta)
+{
+    ham_t Hs = {n, h, eri, ecore};
+    const ham_t *H = &Hs;
+    double e = ecore;
+    for (int p = 0; p < n; ++p)
+        if ((alpha >> p) & 1ull)
+            e = e + H1(H, p, p);
+    for (int p = 0; p < n; ++p)
+        if ((beta >> p) & 1ull)
+            e = e + H1(H, p, p);
+    for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q)
+            if (((alpha >> p) & 1ull) && ((alpha >> q) & 1ull))
+                e = e + (V(H, p, p, q, q) - V(H, p, q, q, p));
+    for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q)
+            if (((beta >> p) & 1ull) && ((beta >> q) & 1ull))
+                e = e + (V(H, p, p, q, q) - V(H, p, q, q, p));
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            if (((alpha >> p) & 1ull) && ((beta >> q) & 1ull))
+                e = e + V(H, p, p, q, q);
+    return e;
+}
+
+/* single excitation p -> q in the string `same` (spin s) of determinant i,
+ * with `other` the string of the other spin of i */
+static double single_elem(const ham_t *H, uint64_t same, uint64_t other, int p, int q)
+{
+    double v = H1(H, q, p);
+    for (int r = 0; r < H->n; ++r)
+        if (r != p && ((same >> r) & 1ull))
+            v = v + (V(H, q, p, r, r) - V(H, q, r, r, p));
+    for (int r = 0; r < H->n; ++r)
+        if ((other >> r) & 1ull)
+            v = v + V(H, q, p, r, r);
+    return between_sign(same, p, q) * v;
+}
+
+/* <a|H|i> for two determinants; zero beyond double excitations */
+double oracle_helem(const double *h, const double *eri, int n, double ecore,
+                    uint64_t a_alpha, uint64_t a_beta, uint64_t i_alpha, uint64_t i_beta)
+{
+    ham_t Hs = {n, h, eri, ecore};
+    const ham_t *H = &Hs;
+    uint64_t da = a_alpha ^ i_alpha, db = a_beta ^ i_beta;
+    int ea = popc(da) / 2, eb = popc(db) / 2;
+    if (ea + eb == 0)
+        return oracle_hdiag(h, eri, n, ecore, a_alpha, a_beta);
+    if (ea + eb > 2)
+        return 0.0;
+    if (ea == 1 && eb == 0) {
+        int p = first_bit(i_alpha & ~a_alpha), q = first_bit(a_alpha & ~i_alpha);
+        return single_elem(H, i_alpha, i_beta, p, q);
+    }
+    if (ea == 0 && eb == 1) {
+        int p = first_bit(i_beta & ~a_beta), q = first_bit(a_beta & ~i_beta);
+        return single_elem(H, i_beta, i_alpha, p, q);
+    }
+    if (ea == 1 && eb == 1) {
+        int p = first_bit(i_alpha & ~a_alpha), q = first_bit(a_alpha & ~i_alpha);
+        int r = first_bit(i_beta & ~a_beta), s = first_bit(a_beta & ~i_beta);
+        int sg = between_sign(i_alpha, p, q) * between_sign(i_beta, r, s);
+        return sg * V(H, q, p, s, r);
+    }
+    /* same-spin double */
+    uint64_t si = ea == 2 ? i_alpha : i_beta;
+    uint64_t sa = ea == 2 ? a_alpha : a_beta;
+    uint64_t holes = si & ~sa, parts = sa & ~si;
+    int p = first_bit(holes), r = first_bit(holes & (holes - 1));
+    int q = first_bit(parts), s = first_bit(parts & (parts - 1));
+    int s1 = between_sign(si, p, q);
+    uint64_t mid = (si & ~(1ull << p)) | (1ull << q);
+    int s2 = between_sign(mid, r, s);
+    return s1 * s2 * (V(H, q, p, s, r) - V(H, q, r, s, p));
+}
+
+/* ---- enumeration of the singles and doubles of one determinant (Sec. II.A) ---- */
+
+/* all strings reachable from `x` (width n) by moving exactly m = 1 or 2 electrons */
+static int64_t string_moves(uint64_t x, int n, int m, uint64_t *out)
+{
+    int64_t cnt = 0;
+    for (int p = 0; p < n; ++p) {
+        if (!((x >> p) & 1ull))
+            continue;
+        for (int q = 0; q < n; ++q) {
+            if ((x >> q) & 1ull)
+                continue;
+            uint64_t y = (x & ~(1ull << p)) | (1ull << q);
+            if (m == 1) {
+                out[cnt++] = y;
+                continue;
+            }
+            for (int r = p + 1; r < n; ++r) {
+                if (!((x >> r) & 1ull))
+                    continue;
+                for (int s = q + 1; s < n; ++s) {
+                    if (((x >> s) & 1ull) || s == q)
+                        continue;
+                    out[cnt++] = (y & ~(1ull << r)) | (1ull << s);
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+static int64_t choose2(int64_t k) { return k * (k - 1) / 2; }
+
+/* number of singles + doubles of any determinant with these occupations */
+int64_t oracle_sd_count(int n, int na, int nb)
+{
+    int64_t va = n - na, vb = n - nb;
+    return (int64_t)na * va + (int64_t)nb * vb + choose2(na) * choose2(va) +
+           choose2(nb) * choose2(vb) + (int64_t)na * va * nb * vb;
+}
+
+/* every determinant at excitation degree 1 or 2 from (alpha, beta); returns the count */
+int64_t oracle_sd_targets(int n, uint64_t alpha, uint64_t beta, uint64_t *out /* 2*cap */)
+{
+    int na = popc(alpha), nb = popc(beta);
+    int64_t ma1 = (int64_t)na * (n - na), mb1 = (int64_t)nb * (n - nb);
+    int64_t ma2 = choose2(na) * choose2(n - na), mb2 = choose2(nb) * choose2(n - nb);
+    int64_t cap = ma1 > mb1 ? ma1 : mb1;
+    if (ma2 > cap) cap = ma2;
+    if (mb2 > cap) cap = mb2;
+    uint64_t *a1 = malloc(sizeof(uint64_t) * (size_t)(ma1 + 1));
+    uint64_t *b1 = malloc(sizeof(uint64_t) * (size_t)(mb1 + 1));
+    uint64_t *t2 = malloc(sizeof(uint64_t) * (size_t)(cap + 1));
+    int64_t cnt = 0;
+    string_moves(alpha, n, 1, a1);
+    string_moves(beta, n, 1, b1);
+    for (int64_t x = 0; x < ma1; ++x) { out[2 * cnt] = a1[x]; out[2 * cnt + 1] = beta; ++cnt; }
+    for (int64_t y = 0; y < mb1; ++y) { out[2 * cnt] = alpha; out[2 * cnt + 1] = b1[y]; ++cnt; }
+    int64_t k2 = string_moves(alpha, n, 2, t2);
+    for (int64_t x = 0; x < k2; ++x) { out[2 * cnt] = t2[x]; out[2 * cnt + 1] = beta; ++cnt; }
+    k2 = string_moves(beta, n, 2, t2);
+    for (int64_t y = 0; y < k2; ++y) { out[2 * cnt] = alpha; out[2 * cnt + 1] = t2[y]; ++cnt; }
+    for (int64_t x = 0; x < ma1; ++x)
+        for (int64_t y = 0; y < mb1; ++y) { out[2 * cnt] = a1[x]; out[2 * cnt + 1] = b1[y]; ++cnt; }
+    free(a1);
+    free(b1);
+    free(t2);
+    return cnt;
+}
+
+/* ---- validation ---- */
+
+static int validate(int n, int na, int nb, const uint64_t *dets, int64_t ndets)
+{
+    if (n < 1 || n > 64 || na < 0 || na > n || nb < 0 || nb > n || ndets < 0)
+        return ORACLE_EINVAL;
+    uint64_t full = n == 64 ? ~0ull : ((1ull << n) - 1);
+    for (int64_t i = 0; i < ndets; ++i) {
+        uint64_t a = dets[2 * i], b = dets[2 * i + 1];
+        if ((a & ~full) || (b & ~full) || popc(a) != na || popc(b) != nb)
+            return ORACLE_EINVAL;
+    }
+    return ORACLE_OK;
+}
+
+/* ---- ASCI search (Alg. 2) ---- */
+
+typedef struct {
+    uint64_t a, b;
+    int64_t core;
+    double v;
+} pair_rec;
+
+static int cmp_pair(const void *x, const void *y)
+{
+    const pair_rec *p = x, *q = y;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->b != q->b) return p->b < q->b ? -1 : 1;
+    if (p->core != q->core) return p->core < q->core ? -1 : 1;
+    return 0;
+}
+
+typedef struct { uint64_t a, b; } key_t2;
+
+static int cmp_key(const void *x, const void *y)
+{
+    const key_t2 *p = x, *q = y;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->b != q->b) return p->b < q->b ? -1 : 1;
+    return 0;
+}
+
+typedef struct { double absc; int64_t idx; } core_rank;
+
+static int cmp_core(const void *x, const void *y)
+{
+    const core_rank *p = x, *q = y;
+    if (p->absc != q->absc) return p->absc > q->absc ? -1 : 1;
+    return p->idx < q->idx ? -1 : (p->idx > q->idx);
+}
+
+static int cmp_i64(const void *x, const void *y)
+{
+    int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    return a < b ? -1 : (a > b);
+}
+
+/* Indices of the core determinants in ascending input order: the ncore inputs of
+ * largest |C| (ties: lower index first), or all inputs when ncore <= 0 or ncore >= ndets. */
+int64_t oracle_core_set(const double *coeffs, int64_t ndets, int64_t ncore, int64_t *out)
+{
+    if (ncore <= 0 || ncore >= ndets) {
+        for (int64_t i = 0; i < ndets; ++i) out[i] = i;
+        return ndets;
+    }
+    core_rank *r = malloc(sizeof(core_rank) * (size_t)ndets);
+    for (int64_t i = 0; i < ndets; ++i) { r[i].absc = fabs(coeffs[i]); r[i].idx = i; }
+    qsort(r, (size_t)ndets, sizeof(core_rank), cmp_core);
+    for (int64_t i = 0; i < ncore; ++i) out[i] = r[i].idx;
+    free(r);
+    qsort(out, (size_t)ncore, sizeof(int64_t), cmp_i64);
+    return ncore;
+}
+
+typedef struct {
+    int64_t count;    /* number of candidates */
+    uint64_t *keys;   /* 2*count: alpha, beta, ascending (alpha, beta) */
+    double *num;      /* count: N_a = sum_i H_ai C_i, ascending core index */
+    double *hdiag;    /* count: H_aa */
+    double *score;    /* count: N_a / (E0 - H_aa) */
+    int64_t npairs;   /* number of (core, target) pairs kept */
+} oracle_result;
+
+void oracle_free(oracle_result *r)
+{
+    if (!r) return;
+    free(r->keys);
+    free(r->num);
+    free(r->hdiag);
+    free(r->score);
+    memset(r, 0, sizeof(*r));
+}
+
+/*
+ * The search.  keep_psi != 0 keeps targets that are input determinants (their
+ * N_a is then (H C)_a minus the diagonal term, used to pin E0); 0 is the
+ * search proper.
+ */
+int oracle_search(const double *h, const double *eri, int n, int na, int nb, double ecore,
+                  const uint64_t *dets, const double *coeffs, int64_t ndets, double E0,
+                  int64_t ncore, double eps, int keep_psi, oracle_result *res)
+{
+    memset(res, 0, sizeof(*res));
+    if (validate(n, na, nb, dets, ndets) != ORACLE_OK)
+        return ORACLE_EINVAL;
+    ham_t Hs = {n, h, eri, ecore};
+    const ham_t *H = &Hs;
+    (void)H;
+
+    /* psi as a sorted key list, for exclusion and duplicate detection */
+    key_t2 *psi = malloc(sizeof(key_t2) * (size_t)(ndets + 1));
+    for (int64_t i = 0; i < ndets; ++i) { psi[i].a = dets[2 * i]; psi[i].b = dets[2 * i + 1]; }
+    qsort(psi, (size_t)ndets, sizeof(key_t2), cmp_key);
+    for (int64_t i = 1; i < ndets; ++i)
+        if (cmp_key(&psi[i - 1], &psi[i]) == 0) { free(psi); return ORACLE_EINVAL; }
+
+    int64_t *core = malloc(sizeof(int64_t) * (size_t)(ndets + 1));
+    int64_t nq = oracle_core_set(coeffs, ndets, ncore, core);
+
+    int64_t per = oracle_sd_count(n, na, nb);
+    int64_t cap = per * nq;
+    pair_rec *pairs = malloc(sizeof(pair_rec) * (size_t)(cap + 1));
+    uint64_t *tg = malloc(sizeof(uint64_t) * 2 * (size_t)(per + 1));
+    if (!pairs || !tg) { free(psi); free(core); free(pairs); free(tg); return ORACLE_ENOMEM; }
+
+    /* one pass over the cores in ascending index: generate every single and
+     * double, evaluate the pair value H_ai C_i (and screen it when eps > 0) */
+    int64_t np = 0;
+    for (int64_t c = 0; c < nq; ++c) {
+        int64_t i = core[c];
+        uint64_t ia = dets[2 * i], ib = dets[2 * i + 1];
+        int64_t nt = oracle_sd_targets(n, ia, ib, tg);
+        for (int64_t t = 0; t < nt; ++t) {
+            uint64_t ta = tg[2 * t], tb = tg[2 * t + 1];
+            double v = oracle_helem(h, eri, n, ecore, ta, tb, ia, ib) * coeffs[i];
+            if (eps > 0.0) {
+                double d = E0 - oracle_hdiag(h, eri, n, ecore, ta, tb);
+                if (!(fabs(v / d) > eps))
+                    continue;
+            }
+            pairs[np].a = ta; pairs[np].b = tb; pairs[np].core = i; pairs[np].v = v;
+            ++np;
+        }
+    }
+    free(tg);
+
+    /* sort on the target bitstring (core index breaks ties), then accumulate */
+    qsort(pairs, (size_t)np, sizeof(pair_rec), cmp_pair);
+    int64_t nu = 0;
+    for (int64_t j = 0; j < np; ++j)
+        if (j == 0 || pairs[j].a != pairs[j - 1].a || pairs[j].b != pairs[j - 1].b)
+            ++nu;
+    res->keys = malloc(sizeof(uint64_t) * 2 * (size_t)(nu + 1));
+    res->num = malloc(sizeof(double) * (size_t)(nu + 1));
+    res->hdiag = malloc(sizeof(double) * (size_t)(nu + 1));
+    res->score = malloc(sizeof(double) * (size_t)(nu + 1));
+    int64_t u = 0;
+    for (int64_t j = 0; j < np;) {
+        int64_t e = j;
+        double s = 0.0;
+        while (e < np && pairs[e].a == pairs[j].a && pairs[e].b == pairs[j].b) {
+            s = s + pairs[e].v;
+            ++e;
+        }
+        key_t2 k = {pairs[j].a, pairs[j].b};
+        int in_psi = bsearch(&k, psi, (size_t)ndets, sizeof(key_t2), cmp_key) != NULL;
+        if (keep_psi || !in_psi) {
+            double hd = oracle_hdiag(h, eri, n, ecore, k.a, k.b);
+            res->keys[2 * u] = k.a;
+            res->keys[2 * u + 1] = k.b;
+            res->num[u] = s;
+            res->hdiag[u] = hd;
+            res->score[u] = s / (E0 - hd);
+            ++u;
+        }
+        j = e;
+    }
+    res->count = u;
+    res->npairs = np;
+    free(pairs);
+    free(psi);
+    free(core);
+    return ORACLE_OK;
+}
+
+/* ---- selection of the k largest |score| (Alg. 2, last step; duplicate-aware
+ *      selection semantics of Sec. II.B): order is |score| descending, compared as
+ *      the IEEE-754 bit pattern of |score| (numeric order for non-NaN values),
+ *      ties broken by the (alpha, beta) key ascending ---- */
+
+typedef struct {
+    uint64_t ord, a, b;
+    int64_t idx;
+} sel_rec;
+
+static int cmp_sel(const void *x, const void *y)
+{
+    const sel_rec *p = x, *q = y;
+    if (p->ord != q->ord) return p->ord > q->ord ? -1 : 1;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->b != q->b) return p->b < q->b ? -1 : 1;
+    return 0;
+}
+
+static uint64_t abs_bits(double x)
+{
+    uint64_t u;
+    memcpy(&u, &x, sizeof(u));
+    return u & 0x7fffffffffffffffull;
+}
+
+int64_t oracle_topk(const uint64_t *keys, const double *score, int64_t count, int64_t k,
+                    int64_t *out_idx)
+{
+    if (k < 0)
+        return ORACLE_EINVAL;
+    sel_rec *r = malloc(sizeof(sel_rec) * (size_t)(count + 1));
+    for (int64_t i = 0; i < count; ++i) {
+        r[i].ord = abs_bits(score[i]);
+        r[i].a = keys[2 * i];
+        r[i].b = keys[2 * i + 1];
+        r[i].idx = i;
+    }
+    qsort(r, (size_t)count, sizeof(sel_rec), cmp_sel);
+    int64_t m = k < count ? k : count;
+    for (int64_t i = 0; i < m; ++i) out_idx[i] = r[i].idx;
+    free(r);
+    return m;
+}
+
+/* ---- variational energy <C|H|C> by the plain double loop (Eq. (1), E_k) ---- */
+
+double oracle_energy(const double *h, const double *eri, int n, double ecore,
+                     const uint64_t *dets, const double *coeffs, int64_t ndets)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < ndets; ++i)
+        for (int64_t j = 0; j < ndets; ++j) {
+            uint64_t da = dets[2 * i] ^ dets[2 * j], db = dets[2 * i + 1] ^ dets[2 * j + 1];
+            if (popc(da) + popc(db) > 4)
+                continue;
+            e = e + coeffs[i] * oracle_helem(h, eri, n, ecore, dets[2 * i], dets[2 * i + 1],
+                                             dets[2 * j], dets[2 * j + 1]) * coeffs[j];
+        }
+    return e;
+}
+
+/* ---- pair counts per triplet constraint class (Sec. II.B) ----
+ * A target's class is the set of the three highest occupied orbitals of its alpha
+ * string (all of them when it has fewer than three).  For each core (in the core
+ * set) every single and double is generated and counted against its class.
+ * Classes are reported by their mask; out_masks/out_counts receive the non-empty
+ * classes in ascending mask order.  Returns the number of non-empty classes. */
+
+typedef struct { uint64_t mask; int64_t count; } cls_rec;
+
+static int cmp_cls(const void *x, const void *y)
+{
+    const cls_rec *p = x, *q = y;
+    return p->mask < q->mask ? -1 : (p->mask > q->mask);
+}
+
+static uint64_t top3(uint64_t a)
+{
+    uint64_t m = 0;
+    for (int t = 63, got = 0; t >= 0 && got < 3; --t)
+        if ((a >> t) & 1ull) { m |= 1ull << t; ++got; }
+    return m;
+}
+
+int64_t oracle_class_counts(int n, int na, int nb, const uint64_t *dets, const double *coeffs,
+                            int64_t ndets, int64_t ncore, uint64_t *out_masks,
+                            int64_t *out_counts, int64_t cap)
+{
+    if (validate(n, na, nb, dets, ndets) != ORACLE_OK)
+        return ORACLE_EINVAL;
+    int64_t *core = malloc(sizeof(int64_t) * (size_t)(ndets + 1));
+    int64_t nq = oracle_core_set(coeffs, ndets, ncore, core);
+    int64_t per = oracle_sd_count(n, na, nb);
+    uint64_t *tg = malloc(sizeof(uint64_t) * 2 * (size_t)(per + 1));
+    cls_rec *all = malloc(sizeof(cls_rec) * (size_t)(per * nq + 1));
+    int64_t m = 0;
+    for (int64_t c = 0; c < nq; ++c) {
+        int64_t i = core[c];
+        int64_t nt = oracle_sd_targets(n, dets[2 * i], dets[2 * i + 1], tg);
+        for (int64_t t = 0; t < nt; ++t) { all[m].mask = top3(tg[2 * t]); all[m].count = 1; ++m; }
+    }
+    qsort(all, (size_t)m, sizeof(cls_rec), cmp_cls);
+    int64_t nc = 0;
+    for (int64_t j = 0; j < m;) {
+        int64_t e = j;
+        while (e < m && all[e].mask == all[j].mask) ++e;
+        if (nc < cap) { out_masks[nc] = all[j].mask; out_counts[nc] = e - j; }
+        ++nc;
+        j = e;
+    }
+    free(all);
+    free(tg);
+    free(core);
+    return nc;
+}
