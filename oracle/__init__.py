@@ -71,6 +71,10 @@ def lib():
         L.oracle_class_counts.restype = C.c_int64
         L.oracle_class_counts.argtypes = [C.c_int, C.c_int, C.c_int, up, dp, C.c_int64,
                                           C.c_int64, up, ip, C.c_int64]
+        L.oracle_target_numerators.restype = C.c_int
+        L.oracle_target_numerators.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_double, up, dp,
+                                               C.c_int64, C.c_int64, up, C.c_int64, dp, dp,
+                                               C.POINTER(C.c_int), ip]
         _lib = L
     return _lib
 
@@ -195,3 +199,25 @@ def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0):
             return masks[:m], counts[:m]
         cap = m
     raise RuntimeError("class count changed between calls")
+
+
+def target_numerators(h, eri, norb, nalpha, nbeta, dets, coeffs, targets, ncore=0, ecore=0.0):
+    """For each target determinant: (N_a, H_aa, is an input determinant, number of
+    connected core determinants), evaluated one target at a time."""
+    keep, hp, ep, n = _ham(h, eri)
+    d, dp = _u(dets)
+    c, cp = _d(coeffs)
+    t, tp = _u(np.asarray(targets, dtype=np.uint64).reshape(-1, 2))
+    m = t.shape[0]
+    num = np.zeros(m)
+    hd = np.zeros(m)
+    inp = np.zeros(m, dtype=np.int32)
+    nconn = np.zeros(m, dtype=np.int64)
+    rc = lib().oracle_target_numerators(hp, ep, n, nalpha, nbeta, ecore, dp, cp, len(c), int(ncore), tp, m,
+                                        num.ctypes.data_as(C.POINTER(C.c_double)),
+                                        hd.ctypes.data_as(C.POINTER(C.c_double)),
+                                        inp.ctypes.data_as(C.POINTER(C.c_int)),
+                                        nconn.ctypes.data_as(C.POINTER(C.c_int64)))
+    if rc != 0:
+        raise ValueError("invalid determinants")
+    return num, hd, inp.astype(bool), nconn

@@ -545,3 +545,40 @@ int64_t oracle_class_counts(int n, int na, int nb, const uint64_t *dets, const d
     free(core);
     return nc;
 }
+
+/* ---- numerators of given targets, one at a time (for sampled checks) ----
+ * N_a = sum over core determinants i (ascending input index) that differ from
+ * a by a single or double excitation of H_ai C_i; also reports whether a is an
+ * input determinant.  Same arithmetic as oracle_search, without the sort. */
+int oracle_target_numerators(const double *h, const double *eri, int n, int na, int nb, double ecore,
+                             const uint64_t *dets, const double *coeffs, int64_t ndets, int64_t ncore,
+                             const uint64_t *targets, int64_t ntargets, double *out_num,
+                             double *out_hdiag, int *out_in_psi, int64_t *out_nconn)
+{
+    if (validate(n, na, nb, dets, ndets) != ORACLE_OK)
+        return ORACLE_EINVAL;
+    int64_t *core = malloc(sizeof(int64_t) * (size_t)(ndets + 1));
+    int64_t nq = oracle_core_set(coeffs, ndets, ncore, core);
+    for (int64_t t = 0; t < ntargets; ++t) {
+        uint64_t ta = targets[2 * t], tb = targets[2 * t + 1];
+        double s = 0.0;
+        int64_t nc = 0;
+        for (int64_t c = 0; c < nq; ++c) {
+            int64_t i = core[c];
+            int d = popc(ta ^ dets[2 * i]) + popc(tb ^ dets[2 * i + 1]);
+            if (d == 0 || d > 4)
+                continue;
+            s = s + oracle_helem(h, eri, n, ecore, ta, tb, dets[2 * i], dets[2 * i + 1]) * coeffs[i];
+            ++nc;
+        }
+        int in_psi = 0;
+        for (int64_t i = 0; i < ndets; ++i)
+            if (dets[2 * i] == ta && dets[2 * i + 1] == tb) { in_psi = 1; break; }
+        out_num[t] = s;
+        out_hdiag[t] = oracle_hdiag(h, eri, n, ecore, ta, tb);
+        out_in_psi[t] = in_psi;
+        out_nconn[t] = nc;
+    }
+    free(core);
+    return ORACLE_OK;
+}

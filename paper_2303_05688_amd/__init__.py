@@ -1,0 +1,243 @@
+"""MI355X (gfx950) ASCI determinant search: Python binding of libasci.so.
+
+Argument marshalling only: every step of the search runs in the HIP library.
+Device arrays are torch tensors on a ROCm device (PyTorch provides device
+memory and streams); work is queued on torch's current stream.  Importing this
+package raises if the library has not been built (see ``build.py``); there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasci.so")
+
+ASCI_OK, ASCI_EINVAL, ASCI_ENOMEM, ASCI_EDEVICE = 0, -1, -2, -3
+
+
+class AsciError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % ({-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE"}.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("ncore", C.c_int64), ("eps", C.c_double), ("constraint_level", C.c_int32),
+                ("ecore", C.c_double), ("pair_buffer_bytes", C.c_int64)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libasci.so is not built: run `python -m paper_2303_05688_amd.build` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = C.CDLL(LIB_PATH)
+_vp, _dp, _up, _ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.POINTER(C.c_int64)
+_lib.asci_version.restype = C.c_int
+_lib.asci_strerror.restype = C.c_char_p
+_lib.asci_strerror.argtypes = [C.c_int]
+_lib.asci_last_error.restype = C.c_char_p
+_lib.asci_options_default.argtypes = [C.POINTER(Options)]
+_lib.asci_ctx_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+_lib.asci_ctx_destroy.argtypes = [_vp]
+_lib.asci_search.argtypes = [_dp, _dp, C.c_int, C.c_int, C.c_int, _up, _dp, C.c_int64, C.c_double, C.c_int64,
+                             C.POINTER(Options), _up, _dp, _ip]
+_lib.asci_search_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
+                                    C.c_int64, C.POINTER(Options), _vp, _vp, _ip, _vp]
+_lib.asci_candidates_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64,
+                                        C.c_double, C.POINTER(Options), C.c_int64, _vp, _vp, _vp, _ip, _vp]
+_lib.asci_class_counts_device.argtypes = [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64,
+                                          C.POINTER(Options), C.c_int64, _up, _ip, _ip, _vp]
+_lib.asci_energy_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
+                                    _dp, _vp]
+
+_lib.asci_ctx_set_profiling.argtypes = [_vp, C.c_int]
+_lib.asci_ctx_profile_entry.argtypes = [_vp, C.c_int, C.c_char_p, C.c_int, _dp, _ip, _dp]
+
+EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_default", "asci_ctx_create",
+           "asci_ctx_destroy", "asci_ctx_set_profiling", "asci_ctx_profile_entry", "asci_search",
+           "asci_search_device", "asci_candidates_device", "asci_class_counts_device", "asci_energy_device"]
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != ASCI_OK:
+        raise AsciError(rc, _lib.asci_last_error().decode())
+
+
+def options(ncore=0, eps=0.0, ecore=0.0, pair_buffer_bytes=0, constraint_level=3):
+    o = Options()
+    _lib.asci_options_default(C.byref(o))
+    o.ncore, o.eps, o.ecore = int(ncore), float(eps), float(ecore)
+    o.pair_buffer_bytes, o.constraint_level = int(pair_buffer_bytes), int(constraint_level)
+    return o
+
+
+class Context:
+    """One asci_ctx (device workspace) per device."""
+
+    _cache = {}
+
+    def __init__(self, device=0):
+        self.device = device
+        self.ptr = C.c_void_p()
+        _check(_lib.asci_ctx_create(device, C.byref(self.ptr)))
+
+    @classmethod
+    def get(cls, device=0):
+        if device not in cls._cache:
+            cls._cache[device] = cls(device)
+        return cls._cache[device]
+
+    def set_profiling(self, enable=True):
+        _check(_lib.asci_ctx_set_profiling(self.ptr, int(bool(enable))))
+
+    def profile(self):
+        """{kernel name: (total ms, launches, algorithmic bytes)} since profiling was enabled."""
+        out = {}
+        i = 0
+        buf = C.create_string_buffer(64)
+        ms, nl, by = C.c_double(), C.c_int64(), C.c_double()
+        while _lib.asci_ctx_profile_entry(self.ptr, i, buf, 64, C.byref(ms), C.byref(nl), C.byref(by)) == 0:
+            out[buf.value.decode()] = (ms.value, nl.value, by.value)
+            i += 1
+        return out
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                _lib.asci_ctx_destroy(self.ptr)
+        except Exception:
+            pass
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("expected a tensor on a ROCm device")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("expected a contiguous %s tensor" % dtype)
+    return t.data_ptr()
+
+
+def _stream(device):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dets_tensor(dets):
+    torch = _torch()
+    if dets.dtype == torch.uint64:
+        return dets
+    if dets.dtype == torch.int64:
+        return dets.view(torch.uint64)
+    raise TypeError("determinants must be uint64 (or int64 bit patterns)")
+
+
+def search(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, ecore=0.0,
+           pair_buffer_bytes=0, ctx=None):
+    """ASCI search on device tensors: returns (dets[m, 2] uint64, scores[m] float64)
+    on the same device, ordered by |score| descending, ties by key ascending."""
+    torch = _torch()
+    dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or Context.get(dev)
+    dets = _dets_tensor(dets)
+    out_d = torch.empty((int(k), 2), dtype=torch.uint64, device=h.device)
+    out_s = torch.empty((int(k),), dtype=torch.float64, device=h.device)
+    cnt = C.c_int64(0)
+    o = options(ncore, eps, ecore, pair_buffer_bytes)
+    _check(_lib.asci_search_device(ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
+                                   _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0],
+                                   float(E0), int(k), C.byref(o), out_d.data_ptr(), out_s.data_ptr(),
+                                   C.byref(cnt), _stream(dev)))
+    m = cnt.value
+    return out_d[:m], out_s[:m]
+
+
+def candidates(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, ecore=0.0,
+               pair_buffer_bytes=0, ctx=None):
+    """Every candidate, ascending key: (dets[U, 2], N_a[U], A_a[U]) on the device."""
+    torch = _torch()
+    dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or Context.get(dev)
+    dets = _dets_tensor(dets)
+    o = options(ncore, eps, ecore, pair_buffer_bytes)
+    cnt = C.c_int64(0)
+    args = (ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
+            _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0], float(E0), C.byref(o))
+    rc = _lib.asci_candidates_device(*args, 0, None, None, None, C.byref(cnt), _stream(dev))
+    if rc not in (ASCI_OK, ASCI_ENOMEM) or (rc == ASCI_ENOMEM and cnt.value == 0):
+        _check(rc)
+    U = cnt.value
+    out_d = torch.empty((max(U, 1), 2), dtype=torch.uint64, device=h.device)
+    out_n = torch.empty((max(U, 1),), dtype=torch.float64, device=h.device)
+    out_s = torch.empty((max(U, 1),), dtype=torch.float64, device=h.device)
+    _check(_lib.asci_candidates_device(*args, U, out_d.data_ptr(), out_n.data_ptr(), out_s.data_ptr(),
+                                       C.byref(cnt), _stream(dev)))
+    return out_d[:U], out_n[:U], out_s[:U]
+
+
+def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0, ctx=None):
+    """Non-empty triplet classes: (masks uint64[m], counts int64[m]) as numpy arrays."""
+    torch = _torch()
+    dev = dets.device.index if dets.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or Context.get(dev)
+    dets = _dets_tensor(dets)
+    o = options(ncore)
+    cnt = C.c_int64(0)
+    cap = 1
+    for _ in range(2):
+        masks = np.zeros(cap, dtype=np.uint64)
+        counts = np.zeros(cap, dtype=np.int64)
+        rc = _lib.asci_class_counts_device(ctx.ptr, norb, nalpha, nbeta, _dev(dets, torch.uint64),
+                                           _dev(coeffs, torch.float64), dets.shape[0], C.byref(o), cap,
+                                           masks.ctypes.data_as(_up), counts.ctypes.data_as(_ip), C.byref(cnt),
+                                           _stream(dev))
+        if rc == ASCI_OK:
+            return masks[:cnt.value], counts[:cnt.value]
+        if rc != ASCI_ENOMEM:
+            _check(rc)
+        cap = cnt.value
+    _check(rc)
+
+
+def energy(h, eri, norb, nalpha, nbeta, dets, coeffs, ecore=0.0, ctx=None):
+    """<C|H|C> over the given determinants, computed on the device."""
+    torch = _torch()
+    dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or Context.get(dev)
+    dets = _dets_tensor(dets)
+    e = C.c_double(0.0)
+    _check(_lib.asci_energy_device(ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
+                                   _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0],
+                                   float(ecore), C.byref(e), _stream(dev)))
+    return e.value
+
+
+def search_host(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, ecore=0.0,
+                pair_buffer_bytes=0):
+    """The host-buffer entry point (asci_search): numpy in, numpy out."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    dets = np.ascontiguousarray(dets, dtype=np.uint64)
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+    out_d = np.zeros((int(k), 2), dtype=np.uint64)
+    out_s = np.zeros(int(k), dtype=np.float64)
+    cnt = C.c_int64(0)
+    o = options(ncore, eps, ecore, pair_buffer_bytes)
+    _check(_lib.asci_search(h.ctypes.data_as(_dp), eri.ctypes.data_as(_dp), norb, nalpha, nbeta,
+                            dets.ctypes.data_as(_up), coeffs.ctypes.data_as(_dp), len(coeffs), float(E0), int(k),
+                            C.byref(o), out_d.ctypes.data_as(_up), out_s.ctypes.data_as(_dp), C.byref(cnt)))
+    m = cnt.value
+    return out_d[:m], out_s[:m]

@@ -1,0 +1,332 @@
+// C ABI of the ASCI search library: argument checks, contexts, host-buffer
+// staging, and translation of internal errors into return codes.
+#include "asci_internal.h"
+
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+namespace asci {
+
+void Arena::reserve(size_t bytes)
+{
+    if (bytes <= cap_) return;
+    release();
+    bytes = (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{ASCI_ENOMEM, "hipMalloc of the workspace failed"};
+    }
+    base_ = (char *)p;
+    cap_ = bytes;
+    used_ = 0;
+}
+
+void Arena::release()
+{
+    if (base_) (void)hipFree(base_);
+    base_ = nullptr;
+    cap_ = used_ = 0;
+}
+
+void HostStage::reserve(size_t b)
+{
+    if (b <= bytes) return;
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    ASCI_HIP(hipHostMalloc(&ptr, b, hipHostMallocDefault));
+    bytes = b;
+}
+
+HostStage::~HostStage()
+{
+    if (ptr) (void)hipHostFree(ptr);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(const Error &e)
+{
+    g_last_error = e.what;
+    return e.code;
+}
+
+void check_common(int norb, int nalpha, int nbeta, int64_t ndets)
+{
+    require(norb >= 1 && norb <= 64, ASCI_EINVAL, "norb must be in [1, 64]");
+    require(nalpha >= 0 && nalpha <= norb && nbeta >= 0 && nbeta <= norb, ASCI_EINVAL,
+            "nalpha and nbeta must be in [0, norb]");
+    require(ndets >= 1 && ndets < ((int64_t)1 << 31), ASCI_EINVAL, "ndets must be in [1, 2^31)");
+}
+
+asci_options resolve(const asci_options *opt)
+{
+    asci_options o;
+    asci_options_default(&o);
+    if (opt) o = *opt;
+    require(o.constraint_level == 3, ASCI_EINVAL, "only triplet constraints (level 3) are implemented");
+    require(o.ncore >= 0, ASCI_EINVAL, "ncore must be >= 0");
+    require(o.pair_buffer_bytes >= 0, ASCI_EINVAL, "pair_buffer_bytes must be >= 0");
+    require(!(o.eps < 0.0) && o.eps == o.eps, ASCI_EINVAL, "eps must be >= 0");
+    return o;
+}
+
+struct Staging {
+    Arena io;
+};
+
+std::mutex g_mu;
+std::map<int, std::unique_ptr<asci_ctx>> g_ctx;
+std::map<int, std::unique_ptr<Staging>> g_io;
+
+}  // namespace
+
+}  // namespace asci
+
+using namespace asci;
+
+extern "C" {
+
+int asci_version(void) { return (1 << 16) | 0; }
+
+const char *asci_strerror(int code)
+{
+    switch (code) {
+    case ASCI_OK: return "success";
+    case ASCI_EINVAL: return "invalid argument";
+    case ASCI_ENOMEM: return "out of memory or capacity";
+    case ASCI_EDEVICE: return "HIP device error";
+    default: return "unknown error";
+    }
+}
+
+const char *asci_last_error(void) { return g_last_error.c_str(); }
+
+void asci_options_default(asci_options *opt)
+{
+    if (!opt) return;
+    opt->ncore = 0;
+    opt->eps = 0.0;
+    opt->constraint_level = 3;
+    opt->ecore = 0.0;
+    opt->pair_buffer_bytes = 0;
+}
+
+int asci_ctx_create(int device, asci_ctx **out)
+{
+    try {
+        require(out != nullptr, ASCI_EINVAL, "null output pointer");
+        int ndev = 0;
+        ASCI_HIP(hipGetDeviceCount(&ndev));
+        require(device >= 0 && device < ndev, ASCI_EINVAL, "no such device");
+        ASCI_HIP(hipSetDevice(device));
+        asci_ctx *c = new asci_ctx();
+        c->device = device;
+        *out = c;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_ctx_destroy(asci_ctx *ctx)
+{
+    if (!ctx) return ASCI_OK;
+    try {
+        ASCI_HIP(hipSetDevice(ctx->device));
+        ASCI_HIP(hipDeviceSynchronize());
+    } catch (const Error &e) {
+        delete ctx;
+        return fail(e);
+    }
+    delete ctx;
+    return ASCI_OK;
+}
+
+int asci_ctx_set_profiling(asci_ctx *ctx, int enable)
+{
+    try {
+        require(ctx != nullptr, ASCI_EINVAL, "null context");
+        ASCI_HIP(hipSetDevice(ctx->device));
+        ctx->prof.reset();
+        ctx->prof.on = enable != 0;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_ctx_profile_entry(asci_ctx *ctx, int index, char *name, int name_cap, double *total_ms,
+                           int64_t *launches, double *bytes)
+{
+    try {
+        require(ctx != nullptr, ASCI_EINVAL, "null context");
+        ctx->prof.collect();
+        require(index >= 0 && index < (int)ctx->prof.entries.size(), ASCI_EINVAL, "no such profile entry");
+        const ProfEntry &e = ctx->prof.entries[(size_t)index];
+        if (name && name_cap > 0) {
+            std::strncpy(name, e.name.c_str(), (size_t)name_cap - 1);
+            name[name_cap - 1] = 0;
+        }
+        if (total_ms) *total_ms = e.ms;
+        if (launches) *launches = e.launches;
+        if (bytes) *bytes = e.bytes;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_search_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                       const uint64_t *d_dets, const double *d_coeffs, int64_t ndets, double E0, int64_t k,
+                       const asci_options *opt, uint64_t *d_out_dets, double *d_out_scores, int64_t *out_count,
+                       void *stream)
+{
+    try {
+        require(ctx && d_h && d_eri && d_dets && d_coeffs && d_out_dets && d_out_scores && out_count, ASCI_EINVAL,
+                "null pointer argument");
+        check_common(norb, nalpha, nbeta, ndets);
+        require(k >= 1, ASCI_EINVAL, "k must be >= 1");
+        ASCI_HIP(hipSetDevice(ctx->device));
+        SearchArgs in{d_h, d_eri, norb, nalpha, nbeta, d_dets, d_coeffs, ndets, E0, resolve(opt)};
+        SearchOut out;
+        out.k = k;
+        out.out_dets = d_out_dets;
+        out.out_scores = d_out_scores;
+        search_device(ctx, in, out, (hipStream_t)stream);
+        *out_count = out.count;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_candidates_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha,
+                           int nbeta, const uint64_t *d_dets, const double *d_coeffs, int64_t ndets, double E0,
+                           const asci_options *opt, int64_t capacity, uint64_t *d_out_dets, double *d_out_num,
+                           double *d_out_scores, int64_t *out_count, void *stream)
+{
+    try {
+        require(ctx && d_h && d_eri && d_dets && d_coeffs && out_count, ASCI_EINVAL, "null pointer argument");
+        require(capacity == 0 || (d_out_dets && d_out_num && d_out_scores), ASCI_EINVAL, "null output buffer");
+        require(capacity >= 0, ASCI_EINVAL, "capacity must be >= 0");
+        check_common(norb, nalpha, nbeta, ndets);
+        ASCI_HIP(hipSetDevice(ctx->device));
+        SearchArgs in{d_h, d_eri, norb, nalpha, nbeta, d_dets, d_coeffs, ndets, E0, resolve(opt)};
+        SearchOut out;
+        out.k = 0;
+        out.capacity = capacity;
+        out.out_dets = d_out_dets;
+        out.out_num = d_out_num;
+        out.out_scores = d_out_scores;
+        search_device(ctx, in, out, (hipStream_t)stream);
+        *out_count = out.count;
+        if (out.count > capacity) throw Error{ASCI_ENOMEM, "output capacity below the candidate count"};
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_class_counts_device(asci_ctx *ctx, int norb, int nalpha, int nbeta, const uint64_t *d_dets,
+                             const double *d_coeffs, int64_t ndets, const asci_options *opt, int64_t capacity,
+                             uint64_t *h_masks, int64_t *h_counts, int64_t *out_nclasses, void *stream)
+{
+    try {
+        require(ctx && d_dets && d_coeffs && out_nclasses, ASCI_EINVAL, "null pointer argument");
+        require(capacity >= 0 && (capacity == 0 || (h_masks && h_counts)), ASCI_EINVAL, "bad output buffers");
+        check_common(norb, nalpha, nbeta, ndets);
+        const asci_options o = resolve(opt);
+        ASCI_HIP(hipSetDevice(ctx->device));
+        std::vector<uint64_t> masks, counts;
+        class_counts_device(ctx, norb, nalpha, nbeta, d_dets, d_coeffs, ndets, o.ncore, masks, counts,
+                            (hipStream_t)stream);
+        *out_nclasses = (int64_t)masks.size();
+        require((int64_t)masks.size() <= capacity, ASCI_ENOMEM, "output capacity below the class count");
+        for (size_t i = 0; i < masks.size(); ++i) {
+            h_masks[i] = masks[i];
+            h_counts[i] = (int64_t)counts[i];
+        }
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_energy_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                       const uint64_t *d_dets, const double *d_coeffs, int64_t ndets, double ecore,
+                       double *out_energy, void *stream)
+{
+    try {
+        require(ctx && d_h && d_eri && d_dets && d_coeffs && out_energy, ASCI_EINVAL, "null pointer argument");
+        check_common(norb, nalpha, nbeta, ndets);
+        ASCI_HIP(hipSetDevice(ctx->device));
+        validate_dets(ctx, d_dets, ndets, norb, nalpha, nbeta, (hipStream_t)stream);
+        *out_energy = energy_device(ctx, d_h, d_eri, norb, d_dets, d_coeffs, ndets, ecore, (hipStream_t)stream);
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_search(const double *h, const double *eri, int norb, int nalpha, int nbeta, const uint64_t *dets,
+                const double *coeffs, int64_t ndets, double E0, int64_t k, const asci_options *opt,
+                uint64_t *out_dets, double *out_scores, int64_t *out_count)
+{
+    try {
+        require(h && eri && dets && coeffs && out_dets && out_scores && out_count, ASCI_EINVAL,
+                "null pointer argument");
+        check_common(norb, nalpha, nbeta, ndets);
+        require(k >= 1, ASCI_EINVAL, "k must be >= 1");
+        const asci_options o = resolve(opt);
+        int dev = 0;
+        ASCI_HIP(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto &slot = g_ctx[dev];
+        if (!slot) {
+            asci_ctx *c = nullptr;
+            int rc = asci_ctx_create(dev, &c);
+            if (rc != ASCI_OK) return rc;
+            slot.reset(c);
+        }
+        auto &io = g_io[dev];
+        if (!io) io.reset(new Staging());
+        const size_t n = (size_t)norb, nd = (size_t)ndets;
+        io->io.reset();
+        io->io.reserve(n * n * 8 + n * n * n * n * 8 + nd * 24 + (size_t)k * 24 + 8 * 256);
+        io->io.reset();
+        double *dh = io->io.take<double>(n * n);
+        double *de = io->io.take<double>(n * n * n * n);
+        uint64_t *dd = io->io.take<uint64_t>(2 * nd);
+        double *dc = io->io.take<double>(nd);
+        uint64_t *od = io->io.take<uint64_t>(2 * (size_t)k);
+        double *os = io->io.take<double>((size_t)k);
+        hipStream_t s = nullptr;
+        ASCI_HIP(hipMemcpy(dh, h, n * n * 8, hipMemcpyHostToDevice));
+        ASCI_HIP(hipMemcpy(de, eri, n * n * n * n * 8, hipMemcpyHostToDevice));
+        ASCI_HIP(hipMemcpy(dd, dets, nd * 16, hipMemcpyHostToDevice));
+        ASCI_HIP(hipMemcpy(dc, coeffs, nd * 8, hipMemcpyHostToDevice));
+        SearchArgs in{dh, de, norb, nalpha, nbeta, dd, dc, ndets, E0, o};
+        SearchOut out;
+        out.k = k;
+        out.out_dets = od;
+        out.out_scores = os;
+        search_device(slot.get(), in, out, s);
+        if (out.count > 0) {
+            ASCI_HIP(hipMemcpy(out_dets, od, (size_t)out.count * 16, hipMemcpyDeviceToHost));
+            ASCI_HIP(hipMemcpy(out_scores, os, (size_t)out.count * 8, hipMemcpyDeviceToHost));
+        }
+        *out_count = out.count;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// Internal declarations of the ASCI search library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/asci.h"
+
+namespace asci {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string what;
+};
+
+#define ASCI_HIP(call)                                                              \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            throw ::asci::Error{e_ == hipErrorOutOfMemory ? ASCI_ENOMEM : ASCI_EDEVICE, \
+                                std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define ASCI_LAUNCH_CHECK() ASCI_HIP(hipGetLastError())
+
+inline void require(bool ok, int code, const char *what)
+{
+    if (!ok)
+        throw Error{code, what};
+}
+
+// ---------------------------------------------------------------- workspace
+// A bump allocator over one device allocation that grows on demand.  Every
+// search carves its buffers from it; nothing is freed until the context dies.
+class Arena {
+  public:
+    ~Arena() { release(); }
+    void reserve(size_t bytes);  // ensure capacity; invalidates earlier carves
+    void reset() { used_ = 0; }
+    template <typename T> T *take(size_t count)
+    {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        require(used_ + bytes <= cap_, ASCI_ENOMEM, "workspace exhausted (internal sizing error)");
+        T *p = reinterpret_cast<T *>(base_ + used_);
+        used_ += bytes;
+        return p;
+    }
+    size_t used() const { return used_; }
+    size_t capacity() const { return cap_; }
+    void release();
+
+  private:
+    char *base_ = nullptr;
+    size_t cap_ = 0, used_ = 0;
+};
+
+// Pinned host staging for small device->host reads.
+struct HostStage {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void reserve(size_t b);
+    ~HostStage();
+};
+
+// Per-kernel timing with HIP events on the launching stream (opt-in).  Each
+// timed launch also carries its algorithmic byte count, so achieved bandwidth
+// can be derived from the events alone.
+struct ProfEntry {
+    std::string name;
+    double ms = 0.0;
+    int64_t launches = 0;
+    double bytes = 0.0;
+};
+
+class Profiler {
+  public:
+    ~Profiler();
+    bool on = false;
+    std::vector<ProfEntry> entries;
+    int begin(const char *name, double bytes, hipStream_t s);  // -1 when off
+    void end(int token, hipStream_t s);
+    void collect();  // after the stream has been synchronised
+    void reset();
+
+  private:
+    struct Pending {
+        int entry;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Pending> pending_;
+    std::vector<hipEvent_t> pool_;
+    hipEvent_t get_event();
+};
+
+// RAII helper: times the launches issued in its scope
+struct ProfScope {
+    Profiler *p;
+    int tok;
+    hipStream_t s;
+    ProfScope(Profiler *p_, const char *name, double bytes, hipStream_t s_) : p(p_), tok(-1), s(s_)
+    {
+        if (p && p->on) tok = p->begin(name, bytes, s);
+    }
+    ~ProfScope()
+    {
+        if (p && tok >= 0) p->end(tok, s);
+    }
+};
+
+}  // namespace asci
+
+struct asci_ctx {
+    int device = 0;
+    asci::Profiler prof;
+    asci::Arena setup;  // inputs, sorted psi keys, core set, class totals
+    asci::Arena main;   // per-batch pair buffers, candidate pool, selection
+    asci::HostStage stage;
+};
+
+namespace asci {
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+__device__ __forceinline__ int lowbit(uint64_t x) { return __ffsll((unsigned long long)x) - 1; }
+
+// index of the k-th (0-based) set bit of x; requires k < popc64(x)
+__device__ __forceinline__ int select_bit(uint64_t x, int k)
+{
+    int pos = 0;
+    int c = __popc((uint32_t)x);
+    if (k >= c) { k -= c; x >>= 32; pos += 32; }
+    c = __popc((uint32_t)x & 0xFFFFu);
+    if (k >= c) { k -= c; x >>= 16; pos += 16; }
+    c = __popc((uint32_t)x & 0xFFu);
+    if (k >= c) { k -= c; x >>= 8; pos += 8; }
+    c = __popc((uint32_t)x & 0xFu);
+    if (k >= c) { k -= c; x >>= 4; pos += 4; }
+    c = __popc((uint32_t)x & 0x3u);
+    if (k >= c) { k -= c; x >>= 2; pos += 2; }
+    if (k >= (int)(x & 1u)) pos += 1;
+    return pos;
+}
+
+// (-1)^(set bits of occ strictly between orbitals p and q), p != q
+__device__ __forceinline__ int between_sign(uint64_t occ, int p, int q)
+{
+    int lo = p < q ? p : q, hi = p < q ? q : p;
+    uint64_t m = ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
+    return (popc64(occ & m) & 1) ? -1 : 1;
+}
+
+// pairs (i < j) enumerated j-major: x = j(j-1)/2 + i
+__device__ __forceinline__ void unrank_pair(uint32_t x, int &i, int &j)
+{
+    int jj = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)x)) * 0.5f);
+    while ((uint32_t)(jj * (jj - 1) / 2) > x) --jj;
+    while ((uint32_t)((jj + 1) * jj / 2) <= x) ++jj;
+    j = jj;
+    i = (int)(x - (uint32_t)(jj * (jj - 1) / 2));
+}
+
+__device__ __forceinline__ uint64_t choose_small(uint64_t x, int k)
+{
+    return k == 0 ? 1ull : (k == 1 ? x : (x * (x - 1ull)) / 2ull);
+}
+
+// k (0, 1 or 2) set bits of `mask`, chosen by index idx in [0, C(popc(mask), k))
+__device__ __forceinline__ uint64_t pick_bits(uint64_t mask, int k, uint32_t idx)
+{
+    if (k == 0) return 0ull;
+    if (k == 1) return 1ull << select_bit(mask, (int)idx);
+    int i, j;
+    unrank_pair(idx, i, j);
+    return (1ull << select_bit(mask, i)) | (1ull << select_bit(mask, j));
+}
+
+// IEEE-754 bit pattern of |x|: orders non-negative doubles as integers
+__device__ __forceinline__ uint64_t abs_order(double x)
+{
+    return (uint64_t)__double_as_longlong(x) & 0x7fffffffffffffffull;
+}
+
+// ---------------------------------------------------------------- key layout
+// Keys: for norb <= 32 a single word (alpha << norb) | beta ("packed"); above,
+// two words (hi = alpha, lo = beta).  Both orders equal (alpha, beta) order.
+struct KeySpec {
+    int norb;
+    int words;  // 1 or 2
+};
+
+// ---------------------------------------------------------------- primitives (prims.hip)
+constexpr int kScanTile = 4096;
+
+// exclusive scan of n uint32 values (n < 2^28); *d_total (device) gets the sum
+void scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, Arena &ar,
+              hipStream_t s, Profiler *prof = nullptr);
+
+// stable LSD radix sort by selected 8-bit digits of a 1- or 2-word key, with a
+// payload.  keys_lo/keys_hi/vals are ping-pong pairs; `digits` lists (word,
+// shift) from least significant.  Returns the index (0/1) of the buffer that
+// holds the result.
+struct Digit {
+    int word;   // 0 = lo word, 1 = hi word
+    int shift;  // bit offset of the 8-bit digit
+};
+template <typename V>
+int radix_sort(uint64_t *keys_lo[2], uint64_t *keys_hi[2], V *vals[2], size_t n, int words,
+               const std::vector<Digit> &digits, Arena &ar, hipStream_t s, Profiler *prof = nullptr);
+
+// radix selection on the IEEE bit pattern of |score[j]|, j < n: finds t, the
+// k-th largest value (1 <= k <= n), and how many entries equal to t must be
+// taken (device struct).  The caller then keeps ord > t, plus the first
+// `take_equal` entries with ord == t.
+struct SelectState {
+    uint64_t prefix;
+    uint64_t mask;
+    uint64_t krem;  // after the passes: number of entries equal to t to take
+    uint32_t hist[256];
+};
+void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_state,
+                      hipStream_t s, Profiler *prof = nullptr);
+
+// ---------------------------------------------------------------- search (search.hip)
+struct SearchArgs {
+    const double *h, *eri;  // device
+    int n, na, nb;
+    const uint64_t *dets;   // device, ndets x 2
+    const double *coeffs;   // device
+    int64_t ndets;
+    double E0;
+    asci_options opt;
+};
+
+struct SearchOut {
+    int64_t k = 0;                 // > 0: top-k mode; 0: every candidate
+    uint64_t *out_dets = nullptr;  // device
+    double *out_scores = nullptr;  // device
+    int64_t capacity = 0;          // every-candidate mode: output length
+    double *out_num = nullptr;     // every-candidate mode: N_a (device)
+    int64_t count = 0;             // result count
+};
+
+void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s);
+void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *dets, const double *coeffs,
+                         int64_t ndets, int64_t ncore, std::vector<uint64_t> &masks,
+                         std::vector<uint64_t> &counts, hipStream_t s);
+// throws ASCI_EINVAL unless every determinant has na/nb electrons inside norb orbitals
+void validate_dets(asci_ctx *ctx, const uint64_t *dets, int64_t ndets, int n, int na, int nb, hipStream_t s);
+double energy_device(asci_ctx *ctx, const double *h, const double *eri, int n, const uint64_t *dets,
+                     const double *coeffs, int64_t ndets, double ecore, hipStream_t s);
+
+}  // namespace asci

@@ -1,0 +1,93 @@
+// Slater-Condon matrix elements on 64-bit occupation strings (device side).
+//
+// Phase convention: spin orbitals alpha first then beta, ascending; a^+_q a_p
+// on a determinant has sign (-1)^(occupied orbitals of that spin strictly
+// between p and q).  Integrals: h[p*n+q], eri[((p*n+q)*n+r)*n+s] = (pq|rs).
+// Sums run in ascending orbital order and the library is built without
+// floating-point contraction, so every value is reproducible bit for bit.
+#pragma once
+
+#include "asci_internal.h"
+
+namespace asci {
+
+// Orbital indices come from validated bit strings; the clamp only keeps a
+// logic error from turning into an out-of-bounds load.
+__device__ __forceinline__ int orb(int p, int n) { return (int)min((unsigned)p, (unsigned)(n - 1)); }
+
+__device__ __forceinline__ double eri4(const double *__restrict__ eri, int n, int p, int q, int r, int s)
+{
+    return eri[(((size_t)orb(p, n) * n + orb(q, n)) * n + orb(r, n)) * n + orb(s, n)];
+}
+
+// <a|H|i> for a single p -> q in the spin string `same` of i; `other` is the
+// other spin string of i:
+//   sign * ( h_qp + sum_{r in same, r != p} [(qp|rr) - (qr|rp)] + sum_{r in other} (qp|rr) )
+__device__ __forceinline__ double single_value(const double *__restrict__ h,
+                                               const double *__restrict__ eri, int n, uint64_t same,
+                                               uint64_t other, int p, int q)
+{
+    double v = h[(size_t)orb(q, n) * n + orb(p, n)];
+    for (uint64_t m = same & ~(1ull << p); m; m &= m - 1ull) {
+        const int r = lowbit(m);
+        v = v + (eri4(eri, n, q, p, r, r) - eri4(eri, n, q, r, r, p));
+    }
+    for (uint64_t m = other; m; m &= m - 1ull) {
+        const int r = lowbit(m);
+        v = v + eri4(eri, n, q, p, r, r);
+    }
+    return between_sign(same, p, q) * v;
+}
+
+// same-spin double: holes p < r (in string si), particles q < s
+//   sign(p->q on si) * sign(r->s on si') * [(qp|sr) - (qr|sp)]
+__device__ __forceinline__ double double_same_value(const double *__restrict__ eri, int n, uint64_t si,
+                                                    uint64_t holes, uint64_t parts)
+{
+    const int p = lowbit(holes), r = lowbit(holes & (holes - 1ull));
+    const int q = lowbit(parts), s = lowbit(parts & (parts - 1ull));
+    const int s1 = between_sign(si, p, q);
+    const uint64_t mid = (si & ~(1ull << p)) | (1ull << q);
+    const int s2 = between_sign(mid, r, s);
+    return s1 * s2 * (eri4(eri, n, q, p, s, r) - eri4(eri, n, q, r, s, p));
+}
+
+// opposite-spin double: alpha p -> q, beta r -> s: sign_a * sign_b * (qp|sr)
+__device__ __forceinline__ double double_opp_value(const double *__restrict__ eri, int n, uint64_t ia,
+                                                   uint64_t ib, int p, int q, int r, int s)
+{
+    const int sg = between_sign(ia, p, q) * between_sign(ib, r, s);
+    return sg * eri4(eri, n, q, p, s, r);
+}
+
+// H_aa from a J/K table (J[p*n+q] = (pp|qq), K[p*n+q] = (pq|qp)) and the
+// diagonal of h, in this order: ecore, alpha h_pp, beta h_pp, alpha pairs
+// p<q of (J-K), beta pairs, then alpha x beta J.
+__device__ __forceinline__ double diag_value(const double *J, const double *K, const double *hd, int n,
+                                             double ecore, uint64_t a, uint64_t b)
+{
+    double e = ecore;
+    for (uint64_t m = a; m; m &= m - 1ull) e = e + hd[lowbit(m)];
+    for (uint64_t m = b; m; m &= m - 1ull) e = e + hd[lowbit(m)];
+    for (uint64_t m = a; m; m &= m - 1ull) {
+        const int p = lowbit(m);
+        for (uint64_t m2 = m & (m - 1ull); m2; m2 &= m2 - 1ull) {
+            const int q = lowbit(m2);
+            e = e + (J[p * n + q] - K[p * n + q]);
+        }
+    }
+    for (uint64_t m = b; m; m &= m - 1ull) {
+        const int p = lowbit(m);
+        for (uint64_t m2 = m & (m - 1ull); m2; m2 &= m2 - 1ull) {
+            const int q = lowbit(m2);
+            e = e + (J[p * n + q] - K[p * n + q]);
+        }
+    }
+    for (uint64_t m = a; m; m &= m - 1ull) {
+        const int p = lowbit(m);
+        for (uint64_t m2 = b; m2; m2 &= m2 - 1ull) e = e + J[p * n + lowbit(m2)];
+    }
+    return e;
+}
+
+}  // namespace asci

@@ -1,0 +1,58 @@
+"""The C-ABI library loads and exports every entry point include/asci.h declares
+(CPU only: no compute call is made)."""
+import ctypes
+import importlib.util
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2303_05688_amd", "libasci.so")
+
+
+def _declared():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(asci_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def built_lib():
+    if not os.path.exists(LIB):
+        spec = importlib.util.spec_from_file_location("asci_build", os.path.join(ROOT, "paper_2303_05688_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_search_entry_points():
+    names = _declared()
+    for must in ("asci_search", "asci_search_device", "asci_candidates_device", "asci_class_counts_device",
+                 "asci_energy_device", "asci_ctx_create", "asci_ctx_destroy", "asci_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(built_lib):
+    missing = [n for n in _declared() if not hasattr(built_lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls(built_lib):
+    built_lib.asci_version.restype = ctypes.c_int
+    assert built_lib.asci_version() >> 16 == 1
+    built_lib.asci_strerror.restype = ctypes.c_char_p
+    assert built_lib.asci_strerror(-1) == b"invalid argument"
+    assert built_lib.asci_strerror(0) == b"success"
+
+
+def test_binding_names_match_header(built_lib):
+    import paper_2303_05688_amd as pkg
+
+    assert sorted(pkg.EXPORTS) == _declared()

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP search (through the C ABI) against the CPU oracle.
+
+Bar: candidate sets and top-k keys bit-exact; N_a and A_a within 1e-12
+relative (both sides use the same canonical evaluation order without FMA, so
+they are expected to agree bit for bit; the tolerance is the stated bar).
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import asci_synth as syn
+from gpu_util import assert_topk_parity, host, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def asci():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_05688_amd as pkg
+
+    return pkg
+
+
+def _case(n, na, nb, ndets, seed, sampler="uniform"):
+    return syn.make_case(n, na, nb, ndets, seed, sampler=sampler, tau=max(ndets / 5.0, 1.0))
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, "search_%s.json" % name)) as f:
+        return json.load(f)
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _all_parity(asci, oracle_lib, c, E0, ncore=0, pair_buffer_bytes=0):
+    d = to_dev(c)
+    n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
+    print("case n=%d na=%d nb=%d ndets=%d seed=%s ncore=%d buf=%d" % (n, na, nb, len(c["coeffs"]), c["seed"],
+                                                                     ncore, pair_buffer_bytes), flush=True)
+    keys, num, score = asci.candidates(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, ncore=ncore,
+                                       pair_buffer_bytes=pair_buffer_bytes)
+    want = oracle_lib.search_all(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, ncore=ncore)
+    gk = host(keys)
+    assert gk.shape == want["keys"].shape
+    assert (gk == want["keys"]).all()
+    assert rel_err(host(num), want["num"]).max(initial=0) <= TOL
+    assert rel_err(host(score), want["score"]).max(initial=0) <= TOL
+    return want
+
+
+TINY = [
+    (4, 2, 2, 5, 0), (5, 2, 1, 7, 0), (6, 3, 3, 20, 0), (6, 3, 3, 20, 6), (7, 1, 2, 10, 0),
+    (7, 0, 3, 6, 0), (6, 6, 2, 4, 0), (8, 4, 3, 40, 0), (9, 5, 4, 60, 17), (10, 3, 3, 90, 0),
+    (12, 6, 6, 150, 0), (1, 1, 0, 1, 0), (3, 1, 1, 9, 0),
+]
+
+
+@pytest.mark.parametrize("n,na,nb,ndets,ncore", TINY)
+def test_candidates_tiny(asci, oracle_lib, n, na, nb, ndets, ncore):
+    c = _case(n, na, nb, ndets, seed=1000 + n * 31 + ndets)
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    _all_parity(asci, oracle_lib, c, E0, ncore=ncore)
+
+
+@pytest.mark.parametrize("n,na,nb,ndets", [(33, 3, 2, 12), (40, 4, 4, 8), (36, 2, 3, 20)])
+def test_candidates_two_word_keys(asci, oracle_lib, n, na, nb, ndets):
+    c = _case(n, na, nb, ndets, seed=77 + n)
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    _all_parity(asci, oracle_lib, c, E0)
+
+
+def test_candidates_8e12o(asci, oracle_lib):
+    c = syn.workload("8e12o")
+    g = _golden("8e12o")
+    E0 = float.fromhex(g["E0"])
+    want = _all_parity(asci, oracle_lib, c, E0)
+    assert len(want["keys"]) == g["ncandidates"]
+
+
+@pytest.mark.parametrize("buf", [1 << 16, 3 << 18, 1 << 21])
+def test_small_pair_buffer_gives_same_result(asci, oracle_lib, buf):
+    """A forced small pair buffer splits the classes into many batches."""
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    _all_parity(asci, oracle_lib, c, E0, pair_buffer_bytes=buf)
+    d = to_dev(c)
+    k1, s1 = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 2000, pair_buffer_bytes=buf)
+    k2, s2 = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 2000)
+    assert (host(k1) == host(k2)).all() and (host(s1) == host(s2)).all()
+
+
+@pytest.mark.parametrize("k", [1, 7, 2000, 50_000, 10**7])
+def test_topk_8e12o(asci, oracle_lib, k):
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    d = to_dev(c)
+    gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, k)
+    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, k)
+    assert_topk_parity(host(gk), host(gs), wk, ws, TOL)
+
+
+def test_topk_8e12o_matches_golden_hash(asci):
+    c = syn.workload("8e12o")
+    g = _golden("8e12o")
+    d = to_dev(c)
+    gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], float.fromhex(g["E0"]), c["k"])
+    assert len(gk) == g["topk_count"]
+    assert _sha(host(gk)) == g["topk_keys_sha256"]
+
+
+@pytest.mark.parametrize("ncore", [1, 50, 200])
+def test_topk_core_subset(asci, oracle_lib, ncore):
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    d = to_dev(c)
+    gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 500, ncore=ncore)
+    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 500, ncore=ncore)
+    assert_topk_parity(host(gk), host(gs), wk, ws, TOL)
+
+
+def test_host_entry_point_matches_device(asci, oracle_lib):
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    hk, hs = asci.search_host(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 1000)
+    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 1000)
+    assert_topk_parity(hk, hs, wk, ws, TOL)
+
+
+def test_class_counts(asci, oracle_lib):
+    for c in (syn.workload("8e12o"), _case(9, 4, 2, 40, 5), _case(7, 2, 3, 15, 6), _case(6, 0, 2, 5, 7),
+              _case(34, 3, 3, 10, 8)):
+        d = to_dev(c)
+        gm, gc = asci.class_counts(c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"])
+        wm, wc = oracle_lib.class_counts(c["norb"], c["nalpha"], c["nbeta"], c["dets"], c["coeffs"])
+        assert (gm == wm).all() and (gc == wc).all()
+        gm, gc = asci.class_counts(c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], ncore=3)
+        wm, wc = oracle_lib.class_counts(c["norb"], c["nalpha"], c["nbeta"], c["dets"], c["coeffs"], ncore=3)
+        assert (gm == wm).all() and (gc == wc).all()
+
+
+def test_class_counts_sum_to_closed_form_16e20o(asci, oracle_lib):
+    c = syn.workload("16e20o")
+    d = to_dev(c)
+    gm, gc = asci.class_counts(20, 8, 8, d["dets"], d["coeffs"])
+    assert len(gm) == 455  # C(20 - 8 + 3, 3) triplet classes, all non-empty here
+    assert int(gc.sum()) == _golden("16e20o")["pairs_closed_form"] == 10_000 * oracle_lib.sd_count(20, 8, 8)
+
+
+@pytest.mark.parametrize("name", ["8e12o", "16e20o"])
+def test_energy(asci, oracle_lib, name):
+    c = syn.workload(name)
+    d = to_dev(c)
+    e = asci.energy(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"])
+    assert e == pytest.approx(float.fromhex(_golden(name)["E0"]), rel=TOL)
+
+
+def test_deterministic_and_permutation_invariant(asci, oracle_lib):
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    d = to_dev(c)
+    k1, s1 = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 2000)
+    k2, s2 = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 2000)
+    assert (host(k1) == host(k2)).all() and (host(s1) == host(s2)).all()
+    perm = np.random.default_rng(0).permutation(len(c["coeffs"]))
+    cp = dict(c, dets=c["dets"][perm], coeffs=c["coeffs"][perm])
+    dp = to_dev(cp)
+    k3, s3 = asci.search(dp["h"], dp["eri"], 12, 4, 4, dp["dets"], dp["coeffs"], E0, 2000)
+    wk, ws = oracle_lib.search(cp["h"], cp["eri"], 12, 4, 4, cp["dets"], cp["coeffs"], E0, 2000)
+    assert_topk_parity(host(k3), host(s3), wk, ws, TOL)
+    assert_topk_parity(host(k3), host(s3), host(k1), host(s1), 1e-10)
+
+
+def test_invalid_inputs(asci):
+    import torch
+
+    c = _case(6, 3, 3, 10, 3)
+    d = to_dev(c)
+    bad = d["dets"].clone().view(torch.int64)
+    bad[2, 0] = 0b1111  # four alpha electrons
+    with pytest.raises(asci.AsciError) as e:
+        asci.search(d["h"], d["eri"], 6, 3, 3, bad.view(torch.uint64), d["coeffs"], 0.0, 10)
+    assert e.value.code == asci.ASCI_EINVAL
+    dup = d["dets"].clone().view(torch.int64)
+    dup[3] = dup[1]
+    with pytest.raises(asci.AsciError):
+        asci.search(d["h"], d["eri"], 6, 3, 3, dup.view(torch.uint64), d["coeffs"], 0.0, 10)
+    high = d["dets"].clone().view(torch.int64)
+    high[1, 1] = (1 << 6) | 0b11
+    with pytest.raises(asci.AsciError):
+        asci.search(d["h"], d["eri"], 6, 3, 3, high.view(torch.uint64), d["coeffs"], 0.0, 10)
+    with pytest.raises(asci.AsciError):
+        asci.search(d["h"], d["eri"], 6, 3, 3, d["dets"], d["coeffs"], 0.0, 0)
+    with pytest.raises(asci.AsciError):
+        asci.search(d["h"], d["eri"], 65, 3, 3, d["dets"], d["coeffs"], 0.0, 10)
+    with pytest.raises(asci.AsciError):
+        asci.search(d["h"], d["eri"], 6, 3, 3, d["dets"], d["coeffs"], 0.0, 10, eps=-1.0)
+
+
+def _sampled_checks(oracle_lib, c, E0, gk, gs, ncheck=1500, seed=0):
+    """Check returned candidates one at a time against the oracle: connected to
+    the core set, not an input determinant, A_a = N_a / (E0 - H_aa) within TOL."""
+    n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
+    rng = np.random.default_rng(seed)
+    m = len(gk)
+    idx = np.unique(np.concatenate([np.arange(min(m, ncheck // 3)),
+                                    rng.integers(0, m, ncheck - ncheck // 3), [m - 1]]))
+    num, hd, inp, nconn = oracle_lib.target_numerators(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"],
+                                                       gk[idx])
+    assert not inp.any()
+    assert (nconn >= 1).all()
+    want = num / (E0 - hd)
+    assert rel_err(gs[idx], want).max() <= TOL
+
+
+def test_full_size_16e20o(asci, oracle_lib):
+    """The bench workload at full size: exact candidate set and top-k against
+    the oracle's stored hashes, plus per-candidate oracle checks."""
+    c = syn.workload("16e20o")
+    g = _golden("16e20o")
+    E0 = float.fromhex(g["E0"])
+    d = to_dev(c)
+    keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], E0)
+    hk = host(keys)
+    assert len(hk) == g["ncandidates"]
+    assert _sha(hk) == g["cand_keys_sha256"]
+    hs = host(score)
+    if _sha(hs) != g["cand_score_sha256"]:  # not bit-exact: fall back to the tolerance bar, sampled
+        _sampled_checks(oracle_lib, c, E0, hk, hs, ncheck=3000, seed=1)
+    del keys, num, score
+    gk, gs = asci.search(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], E0, c["k"])
+    gk, gs = host(gk), host(gs)
+    assert len(gk) == g["topk_count"]
+    head = np.array([[a, b] for a, b, _ in g["topk_head"]], dtype=np.uint64)
+    assert (gk[:len(head)] == head).all()
+    assert rel_err(gs[:len(head)], [float.fromhex(x) for _, _, x in g["topk_head"]]).max() <= TOL
+    assert _sha(gk) == g["topk_keys_sha256"]
+    _sampled_checks(oracle_lib, c, E0, gk, gs)
+    order = np.lexsort((gk[:, 1], gk[:, 0], -np.abs(gs)))
+    assert (order == np.arange(len(gk))).all()
+
+
+def test_full_size_24e30o_sampled(asci, oracle_lib):
+    """The Cr2-shaped (24e,30o) workload: 6.7e9 pairs in class batches; checked
+    per candidate against the oracle, plus ordering and count invariants."""
+    c = syn.workload("24e30o")
+    g = _golden("24e30o")
+    E0 = float.fromhex(g["E0"])
+    d = to_dev(c)
+    gk, gs = asci.search(d["h"], d["eri"], 30, 12, 12, d["dets"], d["coeffs"], E0, c["k"])
+    gk, gs = host(gk), host(gs)
+    assert len(gk) == c["k"]
+    assert len(np.unique(gk, axis=0)) == len(gk)
+    order = np.lexsort((gk[:, 1], gk[:, 0], -np.abs(gs)))
+    assert (order == np.arange(len(gk))).all()
+    _sampled_checks(oracle_lib, c, E0, gk, gs, ncheck=600, seed=3)
