@@ -25,6 +25,7 @@ namespace asci {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr uint32_t kMaxBatchClasses = 2048;
 
 // ---------------------------------------------------------------- class items
 // Counts of one (class T, core alpha string a) item.  A target is in class T
@@ -111,110 +112,248 @@ __device__ __forceinline__ void put_key(uint64_t *klo, uint64_t *khi, size_t j, 
     }
 }
 
-// one wavefront per (class, core) entry of the batch
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_generate(
-    const uint64_t *__restrict__ core_a, const uint64_t *__restrict__ core_b,
-    const double *__restrict__ core_c, uint32_t nq, const uint64_t *__restrict__ cls, uint32_t c0,
-    uint32_t nentries, const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets,
-    const double *__restrict__ h, const double *__restrict__ eri, int n, uint64_t full, BetaFactors bf,
-    uint64_t *__restrict__ klo, uint64_t *__restrict__ khi, double *__restrict__ vals, size_t cap,
-    unsigned long long *__restrict__ key_or_and)
+// class index of an alpha string: the rank of its top-L occupied orbitals
+// among all admissible L-subsets in ascending mask order (combinatorial number
+// system on x = orbital - L0, L0 = n_alpha - L); equals the position of the
+// class in make_classes()
+__device__ __forceinline__ uint32_t class_index(uint64_t a, int L, int L0)
 {
-    const uint32_t e = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (e >= nentries) return;
-    const uint32_t cnt = counts[e];
-    if (cnt == 0) return;
-    const uint32_t i = e % nq;
-    const uint32_t c = c0 + e / nq;
-    const uint64_t a = core_a[i], b = core_b[i];
-    const double ci = core_c[i];
-    const ClassItem it = class_item(a, cls[c], full, bf);
-    const uint32_t off = offsets[e];
-    const uint64_t bvir = ~b & full;
-    const uint32_t nbvb = bf.nb * bf.vb;
+    if (L == 0) return 0u;
+    const int o1 = 63 - __clzll((long long)a);
+    a &= ~(1ull << o1);
+    const uint32_t x1 = (uint32_t)(o1 - L0);
+    if (L == 1) return x1;
+    const int o2 = 63 - __clzll((long long)a);
+    a &= ~(1ull << o2);
+    const uint32_t x2 = (uint32_t)(o2 - L0);
+    if (L == 2) return x1 * (x1 - 1u) / 2u + x2;
+    const int o3 = 63 - __clzll((long long)a);
+    const uint32_t x3 = (uint32_t)(o3 - L0);
+    return x1 * (x1 - 1u) * (x1 - 2u) / 6u + x2 * (x2 - 1u) / 2u + x3;
+}
 
-    uint64_t kor0 = 0, kand0 = ~0ull, kor1 = 0, kand1 = ~0ull;
-    for (uint32_t j0 = lane; j0 < cnt; j0 += 64) {
-        uint32_t j = j0;
-        int m;
-        if (j < it.cnt[0]) {
-            m = 0;
-        } else {
-            j -= it.cnt[0];
-            if (j < it.cnt[1]) {
-                m = 1;
+// lanes of the wave whose (active, key) equal this lane's, key < 2^nbits
+__device__ __forceinline__ uint64_t match_peers(uint32_t key, bool active, int nbits)
+{
+    uint64_t peers = __ballot(active);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+    }
+    return peers;
+}
+
+struct GenArgs {
+    const uint64_t *core_a, *core_b;
+    const double *core_c;
+    uint32_t nq;
+    uint32_t c0, nc;          // batch classes [c0, c0 + nc)
+    int nbits;                // bits of nc - 1
+    const uint32_t *offsets;  // [nc][nq] start of every (class, core) item
+    const double *h, *eri;
+    int n, na, nb, L, L0;
+    uint64_t full;
+    uint32_t nas, nbs, f0, f1, pva2, npa2, pvb2;  // table sizes and block sizes
+    uint64_t *klo, *khi;
+    double *vals;
+    size_t cap;
+    unsigned long long *key_or_and;
+};
+
+template <int W>
+__device__ __forceinline__ void emit(const GenArgs &g, size_t dst, uint64_t a2, uint64_t b2, double v,
+                                     uint64_t &or0, uint64_t &and0, uint64_t &or1, uint64_t &and1)
+{
+    if (dst < g.cap) {
+        put_key<W>(g.klo, g.khi, dst, a2, b2, g.n);
+        g.vals[dst] = v;
+    }
+    if (W == 1) {
+        const uint64_t k = (a2 << g.n) | b2;
+        or0 |= k;
+        and0 &= k;
+    } else {
+        or0 |= b2;
+        and0 &= b2;
+        or1 |= a2;
+        and1 &= a2;
+    }
+}
+
+// One wavefront per core determinant: emits every single and double of the
+// core whose target lies in the batch's classes, at the slots of the
+// (class, core) items.  Per-core tables in LDS: occupied / virtual orbital
+// lists, all alpha singles (target string, H value, class, slot) and all beta
+// singles (target string, orbitals, sign).  Records are emitted by type in
+// flattened lane-parallel loops:
+//   f0 block (alpha unchanged): beta singles, then beta-beta doubles;
+//   one block per alpha single p->q: the single itself, then the alpha-beta
+//     doubles with every beta single;
+//   alpha-alpha doubles, one record each.
+// Inside an item the record order is arbitrary (each target appears once per
+// core); items are laid out (class, core), so equal keys of different cores
+// stay in ascending core order through the stable sort.
+template <int W>
+__global__ __launch_bounds__(64) void k_generate(GenArgs g)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int n = g.n;
+    const uint32_t va = (uint32_t)(n - g.na), vb = (uint32_t)(n - g.nb);
+
+    double *asV = (double *)smem;                     // nas
+    uint64_t *asA = (uint64_t *)(asV + g.nas);        // nas
+    uint64_t *bsB = asA + g.nas;                      // nbs
+    uint32_t *asP = (uint32_t *)(bsB + g.nbs);        // nas: slot, or ~0 outside the batch
+    uint32_t *asX = asP + g.nas;                      // nas: p | q << 8 | (sign < 0) << 16
+    uint32_t *asL = asX + g.nas;                      // nas: compacted in-batch alpha singles
+    uint32_t *bsX = asL + g.nas;                      // nbs: r | s << 8 | (sign < 0) << 16
+    uint32_t *cur = bsX + g.nbs;                      // nc cursors
+    uint8_t *occA = (uint8_t *)(cur + g.nc), *virA = occA + 64, *occB = occA + 128, *virB = occA + 192;
+    __shared__ uint32_t s_nsel;
+
+    const uint64_t a = g.core_a[i], b = g.core_b[i];
+    const double ci = g.core_c[i];
+    {
+        const bool inr = lane < n;
+        const bool oa = inr && ((a >> lane) & 1ull), ob = inr && ((b >> lane) & 1ull);
+        const uint64_t boa = __ballot(oa), bva = __ballot(inr && !oa);
+        const uint64_t bob = __ballot(ob), bvb = __ballot(inr && !ob);
+        if (oa) occA[__popcll(boa & lt)] = (uint8_t)lane;
+        else if (inr) virA[__popcll(bva & lt)] = (uint8_t)lane;
+        if (ob) occB[__popcll(bob & lt)] = (uint8_t)lane;
+        else if (inr) virB[__popcll(bvb & lt)] = (uint8_t)lane;
+        for (uint32_t t = lane; t < g.nc; t += 64) cur[t] = 0u;
+    }
+    __syncthreads();
+    // alpha singles: target, class, H value (the O(n) sums, lane-parallel)
+    for (uint32_t u = lane; u < g.nas; u += 64) {
+        const int p = occA[u / va], q = virA[u % va];
+        const uint64_t a2 = (a & ~(1ull << p)) | (1ull << q);
+        const uint32_t c = class_index(a2, g.L, g.L0);
+        asA[u] = a2;
+        asV[u] = single_value(g.h, g.eri, n, a, b, p, q);
+        asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u);
+        asP[u] = (c >= g.c0 && c < g.c0 + g.nc) ? c - g.c0 : ~0u;
+    }
+    // beta singles: target, orbitals, sign
+    for (uint32_t t = lane; t < g.nbs; t += 64) {
+        const int r = occB[t / vb], s = virB[t % vb];
+        bsB[t] = (b & ~(1ull << r)) | (1ull << s);
+        bsX[t] = (uint32_t)r | ((uint32_t)s << 8) | (between_sign(b, r, s) < 0 ? (1u << 16) : 0u);
+    }
+    const uint32_t cs = class_index(a, g.L, g.L0);
+    const bool self_in = cs >= g.c0 && cs < g.c0 + g.nc;
+    if (lane == 0 && self_in) cur[cs - g.c0] = g.f0;
+    __syncthreads();
+
+    uint64_t or0 = 0ull, and0 = ~0ull, or1 = 0ull, and1 = ~0ull;
+    // f0 block: the alpha string is unchanged
+    if (self_in && g.f0) {
+        const size_t base = g.offsets[(size_t)(cs - g.c0) * g.nq + i];
+        for (uint32_t t = lane; t < g.f0; t += 64) {
+            uint64_t b2;
+            double hv;
+            if (t < g.nbs) {
+                const uint32_t x = bsX[t];
+                b2 = bsB[t];
+                hv = single_value(g.h, g.eri, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
             } else {
-                j -= it.cnt[1];
-                m = 2;
-            }
-        }
-        const uint32_t fm = m == 0 ? bf.f[0] : (m == 1 ? bf.f[1] : bf.f[2]);
-        const uint32_t ac = j / fm, bc = j - ac * fm;
-        const int kh = m - it.nr, kp = m - it.nA;
-        const uint32_t npart = (uint32_t)choose_small(it.nv, kp);
-        const uint32_t hidx = ac / npart, pidx = ac - hidx * npart;
-        const uint64_t holes = it.R | pick_bits(it.lo_occ, kh, hidx);
-        const uint64_t parts = it.A | pick_bits(it.lo_vir, kp, pidx);
-        const uint64_t a2 = (a & ~holes) | parts;
-        uint64_t b2 = b;
-        double hv;
-        if (m == 0) {
-            if (bc < nbvb) {
-                const uint32_t hh = bc / bf.vb, pp = bc - hh * bf.vb;
-                const int r = select_bit(b, (int)hh), s = select_bit(bvir, (int)pp);
-                b2 = (b & ~(1ull << r)) | (1ull << s);
-                hv = single_value(h, eri, n, b, a, r, s);
-            } else {
-                const uint32_t x = bc - nbvb;
-                const uint32_t hh = x / bf.pairs_vb, pp = x - hh * bf.pairs_vb;
-                const uint64_t hb = pick_bits(b, 2, hh), pb = pick_bits(bvir, 2, pp);
+                const uint32_t y = t - g.nbs;
+                const uint32_t hp = y / g.pvb2, pp = y - hp * g.pvb2;
+                int i1, j1, i2, j2;
+                unrank_pair(hp, i1, j1);
+                unrank_pair(pp, i2, j2);
+                const uint64_t hb = (1ull << occB[i1]) | (1ull << occB[j1]);
+                const uint64_t pb = (1ull << virB[i2]) | (1ull << virB[j2]);
                 b2 = (b & ~hb) | pb;
-                hv = double_same_value(eri, n, b, hb, pb);
+                hv = double_same_value(g.eri, n, b, hb, pb);
             }
-        } else if (m == 1) {
-            const int p = lowbit(holes), q = lowbit(parts);
-            if (bc == 0) {
-                hv = single_value(h, eri, n, a, b, p, q);
+            emit<W>(g, base + t, a, b2, hv * ci, or0, and0, or1, and1);
+        }
+    }
+    // slots of the alpha-single blocks: rank among equal classes, in u order
+    if (lane == 0) s_nsel = 0u;
+    __syncthreads();
+    for (uint32_t u0 = 0; u0 < g.nas; u0 += 64) {
+        const uint32_t u = u0 + lane;
+        const uint32_t lc = u < g.nas ? asP[u] : ~0u;
+        const bool act = lc != ~0u;
+        const uint32_t key = act ? lc : 0u;
+        const uint64_t peers = match_peers(key, act, g.nbits);
+        const uint32_t before = cur[key];
+        const uint64_t sel = __ballot(act);
+        const uint32_t nsel0 = s_nsel;
+        if (act) {
+            asP[u] = g.offsets[(size_t)lc * g.nq + i] + before + (uint32_t)__popcll(peers & lt) * g.f1;
+            asL[nsel0 + __popcll(sel & lt)] = u;
+            if ((peers & lt) == 0ull) cur[key] = before + (uint32_t)__popcll(peers) * g.f1;
+        }
+        if (lane == 0) s_nsel = nsel0 + (uint32_t)__popcll(sel);
+        __syncthreads();
+    }
+    // alpha-single blocks, flattened over (selected single, record)
+    {
+        const uint32_t total = s_nsel * g.f1;
+        for (uint32_t t = lane; t < total; t += 64) {
+            const uint32_t k = t / g.f1, j = t - k * g.f1;
+            const uint32_t u = asL[k];
+            const uint64_t a2 = asA[u];
+            const size_t dst = (size_t)asP[u] + j;
+            if (j == 0) {
+                emit<W>(g, dst, a2, b, asV[u] * ci, or0, and0, or1, and1);
             } else {
-                const uint32_t x = bc - 1;
-                const uint32_t hh = x / bf.vb, pp = x - hh * bf.vb;
-                const int r = select_bit(b, (int)hh), s = select_bit(bvir, (int)pp);
-                b2 = (b & ~(1ull << r)) | (1ull << s);
-                hv = double_opp_value(eri, n, a, b, p, q, r, s);
+                const uint32_t x = bsX[j - 1], xa = asX[u];
+                const int p = (int)(xa & 0xFFu), q = (int)((xa >> 8) & 0xFFu);
+                const int r = (int)(x & 0xFFu), s = (int)((x >> 8) & 0xFFu);
+                const int sg = (((xa ^ x) >> 16) & 1u) ? -1 : 1;
+                emit<W>(g, dst, a2, bsB[j - 1], (sg * eri4(g.eri, n, q, p, s, r)) * ci, or0, and0, or1, and1);
             }
-        } else {
-            hv = double_same_value(eri, n, a, holes, parts);
         }
-        const size_t dst = (size_t)off + j0;
-        if (dst < cap) {
-            put_key<W>(klo, khi, dst, a2, b2, n);
-            vals[dst] = hv * ci;
-        }
-        if (W == 1) {
-            const uint64_t k = (a2 << n) | b2;
-            kor0 |= k;
-            kand0 &= k;
-        } else {
-            kor0 |= b2;
-            kand0 &= b2;
-            kor1 |= a2;
-            kand1 &= a2;
+    }
+    // alpha-alpha doubles, one record each
+    {
+        const uint32_t total = g.npa2 * g.pva2;
+        for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+            const uint32_t t = t0 + lane;
+            uint64_t holes = 0ull, parts = 0ull, a2 = a;
+            uint32_t c = ~0u;
+            if (t < total) {
+                const uint32_t hp = t / g.pva2, pp = t - hp * g.pva2;
+                int i1, j1, i2, j2;
+                unrank_pair(hp, i1, j1);
+                unrank_pair(pp, i2, j2);
+                holes = (1ull << occA[i1]) | (1ull << occA[j1]);
+                parts = (1ull << virA[i2]) | (1ull << virA[j2]);
+                a2 = (a & ~holes) | parts;
+                c = class_index(a2, g.L, g.L0);
+            }
+            const bool act = c >= g.c0 && c < g.c0 + g.nc;
+            const uint32_t key = act ? c - g.c0 : 0u;
+            const uint64_t peers = match_peers(key, act, g.nbits);
+            const uint32_t before = cur[key];
+            if (act) {
+                const size_t dst = (size_t)g.offsets[(size_t)key * g.nq + i] + before + (uint32_t)__popcll(peers & lt);
+                if ((peers & lt) == 0ull) cur[key] = before + (uint32_t)__popcll(peers);
+                emit<W>(g, dst, a2, b, double_same_value(g.eri, n, a, holes, parts) * ci, or0, and0, or1, and1);
+            }
         }
     }
     for (int d = 32; d >= 1; d >>= 1) {
-        kor0 |= __shfl_xor(kor0, d, 64);
-        kand0 &= __shfl_xor(kand0, d, 64);
-        kor1 |= __shfl_xor(kor1, d, 64);
-        kand1 &= __shfl_xor(kand1, d, 64);
+        or0 |= __shfl_xor(or0, d, 64);
+        and0 &= __shfl_xor(and0, d, 64);
+        or1 |= __shfl_xor(or1, d, 64);
+        and1 &= __shfl_xor(and1, d, 64);
     }
     if (lane == 0) {
-        atomicOr(&key_or_and[0], (unsigned long long)kor0);
-        atomicAnd(&key_or_and[1], (unsigned long long)kand0);
+        atomicOr(&g.key_or_and[0], (unsigned long long)or0);
+        atomicAnd(&g.key_or_and[1], (unsigned long long)and0);
         if (W == 2) {
-            atomicOr(&key_or_and[2], (unsigned long long)kor1);
-            atomicAnd(&key_or_and[3], (unsigned long long)kand1);
+            atomicOr(&g.key_or_and[2], (unsigned long long)or1);
+            atomicAnd(&g.key_or_and[3], (unsigned long long)and1);
         }
     }
 }
@@ -689,7 +828,9 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     for (uint32_t c = 0; c < ncls;) {
         uint64_t sum = 0;
         uint32_t c1 = c;
-        while (c1 < ncls && (c1 == c || sum + pp.totals[c1] <= cap)) sum += pp.totals[c1++];
+        // at most kMaxBatchClasses classes: the generator keeps one LDS cursor per class
+        while (c1 < ncls && c1 - c < kMaxBatchClasses && (c1 == c || sum + pp.totals[c1] <= cap))
+            sum += pp.totals[c1++];
         require(sum < (1ull << 31), ASCI_ENOMEM, "one constraint class exceeds 2^31 pairs");
         batches.push_back({c, c1});
         max_batch = std::max(max_batch, sum);
@@ -785,13 +926,42 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         // step 5: generate
         k_init_or_and<<<1, 64, 0, s>>>(d_misc);
         ASCI_LAUNCH_CHECK();
-        const unsigned gblocks = (unsigned)((ent + (kBlock / 64) - 1) / (kBlock / 64));
         {
-        ProfScope ps(prof, "generate", (8.0 * W + 8.0) * P, s);
-        k_generate<W><<<gblocks, kBlock, 0, s>>>(pp.q_a, pp.q_b, pp.q_c, (uint32_t)nq, pp.d_cls, c0, (uint32_t)ent,
-                                                 counts, offs, in.h, in.eri, n, full, bf, k_lo[0], k_hi[0], v[0], Pb,
-                                                 d_misc);
-        ASCI_LAUNCH_CHECK();
+            ProfScope ps(prof, "generate", (8.0 * W + 8.0) * P, s);
+            GenArgs ga;
+            ga.core_a = pp.q_a;
+            ga.core_b = pp.q_b;
+            ga.core_c = pp.q_c;
+            ga.nq = (uint32_t)nq;
+            ga.c0 = c0;
+            ga.nc = nc;
+            ga.nbits = 1;
+            while ((1u << ga.nbits) < nc) ++ga.nbits;
+            ga.offsets = offs;
+            ga.h = in.h;
+            ga.eri = in.eri;
+            ga.n = n;
+            ga.na = in.na;
+            ga.nb = in.nb;
+            ga.L = in.na < 3 ? in.na : 3;
+            ga.L0 = in.na - ga.L;
+            ga.full = full;
+            const uint32_t va = (uint32_t)(n - in.na), vb = (uint32_t)(n - in.nb);
+            ga.nas = (uint32_t)in.na * va;
+            ga.nbs = (uint32_t)in.nb * vb;
+            ga.f0 = bf.f[0];
+            ga.f1 = bf.f[1];
+            ga.pva2 = va * (va - (va ? 1u : 0u)) / 2u;
+            ga.npa2 = (uint32_t)in.na * (uint32_t)(in.na - (in.na ? 1 : 0)) / 2u;
+            ga.pvb2 = bf.pairs_vb;
+            ga.klo = k_lo[0];
+            ga.khi = k_hi[0];
+            ga.vals = v[0];
+            ga.cap = Pb;
+            ga.key_or_and = d_misc;
+            const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 + 64;
+            k_generate<W><<<(unsigned)nq, 64, lds, s>>>(ga);
+            ASCI_LAUNCH_CHECK();
         }
         ASCI_HIP(hipMemcpyAsync(h_misc, d_misc, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         ASCI_HIP(hipStreamSynchronize(s));
