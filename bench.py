@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="16e20o")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--finish-cap", type=int, default=0, help="records per LDS bucket (tuning parameter)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the search shards by "
@@ -77,6 +78,8 @@ def main():
     dets = torch.from_numpy(np.ascontiguousarray(case["dets"]).view(np.int64)).to(dev).view(torch.uint64)
     coeffs = torch.from_numpy(case["coeffs"]).to(dev)
     ctx = asci.Context.get(0)
+    if args.finish_cap:
+        ctx.set_param("finish_cap", args.finish_cap)
     E0 = asci.energy(h, eri, n, na, nb, dets, coeffs, ctx=ctx)
     P = nd * sd_per_det(n, na, nb)
 
@@ -124,8 +127,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: (%de,%do) synthetic integrals, %d core determinants, keep %d" % (
             args.workload, na + nb, n, nd, k), "norb": n, "nalpha": na, "nbeta": nb, "ndets": nd, "k": k,
-            "contributions": P, "seed": case["seed"]},
+            "contributions": P, "seed": case["seed"], "finish_cap": ctx.get_param("finish_cap")},
         "search_wall_ms": round(ms, 4),
+        "diagnostics": {kk: ctx.get_param(kk) for kk in ("last_batches", "last_finals", "last_levels",
+                                                          "last_candidates")},
         "selected": int(out_k.shape[0]),
         "roofline": roofline,
         "phases": phases,

@@ -83,6 +83,20 @@ int asci_ctx_create(int device, asci_ctx **out);
 int asci_ctx_destroy(asci_ctx *ctx);
 
 /*
+ * Tuning parameters of a context (they change speed, never results):
+ *   "finish_cap": records per LDS bucket in the sort-and-accumulate finish,
+ *                 1024, 2048 or 4096 (default 4096; two-word keys use at most
+ *                 2048).  Smaller buckets let two workgroups share a CU.
+ *   "batch_slots": concurrent searches of asci_search_batch, 1..8 (default 2).
+ * Read-only diagnostics of the last search on ctx (asci_ctx_get_param):
+ *   "last_batches" (class batches), "last_finals" (LDS buckets),
+ *   "last_levels" (deepest bucket split), "last_candidates" (candidates).
+ * Unknown names or values: ASCI_EINVAL.
+ */
+int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value);
+int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value);
+
+/*
  * Per-kernel timing (measurement support, not part of the method).  With
  * profiling on, every timed kernel launch of later calls on ctx is bracketed by
  * HIP events on the call's stream; entries accumulate per kernel name: total
@@ -161,6 +175,96 @@ int asci_class_counts_device(asci_ctx *ctx, int norb, int nalpha, int nbeta,
 int asci_energy_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb,
                        int nalpha, int nbeta, const uint64_t *d_dets, const double *d_coeffs,
                        int64_t ndets, double ecore, double *out_energy, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched and served searches.
+ *
+ * A request names device buffers that stay resident (integrals, determinant
+ * sets) and device outputs of capacity k; its result equals the result of
+ * asci_search_device on the same inputs, bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct asci_request {
+    const double *h, *eri;     /* device */
+    int norb, nalpha, nbeta;
+    const uint64_t *dets;      /* device, ndets x 2 */
+    const double *coeffs;      /* device */
+    int64_t ndets;
+    double E0;
+    int64_t k;
+    asci_options opt;
+    uint64_t *out_dets;        /* device, k x 2 */
+    double *out_scores;        /* device, k */
+} asci_request;
+
+typedef struct asci_result {
+    int status;                /* ASCI_OK or an error code */
+    int64_t count;             /* candidates written */
+    double latency_ms;         /* submission to completion */
+    double run_ms;             /* admission to completion */
+    int64_t contributions;     /* pairs the search generated */
+} asci_result;
+
+/* Device bytes the library budgets for one request (workspace estimate). */
+int64_t asci_request_footprint(const asci_request *req);
+
+/*
+ * Run nreq searches as one batch on ctx's device: the requests are ordered by
+ * estimated cost (largest first) and run concurrently on `slots` worker
+ * streams (ctx parameter "batch_slots", default 2; see asci_autotune), each
+ * with its own workspace.  Work already queued on `stream` completes first;
+ * the call returns when every result is written.  res[i] is request i's
+ * result; the return value is ASCI_OK when every request succeeded, else the
+ * first error code.
+ */
+int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_result *res, void *stream);
+
+/*
+ * Pick ctx's "batch_slots" (1..4) and "finish_cap" (2048 or 4096) by timing
+ * asci_search_batch on the given sample requests; the chosen values are
+ * stored in ctx and returned.  Results never depend on them.
+ */
+int asci_autotune(asci_ctx *ctx, const asci_request *sample, int nsample, int64_t *best_slots,
+                  int64_t *best_finish_cap);
+
+/*
+ * A request loop with continuous batching on one device.  Requests wait in a
+ * FIFO queue and are admitted while a worker slot is free and the bytes
+ * budgeted for the running requests plus the workspace the workers keep
+ * stay within hbm_budget; requests that arrive while others run are admitted
+ * as slots and memory free up, and their kernels overlap on the device.
+ * A request whose footprint alone exceeds hbm_budget is rejected at
+ * submission with ASCI_ENOMEM.  Request buffers must stay valid until the
+ * request completes.
+ */
+typedef struct asci_server asci_server;
+
+typedef struct asci_server_stats {
+    int64_t submitted, completed, failed, rejected;
+    int64_t max_running;        /* most requests running at once */
+    int64_t peak_bytes;         /* most bytes budgeted at once (<= hbm_budget) */
+    double p50_ms, p99_ms, mean_ms;  /* latency: submission to completion */
+    double wall_s;              /* first submission to last completion */
+    int64_t contributions;      /* pairs generated by completed requests */
+} asci_server_stats;
+
+int asci_server_create(int device, int64_t hbm_budget, int slots, asci_server **out);
+/* Scheduler test double: no GPU is touched; a request "runs" for
+ * footprint * ns_per_byte nanoseconds and keeps its footprint resident. */
+int asci_server_create_fake(int64_t hbm_budget, int slots, double ns_per_byte, asci_server **out);
+int asci_server_submit(asci_server *srv, const asci_request *req, uint64_t *ticket);
+/* Bytes this server budgets for a request: the server caps each request's
+ * pair buffer at hbm_budget / (slots * 160) records, so large requests run in
+ * more class batches instead of being refused. */
+int64_t asci_server_footprint(asci_server *srv, const asci_request *req);
+/* ASCI_OK and *res when the request has completed, ASCI_EAGAIN (1) while it
+ * has not; ASCI_EINVAL for an unknown ticket. */
+int asci_server_poll(asci_server *srv, uint64_t ticket, asci_result *res);
+int asci_server_wait(asci_server *srv, uint64_t ticket, asci_result *res);
+int asci_server_get_stats(asci_server *srv, asci_server_stats *st);
+/* Waits for running requests, then frees the server. */
+int asci_server_destroy(asci_server *srv);
+
+#define ASCI_EAGAIN 1
 
 #ifdef __cplusplus
 }

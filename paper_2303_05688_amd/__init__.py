@@ -30,6 +30,25 @@ class Options(C.Structure):
                 ("ecore", C.c_double), ("pair_buffer_bytes", C.c_int64)]
 
 
+class Request(C.Structure):
+    _fields_ = [("h", C.c_void_p), ("eri", C.c_void_p), ("norb", C.c_int), ("nalpha", C.c_int),
+                ("nbeta", C.c_int), ("dets", C.c_void_p), ("coeffs", C.c_void_p), ("ndets", C.c_int64),
+                ("E0", C.c_double), ("k", C.c_int64), ("opt", Options), ("out_dets", C.c_void_p),
+                ("out_scores", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("count", C.c_int64), ("latency_ms", C.c_double), ("run_ms", C.c_double),
+                ("contributions", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("rejected", C.c_int64), ("max_running", C.c_int64), ("peak_bytes", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("wall_s", C.c_double),
+                ("contributions", C.c_int64)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libasci.so is not built: run `python -m paper_2303_05688_amd.build` "
                       "(or __graft_entry__.build()) first")
@@ -55,11 +74,32 @@ _lib.asci_energy_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _v
                                     _dp, _vp]
 
 _lib.asci_ctx_set_profiling.argtypes = [_vp, C.c_int]
+_lib.asci_ctx_set_param.argtypes = [_vp, C.c_char_p, C.c_int64]
+_lib.asci_ctx_get_param.argtypes = [_vp, C.c_char_p, _ip]
 _lib.asci_ctx_profile_entry.argtypes = [_vp, C.c_int, C.c_char_p, C.c_int, _dp, _ip, _dp]
 
+_lib.asci_request_footprint.restype = C.c_int64
+_lib.asci_request_footprint.argtypes = [C.POINTER(Request)]
+_lib.asci_search_batch.argtypes = [_vp, C.POINTER(Request), C.c_int, C.POINTER(Result), _vp]
+_lib.asci_autotune.argtypes = [_vp, C.POINTER(Request), C.c_int, _ip, _ip]
+_lib.asci_server_create.argtypes = [C.c_int, C.c_int64, C.c_int, C.POINTER(C.c_void_p)]
+_lib.asci_server_create_fake.argtypes = [C.c_int64, C.c_int, C.c_double, C.POINTER(C.c_void_p)]
+_lib.asci_server_submit.argtypes = [_vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+_lib.asci_server_poll.argtypes = [_vp, C.c_uint64, C.POINTER(Result)]
+_lib.asci_server_footprint.restype = C.c_int64
+_lib.asci_server_footprint.argtypes = [_vp, C.POINTER(Request)]
+_lib.asci_server_wait.argtypes = [_vp, C.c_uint64, C.POINTER(Result)]
+_lib.asci_server_get_stats.argtypes = [_vp, C.POINTER(ServerStats)]
+_lib.asci_server_destroy.argtypes = [_vp]
+
 EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_default", "asci_ctx_create",
-           "asci_ctx_destroy", "asci_ctx_set_profiling", "asci_ctx_profile_entry", "asci_search",
-           "asci_search_device", "asci_candidates_device", "asci_class_counts_device", "asci_energy_device"]
+           "asci_ctx_destroy", "asci_ctx_set_param", "asci_ctx_get_param", "asci_ctx_set_profiling",
+           "asci_ctx_profile_entry", "asci_search",
+           "asci_search_device", "asci_candidates_device", "asci_class_counts_device", "asci_energy_device",
+           "asci_request_footprint", "asci_search_batch", "asci_autotune", "asci_server_create",
+           "asci_server_create_fake", "asci_server_submit", "asci_server_footprint", "asci_server_poll",
+           "asci_server_wait",
+           "asci_server_get_stats", "asci_server_destroy"]
 
 
 def lib():
@@ -94,6 +134,14 @@ class Context:
         if device not in cls._cache:
             cls._cache[device] = cls(device)
         return cls._cache[device]
+
+    def set_param(self, name, value):
+        _check(_lib.asci_ctx_set_param(self.ptr, name.encode(), int(value)))
+
+    def get_param(self, name):
+        v = C.c_int64()
+        _check(_lib.asci_ctx_get_param(self.ptr, name.encode(), C.byref(v)))
+        return v.value
 
     def set_profiling(self, enable=True):
         _check(_lib.asci_ctx_set_profiling(self.ptr, int(bool(enable))))
@@ -241,3 +289,113 @@ def search_host(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0
                             C.byref(o), out_d.ctypes.data_as(_up), out_s.ctypes.data_as(_dp), C.byref(cnt)))
     m = cnt.value
     return out_d[:m], out_s[:m]
+
+
+# ---------------------------------------------------------------- batch and serving
+
+
+class SearchRequest:
+    """A device-side search request; allocates its outputs (k results) on the
+    device and keeps references to every buffer it names."""
+
+    def __init__(self, h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, ecore=0.0,
+                 pair_buffer_bytes=0):
+        torch = _torch()
+        dets = _dets_tensor(dets)
+        self.keep = (h, eri, dets, coeffs)
+        self.out_dets = torch.empty((int(k), 2), dtype=torch.uint64, device=h.device)
+        self.out_scores = torch.empty((int(k),), dtype=torch.float64, device=h.device)
+        self.c = Request(_dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
+                         _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0], float(E0), int(k),
+                         options(ncore, eps, ecore, pair_buffer_bytes), self.out_dets.data_ptr(),
+                         self.out_scores.data_ptr())
+
+    def result(self, count):
+        return self.out_dets[:count], self.out_scores[:count]
+
+
+def fake_request(norb, nalpha, nbeta, ndets, k):
+    """A request with no buffers, for the fake (host-only) server."""
+    return Request(None, None, norb, nalpha, nbeta, None, None, ndets, 0.0, k, options(), None, None)
+
+
+def footprint(req):
+    c = req.c if isinstance(req, SearchRequest) else req
+    return _lib.asci_request_footprint(C.byref(c))
+
+
+def search_batch(requests, ctx=None):
+    """Run SearchRequests as one batch; returns the list of Result structs."""
+    torch = _torch()
+    ctx = ctx or Context.get(torch.cuda.current_device())
+    arr = (Request * len(requests))(*[r.c for r in requests])
+    res = (Result * len(requests))()
+    rc = _lib.asci_search_batch(ctx.ptr, arr, len(requests), res, _stream(torch.cuda.current_device()))
+    if rc != ASCI_OK:
+        raise AsciError(rc, "batch: " + ", ".join(str(r.status) for r in res))
+    return list(res)
+
+
+def autotune(sample_requests, ctx=None):
+    torch = _torch()
+    ctx = ctx or Context.get(torch.cuda.current_device())
+    arr = (Request * len(sample_requests))(*[r.c for r in sample_requests])
+    bs, bc = C.c_int64(), C.c_int64()
+    _check(_lib.asci_autotune(ctx.ptr, arr, len(sample_requests), C.byref(bs), C.byref(bc)))
+    return {"batch_slots": bs.value, "finish_cap": bc.value}
+
+
+class Server:
+    """Continuous-batching request loop (asci_server_*)."""
+
+    def __init__(self, device=0, hbm_budget=None, slots=4, fake_ns_per_byte=None):
+        self.ptr = C.c_void_p()
+        if fake_ns_per_byte is not None:
+            _check(_lib.asci_server_create_fake(int(hbm_budget), int(slots), float(fake_ns_per_byte),
+                                                C.byref(self.ptr)))
+        else:
+            if hbm_budget is None:
+                torch = _torch()
+                free, _ = torch.cuda.mem_get_info(device)
+                hbm_budget = int(free * 0.7)
+            _check(_lib.asci_server_create(int(device), int(hbm_budget), int(slots), C.byref(self.ptr)))
+        self.requests = {}
+
+    def submit(self, req):
+        c = req.c if isinstance(req, SearchRequest) else req
+        t = C.c_uint64()
+        rc = _lib.asci_server_submit(self.ptr, C.byref(c), C.byref(t))
+        self.requests[t.value] = req
+        if rc not in (ASCI_OK, ASCI_ENOMEM):
+            _check(rc)
+        return t.value
+
+    def footprint(self, req):
+        c = req.c if isinstance(req, SearchRequest) else req
+        return _lib.asci_server_footprint(self.ptr, C.byref(c))
+
+    def poll(self, ticket):
+        r = Result()
+        rc = _lib.asci_server_poll(self.ptr, ticket, C.byref(r))
+        return r if rc == ASCI_OK else None
+
+    def wait(self, ticket):
+        r = Result()
+        _check(_lib.asci_server_wait(self.ptr, ticket, C.byref(r)))
+        return r
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.asci_server_get_stats(self.ptr, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.ptr:
+            _lib.asci_server_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

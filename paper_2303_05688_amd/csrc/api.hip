@@ -149,6 +149,46 @@ int asci_ctx_destroy(asci_ctx *ctx)
     return ASCI_OK;
 }
 
+int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
+{
+    try {
+        require(ctx != nullptr && name != nullptr, ASCI_EINVAL, "null argument");
+        const std::string key(name);
+        if (key == "finish_cap") {
+            require(value == 1024 || value == 2048 || value == 4096, ASCI_EINVAL,
+                    "finish_cap must be 1024, 2048 or 4096");
+            ctx->finish_cap = (int)value;
+            return ASCI_OK;
+        }
+        if (key == "batch_slots") {
+            require(value >= 1 && value <= 8, ASCI_EINVAL, "batch_slots must be in [1, 8]");
+            ctx->batch_slots = (int)value;
+            return ASCI_OK;
+        }
+        throw Error{ASCI_EINVAL, "unknown parameter: " + key};
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value)
+{
+    try {
+        require(ctx != nullptr && name != nullptr && value != nullptr, ASCI_EINVAL, "null argument");
+        const std::string key(name);
+        if (key == "finish_cap") *value = ctx->finish_cap;
+        else if (key == "batch_slots") *value = ctx->batch_slots;
+        else if (key == "last_batches") *value = ctx->last_batches;
+        else if (key == "last_finals") *value = ctx->last_finals;
+        else if (key == "last_levels") *value = ctx->last_levels;
+        else if (key == "last_candidates") *value = ctx->last_candidates;
+        else throw Error{ASCI_EINVAL, "unknown parameter: " + key};
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
 int asci_ctx_set_profiling(asci_ctx *ctx, int enable)
 {
     try {

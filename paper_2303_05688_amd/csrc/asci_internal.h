@@ -117,6 +117,10 @@ struct ProfScope {
 
 struct asci_ctx {
     int device = 0;
+    int finish_cap = 4096;  // tunable: records per LDS bucket (see asci_ctx_set_param)
+    int batch_slots = 2;    // tunable: concurrent searches of a batch
+    // diagnostics of the last search
+    int64_t last_batches = 0, last_finals = 0, last_levels = 0, last_candidates = 0;
     asci::Profiler prof;
     asci::Arena setup;  // inputs, sorted psi keys, core set, class totals
     asci::Arena main;   // per-batch pair buffers, candidate pool, selection
@@ -226,6 +230,38 @@ struct SelectState {
 void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_state,
                       hipStream_t s, Profiler *prof = nullptr);
 
+// ---------------------------------------------------------------- buckets (bucket.hip)
+struct BucketArgs {
+    size_t P;                       // records of the batch
+    uint32_t c0, nc, nq;            // classes [c0, c0 + nc), core count
+    int n;
+    const uint64_t *cls;            // class masks (all classes)
+    const uint32_t *offsets;        // [nc][nq] item starts
+    const uint32_t *total;          // device: records of the batch
+    uint64_t *klo[2], *khi[2];      // record buffers (ping-pong)
+    double *val[2];
+    const uint64_t *plo, *phi;      // sorted input keys
+    uint32_t npsi;
+    const double *jk, *h;
+    double ecore, E0, eps;
+    int finish_cap = 4096;          // LDS capacity of a final segment (tunable)
+    uint64_t *clo, *chi;            // candidate slots (P)
+    double *cnum, *cscore;
+    // results of bucket_accumulate
+    uint32_t nfinal = 0, V = 0, levels = 0;
+    const uint32_t *order = nullptr, *cnt_sorted = nullptr, *off = nullptr;
+    const void *finals = nullptr;
+    // destination of bucket_collect
+    uint64_t *pool_lo = nullptr, *pool_hi = nullptr;
+    double *pool_num = nullptr, *pool_score = nullptr;
+    size_t pool_base = 0, pool_cap = 0;
+};
+size_t bucket_workspace_bytes(size_t P, size_t nc, int W);
+template <int W>
+void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, HostStage &hs);
+template <int W>
+void bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof);
+
 // ---------------------------------------------------------------- search (search.hip)
 struct SearchArgs {
     const double *h, *eri;  // device
@@ -250,6 +286,10 @@ void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStrea
 void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *dets, const double *coeffs,
                          int64_t ndets, int64_t ncore, std::vector<uint64_t> &masks,
                          std::vector<uint64_t> &counts, hipStream_t s);
+// closed-form pair count and workspace estimate of a request (server.hip)
+int64_t request_pairs(const asci_request &r);
+int64_t request_footprint(const asci_request &r, uint64_t cap_records);
+
 // throws ASCI_EINVAL unless every determinant has na/nb electrons inside norb orbitals
 void validate_dets(asci_ctx *ctx, const uint64_t *dets, int64_t ndets, int n, int na, int nb, hipStream_t s);
 double energy_device(asci_ctx *ctx, const double *h, const double *eri, int n, const uint64_t *dets,

@@ -1,0 +1,1007 @@
+// Sort-and-accumulate of one class batch by buckets (Alg. 2, the sort on
+// the target bitstring and the sum per unique target), built for LDS:
+//
+//   segments: contiguous record ranges whose keys agree on every bit at or
+//             above `top`; the classes of the batch are the first segments
+//             (the generator lays records out class by class).
+//   split   : a segment larger than the LDS capacity is split, stably, on the
+//             8 key bits just below `top` (per-tile digit histograms laid out
+//             segment by segment, one global exclusive scan, ranked scatter
+//             into the other buffer).  A segment whose digit is constant only
+//             lowers `top`.  Repeat level by level.
+//   finish  : one workgroup per final segment sorts it in LDS (stable LSD on
+//             bits below `top`), sums every run of equal keys in record order
+//             (record order is ascending core index), drops input
+//             determinants, forms H_aa and A_a, and writes the surviving
+//             candidates, compacted, at the segment's start in slot arrays.
+//   collect : final segments ordered by start (= key order), their candidate
+//             counts scanned, and the candidates copied to the pool.
+//
+// Keys are handled as the 2n-bit value (alpha << n) | beta: one word for
+// n <= 32, two words (hi = alpha, lo = beta) above.
+#include "hamiltonian.h"
+
+#include <algorithm>
+
+namespace asci {
+
+namespace {
+
+constexpr int kTileT = 256;           // threads of tile kernels
+constexpr int kTileItems = 16;
+constexpr int kTileN = kTileT * kTileItems;  // 4096 records per tile
+
+struct Seg {
+    uint32_t start, size, meta;  // meta: top (bits 0-7) | buf (bit 8) | single key (bit 9)
+};
+
+__host__ __device__ __forceinline__ uint32_t seg_top(const Seg &s) { return s.meta & 0xFFu; }
+__host__ __device__ __forceinline__ uint32_t seg_buf(const Seg &s) { return (s.meta >> 8) & 1u; }
+__host__ __device__ __forceinline__ bool seg_single(const Seg &s) { return (s.meta >> 9) & 1u; }
+__host__ __device__ __forceinline__ uint32_t make_meta(uint32_t top, uint32_t buf, bool single)
+{
+    return top | (buf << 8) | (single ? 512u : 0u);
+}
+
+// bits [sh, sh + w) of the 2n-bit key, w <= 8
+template <int W>
+__device__ __forceinline__ uint32_t vdigit(uint64_t lo, uint64_t hi, int n, int sh, int w)
+{
+    uint64_t x;
+    if (W == 1) {
+        x = lo >> sh;
+    } else if (sh >= n) {
+        x = hi >> (sh - n);
+    } else {
+        x = lo >> sh;
+        if (sh + w > n) x |= hi << (n - sh);
+    }
+    return (uint32_t)x & ((1u << w) - 1u);
+}
+
+template <int W>
+__device__ __forceinline__ bool key_less(uint64_t alo, uint64_t ahi, uint64_t blo, uint64_t bhi)
+{
+    return W == 1 ? alo < blo : (ahi < bhi || (ahi == bhi && alo < blo));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// exclusive scan over the block (NW waves); every thread must call it
+template <int NW>
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t x = wave_incl_scan(v);
+    if (lane == 63) s_tmp[w] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const uint32_t t = s_tmp[i];
+        base += (i < w) ? t : 0u;
+        tot += t;
+    }
+    total = tot;
+    __syncthreads();
+    return base + x - v;
+}
+
+// ---------------------------------------------------------------- split level
+struct SplitArgs {
+    const Seg *segs;          // large segments of this level
+    uint32_t nseg;
+    const uint32_t *tile_base;  // per segment: first tile (exclusive scan of tile counts)
+    const uint32_t *tile_seg;   // per tile: its segment
+    uint32_t ntiles;
+    uint32_t *hist;             // [tiles * 256], segment-major, digit-major inside a segment
+    uint64_t *klo[2], *khi[2];
+    double *val[2];
+    int n;
+    uint32_t cap;
+};
+
+// digit of a split: the w bits just below `top`, with w the smallest width
+// (at most 8) whose 2^w children average at most half the LDS capacity
+__device__ __forceinline__ void split_digit(const Seg &s, uint32_t cap, int &sh, int &w)
+{
+    const int top = (int)seg_top(s);
+    int want = 1;
+    while (want < 8 && ((uint64_t)s.size << 1) > ((uint64_t)cap << want)) ++want;
+    w = want < top ? want : top;
+    sh = top - w;
+}
+
+// per segment: number of tiles
+__global__ __launch_bounds__(256) void k_seg_tiles(const Seg *__restrict__ segs, uint32_t nseg,
+                                                   uint32_t *__restrict__ ntile)
+{
+    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s < nseg) ntile[s] = (segs[s].size + kTileN - 1) / kTileN;
+}
+
+__global__ __launch_bounds__(256) void k_seg_expand(const Seg *__restrict__ segs, uint32_t nseg,
+                                                    const uint32_t *__restrict__ tile_base,
+                                                    uint32_t *__restrict__ tile_seg)
+{
+    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= nseg) return;
+    const uint32_t nt = (segs[s].size + kTileN - 1) / kTileN, tb = tile_base[s];
+    for (uint32_t t = 0; t < nt; ++t) tile_seg[tb + t] = s;
+}
+
+template <int W>
+__global__ __launch_bounds__(kTileT) void k_split_hist(SplitArgs a)
+{
+    __shared__ uint32_t h[kTileT / 64][256];
+    const uint32_t t = blockIdx.x;
+    const uint32_t s = a.tile_seg[t];
+    const Seg sg = a.segs[s];
+    const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
+    int sh, w;
+    split_digit(sg, a.cap, sh, w);
+    const uint32_t buf = seg_buf(sg);
+    for (int i = threadIdx.x; i < (kTileT / 64) * 256; i += kTileT) (&h[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t r0 = tl * kTileN, r1 = min(sg.size, r0 + kTileN);
+    const int wv = threadIdx.x >> 6;
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kTileT) {
+        const size_t j = (size_t)sg.start + r;
+        const uint64_t lo = a.klo[buf][j];
+        const uint64_t hi = W == 2 ? a.khi[buf][j] : 0ull;
+        atomicAdd(&h[wv][vdigit<W>(lo, hi, a.n, sh, w)], 1u);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kTileT / 64; ++i) c += h[i][d];
+    a.hist[(size_t)tb * 256 + (size_t)d * nt + tl] = c;
+}
+
+// children of every large segment (one block of 256 threads per segment).
+// Digits larger than the LDS capacity become large segments of the next level
+// (or single-key finals once no bits are left); runs of consecutive smaller
+// digits are coalesced into final segments of at most `cap` records, so the
+// finish never sees fragments.  A segment whose records all share the digit
+// is not moved: skip[s] = 1 and its child keeps its buffer.
+__device__ __forceinline__ void push_seg(Seg *list, uint32_t *count, uint32_t capacity, const Seg &c,
+                                         uint32_t *overflow)
+{
+    const uint32_t at = atomicAdd(count, 1u);
+    if (at < capacity) list[at] = c;
+    else atomicOr(overflow, 1u);
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ segs, uint32_t nseg,
+                                                        const uint32_t *__restrict__ tile_base,
+                                                        const uint32_t *__restrict__ scan, uint32_t cap,
+                                                        uint32_t *__restrict__ skip, Seg *__restrict__ finals,
+                                                        uint32_t *__restrict__ nfinal, uint32_t finals_cap,
+                                                        Seg *__restrict__ next, uint32_t *__restrict__ nnext,
+                                                        uint32_t next_cap, uint32_t *__restrict__ overflow)
+{
+    __shared__ uint32_t s_cnt[256], s_off[256];
+    const uint32_t s = blockIdx.x;
+    const Seg sg = segs[s];
+    const uint32_t tb = tile_base[s], nt = (sg.size + kTileN - 1) / kTileN;
+    int sh, w;
+    split_digit(sg, cap, sh, w);
+    const uint32_t d = threadIdx.x;
+    const size_t b0 = (size_t)tb * 256;
+    const uint32_t base = scan[b0];
+    const uint32_t off = scan[b0 + (size_t)d * nt] - base;
+    const uint32_t end = (d + 1 < 256u) ? scan[b0 + (size_t)(d + 1) * nt] - base : sg.size;
+    s_cnt[d] = (d < (1u << w)) ? end - off : 0u;
+    s_off[d] = off;
+    __syncthreads();
+    if (d != 0) return;
+    const uint32_t top = (uint32_t)sh, ptop = seg_top(sg);
+    for (uint32_t x = 0; x < (1u << w); ++x) {
+        if (s_cnt[x] == sg.size) {  // one digit holds everything: relabel, do not move
+            skip[s] = 1u;
+            Seg c{sg.start, sg.size, 0u};
+            if (sg.size <= cap || top == 0) {
+                c.meta = make_meta(top, seg_buf(sg), sg.size > cap);
+                push_seg(finals, nfinal, finals_cap, c, overflow);
+            } else {
+                c.meta = make_meta(top, seg_buf(sg), false);
+                push_seg(next, nnext, next_cap, c, overflow);
+            }
+            return;
+        }
+    }
+    const uint32_t buf = seg_buf(sg) ^ 1u;
+    uint32_t g_start = 0, g_size = 0, g_digits = 0;
+    auto flush = [&]() {
+        if (g_size) {
+            Seg c{sg.start + g_start, g_size, make_meta(g_digits == 1 ? top : ptop, buf, false)};
+            push_seg(finals, nfinal, finals_cap, c, overflow);
+        }
+        g_size = 0;
+        g_digits = 0;
+    };
+    for (uint32_t x = 0; x < (1u << w); ++x) {
+        const uint32_t c = s_cnt[x];
+        if (c == 0) continue;
+        if (c > cap) {
+            flush();
+            Seg L{sg.start + s_off[x], c, 0u};
+            if (top == 0) {
+                L.meta = make_meta(0u, buf, true);
+                push_seg(finals, nfinal, finals_cap, L, overflow);
+            } else {
+                L.meta = make_meta(top, buf, false);
+                push_seg(next, nnext, next_cap, L, overflow);
+            }
+            continue;
+        }
+        if (g_size + c > cap) flush();
+        if (g_size == 0) g_start = s_off[x];
+        g_size += c;
+        ++g_digits;
+    }
+    flush();
+}
+
+template <int W>
+__global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uint32_t *__restrict__ scan,
+                                                          const uint32_t *__restrict__ skip)
+{
+    constexpr int NW = kTileT / 64;
+    __shared__ uint64_t s_lo[kTileN];
+    __shared__ uint64_t s_hi[W == 2 ? kTileN : 1];
+    __shared__ double s_val[kTileN];
+    __shared__ uint32_t s_wcnt[NW][256];
+    __shared__ uint32_t s_dbase[256];
+    __shared__ uint32_t s_gbase[256];
+    __shared__ uint32_t s_tmp[NW];
+
+    const uint32_t t = blockIdx.x;
+    const uint32_t s = a.tile_seg[t];
+    if (skip[s]) return;  // uniform per block
+    const Seg sg = a.segs[s];
+    const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
+    int sh, w;
+    split_digit(sg, a.cap, sh, w);
+    const uint32_t ib = seg_buf(sg), ob = ib ^ 1u;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int i = tid; i < NW * 256; i += kTileT) (&s_wcnt[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t r0 = tl * kTileN, rn = min(sg.size - r0, (uint32_t)kTileN);
+    uint64_t rlo[kTileItems], rhi[kTileItems];
+    double rv[kTileItems];
+    uint32_t rrank[kTileItems];
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int q = 0; q < kTileItems; ++q) {
+        const uint32_t li = (uint32_t)wv * 64 * kTileItems + (uint32_t)q * 64 + lane;
+        const bool valid = li < rn;
+        const size_t j = (size_t)sg.start + r0 + li;
+        rlo[q] = valid ? a.klo[ib][j] : 0ull;
+        rhi[q] = (W == 2 && valid) ? a.khi[ib][j] : 0ull;
+        rv[q] = valid ? a.val[ib][j] : 0.0;
+        const uint32_t d = vdigit<W>(rlo[q], rhi[q], a.n, sh, w);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t before = s_wcnt[wv][d];
+        rrank[q] = before + (uint32_t)__popcll(peers & lt);
+        if (valid && (peers & lt) == 0ull) s_wcnt[wv][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        const int d = tid;
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const uint32_t c = s_wcnt[i][d];
+            s_wcnt[i][d] = run;
+            run += c;
+        }
+        uint32_t tot;
+        s_dbase[d] = block_scan<NW>(run, s_tmp, tot);
+        const size_t b0 = (size_t)tb * 256;
+        s_gbase[d] = sg.start + (a.hist[b0 + (size_t)d * nt + tl] - a.hist[b0]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kTileItems; ++q) {
+        const uint32_t li = (uint32_t)wv * 64 * kTileItems + (uint32_t)q * 64 + lane;
+        if (li < rn) {
+            const uint32_t d = vdigit<W>(rlo[q], rhi[q], a.n, sh, w);
+            const uint32_t p = min(s_dbase[d] + s_wcnt[wv][d] + rrank[q], (uint32_t)kTileN - 1u);
+            s_lo[p] = rlo[q];
+            if (W == 2) s_hi[p] = rhi[q];
+            s_val[p] = rv[q];
+        }
+    }
+    __syncthreads();
+    const uint32_t seg_end = sg.start + sg.size;
+    for (uint32_t i = tid; i < rn; i += kTileT) {
+        const uint64_t lo = s_lo[i];
+        const uint64_t hi = W == 2 ? s_hi[i] : 0ull;
+        const uint32_t d = vdigit<W>(lo, hi, a.n, sh, w);
+        const uint32_t g = s_gbase[d] + (i - s_dbase[d]);
+        if (g >= sg.start && g < seg_end) {
+            a.klo[ob][g] = lo;
+            if (W == 2) a.khi[ob][g] = hi;
+            a.val[ob][g] = s_val[i];
+        }
+    }
+    (void)scan;
+}
+
+// ---------------------------------------------------------------- finish
+struct FinishArgs {
+    const Seg *finals;
+    uint64_t *klo[2], *khi[2];
+    double *val[2];
+    int n;
+    const uint64_t *plo, *phi;  // sorted keys of the input determinants
+    uint32_t npsi;
+    const double *jk, *h;       // J|K table (2 n^2), h (n^2)
+    double ecore, E0, eps;      // eps > 0: keep a pair only if |H_ai C_i / (E0 - H_aa)| > eps
+    uint64_t *clo, *chi;        // slot arrays (batch positions)
+    double *cnum, *cscore;
+    uint32_t *cnt;              // per final segment: candidates written
+    uint32_t nfinal;
+    const uint32_t *psi_range;  // per final segment: [first, last) input keys inside its key range
+    int tab_in_lds;             // J/K/h_pp staged in LDS (else read from jk / h)
+};
+
+template <int W>
+__device__ __forceinline__ uint32_t psi_lower(const uint64_t *plo, const uint64_t *phi, uint32_t L, uint32_t R,
+                                              uint64_t lo, uint64_t hi)
+{
+    while (L < R) {
+        const uint32_t m = (L + R) >> 1;
+        if (key_less<W>(plo[m], W == 2 ? phi[m] : 0ull, lo, hi)) L = m + 1;
+        else R = m;
+    }
+    return L;
+}
+
+template <int W, int CAP, int NT>
+struct FinishLds {
+    static constexpr int NW = NT / 64;
+    uint64_t klo[2][CAP];
+    uint64_t khi[2][W == 2 ? CAP : 1];
+    double val[2][CAP];
+    uint32_t wcnt[NW][256];
+    uint32_t dbase[256];
+    uint32_t tmp[NW];
+    uint64_t psi_lo[256], psi_hi[W == 2 ? 256 : 1];
+    uint32_t psi_range[2];
+    uint32_t nruns;
+    uint64_t red[4][NW];  // per-wave OR / AND of the key words
+};
+
+// one final segment, processed by the whole workgroup
+template <int W, int CAP, int NT>
+__device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W, CAP, NT> &S, const double *J,
+                                               const double *K, const double *hd, uint32_t sidx)
+{
+    using L = FinishLds<W, CAP, NT>;
+    constexpr int NW = L::NW;
+    constexpr int IT = CAP / NT;
+    const int n = f.n;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+
+    const Seg sg = f.finals[sidx];
+    const uint32_t buf = seg_buf(sg);
+    const uint64_t nmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+
+    if (seg_single(sg)) {
+        // more records than fit in LDS, all with one key: sum in record order
+        __syncthreads();
+        if (tid == 0) {
+            const size_t j0 = sg.start;
+            const uint64_t lo = f.klo[buf][j0], hi = W == 2 ? f.khi[buf][j0] : 0ull;
+            const uint32_t at = psi_lower<W>(f.plo, f.phi, 0u, f.npsi, lo, hi);
+            const bool ex = at < f.npsi && f.plo[at] == lo && (W == 1 || f.phi[at] == hi);
+            uint32_t c = 0;
+            if (!ex) {
+                const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
+                const double den = f.E0 - diag_value(J, K, hd, n, f.ecore, a, b);
+                double sum = 0.0;
+                uint32_t kept = 0;
+                for (uint32_t r = 0; r < sg.size; ++r) {
+                    const double v = f.val[buf][j0 + r];
+                    if (f.eps > 0.0 && !(fabs(v / den) > f.eps)) continue;
+                    sum = sum + v;
+                    ++kept;
+                }
+                if (kept) {
+                    f.clo[j0] = lo;
+                    if (W == 2) f.chi[j0] = hi;
+                    f.cnum[j0] = sum;
+                    f.cscore[j0] = sum / den;
+                    c = 1;
+                }
+            }
+            f.cnt[sidx] = c;
+        }
+        return;
+    }
+
+    const uint32_t size = sg.size;
+    const int top = (int)seg_top(sg);
+    // load
+    for (uint32_t r = tid; r < size; r += NT) {
+        const size_t j = (size_t)sg.start + r;
+        S.klo[0][r] = f.klo[buf][j];
+        if (W == 2) S.khi[0][r] = f.khi[buf][j];
+        S.val[0][r] = f.val[buf][j];
+    }
+    // bits that vary inside the segment: digits without any are not sorted
+    {
+        uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
+        for (uint32_t r = tid; r < size; r += NT) {
+            const uint64_t lo = S.klo[0][r];
+            o0 |= lo;
+            a0 &= lo;
+            if (W == 2) {
+                const uint64_t hi = S.khi[0][r];
+                o1 |= hi;
+                a1 &= hi;
+            }
+        }
+        for (int d = 32; d >= 1; d >>= 1) {
+            o0 |= __shfl_xor(o0, d, 64);
+            a0 &= __shfl_xor(a0, d, 64);
+            o1 |= __shfl_xor(o1, d, 64);
+            a1 &= __shfl_xor(a1, d, 64);
+        }
+        if (lane == 0) {
+            S.red[0][wv] = o0;
+            S.red[1][wv] = a0;
+            S.red[2][wv] = o1;
+            S.red[3][wv] = a1;
+        }
+    }
+    __syncthreads();
+    uint64_t var_lo = 0ull, var_hi = 0ull;
+    {
+        uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            o0 |= S.red[0][i];
+            a0 &= S.red[1][i];
+            o1 |= S.red[2][i];
+            a1 &= S.red[3][i];
+        }
+        var_lo = o0 ^ a0;
+        var_hi = W == 2 ? (o1 ^ a1) : 0ull;
+    }
+    // stable LSD radix sort in LDS on the varying digits below `top`
+    int cur = 0;
+    for (int sh = 0; sh < top; sh += 8) {
+        const int w = (top - sh) < 8 ? (top - sh) : 8;
+        if (vdigit<W>(var_lo, var_hi, n, sh, w) == 0u) continue;  // uniform: constant digit
+        for (int i = tid; i < NW * 256; i += NT) (&S.wcnt[0][0])[i] = 0u;
+        __syncthreads();
+        uint32_t rrank[IT];
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+            const bool valid = li < size;
+            const uint64_t lo = valid ? S.klo[cur][li] : 0ull;
+            const uint64_t hi = (W == 2 && valid) ? S.khi[cur][li] : 0ull;
+            const uint32_t d = vdigit<W>(lo, hi, n, sh, w);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bb = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? bb : ~bb;
+            }
+            const uint32_t before = S.wcnt[wv][d];
+            rrank[q] = before + (uint32_t)__popcll(peers & lt);
+            if (valid && (peers & lt) == 0ull) S.wcnt[wv][d] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        {
+            uint32_t run = 0;
+            if (tid < 256) {
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const uint32_t c = S.wcnt[i][tid];
+                    S.wcnt[i][tid] = run;
+                    run += c;
+                }
+            }
+            uint32_t tot;
+            const uint32_t e = block_scan<NW>(tid < 256 ? run : 0u, S.tmp, tot);
+            if (tid < 256) S.dbase[tid] = e;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < IT; ++q) {
+            const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+            if (li < size) {
+                const uint64_t lo = S.klo[cur][li];
+                const uint64_t hi = W == 2 ? S.khi[cur][li] : 0ull;
+                const uint32_t d = vdigit<W>(lo, hi, n, sh, w);
+                const uint32_t p = min(S.dbase[d] + S.wcnt[wv][d] + rrank[q], (uint32_t)CAP - 1u);
+                S.klo[cur ^ 1][p] = lo;
+                if (W == 2) S.khi[cur ^ 1][p] = hi;
+                S.val[cur ^ 1][p] = S.val[cur][li];
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // runs of equal keys (record order inside a run is the input order); the
+    // run heads live in the key buffer the sort no longer needs
+    uint16_t *head = reinterpret_cast<uint16_t *>(&S.klo[cur ^ 1][0]);
+    {
+        uint32_t base = 0;
+        for (uint32_t r0 = 0; r0 < size; r0 += NT) {
+            const uint32_t r = r0 + tid;
+            bool hd_ = false;
+            if (r < size) {
+                hd_ = r == 0 || S.klo[cur][r] != S.klo[cur][r - 1] ||
+                      (W == 2 && S.khi[cur][r] != S.khi[cur][r - 1]);
+            }
+            uint32_t tot;
+            const uint32_t e = block_scan<NW>(hd_ ? 1u : 0u, S.tmp, tot);
+            if (hd_) head[base + e] = (uint16_t)r;
+            base += tot;
+        }
+        if (tid == 0) {
+            head[base] = (uint16_t)min(size, (uint32_t)CAP);
+            S.nruns = base;
+            S.psi_range[0] = f.psi_range[2 * sidx];
+            S.psi_range[1] = f.psi_range[2 * sidx + 1];
+        }
+        __syncthreads();
+        const uint32_t pa = S.psi_range[0], pb = min(S.psi_range[1], S.psi_range[0] + 256u);
+        for (uint32_t t = tid; t < pb - pa; t += NT) {
+            S.psi_lo[t] = f.plo[pa + t];
+            if (W == 2) S.psi_hi[t] = f.phi[pa + t];
+        }
+        __syncthreads();
+    }
+    // one thread per run: sum, exclusion, diagonal, score; compacted writes
+    const uint32_t nruns = S.nruns, npl = S.psi_range[1] - S.psi_range[0];
+    const bool psi_overflow = npl > 256u;
+    uint32_t written = 0;
+    for (uint32_t u0 = 0; u0 < nruns; u0 += NT) {
+        const uint32_t u = u0 + tid;
+        bool keep = false;
+        double sum = 0.0, score = 0.0;
+        uint64_t lo = 0ull, hi = 0ull;
+        if (u < nruns) {
+            const uint32_t j0 = head[u], j1 = head[u + 1];
+            lo = S.klo[cur][j0];
+            hi = W == 2 ? S.khi[cur][j0] : 0ull;
+            uint32_t at;
+            bool ex;
+            if (!psi_overflow) {
+                at = psi_lower<W>(S.psi_lo, S.psi_hi, 0u, npl, lo, hi);
+                ex = at < npl && S.psi_lo[at] == lo && (W == 1 || S.psi_hi[at] == hi);
+            } else {
+                at = psi_lower<W>(f.plo, f.phi, S.psi_range[0], S.psi_range[1], lo, hi);
+                ex = at < f.npsi && f.plo[at] == lo && (W == 1 || f.phi[at] == hi);
+            }
+            if (!ex) {
+                const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
+                const double den = f.E0 - diag_value(J, K, hd, n, f.ecore, a, b);
+                if (f.eps > 0.0) {
+                    // Alg. 2's threshold, per pair, in record (ascending core) order
+                    for (uint32_t j = j0; j < j1; ++j) {
+                        const double v = S.val[cur][j];
+                        if (fabs(v / den) > f.eps) {
+                            sum = sum + v;
+                            keep = true;
+                        }
+                    }
+                } else {
+                    for (uint32_t j = j0; j < j1; ++j) sum = sum + S.val[cur][j];
+                    keep = true;
+                }
+                score = sum / den;
+            }
+        }
+        uint32_t tot;
+        const uint32_t e = block_scan<NW>(keep ? 1u : 0u, S.tmp, tot);
+        if (keep) {
+            const size_t d = (size_t)sg.start + written + e;
+            f.clo[d] = lo;
+            if (W == 2) f.chi[d] = hi;
+            if (f.cnum) f.cnum[d] = sum;
+            f.cscore[d] = score;
+        }
+        written += tot;
+    }
+    if (tid == 0) f.cnt[sidx] = written;
+}
+
+// persistent workgroups loop over the final segments (a grid of one
+// workgroup per segment could exceed the 2^32 work-item limit of a dispatch)
+template <int W, int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_finish(FinishArgs f)
+{
+    using L = FinishLds<W, CAP, NT>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    L &S = *reinterpret_cast<L *>(smem_raw);
+    double *tab = reinterpret_cast<double *>(smem_raw + ((sizeof(L) + 15) & ~size_t(15)));
+    const int n = f.n;
+    const int tid = threadIdx.x;
+    const double *J, *K, *hd;
+    if (f.tab_in_lds) {
+        for (int t = tid; t < 2 * n * n; t += NT) tab[t] = f.jk[t];
+        for (int t = tid; t < n; t += NT) tab[2 * n * n + t] = f.h[(size_t)t * n + t];
+        J = tab;
+        K = tab + n * n;
+        hd = tab + 2 * n * n;
+    } else {
+        J = f.jk;
+        K = f.jk + n * n;
+        hd = f.jk + 2 * n * n;
+    }
+    for (uint32_t sidx = blockIdx.x; sidx < f.nfinal; sidx += gridDim.x) {
+        __syncthreads();
+        finish_segment<W, CAP, NT>(f, S, J, K, hd, sidx);
+    }
+}
+
+// input keys inside every final segment's key range (its constant prefix above
+// `top`, any bits below): two binary searches per segment, one thread each
+template <int W>
+__global__ __launch_bounds__(256) void k_psi_ranges(const Seg *__restrict__ finals, uint32_t nf,
+                                                    uint64_t *const *__restrict__ klo_,
+                                                    uint64_t *const *__restrict__ khi_, int n,
+                                                    const uint64_t *__restrict__ plo, const uint64_t *__restrict__ phi,
+                                                    uint32_t npsi, uint32_t *__restrict__ range)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nf) return;
+    const Seg sg = finals[j];
+    const uint32_t buf = seg_buf(sg);
+    const uint64_t *klo = klo_[buf];
+    const uint64_t *khi = khi_[buf];
+    const uint64_t lo = klo[sg.start], hi = W == 2 ? khi[sg.start] : 0ull;
+    const int top = (int)seg_top(sg);
+    uint64_t llo, lhi, ulo, uhi;
+    if (W == 1) {
+        const uint64_t m = top >= 64 ? ~0ull : ((1ull << top) - 1ull);
+        llo = lo & ~m;
+        ulo = lo | m;
+        lhi = uhi = 0ull;
+    } else {
+        // virtual bits [0, n) are the lo word, [n, 2n) the hi word
+        const int tlo = top < n ? top : n, thi = top > n ? top - n : 0;
+        const uint64_t mlo = tlo >= 64 ? ~0ull : ((1ull << tlo) - 1ull);
+        const uint64_t mhi = thi >= 64 ? ~0ull : ((1ull << thi) - 1ull);
+        llo = lo & ~mlo;
+        ulo = lo | mlo;
+        lhi = hi & ~mhi;
+        uhi = hi | mhi;
+    }
+    const uint32_t a = psi_lower<W>(plo, phi, 0u, npsi, llo, lhi);
+    // first input key greater than the upper bound
+    uint32_t L = a, R = npsi;
+    while (L < R) {
+        const uint32_t m = (L + R) >> 1;
+        if (!key_less<W>(ulo, uhi, plo[m], W == 2 ? phi[m] : 0ull)) L = m + 1;
+        else R = m;
+    }
+    range[2 * j] = a;
+    range[2 * j + 1] = L;
+}
+
+// ---------------------------------------------------------------- collect
+__global__ __launch_bounds__(256) void k_final_keys_start(const Seg *__restrict__ finals, uint32_t nf,
+                                                          uint64_t *__restrict__ key, uint32_t *__restrict__ idx)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nf) return;
+    key[j] = finals[j].start;
+    idx[j] = j;
+}
+
+__global__ __launch_bounds__(256) void k_gather_counts(const uint32_t *__restrict__ order,
+                                                       const uint32_t *__restrict__ cnt, uint32_t nf,
+                                                       uint32_t *__restrict__ out)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j < nf) out[j] = cnt[order[j]];
+}
+
+// one block per final segment (in key order): copy its candidates to the pool
+template <int W>
+__global__ __launch_bounds__(256) void k_collect(const Seg *__restrict__ finals, uint32_t nf,
+                                                 const uint32_t *__restrict__ order,
+                                                 const uint32_t *__restrict__ cnt_sorted,
+                                                 const uint32_t *__restrict__ off, const uint64_t *__restrict__ clo,
+                                                 const uint64_t *__restrict__ chi, const double *__restrict__ cnum,
+                                                 const double *__restrict__ cscore, uint64_t *__restrict__ plo,
+                                                 uint64_t *__restrict__ phi, double *__restrict__ pnum,
+                                                 double *__restrict__ pscore, size_t base, size_t cap)
+{
+    for (uint32_t j = blockIdx.x; j < nf; j += gridDim.x) {
+        const Seg sg = finals[order[j]];
+        const uint32_t c = cnt_sorted[j];
+        const size_t dst0 = base + off[j];
+        for (uint32_t t = threadIdx.x; t < c; t += 256) {
+            const size_t s = (size_t)sg.start + t, d = dst0 + t;
+            if (d >= cap) break;
+            plo[d] = clo[s];
+            if (W == 2) phi[d] = chi[s];
+            if (pnum) pnum[d] = cnum[s];
+            pscore[d] = cscore[s];
+        }
+    }
+}
+
+__global__ void k_class_segs(const uint64_t *__restrict__ cls, uint32_t c0, uint32_t nc, uint32_t nq,
+                             const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ total, int n,
+                             uint32_t cap, Seg *__restrict__ large, uint32_t *__restrict__ nlarge,
+                             Seg *__restrict__ finals, uint32_t *__restrict__ nfinal)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // a class's keys share every bit at or above n + (lowest bit of its mask);
+    // a run of classes shares the bits above the highest bit where its first
+    // lower bound and last upper bound differ
+    uint32_t g_start = 0, g_size = 0, g_first = 0, g_last = 0;
+    auto top_of = [&](uint32_t cf, uint32_t cl) -> uint32_t {
+        const uint64_t Tf = cls[c0 + cf], Tl = cls[c0 + cl];
+        const int of = Tf ? __ffsll((unsigned long long)Tf) - 1 : 0;
+        const int ol = Tl ? __ffsll((unsigned long long)Tl) - 1 : 0;
+        if (cf == cl) return (uint32_t)(n + of);
+        // alpha range [Tf, Tl | (2^ol - 1)]
+        const uint64_t lo = Tf, hi = Tl | ((1ull << ol) - 1ull);
+        const uint64_t diff = lo ^ hi;
+        return (uint32_t)n + (diff ? (uint32_t)(64 - __clzll((long long)diff)) : 0u);
+    };
+    auto flush = [&]() {
+        if (g_size) finals[(*nfinal)++] = Seg{g_start, g_size, make_meta(top_of(g_first, g_last), 0u, false)};
+        g_size = 0;
+    };
+    for (uint32_t c = 0; c < nc; ++c) {
+        const uint32_t start = offsets[(size_t)c * nq];
+        const uint32_t end = (c + 1 < nc) ? offsets[(size_t)(c + 1) * nq] : *total;
+        if (end <= start) continue;
+        const uint32_t size = end - start;
+        if (size > cap) {
+            flush();
+            large[(*nlarge)++] = Seg{start, size, make_meta(top_of(c, c), 0u, false)};
+            continue;
+        }
+        if (g_size + size > cap) flush();
+        if (g_size == 0) {
+            g_start = start;
+            g_first = c;
+        }
+        g_size += size;
+        g_last = c;
+    }
+    flush();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+template <int W, int CAP, int NT>
+static constexpr size_t lds_max()
+{
+    return 160 * 1024;
+}
+
+
+size_t bucket_workspace_bytes(size_t P, size_t nc, int W)
+{
+    const size_t cap = W == 1 ? 4096 : 2048;
+    const size_t finals = nc + P / 8 + 65536, level = P / cap + nc + 16;
+    const size_t tiles = (P + kTileN - 1) / kTileN + level;
+    return finals * sizeof(Seg) + 2 * level * sizeof(Seg) + level * 16 + tiles * (256 * 8 + 8) +
+           finals * (8 * 2 + 4 * 4 + 8) + (finals + tiles * 256) / 1024 + (4 << 20);
+}
+
+template <int W, int CAP, int NT>
+static void launch_finish(FinishArgs &fa, const BucketArgs &b, uint32_t nf, hipStream_t s, Profiler *prof)
+{
+    const size_t base_lds = (sizeof(FinishLds<W, CAP, NT>) + 15) & ~size_t(15);
+    const size_t tab_lds = ((size_t)2 * b.n * b.n + b.n) * 8;
+    fa.tab_in_lds = base_lds + tab_lds <= lds_max<W, CAP, NT>() ? 1 : 0;
+    const size_t lds = base_lds + (fa.tab_in_lds ? tab_lds : 0);
+    ASCI_HIP(hipFuncSetAttribute((const void *)k_finish<W, CAP, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds_max<W, CAP, NT>()));
+    ProfScope ps(prof, "finish", (8.0 * W + 8.0) * (double)b.P, s);
+    k_finish<W, CAP, NT><<<std::min<uint32_t>(nf, 4096u), NT, lds, s>>>(fa);
+    ASCI_LAUNCH_CHECK();
+}
+
+template <int W>
+void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, HostStage &hs)
+{
+    // LDS capacity of a final segment: 4096 or 2048 records (one-word keys),
+    // 2048 or 1024 (two-word keys)
+    const int CAP = W == 1 ? (b.finish_cap >= 4096 ? 4096 : (b.finish_cap >= 2048 ? 2048 : 1024))
+                           : (b.finish_cap >= 2048 ? 2048 : 1024);
+    const size_t P = b.P;
+    const uint32_t finals_cap = (uint32_t)std::min<size_t>(b.nc + P / 8 + 65536, 0xFFFFFFF0u);
+    const uint32_t level_cap = (uint32_t)(P / CAP + b.nc + 16);
+    Seg *finals = ar.take<Seg>(finals_cap);
+    Seg *lv[2] = {ar.take<Seg>(level_cap), ar.take<Seg>(level_cap)};
+    uint32_t *ctr = ar.take<uint32_t>(8);  // 0: finals, 1/2: large segments per level parity, 3: overflow
+    uint32_t *hcnt = (uint32_t *)hs.ptr;
+    ASCI_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(uint32_t), s));
+    k_class_segs<<<1, 64, 0, s>>>(b.cls, b.c0, b.nc, b.nq, b.offsets, b.total, b.n, (uint32_t)CAP, lv[0], ctr + 1,
+                                  finals, ctr);
+    ASCI_LAUNCH_CHECK();
+    ASCI_HIP(hipMemcpyAsync(hcnt, ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    ASCI_HIP(hipStreamSynchronize(s));
+    uint32_t nlarge = hcnt[1];
+    int lev = 0;
+    const size_t mark = ar.used();
+    while (nlarge > 0) {
+        ar.reset();
+        (void)ar.take<char>(mark);
+        require(lev < 16, ASCI_EDEVICE, "bucket split did not converge");
+        Seg *segs = lv[lev & 1], *next = lv[(lev & 1) ^ 1];
+        uint32_t *nnext = ctr + 1 + ((lev & 1) ^ 1);
+        ASCI_HIP(hipMemsetAsync(nnext, 0, sizeof(uint32_t), s));
+        uint32_t *ntile = ar.take<uint32_t>(nlarge + 1);
+        uint32_t *tbase = ar.take<uint32_t>(nlarge + 1);
+        uint32_t *skip = ar.take<uint32_t>(nlarge + 1);
+        uint32_t *d_ntiles = ar.take<uint32_t>(4);
+        ASCI_HIP(hipMemsetAsync(skip, 0, (nlarge + 1) * sizeof(uint32_t), s));
+        k_seg_tiles<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, ntile);
+        ASCI_LAUNCH_CHECK();
+        scan_u32(ntile, tbase, nlarge, d_ntiles, ar, s, prof);
+        ASCI_HIP(hipMemcpyAsync(hcnt + 4, d_ntiles, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        ASCI_HIP(hipStreamSynchronize(s));
+        const uint32_t ntiles = hcnt[4];
+        uint32_t *tseg = ar.take<uint32_t>(ntiles + 1);
+        uint32_t *hist = ar.take<uint32_t>((size_t)ntiles * 256 + 1);
+        uint32_t *hscan = ar.take<uint32_t>((size_t)ntiles * 256 + 1);
+        k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg);
+        ASCI_LAUNCH_CHECK();
+        SplitArgs sa;
+        sa.segs = segs;
+        sa.nseg = nlarge;
+        sa.tile_base = tbase;
+        sa.tile_seg = tseg;
+        sa.ntiles = ntiles;
+        sa.hist = hist;
+        sa.klo[0] = b.klo[0];
+        sa.klo[1] = b.klo[1];
+        sa.khi[0] = b.khi[0];
+        sa.khi[1] = b.khi[1];
+        sa.val[0] = b.val[0];
+        sa.val[1] = b.val[1];
+        sa.n = b.n;
+        sa.cap = (uint32_t)CAP;
+        {
+            ProfScope ps(prof, "split_hist", (8.0 * W) * (double)ntiles * kTileN, s);
+            k_split_hist<W><<<ntiles, kTileT, 0, s>>>(sa);
+            ASCI_LAUNCH_CHECK();
+        }
+        scan_u32(hist, hscan, (size_t)ntiles * 256, nullptr, ar, s, prof);
+        k_split_children<W><<<nlarge, 256, 0, s>>>(segs, nlarge, tbase, hscan, (uint32_t)CAP, skip, finals, ctr,
+                                                   finals_cap, next, nnext, level_cap, ctr + 3);
+        ASCI_LAUNCH_CHECK();
+        sa.hist = hscan;
+        {
+            ProfScope ps(prof, "split_scatter", 2.0 * (8.0 * W + 8.0) * (double)ntiles * kTileN, s);
+            k_split_scatter<W><<<ntiles, kTileT, 0, s>>>(sa, hscan, skip);
+            ASCI_LAUNCH_CHECK();
+        }
+        ASCI_HIP(hipMemcpyAsync(hcnt, ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        ASCI_HIP(hipStreamSynchronize(s));
+        require(hcnt[3] == 0, ASCI_EDEVICE, "bucket segment list overflow");
+        nlarge = hcnt[1 + ((lev & 1) ^ 1)];
+        ++lev;
+    }
+    ar.reset();
+    (void)ar.take<char>(mark);
+    const uint32_t nf = hcnt[0];
+    b.nfinal = nf;
+    b.levels = (uint32_t)lev;
+    uint32_t *cnt = ar.take<uint32_t>(nf + 1);
+    uint32_t *prange = ar.take<uint32_t>(2 * (size_t)nf + 2);
+    uint64_t **bufptr = ar.take<uint64_t *>(4);
+    if (nf) {
+        uint64_t *hb[4] = {b.klo[0], b.klo[1], b.khi[0], b.khi[1]};
+        uint64_t **hstage = (uint64_t **)((char *)hs.ptr + 64);
+        for (int i = 0; i < 4; ++i) hstage[i] = hb[i];
+        ASCI_HIP(hipMemcpyAsync(bufptr, hstage, 4 * sizeof(uint64_t *), hipMemcpyHostToDevice, s));
+        {
+            ProfScope ps(prof, "psi_ranges", 0.0, s);
+            k_psi_ranges<W><<<(nf + 255) / 256, 256, 0, s>>>(finals, nf, bufptr, bufptr + 2, b.n, b.plo, b.phi,
+                                                             b.npsi, prange);
+            ASCI_LAUNCH_CHECK();
+        }
+        FinishArgs fa;
+        fa.finals = finals;
+        fa.klo[0] = b.klo[0];
+        fa.klo[1] = b.klo[1];
+        fa.khi[0] = b.khi[0];
+        fa.khi[1] = b.khi[1];
+        fa.val[0] = b.val[0];
+        fa.val[1] = b.val[1];
+        fa.n = b.n;
+        fa.plo = b.plo;
+        fa.phi = b.phi;
+        fa.npsi = b.npsi;
+        fa.jk = b.jk;
+        fa.h = b.h;
+        fa.ecore = b.ecore;
+        fa.E0 = b.E0;
+        fa.eps = b.eps;
+        fa.clo = b.clo;
+        fa.chi = b.chi;
+        fa.cnum = b.cnum;
+        fa.cscore = b.cscore;
+        fa.cnt = cnt;
+        fa.nfinal = nf;
+        fa.psi_range = prange;
+        if constexpr (W == 1) {
+            if (CAP == 4096) launch_finish<1, 4096, 512>(fa, b, nf, s, prof);
+            else if (CAP == 2048) launch_finish<1, 2048, 256>(fa, b, nf, s, prof);
+            else launch_finish<1, 1024, 256>(fa, b, nf, s, prof);
+        } else {
+            if (CAP == 2048) launch_finish<2, 2048, 256>(fa, b, nf, s, prof);
+            else launch_finish<2, 1024, 256>(fa, b, nf, s, prof);
+        }
+    }
+    // candidates in key order: final segments by start, counts scanned
+    uint64_t *sk[2] = {ar.take<uint64_t>(nf + 1), ar.take<uint64_t>(nf + 1)};
+    uint32_t *si[2] = {ar.take<uint32_t>(nf + 1), ar.take<uint32_t>(nf + 1)};
+    uint32_t *cs = ar.take<uint32_t>(nf + 1);
+    uint32_t *co = ar.take<uint32_t>(nf + 1);
+    uint32_t *d_v = ar.take<uint32_t>(4);
+    uint64_t *nohi[2] = {nullptr, nullptr};
+    int r = 0;
+    if (nf) {
+        k_final_keys_start<<<(nf + 255) / 256, 256, 0, s>>>(finals, nf, sk[0], si[0]);
+        ASCI_LAUNCH_CHECK();
+        std::vector<Digit> dg;
+        for (int sh = 0; sh < 32; sh += 8) dg.push_back({0, sh});
+        r = radix_sort<uint32_t>(sk, nohi, si, nf, 1, dg, ar, s, nullptr);
+        k_gather_counts<<<(nf + 255) / 256, 256, 0, s>>>(si[r], cnt, nf, cs);
+        ASCI_LAUNCH_CHECK();
+    }
+    scan_u32(cs, co, nf, d_v, ar, s, nullptr);
+    ASCI_HIP(hipMemcpyAsync(hcnt + 6, d_v, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    ASCI_HIP(hipStreamSynchronize(s));
+    b.V = hcnt[6];
+    b.order = si[r];
+    b.cnt_sorted = cs;
+    b.off = co;
+    b.finals = finals;
+}
+
+template <int W>
+void bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof)
+{
+    if (b.nfinal == 0 || b.V == 0) return;
+    ProfScope ps(prof, "collect", (8.0 * W + 8.0) * 2.0 * b.V, s);
+    k_collect<W><<<std::min<uint32_t>(b.nfinal, 65536u), 256, 0, s>>>((const Seg *)b.finals, b.nfinal, b.order, b.cnt_sorted, b.off, b.clo, b.chi, b.cnum,
+                                         b.cscore, b.pool_lo, b.pool_hi, b.pool_num, b.pool_score, b.pool_base,
+                                         b.pool_cap);
+    ASCI_LAUNCH_CHECK();
+}
+
+template void bucket_accumulate<1>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);
+template void bucket_accumulate<2>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);
+template void bucket_collect<1>(BucketArgs &, hipStream_t, Profiler *);
+template void bucket_collect<2>(BucketArgs &, hipStream_t, Profiler *);
+
+}  // namespace asci

@@ -363,110 +363,6 @@ __global__ void k_init_or_and(unsigned long long *p)
     if (threadIdx.x < 4) p[threadIdx.x] = (threadIdx.x & 1) ? ~0ull : 0ull;
 }
 
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_head_flags(const uint64_t *__restrict__ klo,
-                                                       const uint64_t *__restrict__ khi, size_t n,
-                                                       uint32_t *__restrict__ flag)
-{
-    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    bool head = j == 0 || klo[j] != klo[j - 1];
-    if (W == 2 && j > 0) head = head || khi[j] != khi[j - 1];
-    flag[j] = head ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(kBlock) void k_head_scatter(const uint32_t *__restrict__ flag,
-                                                         const uint32_t *__restrict__ pos, size_t n,
-                                                         uint32_t *__restrict__ heads,
-                                                         const uint32_t *__restrict__ d_count)
-{
-    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < n && flag[j] && pos[j] < n) heads[pos[j]] = (uint32_t)j;
-    if (j == 0) heads[min((size_t)*d_count, n)] = (uint32_t)n;
-}
-
-// binary search of (a, b) in the sorted input keys
-template <int W>
-__device__ __forceinline__ bool in_psi(const uint64_t *__restrict__ plo, const uint64_t *__restrict__ phi,
-                                       uint32_t npsi, uint64_t lo, uint64_t hi)
-{
-    uint32_t L = 0, R = npsi;
-    while (L < R) {
-        const uint32_t mid = (L + R) >> 1;
-        const uint64_t ml = plo[mid];
-        bool less;
-        if (W == 1) {
-            less = ml < lo;
-        } else {
-            const uint64_t mh = phi[mid];
-            less = mh < hi || (mh == hi && ml < lo);
-        }
-        if (less) L = mid + 1;
-        else R = mid;
-    }
-    if (L >= npsi) return false;
-    return plo[L] == lo && (W == 1 || phi[L] == hi);
-}
-
-// one thread per run of equal keys (grid-stride); J/K/h-diagonal in LDS
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_reduce_score(
-    const uint64_t *__restrict__ klo, const uint64_t *__restrict__ khi, const double *__restrict__ vals,
-    const uint32_t *__restrict__ heads, const uint32_t *__restrict__ d_nuniq, uint32_t nrec,
-    const uint64_t *__restrict__ plo, const uint64_t *__restrict__ phi, uint32_t npsi,
-    const double *__restrict__ jk, const double *__restrict__ h, int n, double ecore, double E0,
-    uint64_t *__restrict__ clo, uint64_t *__restrict__ chi, double *__restrict__ cnum,
-    double *__restrict__ cscore, uint32_t *__restrict__ keep)
-{
-    extern __shared__ double s_tab[];
-    double *J = s_tab, *K = s_tab + n * n, *hd = s_tab + 2 * n * n;
-    for (int t = threadIdx.x; t < 2 * n * n; t += kBlock) s_tab[t] = jk[t];
-    for (int t = threadIdx.x; t < n; t += kBlock) hd[t] = h[(size_t)t * n + t];
-    __syncthreads();
-    const uint32_t nu = *d_nuniq;
-    const uint64_t nmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
-    for (uint32_t u = blockIdx.x * kBlock + threadIdx.x; u < nu; u += gridDim.x * kBlock) {
-        const uint32_t j0 = heads[u], j1 = min(heads[u + 1], nrec);
-        double s = 0.0;
-        for (uint32_t j = j0; j < j1; ++j) s = s + vals[j];
-        const uint64_t lo = klo[j0];
-        const uint64_t hi = (W == 2) ? khi[j0] : 0ull;
-        const uint64_t a = (W == 1) ? (lo >> n) : hi;
-        const uint64_t b = (W == 1) ? (lo & nmask) : lo;
-        const bool ex = in_psi<W>(plo, phi, npsi, lo, hi);
-        const double hdv = diag_value(J, K, hd, n, ecore, a, b);
-        clo[u] = lo;
-        if (W == 2) chi[u] = hi;
-        cnum[u] = s;
-        cscore[u] = s / (E0 - hdv);
-        keep[u] = ex ? 0u : 1u;
-    }
-}
-
-// append kept candidates to the pool (stable)
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_append(const uint64_t *__restrict__ clo,
-                                                   const uint64_t *__restrict__ chi,
-                                                   const double *__restrict__ cnum,
-                                                   const double *__restrict__ cscore,
-                                                   const uint32_t *__restrict__ keep,
-                                                   const uint32_t *__restrict__ pos,
-                                                   const uint32_t *__restrict__ d_n, uint64_t *__restrict__ plo,
-                                                   uint64_t *__restrict__ phi, double *__restrict__ pnum,
-                                                   double *__restrict__ pscore, size_t base, size_t cap)
-{
-    const uint32_t n = *d_n;
-    for (uint32_t u = blockIdx.x * kBlock + threadIdx.x; u < n; u += gridDim.x * kBlock) {
-        if (!keep[u]) continue;
-        const size_t d = base + pos[u];
-        if (d >= cap) continue;
-        plo[d] = clo[u];
-        if (W == 2) phi[d] = chi[u];
-        if (pnum) pnum[d] = cnum[u];
-        pscore[d] = cscore[u];
-    }
-}
-
 // ---------------------------------------------------------------- selection helpers
 __global__ __launch_bounds__(kBlock) void k_flag_equal(const double *__restrict__ score, size_t n,
                                                        const SelectState *__restrict__ st,
@@ -614,13 +510,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_core(const uint64_t *__restri
     qc[j] = c[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_jk(const double *__restrict__ eri, int n, double *__restrict__ jk)
+// J_pq = (pp|qq), K_pq = (pq|qp), then h_pp: the tables of the diagonal H_aa
+__global__ __launch_bounds__(kBlock) void k_jk(const double *__restrict__ eri, const double *__restrict__ h, int n,
+                                               double *__restrict__ jk)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= n * n) return;
     const int p = t / n, q = t % n;
     jk[t] = eri4(eri, n, p, p, q, q);
     jk[n * n + t] = eri4(eri, n, p, q, q, p);
+    if (q == 0) jk[2 * n * n + p] = h[(size_t)p * n + p];
 }
 
 inline unsigned grid_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -706,7 +605,7 @@ static std::vector<Digit> full_key_digits(int n, int W)
 // Validate the determinants, sort their keys, pick the core set and count the
 // pairs of every constraint class.  All buffers live in ctx->setup.
 template <int W>
-static void prepare(asci_ctx *ctx, const double *d_eri, int n, int na, int nb, const uint64_t *dets,
+static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n, int na, int nb, const uint64_t *dets,
                     const double *coeffs, int64_t ndets, int64_t ncore, bool need_psi, Prepared<W> &pp,
                     hipStream_t s)
 {
@@ -729,7 +628,7 @@ static void prepare(asci_ctx *ctx, const double *d_eri, int n, int na, int nb, c
     unsigned int *d_err = ar.take<unsigned int>(16);
     pp.d_cls = ar.take<uint64_t>(ncls);
     unsigned long long *d_tot = ar.take<unsigned long long>(ncls);
-    pp.d_jk = ar.take<double>((size_t)2 * n * n);
+    pp.d_jk = ar.take<double>((size_t)2 * n * n + n);
     uint64_t *psi_lo[2] = {ar.take<uint64_t>(nd), ar.take<uint64_t>(nd)};
     uint64_t *psi_hi[2] = {W == 2 ? ar.take<uint64_t>(nd) : nullptr, W == 2 ? ar.take<uint64_t>(nd) : nullptr};
     uint32_t *psi_idx[2] = {ar.take<uint32_t>(nd), ar.take<uint32_t>(nd)};
@@ -742,8 +641,8 @@ static void prepare(asci_ctx *ctx, const double *d_eri, int n, int na, int nb, c
     ASCI_HIP(hipMemcpyAsync(pp.d_cls, pp.cls.data(), ncls * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     k_validate<<<grid_for(nd), kBlock, 0, s>>>(dets, nd, full, na, nb, d_err);
     ASCI_LAUNCH_CHECK();
-    if (d_eri) {
-        k_jk<<<grid_for((size_t)n * n), kBlock, 0, s>>>(d_eri, n, pp.d_jk);
+    if (d_eri && d_h) {
+        k_jk<<<grid_for((size_t)n * n), kBlock, 0, s>>>(d_eri, d_h, n, pp.d_jk);
         ASCI_LAUNCH_CHECK();
     }
     if (need_psi) {
@@ -803,11 +702,10 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     const uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
     const BetaFactors bf = beta_factors(n, in.nb);
     const bool topk = out.k > 0;
-    require(!(in.opt.eps > 0.0), ASCI_EINVAL, "eps > 0 is not supported by this build");
 
     Profiler *prof = &ctx->prof;
     Prepared<W> pp;
-    prepare<W>(ctx, in.eri, n, in.na, in.nb, in.dets, in.coeffs, in.ndets, in.opt.ncore, true, pp, s);
+    prepare<W>(ctx, in.h, in.eri, n, in.na, in.nb, in.dets, in.coeffs, in.ndets, in.opt.ncore, true, pp, s);
     const size_t nd = pp.nd, nq = pp.nq;
     const uint32_t ncls = (uint32_t)pp.cls.size();
 
@@ -847,23 +745,20 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     if (topk) pool_cap = (size_t)std::min<uint64_t>(total + 1, std::max<uint64_t>(4 * (uint64_t)out.k, Pb) + (uint64_t)out.k);
     else pool_cap = total + 1;
     require(pool_cap < (1ull << 32), ASCI_ENOMEM, "candidate pool too large");
-    const size_t nbp = (Pb + kScanTile - 1) / kScanTile;
-    const size_t scan_tmp = ((std::max<size_t>(Pb, std::max<size_t>(E, nbp * 256)) + kScanTile - 1) / kScanTile) * 4 + 4096;
+    const size_t scan_tmp = ((std::max<size_t>(Pb, E) + kScanTile - 1) / kScanTile) * 4 + 4096;
     const size_t kk_max = topk ? (size_t)std::min<uint64_t>((uint64_t)out.k, pool_cap) : 0;
+    uint32_t max_nc = 1;
+    for (const auto &bt : batches) max_nc = std::max<uint32_t>(max_nc, bt.second - bt.first);
     Arena &ar = ctx->main;
     ar.reset();
-    ar.reserve(E * 8 + Pb * rec_bytes + 3 * (Pb + 1) * 4 + nbp * 256 * 4 + scan_tmp +
-               Pb * (8 * W + 16) + pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 12) +
-               kk_max * 24 + 64 * 256 + (1 << 16));
+    ar.reserve(E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, max_nc, W) +
+               pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 12) + kk_max * 24 + 64 * 256 + (1 << 16));
     ar.reset();
     uint32_t *counts = ar.take<uint32_t>(E);
     uint32_t *offs = ar.take<uint32_t>(E);
     uint64_t *k_lo[2] = {ar.take<uint64_t>(Pb), ar.take<uint64_t>(Pb)};
     uint64_t *k_hi[2] = {W == 2 ? ar.take<uint64_t>(Pb) : nullptr, W == 2 ? ar.take<uint64_t>(Pb) : nullptr};
     double *v[2] = {ar.take<double>(Pb), ar.take<double>(Pb)};
-    uint32_t *flag = ar.take<uint32_t>(Pb + 1);
-    uint32_t *pos = ar.take<uint32_t>(Pb + 1);
-    uint32_t *heads = ar.take<uint32_t>(Pb + 1);
     uint64_t *c_lo = ar.take<uint64_t>(Pb);
     uint64_t *c_hi = W == 2 ? ar.take<uint64_t>(Pb) : nullptr;
     double *c_num = ar.take<double>(Pb);
@@ -882,13 +777,14 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
 
     HostStage &hs = ctx->stage;
     hs.reserve(256);
-    unsigned long long *h_misc = (unsigned long long *)hs.ptr;
-    const size_t jk_lds = ((size_t)2 * n * n + n) * sizeof(double);
     int pcur = 0;
     size_t pool_n = 0;
+    ctx->last_batches = (int64_t)batches.size();
+    ctx->last_finals = ctx->last_levels = ctx->last_candidates = 0;
 
     // keep the pool's keepk entries of largest |score|, in ascending key order
     auto prune = [&](size_t keepk) {
+        const size_t entry_mark = ar.used();
         radix_select_abs(p_score[pcur], pool_n, keepk, d_sel, s, prof);
         k_flag_equal<<<grid_for(pool_n), kBlock, 0, s>>>(p_score[pcur], pool_n, d_sel, pflag);
         ASCI_LAUNCH_CHECK();
@@ -903,7 +799,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         pcur = o;
         pool_n = keepk;
         ar.reset();
-        (void)ar.take<char>(loop_mark);
+        (void)ar.take<char>(entry_mark);
     };
 
     for (const auto &bt : batches) {
@@ -922,7 +818,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             k_count<<<g, kBlock, 0, s>>>(pp.q_a, (uint32_t)nq, pp.d_cls, c0, full, bf, counts, nullptr);
             ASCI_LAUNCH_CHECK();
         }
-        scan_u32(counts, offs, ent, nullptr, ar, s, prof);
+        scan_u32(counts, offs, ent, d_cnt + 2, ar, s, prof);
         // step 5: generate
         k_init_or_and<<<1, 64, 0, s>>>(d_misc);
         ASCI_LAUNCH_CHECK();
@@ -963,58 +859,53 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             k_generate<W><<<(unsigned)nq, 64, lds, s>>>(ga);
             ASCI_LAUNCH_CHECK();
         }
-        ASCI_HIP(hipMemcpyAsync(h_misc, d_misc, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        ASCI_HIP(hipStreamSynchronize(s));
-        // step 6: sort on the digits that vary inside the batch
-        std::vector<Digit> dig;
-        if (W == 1) {
-            const uint64_t var = h_misc[0] ^ h_misc[1];
-            for (int sh = 0; sh < 2 * n; sh += 8)
-                if ((var >> sh) & 0xFFull) dig.push_back({0, sh});
-        } else {
-            const uint64_t var0 = h_misc[0] ^ h_misc[1], var1 = h_misc[2] ^ h_misc[3];
-            for (int sh = 0; sh < n; sh += 8)
-                if ((var0 >> sh) & 0xFFull) dig.push_back({0, sh});
-            for (int sh = 0; sh < n; sh += 8)
-                if ((var1 >> sh) & 0xFFull) dig.push_back({1, sh});
-        }
-        const int r = radix_sort<double>(k_lo, k_hi, v, P, W, dig, ar, s, prof);
-        // steps 7-9: runs of equal keys, sum, exclusion, H_aa, score
-        {
-            ProfScope ps(prof, "head_flags", (8.0 * W + 4.0) * P, s);
-            k_head_flags<W><<<grid_for(P), kBlock, 0, s>>>(k_lo[r], k_hi[r], P, flag);
-            ASCI_LAUNCH_CHECK();
-        }
-        scan_u32(flag, pos, P, d_cnt, ar, s, prof);
-        ASCI_HIP(hipMemcpyAsync(h_misc, d_cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        ASCI_HIP(hipStreamSynchronize(s));
-        const uint32_t U = *(uint32_t *)h_misc;
-        {
-            ProfScope ps(prof, "head_scatter", 8.0 * P + 4.0 * U, s);
-            k_head_scatter<<<grid_for(P), kBlock, 0, s>>>(flag, pos, P, heads, d_cnt);
-            ASCI_LAUNCH_CHECK();
-        }
-        {
-            ProfScope ps(prof, "reduce_score", 8.0 * P + (8.0 * W + 8.0) * U + (8.0 * W + 20.0) * U, s);
-            const unsigned rg = (unsigned)std::max<size_t>(1, std::min<size_t>(grid_for(U), 4096));
-            k_reduce_score<W><<<rg, kBlock, jk_lds, s>>>(k_lo[r], k_hi[r], v[r], heads, d_cnt, (uint32_t)P, pp.plo,
-                                                         pp.phi,
-                                                         (uint32_t)nd, pp.d_jk, in.h, n, in.opt.ecore, in.E0, c_lo,
-                                                         c_hi, c_num, c_score, flag);
-            ASCI_LAUNCH_CHECK();
-        }
-        scan_u32(flag, pos, U, d_cnt + 1, ar, s, prof);
-        ASCI_HIP(hipMemcpyAsync(h_misc, d_cnt + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        ASCI_HIP(hipStreamSynchronize(s));
-        const uint32_t V = *(uint32_t *)h_misc;
+        // steps 6-9: bucket sort-and-accumulate, exclusion, diagonal, score
+        BucketArgs ba;
+        ba.P = P;
+        ba.c0 = c0;
+        ba.nc = nc;
+        ba.nq = (uint32_t)nq;
+        ba.n = n;
+        ba.cls = pp.d_cls;
+        ba.offsets = offs;
+        ba.total = d_cnt + 2;
+        ba.klo[0] = k_lo[0];
+        ba.klo[1] = k_lo[1];
+        ba.khi[0] = k_hi[0];
+        ba.khi[1] = k_hi[1];
+        ba.val[0] = v[0];
+        ba.val[1] = v[1];
+        ba.plo = pp.plo;
+        ba.phi = pp.phi;
+        ba.npsi = (uint32_t)nd;
+        ba.jk = pp.d_jk;
+        ba.h = in.h;
+        ba.ecore = in.opt.ecore;
+        ba.E0 = in.E0;
+        ba.eps = in.opt.eps;
+        ba.finish_cap = ctx->finish_cap;
+        ba.clo = c_lo;
+        ba.chi = c_hi;
+        ba.cnum = c_num;
+        ba.cscore = c_score;
+        bucket_accumulate<W>(ba, ar, s, prof, hs);
+        const uint32_t V = ba.V;
+        ctx->last_finals += ba.nfinal;
+        ctx->last_levels = std::max<int64_t>(ctx->last_levels, ba.levels);
+        ctx->last_candidates += V;
         if (topk && pool_n + V > pool_cap) prune((size_t)std::min<uint64_t>(pool_n, (uint64_t)out.k));
-        require(pool_n + V <= pool_cap, ASCI_ENOMEM, "candidate pool overflow");
-        {
-            ProfScope ps(prof, "append", (8.0 * W + 24.0) * U + (8.0 * W + 8.0) * V, s);
-            k_append<W><<<1024, kBlock, 0, s>>>(c_lo, c_hi, c_num, c_score, flag, pos, d_cnt, p_lo[pcur],
-                                                p_hi[pcur], p_num, p_score[pcur], pool_n, pool_cap);
-            ASCI_LAUNCH_CHECK();
-        }
+        if (pool_n + V > pool_cap)
+            throw Error{ASCI_ENOMEM, "candidate pool overflow: pool " + std::to_string(pool_n) + " + batch " +
+                                         std::to_string(V) + " > capacity " + std::to_string(pool_cap) +
+                                         " (batch pairs " + std::to_string(P) + ", finals " +
+                                         std::to_string(ba.nfinal) + ", max batch " + std::to_string(Pb) + ")"};
+        ba.pool_lo = p_lo[pcur];
+        ba.pool_hi = p_hi[pcur];
+        ba.pool_num = p_num;
+        ba.pool_score = p_score[pcur];
+        ba.pool_base = pool_n;
+        ba.pool_cap = pool_cap;
+        bucket_collect<W>(ba, s, prof);
         pool_n += V;
     }
 
@@ -1098,11 +989,11 @@ void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *d
     };
     if (n <= 32) {
         Prepared<1> pp;
-        prepare<1>(ctx, nullptr, n, na, nb, dets, coeffs, ndets, ncore, false, pp, s);
+        prepare<1>(ctx, nullptr, nullptr, n, na, nb, dets, coeffs, ndets, ncore, false, pp, s);
         collect(pp.cls, pp.totals);
     } else {
         Prepared<2> pp;
-        prepare<2>(ctx, nullptr, n, na, nb, dets, coeffs, ndets, ncore, false, pp, s);
+        prepare<2>(ctx, nullptr, nullptr, n, na, nb, dets, coeffs, ndets, ncore, false, pp, s);
         collect(pp.cls, pp.totals);
     }
 }

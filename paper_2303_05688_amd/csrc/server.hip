@@ -1,0 +1,499 @@
+// Batched searches and a continuous-batching request loop.
+//
+// A worker pool: each worker owns a context (workspace arenas) and a HIP
+// stream, so searches on different workers overlap on the device.  Requests
+// are admitted from a FIFO queue while a worker is free and the bytes budgeted
+// for running requests, plus the workspace idle workers keep, fit the HBM
+// budget; idle workers give their workspace back when a request needs room.
+// The batch entry point runs a transient pool over a fixed request list,
+// largest estimated cost first.
+#include "asci_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace asci {
+
+namespace {
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t c2(int64_t x) { return x * (x - 1) / 2; }
+
+}  // namespace
+
+int64_t request_pairs(const asci_request &r)
+{
+    const int64_t n = r.norb, na = r.nalpha, nb = r.nbeta, va = n - na, vb = n - nb;
+    const int64_t per = na * va + nb * vb + c2(na) * c2(va) + c2(nb) * c2(vb) + na * va * nb * vb;
+    const int64_t nq = (r.opt.ncore > 0 && r.opt.ncore < r.ndets) ? r.opt.ncore : r.ndets;
+    return nq * per;
+}
+
+int64_t request_footprint(const asci_request &r, uint64_t cap_records)
+{
+    const int W = r.norb <= 32 ? 1 : 2;
+    const int L = r.nalpha < 3 ? r.nalpha : 3;
+    // number of classes: C(n - na + L, L)
+    int64_t ncls = 1;
+    for (int i = 1; i <= L; ++i) ncls = ncls * (r.norb - r.nalpha + i) / i;
+    const int64_t nq = (r.opt.ncore > 0 && r.opt.ncore < r.ndets) ? r.opt.ncore : r.ndets;
+    const uint64_t P = (uint64_t)request_pairs(r);
+    uint64_t Pb = std::min<uint64_t>(P, cap_records);
+    if (r.opt.pair_buffer_bytes > 0) Pb = std::min<uint64_t>(Pb, (uint64_t)r.opt.pair_buffer_bytes / (2 * (8 * W + 8)));
+    Pb = std::max<uint64_t>(Pb, 1) + Pb / 8;  // a class may overshoot the cap
+    const uint64_t nc = (uint64_t)std::min<int64_t>(ncls, 2048);
+    const uint64_t E = nc * (uint64_t)nq;
+    const uint64_t k = (uint64_t)std::max<int64_t>(r.k, 1);
+    const uint64_t pool = std::min<uint64_t>(P + 1, std::max<uint64_t>(4 * k, Pb) + k);
+    const uint64_t setup = (uint64_t)r.ndets * 128 + (uint64_t)nq * 64 + (uint64_t)ncls * 16 +
+                           (uint64_t)(2 * r.norb * r.norb + r.norb) * 8 + (1 << 20);
+    const uint64_t main = E * 8 + Pb * (2 * (8 * W + 8)) + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, nc, W) +
+                          pool * ((8 * W + 8) * 2 + 12) + std::min(k, pool) * 24 + (1 << 20);
+    return (int64_t)(setup + main);
+}
+
+// ---------------------------------------------------------------- the pool
+struct Job {
+    asci_request req;
+    uint64_t ticket;
+    double t_submit;
+    int64_t footprint;
+    int64_t pairs;
+};
+
+struct WorkerState {
+    std::unique_ptr<asci_ctx> ctx;
+    hipStream_t stream = nullptr;
+    int64_t resident = 0;  // workspace the worker keeps between requests
+    int64_t reserved = 0;  // bytes budgeted while running
+    bool busy = false;
+    std::thread th;
+};
+
+class Pool {
+  public:
+    Pool(int device, int64_t budget, int slots, bool fake, double ns_per_byte, int finish_cap,
+         hipStream_t after = nullptr)
+        : device_(device), budget_(budget), fake_(fake), ns_per_byte_(ns_per_byte)
+    {
+        slots = std::max(1, std::min(slots, 16));
+        cap_records_ = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(1ll << 30, budget / slots / 160));
+        hipEvent_t ready = nullptr;
+        if (!fake_ && after) {
+            ASCI_HIP(hipSetDevice(device_));
+            ASCI_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+            ASCI_HIP(hipEventRecord(ready, after));
+        }
+        ws_.resize((size_t)slots);
+        for (auto &w : ws_) {
+            w = std::make_unique<WorkerState>();
+            if (!fake_) {
+                ASCI_HIP(hipSetDevice(device_));
+                w->ctx = std::make_unique<asci_ctx>();
+                w->ctx->device = device_;
+                w->ctx->finish_cap = finish_cap;
+                ASCI_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+                if (ready) ASCI_HIP(hipStreamWaitEvent(w->stream, ready, 0));
+            }
+        }
+        if (ready) ASCI_HIP(hipEventDestroy(ready));
+        for (size_t i = 0; i < ws_.size(); ++i) ws_[i]->th = std::thread([this, i] { loop((int)i); });
+    }
+
+    ~Pool()
+    {
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_work_.notify_all();
+        for (auto &w : ws_)
+            if (w->th.joinable()) w->th.join();
+        for (auto &w : ws_)
+            if (w->stream) (void)hipStreamDestroy(w->stream);
+    }
+
+    // the request as this pool runs it: pair buffer capped at cap_records_
+    asci_request shaped(const asci_request &r) const
+    {
+        asci_request q = r;
+        const int64_t capb = (int64_t)(cap_records_ * (r.norb <= 32 ? 32 : 48));
+        if (q.opt.pair_buffer_bytes == 0 || q.opt.pair_buffer_bytes > capb) q.opt.pair_buffer_bytes = capb;
+        return q;
+    }
+
+    int64_t footprint(const asci_request &r) const { return request_footprint(shaped(r), cap_records_); }
+
+    int submit(const asci_request &r, uint64_t *ticket)
+    {
+        Job j;
+        j.req = shaped(r);
+        j.pairs = request_pairs(r);
+        j.footprint = request_footprint(j.req, cap_records_);
+        std::unique_lock<std::mutex> lk(mu_);
+        j.ticket = next_ticket_++;
+        *ticket = j.ticket;
+        ++submitted_;
+        if (first_submit_ < 0) first_submit_ = now_ms();
+        if (j.footprint > budget_) {
+            ++rejected_;
+            asci_result res{};
+            res.status = ASCI_ENOMEM;
+            done_[j.ticket] = res;
+            cv_done_.notify_all();
+            return ASCI_ENOMEM;
+        }
+        j.t_submit = now_ms();
+        queue_.push_back(j);
+        cv_work_.notify_all();
+        return ASCI_OK;
+    }
+
+    int poll(uint64_t t, asci_result *res, bool block)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        if (t == 0 || t >= next_ticket_) return ASCI_EINVAL;
+        for (;;) {
+            auto it = done_.find(t);
+            if (it != done_.end()) {
+                if (res) *res = it->second;
+                return ASCI_OK;
+            }
+            if (!block) return ASCI_EAGAIN;
+            cv_done_.wait(lk);
+        }
+    }
+
+    void drain()
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_done_.wait(lk, [&] { return queue_.empty() && running_ == 0; });
+    }
+
+    void stats(asci_server_stats *st)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        std::vector<double> l = lat_;
+        std::sort(l.begin(), l.end());
+        auto pct = [&](double p) {
+            if (l.empty()) return 0.0;
+            size_t i = (size_t)std::ceil(p * (double)l.size());
+            return l[std::min(l.size() - 1, i ? i - 1 : 0)];
+        };
+        double sum = 0;
+        for (double x : l) sum += x;
+        st->submitted = submitted_;
+        st->completed = completed_;
+        st->failed = failed_;
+        st->rejected = rejected_;
+        st->max_running = max_running_;
+        st->peak_bytes = peak_bytes_;
+        st->p50_ms = pct(0.50);
+        st->p99_ms = pct(0.99);
+        st->mean_ms = l.empty() ? 0.0 : sum / (double)l.size();
+        st->wall_s = (first_submit_ >= 0 && last_done_ >= 0) ? (last_done_ - first_submit_) * 1e-3 : 0.0;
+        st->contributions = contributions_;
+    }
+
+  private:
+    int64_t committed_locked() const
+    {
+        int64_t c = 0;
+        for (auto &w : ws_) c += w->busy ? std::max(w->reserved, w->resident) : w->resident;
+        return c;
+    }
+
+    // bytes this worker would hold for a job of footprint fp
+    int64_t need_for(const WorkerState &w, int64_t fp) const { return std::max(w.resident, fp); }
+
+    void release_locked(WorkerState &w)
+    {
+        if (!fake_ && w.ctx) {
+            (void)hipSetDevice(device_);
+            w.ctx->setup.release();
+            w.ctx->main.release();
+        }
+        w.resident = 0;
+    }
+
+    bool admit_locked(int wi)
+    {
+        WorkerState &me = *ws_[(size_t)wi];
+        if (queue_.empty()) return false;
+        const int64_t fp = queue_.front().footprint;
+        auto fits = [&] { return committed_locked() - me.resident + need_for(me, fp) <= budget_; };
+        if (!fits() && me.resident > fp) release_locked(me);
+        if (!fits()) {
+            for (auto &w : ws_)
+                if (!w->busy && w.get() != &me && w->resident > 0) release_locked(*w);
+        }
+        return fits();
+    }
+
+    void loop(int wi)
+    {
+        WorkerState &me = *ws_[(size_t)wi];
+        if (!fake_) (void)hipSetDevice(device_);
+        for (;;) {
+            Job j;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_work_.wait(lk, [&] { return stop_ || admit_locked(wi); });
+                if (stop_ && queue_.empty()) return;
+                if (stop_ && !admit_locked(wi)) return;
+                j = queue_.front();
+                queue_.pop_front();
+                me.busy = true;
+                me.reserved = need_for(me, j.footprint);
+                ++running_;
+                max_running_ = std::max<int64_t>(max_running_, running_);
+                peak_bytes_ = std::max(peak_bytes_, committed_locked());
+            }
+            const double t_run = now_ms();
+            asci_result res{};
+            res.status = ASCI_OK;
+            if (fake_) {
+                std::this_thread::sleep_for(std::chrono::nanoseconds((int64_t)(j.footprint * ns_per_byte_)));
+                res.count = j.req.k;
+            } else {
+                try {
+                    const asci_request &r = j.req;
+                    require(r.norb >= 1 && r.norb <= 64 && r.k >= 1 && r.ndets >= 1, ASCI_EINVAL, "bad request");
+                    asci_options o;
+                    asci_options_default(&o);
+                    o = r.opt;
+                    SearchArgs in{r.h, r.eri, r.norb, r.nalpha, r.nbeta, r.dets, r.coeffs, r.ndets, r.E0, o};
+                    SearchOut out;
+                    out.k = r.k;
+                    out.out_dets = r.out_dets;
+                    out.out_scores = r.out_scores;
+                    search_device(me.ctx.get(), in, out, me.stream);
+                    res.count = out.count;
+                } catch (const Error &e) {
+                    res.status = e.code;
+                }
+            }
+            const double t_end = now_ms();
+            res.latency_ms = t_end - j.t_submit;
+            res.run_ms = t_end - t_run;
+            res.contributions = j.pairs;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                me.busy = false;
+                me.reserved = 0;
+                me.resident = fake_ ? std::max(me.resident, j.footprint)
+                                    : (int64_t)(me.ctx->setup.capacity() + me.ctx->main.capacity());
+                --running_;
+                done_[j.ticket] = res;
+                if (res.status == ASCI_OK) {
+                    ++completed_;
+                    contributions_ += j.pairs;
+                    lat_.push_back(res.latency_ms);
+                } else {
+                    ++failed_;
+                }
+                last_done_ = t_end;
+            }
+            cv_done_.notify_all();
+            cv_work_.notify_all();
+        }
+    }
+
+    int device_;
+    int64_t budget_;
+    bool fake_;
+    double ns_per_byte_;
+    uint64_t cap_records_ = 1 << 26;
+    std::vector<std::unique_ptr<WorkerState>> ws_;
+    std::mutex mu_;
+    std::condition_variable cv_work_, cv_done_;
+    std::deque<Job> queue_;
+    std::unordered_map<uint64_t, asci_result> done_;
+    uint64_t next_ticket_ = 1;
+    bool stop_ = false;
+    int64_t running_ = 0, max_running_ = 0, peak_bytes_ = 0;
+    int64_t submitted_ = 0, completed_ = 0, failed_ = 0, rejected_ = 0, contributions_ = 0;
+    double first_submit_ = -1, last_done_ = -1;
+    std::vector<double> lat_;
+};
+
+}  // namespace asci
+
+struct asci_server {
+    std::unique_ptr<asci::Pool> pool;
+};
+
+using namespace asci;
+
+namespace {
+
+thread_local std::string g_srv_error;
+
+int srv_fail(const Error &e) { return e.code; }
+
+int64_t device_budget(int device)
+{
+    size_t fr = 0, tt = 0;
+    ASCI_HIP(hipSetDevice(device));
+    ASCI_HIP(hipMemGetInfo(&fr, &tt));
+    return (int64_t)((double)fr * 0.8);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t asci_request_footprint(const asci_request *req)
+{
+    if (!req) return -1;
+    return request_footprint(*req, (uint64_t)1 << 30);
+}
+
+int asci_server_create(int device, int64_t hbm_budget, int slots, asci_server **out)
+{
+    try {
+        require(out != nullptr && hbm_budget > 0 && slots >= 1, ASCI_EINVAL, "bad server arguments");
+        int ndev = 0;
+        ASCI_HIP(hipGetDeviceCount(&ndev));
+        require(device >= 0 && device < ndev, ASCI_EINVAL, "no such device");
+        auto *s = new asci_server();
+        s->pool = std::make_unique<Pool>(device, hbm_budget, slots, false, 0.0, 4096);
+        *out = s;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return srv_fail(e);
+    }
+}
+
+int asci_server_create_fake(int64_t hbm_budget, int slots, double ns_per_byte, asci_server **out)
+{
+    try {
+        require(out != nullptr && hbm_budget > 0 && slots >= 1 && ns_per_byte >= 0, ASCI_EINVAL,
+                "bad server arguments");
+        auto *s = new asci_server();
+        s->pool = std::make_unique<Pool>(0, hbm_budget, slots, true, ns_per_byte, 4096);
+        *out = s;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return srv_fail(e);
+    }
+}
+
+int asci_server_submit(asci_server *srv, const asci_request *req, uint64_t *ticket)
+{
+    if (!srv || !req || !ticket) return ASCI_EINVAL;
+    if (req->k < 1 || req->ndets < 1 || req->norb < 1 || req->norb > 64) return ASCI_EINVAL;
+    return srv->pool->submit(*req, ticket);
+}
+
+int64_t asci_server_footprint(asci_server *srv, const asci_request *req)
+{
+    if (!srv || !req) return -1;
+    return srv->pool->footprint(*req);
+}
+
+int asci_server_poll(asci_server *srv, uint64_t ticket, asci_result *res)
+{
+    if (!srv) return ASCI_EINVAL;
+    return srv->pool->poll(ticket, res, false);
+}
+
+int asci_server_wait(asci_server *srv, uint64_t ticket, asci_result *res)
+{
+    if (!srv) return ASCI_EINVAL;
+    return srv->pool->poll(ticket, res, true);
+}
+
+int asci_server_get_stats(asci_server *srv, asci_server_stats *st)
+{
+    if (!srv || !st) return ASCI_EINVAL;
+    srv->pool->stats(st);
+    return ASCI_OK;
+}
+
+int asci_server_destroy(asci_server *srv)
+{
+    if (!srv) return ASCI_OK;
+    srv->pool->drain();
+    delete srv;
+    return ASCI_OK;
+}
+
+int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_result *res, void *stream)
+{
+    try {
+        require(ctx != nullptr && (nreq == 0 || (reqs && res)), ASCI_EINVAL, "null argument");
+        require(nreq >= 0, ASCI_EINVAL, "nreq must be >= 0");
+        if (nreq == 0) return ASCI_OK;
+        const int64_t budget = device_budget(ctx->device);
+        std::vector<int> order((size_t)nreq);
+        for (int i = 0; i < nreq; ++i) order[(size_t)i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return request_pairs(reqs[a]) > request_pairs(reqs[b]); });
+        std::vector<uint64_t> tickets((size_t)nreq, 0);
+        int rc = ASCI_OK;
+        {
+            Pool pool(ctx->device, budget, ctx->batch_slots, false, 0.0, ctx->finish_cap, (hipStream_t)stream);
+            for (int i : order) {
+                const int r = pool.submit(reqs[i], &tickets[(size_t)i]);
+                if (r != ASCI_OK && rc == ASCI_OK) rc = r;
+            }
+            for (int i = 0; i < nreq; ++i) {
+                pool.poll(tickets[(size_t)i], &res[i], true);
+                if (res[i].status != ASCI_OK && rc == ASCI_OK) rc = res[i].status;
+            }
+        }
+        return rc;
+    } catch (const Error &e) {
+        return srv_fail(e);
+    }
+}
+
+int asci_autotune(asci_ctx *ctx, const asci_request *sample, int nsample, int64_t *best_slots,
+                  int64_t *best_finish_cap)
+{
+    try {
+        require(ctx != nullptr && sample != nullptr && nsample >= 1, ASCI_EINVAL, "bad arguments");
+        std::vector<asci_result> res((size_t)nsample);
+        double best = 1e300;
+        int bs = ctx->batch_slots, bc = ctx->finish_cap;
+        const int caps[2] = {4096, 2048};
+        for (int cap : caps) {
+            for (int slots = 1; slots <= 4; ++slots) {
+                ctx->finish_cap = cap;
+                ctx->batch_slots = slots;
+                // one untimed pass warms the workspaces of this configuration
+                int rc = asci_search_batch(ctx, sample, nsample, res.data(), nullptr);
+                if (rc != ASCI_OK) continue;
+                const double t0 = now_ms();
+                rc = asci_search_batch(ctx, sample, nsample, res.data(), nullptr);
+                const double dt = now_ms() - t0;
+                if (rc == ASCI_OK && dt < best) {
+                    best = dt;
+                    bs = slots;
+                    bc = cap;
+                }
+            }
+        }
+        ctx->batch_slots = bs;
+        ctx->finish_cap = bc;
+        if (best_slots) *best_slots = bs;
+        if (best_finish_cap) *best_finish_cap = bc;
+        return best < 1e300 ? ASCI_OK : ASCI_EDEVICE;
+    } catch (const Error &e) {
+        return srv_fail(e);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+"""Batched and served searches on the GPU: every result equals the same
+search run alone (bit for bit), and agrees with the oracle."""
+import numpy as np
+import pytest
+
+import asci_synth as syn
+from gpu_util import assert_topk_parity, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [(12, 4, 4, 150, 1), (14, 5, 4, 300, 2), (16, 6, 6, 500, 3), (10, 3, 3, 80, 4), (18, 5, 5, 400, 5),
+         (13, 6, 5, 250, 6), (16, 4, 4, 600, 7), (11, 2, 3, 60, 8), (20, 6, 6, 300, 9), (15, 7, 7, 200, 10)]
+
+
+@pytest.fixture(scope="module")
+def setup(oracle_lib):
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_05688_amd as asci
+
+    cases = []
+    for n, na, nb, nd, seed in SPECS:
+        c = syn.make_case(n, na, nb, nd, seed=500 + seed, sampler="level", tau=nd / 10.0)
+        c["E0"] = oracle_lib.energy(c["h"], c["eri"], c["dets"][:200], c["coeffs"][:200])
+        c["kk"] = 5 * nd
+        c["dev"] = to_dev(c)
+        cases.append(c)
+    alone = []
+    for c in cases:
+        d = c["dev"]
+        k, s = asci.search(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], c["E0"],
+                           c["kk"])
+        alone.append((host(k), host(s)))
+    return asci, cases, alone
+
+
+def _requests(asci, cases):
+    reqs = []
+    for c in cases:
+        d = c["dev"]
+        reqs.append(asci.SearchRequest(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"],
+                                       c["E0"], c["kk"]))
+    return reqs
+
+
+def _same(req, res, want):
+    k, s = req.result(res.count)
+    return (host(k) == want[0]).all() and (host(s) == want[1]).all() and len(want[0]) == res.count
+
+
+def test_batch_equals_single(setup, oracle_lib):
+    asci, cases, alone = setup
+    reqs = _requests(asci, cases)
+    res = asci.search_batch(reqs)
+    for r, q, want in zip(res, reqs, alone):
+        assert r.status == 0
+        assert _same(q, r, want)
+    c = cases[2]
+    wk, ws = oracle_lib.search(c["h"], c["eri"], c["norb"], c["nalpha"], c["nbeta"], c["dets"], c["coeffs"],
+                               c["E0"], c["kk"])
+    assert_topk_parity(alone[2][0], alone[2][1], wk, ws, 1e-12)
+
+
+@pytest.mark.parametrize("slots", [1, 3])
+def test_batch_slots_do_not_change_results(setup, slots):
+    asci, cases, alone = setup
+    ctx = asci.Context.get(0)
+    old = ctx.get_param("batch_slots")
+    ctx.set_param("batch_slots", slots)
+    try:
+        reqs = _requests(asci, cases)
+        res = asci.search_batch(reqs, ctx=ctx)
+        assert all(_same(q, r, w) for r, q, w in zip(res, reqs, alone))
+    finally:
+        ctx.set_param("batch_slots", old)
+
+
+def test_server_results_same_alone_and_in_the_mix(setup):
+    asci, cases, alone = setup
+    srv = asci.Server(device=0, slots=3)
+    reqs = _requests(asci, cases) + _requests(asci, cases)
+    tickets = [srv.submit(r) for r in reqs]
+    results = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    for q, r, w in zip(reqs, results, alone + alone):
+        assert r.status == 0
+        assert _same(q, r, w)
+    assert st["completed"] == len(reqs)
+    assert st["max_running"] >= 2
+    assert st["peak_bytes"] > 0
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+
+
+def test_autotune_keeps_results(setup):
+    asci, cases, alone = setup
+    ctx = asci.Context.get(0)
+    old = (ctx.get_param("batch_slots"), ctx.get_param("finish_cap"))
+    try:
+        best = asci.autotune(_requests(asci, cases[:4]), ctx=ctx)
+        assert 1 <= best["batch_slots"] <= 4 and best["finish_cap"] in (2048, 4096)
+        reqs = _requests(asci, cases)
+        res = asci.search_batch(reqs, ctx=ctx)
+        assert all(_same(q, r, w) for r, q, w in zip(res, reqs, alone))
+    finally:
+        ctx.set_param("batch_slots", old[0])
+        ctx.set_param("finish_cap", old[1])

@@ -43,14 +43,14 @@ def _sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def _all_parity(asci, oracle_lib, c, E0, ncore=0, pair_buffer_bytes=0):
+def _all_parity(asci, oracle_lib, c, E0, ncore=0, pair_buffer_bytes=0, eps=0.0):
     d = to_dev(c)
     n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
-    print("case n=%d na=%d nb=%d ndets=%d seed=%s ncore=%d buf=%d" % (n, na, nb, len(c["coeffs"]), c["seed"],
-                                                                     ncore, pair_buffer_bytes), flush=True)
+    print("case n=%d na=%d nb=%d ndets=%d seed=%s ncore=%d buf=%d eps=%g" % (
+        n, na, nb, len(c["coeffs"]), c["seed"], ncore, pair_buffer_bytes, eps), flush=True)
     keys, num, score = asci.candidates(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, ncore=ncore,
-                                       pair_buffer_bytes=pair_buffer_bytes)
-    want = oracle_lib.search_all(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, ncore=ncore)
+                                       pair_buffer_bytes=pair_buffer_bytes, eps=eps)
+    want = oracle_lib.search_all(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, ncore=ncore, eps=eps)
     gk = host(keys)
     assert gk.shape == want["keys"].shape
     assert (gk == want["keys"]).all()
@@ -73,7 +73,7 @@ def test_candidates_tiny(asci, oracle_lib, n, na, nb, ndets, ncore):
     _all_parity(asci, oracle_lib, c, E0, ncore=ncore)
 
 
-@pytest.mark.parametrize("n,na,nb,ndets", [(33, 3, 2, 12), (40, 4, 4, 8), (36, 2, 3, 20)])
+@pytest.mark.parametrize("n,na,nb,ndets", [(33, 3, 2, 12), (40, 4, 4, 8), (36, 2, 3, 20), (50, 2, 2, 6)])
 def test_candidates_two_word_keys(asci, oracle_lib, n, na, nb, ndets):
     c = _case(n, na, nb, ndets, seed=77 + n)
     E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
@@ -86,6 +86,28 @@ def test_candidates_8e12o(asci, oracle_lib):
     E0 = float.fromhex(g["E0"])
     want = _all_parity(asci, oracle_lib, c, E0)
     assert len(want["keys"]) == g["ncandidates"]
+
+
+@pytest.mark.parametrize("eps", [1e-10, 1e-4, 3e-3])
+def test_pair_threshold_eps(asci, oracle_lib, eps):
+    """Alg. 2's threshold: a pair joins the sum only if its partial score
+    exceeds eps in magnitude (1e-10 is the value the paper's runs used)."""
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    want = _all_parity(asci, oracle_lib, c, E0, eps=eps)
+    if eps >= 1e-4:
+        assert len(want["keys"]) < _golden("8e12o")["ncandidates"]
+    d = to_dev(c)
+    gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 700, eps=eps)
+    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 700, eps=eps)
+    assert_topk_parity(host(gk), host(gs), wk, ws, TOL)
+
+
+def test_pair_threshold_eps_tiny(asci, oracle_lib):
+    for (n, na, nb, nd) in [(6, 3, 3, 12), (8, 4, 2, 30)]:
+        c = _case(n, na, nb, nd, seed=300 + n)
+        E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+        _all_parity(asci, oracle_lib, c, E0, eps=1e-3)
 
 
 @pytest.mark.parametrize("buf", [1 << 16, 3 << 18, 1 << 21])
@@ -250,6 +272,18 @@ def test_full_size_16e20o(asci, oracle_lib):
     assert (order == np.arange(len(gk))).all()
 
 
+def test_full_size_16e20o_multi_batch(asci, oracle_lib):
+    """The bench workload split into about five class batches (a forced pair
+    buffer of 1 GiB): the top-k must not change."""
+    c = syn.workload("16e20o")
+    g = _golden("16e20o")
+    d = to_dev(c)
+    gk, gs = asci.search(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], float.fromhex(g["E0"]), c["k"],
+                         pair_buffer_bytes=1 << 30)
+    assert _sha(host(gk)) == g["topk_keys_sha256"]
+    assert _sha(host(gs)) == g["topk_scores_sha256"]
+
+
 def test_full_size_24e30o_sampled(asci, oracle_lib):
     """The Cr2-shaped (24e,30o) workload: 6.7e9 pairs in class batches; checked
     per candidate against the oracle, plus ordering and count invariants."""
@@ -264,3 +298,38 @@ def test_full_size_24e30o_sampled(asci, oracle_lib):
     order = np.lexsort((gk[:, 1], gk[:, 0], -np.abs(gs)))
     assert (order == np.arange(len(gk))).all()
     _sampled_checks(oracle_lib, c, E0, gk, gs, ncheck=600, seed=3)
+
+
+def test_one_target_from_more_cores_than_fit_in_lds(asci, oracle_lib):
+    """psi = every single and double of one determinant t (7875 of them at
+    (10e,20o)): t collects 7875 contributions, more than one LDS bucket holds,
+    and psi is dense in the key ranges around t."""
+    n, na, nb = 20, 5, 5
+    rng = np.random.default_rng(8)
+    h, eri = syn.integrals(n, rng)
+    t = (0b1011000100001 << 2, 0b110000011001)
+    t = (int(t[0]) & ((1 << n) - 1), int(t[1]))
+    assert bin(t[0]).count("1") == na and bin(t[1]).count("1") == nb
+    dets = oracle_lib.sd_targets(n, t[0], t[1])
+    assert len(dets) == 7875
+    C = syn.coefficients(len(dets), 2000.0, rng)
+    c = {"norb": n, "nalpha": na, "nbeta": nb, "h": h, "eri": eri, "dets": dets, "coeffs": C, "seed": 8}
+    E0 = oracle_lib.energy(h, eri, dets[:500], C[:500])
+    d = to_dev(c)
+    keys, num, score = asci.candidates(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0)
+    hk, hn, hs = host(keys), host(num), host(score)
+    at = np.nonzero((hk[:, 0] == t[0]) & (hk[:, 1] == t[1]))[0]
+    assert len(at) == 1
+    wn, wh, inp, nconn = oracle_lib.target_numerators(h, eri, n, na, nb, dets, C, np.array([t], dtype=np.uint64))
+    assert nconn[0] == 7875 and not inp[0]
+    assert rel_err(hn[at], wn)[0] <= TOL
+    assert rel_err(hs[at], wn / (E0 - wh))[0] <= TOL
+    # sampled candidates, and no input determinant among them
+    rng2 = np.random.default_rng(1)
+    idx = rng2.integers(0, len(hk), 400)
+    wn2, wh2, inp2, nconn2 = oracle_lib.target_numerators(h, eri, n, na, nb, dets, C, hk[idx])
+    assert not inp2.any() and (nconn2 >= 1).all()
+    assert rel_err(hn[idx], wn2).max() <= TOL
+    gk, gs = asci.search(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, 1000)
+    order = np.lexsort((host(gk)[:, 1], host(gk)[:, 0], -np.abs(host(gs))))
+    assert (order == np.arange(len(order))).all()

@@ -1,0 +1,80 @@
+"""The request scheduler on the host, with the fake executor (no GPU): a
+request "runs" for footprint x ns_per_byte and keeps its footprint resident."""
+import pytest
+
+import paper_2303_05688_amd as asci
+
+
+def _reqs(specs):
+    return [asci.fake_request(*s) for s in specs]
+
+
+MIX = [(20, 8, 8, 1000, 10_000)] * 14 + [(26, 10, 10, 10_000, 100_000)] * 5 + [(30, 12, 12, 100_000, 1_000_000)]
+
+
+def test_footprint_grows_with_the_request():
+    a, b, c = _reqs([(20, 8, 8, 1000, 10_000), (26, 10, 10, 10_000, 100_000), (30, 12, 12, 100_000, 1_000_000)])
+    fa, fb, fc = asci.footprint(a), asci.footprint(b), asci.footprint(c)
+    assert 0 < fa < fb < fc
+
+
+def test_admission_never_exceeds_the_budget_and_overlaps():
+    reqs = _reqs(MIX)
+    budget = int(8e9)
+    srv = asci.Server(hbm_budget=budget, slots=4, fake_ns_per_byte=1e-2)
+    assert max(srv.footprint(r) for r in reqs) <= budget
+    tickets = [srv.submit(r) for r in reqs]
+    results = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert all(r.status == 0 for r in results)
+    assert st["completed"] == len(reqs) and st["rejected"] == 0
+    assert st["peak_bytes"] <= budget
+    assert st["max_running"] > 1
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+
+
+def test_budget_for_one_request_serialises():
+    reqs = _reqs([(30, 12, 12, 100_000, 1_000_000)] * 4)
+    budget = int(2.5e9)
+    srv = asci.Server(hbm_budget=budget, slots=4, fake_ns_per_byte=5e-3)
+    fp = srv.footprint(reqs[0])
+    assert fp <= budget < 2 * fp
+    for t in [srv.submit(r) for r in reqs]:
+        assert srv.wait(t).status == 0
+    st = srv.stats()
+    srv.close()
+    assert st["max_running"] == 1
+    assert st["peak_bytes"] <= budget
+
+
+def test_oversized_request_is_rejected_not_queued():
+    big, small = _reqs([(30, 12, 12, 100_000, 1_000_000), (20, 8, 8, 1000, 10_000)])
+    srv = asci.Server(hbm_budget=int(5e8), slots=2, fake_ns_per_byte=1e-3)
+    assert srv.footprint(big) > 5e8 >= srv.footprint(small)
+    tb, ts = srv.submit(big), srv.submit(small)
+    assert srv.wait(tb).status == asci.ASCI_ENOMEM
+    assert srv.wait(ts).status == 0
+    st = srv.stats()
+    srv.close()
+    assert st["rejected"] == 1 and st["completed"] == 1
+
+
+def test_poll_reports_pending_then_done():
+    r = _reqs([(26, 10, 10, 10_000, 100_000)])[0]
+    srv = asci.Server(hbm_budget=asci.footprint(r) * 2, slots=1, fake_ns_per_byte=3e-2)
+    t = srv.submit(r)
+    assert srv.poll(t) is None  # still running (about 50 ms)
+    assert srv.wait(t).status == 0
+    assert srv.poll(t) is not None
+    srv.close()
+
+
+def test_fifo_admission_order():
+    reqs = _reqs([(20, 8, 8, 1000, 10_000)] * 6)
+    srv = asci.Server(hbm_budget=asci.footprint(reqs[0]) * 10, slots=1, fake_ns_per_byte=1e-3)
+    ts = [srv.submit(r) for r in reqs]
+    res = [srv.wait(t) for t in ts]
+    srv.close()
+    lat = [r.latency_ms for r in res]
+    assert lat == sorted(lat)
