@@ -54,11 +54,19 @@ typedef struct asci_options {
                                   largest |C| (ties: lower index); 0 = all inputs    */
     double eps;                /* pair threshold eps_search (Alg. 2): keep a pair
                                   only if |H_ai C_i / (E0 - H_aa)| > eps; 0 = exact  */
-    int32_t constraint_level;  /* constraint classes by the top-L occupied alpha
-                                  orbitals (Sec. II.B); only 3 (triplets) for now   */
+    int32_t constraint_level;  /* L in [1, 6]: constraint classes by the top-L
+                                  occupied alpha orbitals (Sec. II.B; 3 = triplets) */
     double ecore;              /* constant added to every H_aa (E0 must include it) */
     int64_t pair_buffer_bytes; /* cap on the pair buffer of one class batch;
                                   0 = automatic                                    */
+    int64_t split_pairs;       /* 0: every class at level L.  > 0: classes start at
+                                  level min(L, 3) and a class with more pairs than
+                                  this is split into the classes of the next level,
+                                  up to L (Sec. II.B: only heavy classes are split).
+                                  Either way a class larger than the pair buffer is
+                                  split further, up to level 6.  The classes only
+                                  partition the work: results do not depend on
+                                  L or split_pairs.                                 */
 } asci_options;
 
 typedef struct asci_ctx asci_ctx;
@@ -73,7 +81,7 @@ const char *asci_strerror(int code);
 const char *asci_last_error(void);
 
 /* Fill *opt with the defaults (ncore 0, eps 0, constraint_level 3, ecore 0,
- * pair_buffer_bytes 0). */
+ * pair_buffer_bytes 0, split_pairs 0). */
 void asci_options_default(asci_options *opt);
 
 /* Create a context bound to HIP device `device`; it owns a workspace that grows
@@ -153,19 +161,48 @@ int asci_candidates_device(asci_ctx *ctx, const double *d_h, const double *d_eri
                            void *stream);
 
 /*
- * Pair counts per triplet constraint class (Sec. II.B; the work estimate of
- * the load-balancing algorithm, Alg. 3): a target belongs to the class named
- * by the mask of the three highest occupied orbitals of its alpha string (all
- * of them when nalpha < 3).  For the core set chosen by opt->ncore, returns
- * the non-empty classes in ascending mask order: h_masks[j], h_counts[j]
- * (host arrays of length capacity).  *out_nclasses receives the number of
- * non-empty classes; beyond capacity the call returns ASCI_ENOMEM.
- * d_dets, d_coeffs: device.
+ * Second-order (Epstein-Nesbet) energy of the candidates, on the search's own
+ * pipeline (Sec. II.A: the PT2 correction is closely related to the scores of
+ * Eq. (1); ASCI's final step in Alg. 1):
+ *     E_PT2 = sum over candidates a of N_a^2 / (E0 - H_aa) = sum_a N_a * A_a,
+ * with N_a, A_a, the core set and eps exactly as in asci_search.  Summation:
+ * per bucket of candidates in key order, then a fixed-order tree, so the
+ * result is reproducible run to run.  *out_count receives the number of
+ * candidates.  d_*: device.
+ */
+int asci_pt2_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha,
+                    int nbeta, const uint64_t *d_dets, const double *d_coeffs, int64_t ndets,
+                    double E0, const asci_options *opt, double *out_energy, int64_t *out_count,
+                    void *stream);
+
+/*
+ * Pair counts per constraint class (Sec. II.B; the work estimate of the
+ * load-balancing algorithm, Alg. 3): a target belongs to the class named by the
+ * mask of the L = opt->constraint_level highest occupied orbitals of its alpha
+ * string (all of them when nalpha < L); with opt->split_pairs > 0 the classes
+ * start at level min(L, 3) and only those with more pairs are split, level by
+ * level, up to L.  For the core set chosen by opt->ncore, returns the non-empty
+ * classes in ascending mask order: h_masks[j], h_counts[j] (host arrays of
+ * length capacity; the level of a class is the popcount of its mask).
+ * *out_nclasses receives the number of non-empty classes; beyond capacity the
+ * call returns ASCI_ENOMEM.  d_dets, d_coeffs: device.
  */
 int asci_class_counts_device(asci_ctx *ctx, int norb, int nalpha, int nbeta,
                              const uint64_t *d_dets, const double *d_coeffs, int64_t ndets,
                              const asci_options *opt, int64_t capacity, uint64_t *h_masks,
                              int64_t *h_counts, int64_t *out_nclasses, void *stream);
+
+/*
+ * Static load balance of Alg. 3 (host only, no device work): the classes are
+ * taken in the given order, and a class with h = counts[c] > 0 pairs goes to
+ * the processing element with the smallest load so far (lowest index on ties),
+ * whose load then grows by h (the load array is updated after every
+ * assignment).  owner[c] receives the element of class c (-1 when h == 0),
+ * load[p] the pairs of element p.  counts, owner (nclasses) and load (npe) are
+ * caller-owned host arrays.  Errors: ASCI_EINVAL for null pointers,
+ * nclasses < 0, npe < 1 or a negative count.
+ */
+int asci_balance_classes(const int64_t *counts, int64_t nclasses, int32_t npe, int32_t *owner, int64_t *load);
 
 /*
  * Variational energy E = <C|H|C> = sum_ij C_i H_ij C_j over the given

@@ -70,11 +70,16 @@ def lib():
         L.oracle_energy.argtypes = [dp, dp, C.c_int, C.c_double, up, dp, C.c_int64]
         L.oracle_class_counts.restype = C.c_int64
         L.oracle_class_counts.argtypes = [C.c_int, C.c_int, C.c_int, up, dp, C.c_int64,
-                                          C.c_int64, up, ip, C.c_int64]
+                                          C.c_int64, C.c_int, up, ip, C.c_int64]
+        L.oracle_pt2.restype = C.c_int
+        L.oracle_pt2.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_double, up, dp, C.c_int64, C.c_double,
+                                 C.c_int64, C.c_double, dp, dp, ip]
         L.oracle_target_numerators.restype = C.c_int
         L.oracle_target_numerators.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_double, up, dp,
                                                C.c_int64, C.c_int64, up, C.c_int64, dp, dp,
                                                C.POINTER(C.c_int), ip]
+        L.oracle_balance.restype = C.c_int
+        L.oracle_balance.argtypes = [ip, C.c_int64, C.c_int, C.POINTER(C.c_int), ip]
         _lib = L
     return _lib
 
@@ -182,15 +187,16 @@ def search(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, e
     return allc["keys"][idx], allc["score"][idx]
 
 
-def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0):
-    """Non-empty triplet classes: (masks ascending, pair counts)."""
+def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0, level=3):
+    """Non-empty constraint classes of the given level (3 = triplets):
+    (masks ascending, pair counts)."""
     d, dp = _u(dets)
     c, cp = _d(coeffs)
     cap = 1
     for _ in range(2):
         masks = np.zeros(cap, dtype=np.uint64)
         counts = np.zeros(cap, dtype=np.int64)
-        m = lib().oracle_class_counts(norb, nalpha, nbeta, dp, cp, len(c), int(ncore),
+        m = lib().oracle_class_counts(norb, nalpha, nbeta, dp, cp, len(c), int(ncore), int(level),
                                       masks.ctypes.data_as(C.POINTER(C.c_uint64)),
                                       counts.ctypes.data_as(C.POINTER(C.c_int64)), cap)
         if m < 0:
@@ -221,3 +227,34 @@ def target_numerators(h, eri, norb, nalpha, nbeta, dets, coeffs, targets, ncore=
     if rc != 0:
         raise ValueError("invalid determinants")
     return num, hd, inp.astype(bool), nconn
+
+
+def pt2(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, ecore=0.0, with_abs=False):
+    """E_PT2 = sum over candidates of N_a^2 / (E0 - H_aa), summed with
+    compensation; returns (energy, candidates), or (energy, candidates, S)
+    with S = sum of |terms| when with_abs is set."""
+    keep, hp, ep, n = _ham(h, eri)
+    d, dp = _u(dets)
+    c, cp = _d(coeffs)
+    e = C.c_double()
+    sabs = C.c_double()
+    cnt = C.c_int64()
+    rc = lib().oracle_pt2(hp, ep, n, nalpha, nbeta, ecore, dp, cp, len(c), float(E0), int(ncore), float(eps),
+                          C.byref(e), C.byref(sabs), C.byref(cnt))
+    if rc != 0:
+        raise ValueError("oracle_pt2 failed with code %d" % rc)
+    if with_abs:
+        return e.value, cnt.value, sabs.value
+    return e.value, cnt.value
+
+
+def balance(counts, npe):
+    """Alg. 3: (owner[m] (-1 for empty classes), work[npe])."""
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    owner = np.zeros(len(c), dtype=np.int32)
+    work = np.zeros(int(npe), dtype=np.int64)
+    rc = lib().oracle_balance(c.ctypes.data_as(C.POINTER(C.c_int64)), len(c), int(npe),
+                              owner.ctypes.data_as(C.POINTER(C.c_int)), work.ctypes.data_as(C.POINTER(C.c_int64)))
+    if rc != 0:
+        raise ValueError("oracle_balance failed with code %d" % rc)
+    return owner, work

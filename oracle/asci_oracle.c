@@ -491,12 +491,14 @@ double oracle_energy(const double *h, const double *eri, int n, double ecore,
     return e;
 }
 
-/* ---- pair counts per triplet constraint class (Sec. II.B) ----
- * A target's class is the set of the three highest occupied orbitals of its alpha
- * string (all of them when it has fewer than three).  For each core (in the core
- * set) every single and double is generated and counted against its class.
- * Classes are reported by their mask; out_masks/out_counts receive the non-empty
- * classes in ascending mask order.  Returns the number of non-empty classes. */
+/* ---- pair counts per constraint class (Sec. II.B: triplets and the
+ * higher-order constraints that split heavy classes) ----
+ * A target's class at level L is the set of the L highest occupied orbitals of
+ * its alpha string (all of them when it has fewer than L).  For each core (in
+ * the core set) every single and double is generated and counted against its
+ * class: brute force, nothing is counted in closed form.  Classes are reported
+ * by their mask; out_masks/out_counts receive the first `cap` non-empty classes
+ * in ascending mask order.  Returns the number of non-empty classes. */
 
 typedef struct { uint64_t mask; int64_t count; } cls_rec;
 
@@ -506,19 +508,21 @@ static int cmp_cls(const void *x, const void *y)
     return p->mask < q->mask ? -1 : (p->mask > q->mask);
 }
 
-static uint64_t top3(uint64_t a)
+/* the constraint of an alpha string: its `level` highest occupied orbitals
+ * (all of them when it has fewer) */
+static uint64_t top_bits(uint64_t a, int level)
 {
     uint64_t m = 0;
-    for (int t = 63, got = 0; t >= 0 && got < 3; --t)
+    for (int t = 63, got = 0; t >= 0 && got < level; --t)
         if ((a >> t) & 1ull) { m |= 1ull << t; ++got; }
     return m;
 }
 
 int64_t oracle_class_counts(int n, int na, int nb, const uint64_t *dets, const double *coeffs,
-                            int64_t ndets, int64_t ncore, uint64_t *out_masks,
+                            int64_t ndets, int64_t ncore, int level, uint64_t *out_masks,
                             int64_t *out_counts, int64_t cap)
 {
-    if (validate(n, na, nb, dets, ndets) != ORACLE_OK)
+    if (validate(n, na, nb, dets, ndets) != ORACLE_OK || level < 1)
         return ORACLE_EINVAL;
     int64_t *core = malloc(sizeof(int64_t) * (size_t)(ndets + 1));
     int64_t nq = oracle_core_set(coeffs, ndets, ncore, core);
@@ -529,7 +533,7 @@ int64_t oracle_class_counts(int n, int na, int nb, const uint64_t *dets, const d
     for (int64_t c = 0; c < nq; ++c) {
         int64_t i = core[c];
         int64_t nt = oracle_sd_targets(n, dets[2 * i], dets[2 * i + 1], tg);
-        for (int64_t t = 0; t < nt; ++t) { all[m].mask = top3(tg[2 * t]); all[m].count = 1; ++m; }
+        for (int64_t t = 0; t < nt; ++t) { all[m].mask = top_bits(tg[2 * t], level); all[m].count = 1; ++m; }
     }
     qsort(all, (size_t)m, sizeof(cls_rec), cmp_cls);
     int64_t nc = 0;
@@ -580,5 +584,70 @@ int oracle_target_numerators(const double *h, const double *eri, int n, int na, 
         out_nconn[t] = nc;
     }
     free(core);
+    return ORACLE_OK;
+}
+
+/* ---- second-order (Epstein-Nesbet) energy of the candidates (Sec. II.A:
+ * the PT2 correction is closely related to the scores of Eq. (1)) ----
+ * E_PT2 = sum over candidates a (ascending key) of N_a^2 / (E0 - H_aa)
+ *       = sum_a N_a * A_a, with N_a and A_a exactly as in oracle_search.
+ * The terms are added with Neumaier's compensated summation, so the result
+ * is the exact sum of the terms to within about 2u|E_PT2| (plus m u^2 S);
+ * out_abs = S = sum_a |N_a * A_a| sizes the error of any other summation
+ * order (Higham, Accuracy and Stability of Numerical Algorithms, ch. 4). */
+int oracle_pt2(const double *h, const double *eri, int n, int na, int nb, double ecore,
+               const uint64_t *dets, const double *coeffs, int64_t ndets, double E0, int64_t ncore,
+               double eps, double *out_e, double *out_abs, int64_t *out_count)
+{
+    oracle_result r;
+    int rc = oracle_search(h, eri, n, na, nb, ecore, dets, coeffs, ndets, E0, ncore, eps, 0, &r);
+    if (rc != ORACLE_OK)
+        return rc;
+    double e = 0.0, comp = 0.0, sabs = 0.0;
+    for (int64_t u = 0; u < r.count; ++u) {
+        const double t = r.num[u] * r.score[u];
+        const double y = e + t;
+        if (fabs(e) >= fabs(t))
+            comp = comp + ((e - y) + t);
+        else
+            comp = comp + ((t - y) + e);
+        e = y;
+        sabs = sabs + fabs(t);
+    }
+    *out_e = e + comp;
+    *out_abs = sabs;
+    *out_count = r.count;
+    oracle_free(&r);
+    return ORACLE_OK;
+}
+
+/* ---- static load balance over processing elements (Alg. 3) ----
+ * The classes are visited in the order given.  A class that yields pairs
+ * (h > 0) is assigned to the element with the smallest accumulated work,
+ * the first such element when several tie, and that element's work grows by h.
+ * (The printed algorithm never adds h to W; the reading taken here adds it,
+ * otherwise every class would land on element 0.)  Classes without pairs are
+ * not assigned (owner -1).  A plain linear arg-min scan over the elements. */
+int oracle_balance(const int64_t *counts, int64_t nclasses, int npe, int *owner, int64_t *work)
+{
+    if (npe < 1 || nclasses < 0)
+        return ORACLE_EINVAL;
+    for (int p = 0; p < npe; ++p)
+        work[p] = 0;
+    for (int64_t c = 0; c < nclasses; ++c) {
+        const int64_t h = counts[c];
+        if (h < 0)
+            return ORACLE_EINVAL;
+        if (h == 0) {
+            owner[c] = -1;
+            continue;
+        }
+        int q = 0;
+        for (int p = 1; p < npe; ++p)
+            if (work[p] < work[q])
+                q = p;
+        owner[c] = q;
+        work[q] += h;
+    }
     return ORACLE_OK;
 }

@@ -13,6 +13,12 @@ import os
 
 import numpy as np
 
+# One HIP runtime per process.  PyTorch-ROCm carries its own libamdhip64 with
+# the same soname as the system one; loading torch first makes libasci.so bind
+# to that copy.  Loaded the other way round, the process would hold two HIP
+# runtimes, and the second one to initialise finds no device.
+import torch  # noqa: E402,F401  (device memory and streams come from torch)
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libasci.so")
 
@@ -27,7 +33,7 @@ class AsciError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("ncore", C.c_int64), ("eps", C.c_double), ("constraint_level", C.c_int32),
-                ("ecore", C.c_double), ("pair_buffer_bytes", C.c_int64)]
+                ("ecore", C.c_double), ("pair_buffer_bytes", C.c_int64), ("split_pairs", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -50,7 +56,7 @@ class ServerStats(C.Structure):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libasci.so is not built: run `python -m paper_2303_05688_amd.build` "
+    raise ImportError("libasci.so is not built: run `python paper_2303_05688_amd/build.py` "
                       "(or __graft_entry__.build()) first")
 
 _lib = C.CDLL(LIB_PATH)
@@ -70,8 +76,11 @@ _lib.asci_candidates_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int
                                         C.c_double, C.POINTER(Options), C.c_int64, _vp, _vp, _vp, _ip, _vp]
 _lib.asci_class_counts_device.argtypes = [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64,
                                           C.POINTER(Options), C.c_int64, _up, _ip, _ip, _vp]
+_lib.asci_pt2_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
+                                 C.POINTER(Options), _dp, _ip, _vp]
 _lib.asci_energy_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
                                     _dp, _vp]
+_lib.asci_balance_classes.argtypes = [_ip, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _ip]
 
 _lib.asci_ctx_set_profiling.argtypes = [_vp, C.c_int]
 _lib.asci_ctx_set_param.argtypes = [_vp, C.c_char_p, C.c_int64]
@@ -95,7 +104,8 @@ _lib.asci_server_destroy.argtypes = [_vp]
 EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_default", "asci_ctx_create",
            "asci_ctx_destroy", "asci_ctx_set_param", "asci_ctx_get_param", "asci_ctx_set_profiling",
            "asci_ctx_profile_entry", "asci_search",
-           "asci_search_device", "asci_candidates_device", "asci_class_counts_device", "asci_energy_device",
+           "asci_search_device", "asci_candidates_device", "asci_pt2_device", "asci_class_counts_device",
+           "asci_energy_device", "asci_balance_classes",
            "asci_request_footprint", "asci_search_batch", "asci_autotune", "asci_server_create",
            "asci_server_create_fake", "asci_server_submit", "asci_server_footprint", "asci_server_poll",
            "asci_server_wait",
@@ -111,11 +121,12 @@ def _check(rc):
         raise AsciError(rc, _lib.asci_last_error().decode())
 
 
-def options(ncore=0, eps=0.0, ecore=0.0, pair_buffer_bytes=0, constraint_level=3):
+def options(ncore=0, eps=0.0, ecore=0.0, pair_buffer_bytes=0, constraint_level=3, split_pairs=0):
     o = Options()
     _lib.asci_options_default(C.byref(o))
     o.ncore, o.eps, o.ecore = int(ncore), float(eps), float(ecore)
     o.pair_buffer_bytes, o.constraint_level = int(pair_buffer_bytes), int(constraint_level)
+    o.split_pairs = int(split_pairs)
     return o
 
 
@@ -194,7 +205,7 @@ def _dets_tensor(dets):
 
 
 def search(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, ecore=0.0,
-           pair_buffer_bytes=0, ctx=None):
+           pair_buffer_bytes=0, constraint_level=3, split_pairs=0, ctx=None):
     """ASCI search on device tensors: returns (dets[m, 2] uint64, scores[m] float64)
     on the same device, ordered by |score| descending, ties by key ascending."""
     torch = _torch()
@@ -204,7 +215,7 @@ def search(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, e
     out_d = torch.empty((int(k), 2), dtype=torch.uint64, device=h.device)
     out_s = torch.empty((int(k),), dtype=torch.float64, device=h.device)
     cnt = C.c_int64(0)
-    o = options(ncore, eps, ecore, pair_buffer_bytes)
+    o = options(ncore, eps, ecore, pair_buffer_bytes, constraint_level, split_pairs)
     _check(_lib.asci_search_device(ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
                                    _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0],
                                    float(E0), int(k), C.byref(o), out_d.data_ptr(), out_s.data_ptr(),
@@ -214,13 +225,13 @@ def search(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, e
 
 
 def candidates(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, ecore=0.0,
-               pair_buffer_bytes=0, ctx=None):
+               pair_buffer_bytes=0, constraint_level=3, split_pairs=0, ctx=None):
     """Every candidate, ascending key: (dets[U, 2], N_a[U], A_a[U]) on the device."""
     torch = _torch()
     dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
     ctx = ctx or Context.get(dev)
     dets = _dets_tensor(dets)
-    o = options(ncore, eps, ecore, pair_buffer_bytes)
+    o = options(ncore, eps, ecore, pair_buffer_bytes, constraint_level, split_pairs)
     cnt = C.c_int64(0)
     args = (ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
             _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0], float(E0), C.byref(o))
@@ -236,13 +247,29 @@ def candidates(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, 
     return out_d[:U], out_n[:U], out_s[:U]
 
 
-def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0, ctx=None):
-    """Non-empty triplet classes: (masks uint64[m], counts int64[m]) as numpy arrays."""
+def pt2(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, ecore=0.0, pair_buffer_bytes=0,
+        constraint_level=3, split_pairs=0, ctx=None):
+    """Second-order energy of the candidates: (E_PT2, number of candidates)."""
+    torch = _torch()
+    dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or Context.get(dev)
+    dets = _dets_tensor(dets)
+    e, cnt = C.c_double(), C.c_int64()
+    o = options(ncore, eps, ecore, pair_buffer_bytes, constraint_level, split_pairs)
+    _check(_lib.asci_pt2_device(ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
+                                _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0], float(E0),
+                                C.byref(o), C.byref(e), C.byref(cnt), _stream(dev)))
+    return e.value, cnt.value
+
+
+def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0, constraint_level=3, split_pairs=0, ctx=None):
+    """Non-empty constraint classes (level 3 = triplets; split_pairs > 0 splits the
+    heavy ones): (masks uint64[m] ascending, pair counts int64[m]) as numpy arrays."""
     torch = _torch()
     dev = dets.device.index if dets.device.index is not None else torch.cuda.current_device()
     ctx = ctx or Context.get(dev)
     dets = _dets_tensor(dets)
-    o = options(ncore)
+    o = options(ncore, constraint_level=constraint_level, split_pairs=split_pairs)
     cnt = C.c_int64(0)
     cap = 1
     for _ in range(2):
@@ -260,6 +287,34 @@ def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0, ctx=None):
     _check(rc)
 
 
+def balance_classes(counts, npe):
+    """Alg. 3's greedy static load balance: (owner int32[m], load int64[npe])."""
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    owner = np.zeros(len(counts), dtype=np.int32)
+    load = np.zeros(int(npe), dtype=np.int64)
+    _check(_lib.asci_balance_classes(counts.ctypes.data_as(_ip), len(counts), int(npe),
+                                     owner.ctypes.data_as(C.POINTER(C.c_int32)), load.ctypes.data_as(_ip)))
+    return owner, load
+
+
+def class_skew(counts, npes=(8, 64, 256, 1024)):
+    """Skew statistics of a class partition (the single-GPU analogue of the
+    per-element pair counts by constraint level): number of non-empty classes,
+    the largest class over the mean, and for each element count P the largest
+    Alg. 3 load over the mean load (1 = perfect balance) and the share of all
+    pairs in the single largest class (indivisible work)."""
+    counts = np.asarray(counts, dtype=np.int64)
+    nz = counts[counts > 0]
+    tot = int(nz.sum())
+    out = {"classes": int(len(nz)), "pairs": tot,
+           "max_over_mean": float(nz.max() / nz.mean()) if len(nz) else 0.0,
+           "largest_share": float(nz.max() / tot) if tot else 0.0, "imbalance": {}}
+    for p in npes:
+        _, load = balance_classes(nz, p)
+        out["imbalance"][int(p)] = float(load.max() / (tot / p)) if tot else 0.0
+    return out
+
+
 def energy(h, eri, norb, nalpha, nbeta, dets, coeffs, ecore=0.0, ctx=None):
     """<C|H|C> over the given determinants, computed on the device."""
     torch = _torch()
@@ -274,7 +329,7 @@ def energy(h, eri, norb, nalpha, nbeta, dets, coeffs, ecore=0.0, ctx=None):
 
 
 def search_host(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, ecore=0.0,
-                pair_buffer_bytes=0):
+                pair_buffer_bytes=0, constraint_level=3, split_pairs=0):
     """The host-buffer entry point (asci_search): numpy in, numpy out."""
     h = np.ascontiguousarray(h, dtype=np.float64)
     eri = np.ascontiguousarray(eri, dtype=np.float64)
@@ -283,7 +338,7 @@ def search_host(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0
     out_d = np.zeros((int(k), 2), dtype=np.uint64)
     out_s = np.zeros(int(k), dtype=np.float64)
     cnt = C.c_int64(0)
-    o = options(ncore, eps, ecore, pair_buffer_bytes)
+    o = options(ncore, eps, ecore, pair_buffer_bytes, constraint_level, split_pairs)
     _check(_lib.asci_search(h.ctypes.data_as(_dp), eri.ctypes.data_as(_dp), norb, nalpha, nbeta,
                             dets.ctypes.data_as(_up), coeffs.ctypes.data_as(_dp), len(coeffs), float(E0), int(k),
                             C.byref(o), out_d.ctypes.data_as(_up), out_s.ctypes.data_as(_dp), C.byref(cnt)))
@@ -299,7 +354,7 @@ class SearchRequest:
     device and keeps references to every buffer it names."""
 
     def __init__(self, h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, ecore=0.0,
-                 pair_buffer_bytes=0):
+                 pair_buffer_bytes=0, constraint_level=3, split_pairs=0):
         torch = _torch()
         dets = _dets_tensor(dets)
         self.keep = (h, eri, dets, coeffs)
@@ -307,7 +362,7 @@ class SearchRequest:
         self.out_scores = torch.empty((int(k),), dtype=torch.float64, device=h.device)
         self.c = Request(_dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
                          _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0], float(E0), int(k),
-                         options(ncore, eps, ecore, pair_buffer_bytes), self.out_dets.data_ptr(),
+                         options(ncore, eps, ecore, pair_buffer_bytes, constraint_level, split_pairs), self.out_dets.data_ptr(),
                          self.out_scores.data_ptr())
 
     def result(self, count):

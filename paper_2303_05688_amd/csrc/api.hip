@@ -2,6 +2,7 @@
 // staging, and translation of internal errors into return codes.
 #include "asci_internal.h"
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -70,7 +71,8 @@ asci_options resolve(const asci_options *opt)
     asci_options o;
     asci_options_default(&o);
     if (opt) o = *opt;
-    require(o.constraint_level == 3, ASCI_EINVAL, "only triplet constraints (level 3) are implemented");
+    require(o.constraint_level >= 1 && o.constraint_level <= 6, ASCI_EINVAL, "constraint_level must be in [1, 6]");
+    require(o.split_pairs >= 0, ASCI_EINVAL, "split_pairs must be >= 0");
     require(o.ncore >= 0, ASCI_EINVAL, "ncore must be >= 0");
     require(o.pair_buffer_bytes >= 0, ASCI_EINVAL, "pair_buffer_bytes must be >= 0");
     require(!(o.eps < 0.0) && o.eps == o.eps, ASCI_EINVAL, "eps must be >= 0");
@@ -116,6 +118,7 @@ void asci_options_default(asci_options *opt)
     opt->constraint_level = 3;
     opt->ecore = 0.0;
     opt->pair_buffer_bytes = 0;
+    opt->split_pairs = 0;
 }
 
 int asci_ctx_create(int device, asci_ctx **out)
@@ -274,6 +277,28 @@ int asci_candidates_device(asci_ctx *ctx, const double *d_h, const double *d_eri
     }
 }
 
+int asci_pt2_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                    const uint64_t *d_dets, const double *d_coeffs, int64_t ndets, double E0,
+                    const asci_options *opt, double *out_energy, int64_t *out_count, void *stream)
+{
+    try {
+        require(ctx && d_h && d_eri && d_dets && d_coeffs && out_energy && out_count, ASCI_EINVAL,
+                "null pointer argument");
+        check_common(norb, nalpha, nbeta, ndets);
+        ASCI_HIP(hipSetDevice(ctx->device));
+        SearchArgs in{d_h, d_eri, norb, nalpha, nbeta, d_dets, d_coeffs, ndets, E0, resolve(opt)};
+        SearchOut out;
+        out.k = 0;
+        out.pt2 = true;
+        search_device(ctx, in, out, (hipStream_t)stream);
+        *out_energy = out.pt2_energy;
+        *out_count = out.count;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
 int asci_class_counts_device(asci_ctx *ctx, int norb, int nalpha, int nbeta, const uint64_t *d_dets,
                              const double *d_coeffs, int64_t ndets, const asci_options *opt, int64_t capacity,
                              uint64_t *h_masks, int64_t *h_counts, int64_t *out_nclasses, void *stream)
@@ -285,13 +310,44 @@ int asci_class_counts_device(asci_ctx *ctx, int norb, int nalpha, int nbeta, con
         const asci_options o = resolve(opt);
         ASCI_HIP(hipSetDevice(ctx->device));
         std::vector<uint64_t> masks, counts;
-        class_counts_device(ctx, norb, nalpha, nbeta, d_dets, d_coeffs, ndets, o.ncore, masks, counts,
+        class_counts_device(ctx, norb, nalpha, nbeta, d_dets, d_coeffs, ndets, o, masks, counts,
                             (hipStream_t)stream);
         *out_nclasses = (int64_t)masks.size();
         require((int64_t)masks.size() <= capacity, ASCI_ENOMEM, "output capacity below the class count");
         for (size_t i = 0; i < masks.size(); ++i) {
             h_masks[i] = masks[i];
             h_counts[i] = (int64_t)counts[i];
+        }
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_balance_classes(const int64_t *counts, int64_t nclasses, int32_t npe, int32_t *owner, int64_t *load)
+{
+    try {
+        require(counts && owner && load, ASCI_EINVAL, "null pointer argument");
+        require(nclasses >= 0 && npe >= 1, ASCI_EINVAL, "nclasses must be >= 0 and npe >= 1");
+        for (int64_t c = 0; c < nclasses; ++c) require(counts[c] >= 0, ASCI_EINVAL, "negative class count");
+        // a binary heap of (load, element) keeps the arg-min at O(log npe)
+        std::vector<std::pair<int64_t, int32_t>> heap((size_t)npe);
+        for (int32_t p = 0; p < npe; ++p) heap[(size_t)p] = {0, p};
+        auto later = [](const std::pair<int64_t, int32_t> &x, const std::pair<int64_t, int32_t> &y) {
+            return x > y;  // min-heap on (load, element)
+        };
+        for (int32_t p = 0; p < npe; ++p) load[p] = 0;
+        for (int64_t c = 0; c < nclasses; ++c) {
+            if (counts[c] == 0) {
+                owner[c] = -1;
+                continue;
+            }
+            std::pop_heap(heap.begin(), heap.end(), later);
+            auto &q = heap.back();
+            owner[c] = q.second;
+            q.first += counts[c];
+            load[q.second] = q.first;
+            std::push_heap(heap.begin(), heap.end(), later);
         }
         return ASCI_OK;
     } catch (const Error &e) {

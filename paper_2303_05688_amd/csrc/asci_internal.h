@@ -230,6 +230,31 @@ struct SelectState {
 void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_state,
                       hipStream_t s, Profiler *prof = nullptr);
 
+// ---------------------------------------------------------------- input-determinant set
+// Open-addressing hash set of the input keys (linear probing; a slot is taken
+// when state != 0): exclusion costs one or two L2-resident probes.
+struct PsiSet {
+    const uint64_t *lo = nullptr, *hi = nullptr;
+    const uint32_t *state = nullptr;
+    uint32_t mask = 0;  // table size - 1 (a power of two minus one)
+};
+
+__device__ __forceinline__ uint32_t psi_hash(uint64_t lo, uint64_t hi, uint32_t mask)
+{
+    const uint64_t h = lo * 0x9E3779B97F4A7C15ull ^ (hi + 0x632BE59BD9B4E019ull) * 0xC2B2AE3D27D4EB4Full;
+    return (uint32_t)(h >> 32) & mask;
+}
+
+__device__ __forceinline__ bool psi_contains(const PsiSet &t, uint64_t lo, uint64_t hi)
+{
+    uint32_t s = psi_hash(lo, hi, t.mask);
+    while (t.state[s]) {
+        if (t.lo[s] == lo && t.hi[s] == hi) return true;
+        s = (s + 1u) & t.mask;
+    }
+    return false;
+}
+
 // ---------------------------------------------------------------- buckets (bucket.hip)
 struct BucketArgs {
     size_t P;                       // records of the batch
@@ -242,6 +267,7 @@ struct BucketArgs {
     double *val[2];
     const uint64_t *plo, *phi;      // sorted input keys
     uint32_t npsi;
+    PsiSet psi;                     // the same keys as a hash set
     const double *jk, *h;
     double ecore, E0, eps;
     int finish_cap = 4096;          // LDS capacity of a final segment (tunable)
@@ -261,6 +287,8 @@ template <int W>
 void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, HostStage &hs);
 template <int W>
 void bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof);
+// sum over the batch's candidates of N_a * A_a (deterministic order)
+double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs);
 
 // ---------------------------------------------------------------- search (search.hip)
 struct SearchArgs {
@@ -279,12 +307,14 @@ struct SearchOut {
     double *out_scores = nullptr;  // device
     int64_t capacity = 0;          // every-candidate mode: output length
     double *out_num = nullptr;     // every-candidate mode: N_a (device)
+    bool pt2 = false;              // second-order energy mode: no candidates are kept
+    double pt2_energy = 0.0;
     int64_t count = 0;             // result count
 };
 
 void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s);
 void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *dets, const double *coeffs,
-                         int64_t ndets, int64_t ncore, std::vector<uint64_t> &masks,
+                         int64_t ndets, const asci_options &opt, std::vector<uint64_t> &masks,
                          std::vector<uint64_t> &counts, hipStream_t s);
 // closed-form pair count and workspace estimate of a request (server.hip)
 int64_t request_pairs(const asci_request &r);

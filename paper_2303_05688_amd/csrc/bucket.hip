@@ -351,29 +351,15 @@ struct FinishArgs {
     uint64_t *klo[2], *khi[2];
     double *val[2];
     int n;
-    const uint64_t *plo, *phi;  // sorted keys of the input determinants
-    uint32_t npsi;
-    const double *jk, *h;       // J|K table (2 n^2), h (n^2)
+    const double *jk, *h;       // J, J-K (n^2 each), h_pp (n); h (n^2)
     double ecore, E0, eps;      // eps > 0: keep a pair only if |H_ai C_i / (E0 - H_aa)| > eps
     uint64_t *clo, *chi;        // slot arrays (batch positions)
     double *cnum, *cscore;
     uint32_t *cnt;              // per final segment: candidates written
     uint32_t nfinal;
-    const uint32_t *psi_range;  // per final segment: [first, last) input keys inside its key range
-    int tab_in_lds;             // J/K/h_pp staged in LDS (else read from jk / h)
+    PsiSet psi;                 // input determinants (exclusion)
+    int tab_in_lds;             // J, J-K, h_pp staged in LDS (else read from jk)
 };
-
-template <int W>
-__device__ __forceinline__ uint32_t psi_lower(const uint64_t *plo, const uint64_t *phi, uint32_t L, uint32_t R,
-                                              uint64_t lo, uint64_t hi)
-{
-    while (L < R) {
-        const uint32_t m = (L + R) >> 1;
-        if (key_less<W>(plo[m], W == 2 ? phi[m] : 0ull, lo, hi)) L = m + 1;
-        else R = m;
-    }
-    return L;
-}
 
 template <int W, int CAP, int NT>
 struct FinishLds {
@@ -384,8 +370,6 @@ struct FinishLds {
     uint32_t wcnt[NW][256];
     uint32_t dbase[256];
     uint32_t tmp[NW];
-    uint64_t psi_lo[256], psi_hi[W == 2 ? 256 : 1];
-    uint32_t psi_range[2];
     uint32_t nruns;
     uint64_t red[4][NW];  // per-wave OR / AND of the key words
 };
@@ -393,7 +377,7 @@ struct FinishLds {
 // one final segment, processed by the whole workgroup
 template <int W, int CAP, int NT>
 __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W, CAP, NT> &S, const double *J,
-                                               const double *K, const double *hd, uint32_t sidx)
+                                               const double *X, const double *hd, uint32_t sidx)
 {
     using L = FinishLds<W, CAP, NT>;
     constexpr int NW = L::NW;
@@ -412,12 +396,11 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         if (tid == 0) {
             const size_t j0 = sg.start;
             const uint64_t lo = f.klo[buf][j0], hi = W == 2 ? f.khi[buf][j0] : 0ull;
-            const uint32_t at = psi_lower<W>(f.plo, f.phi, 0u, f.npsi, lo, hi);
-            const bool ex = at < f.npsi && f.plo[at] == lo && (W == 1 || f.phi[at] == hi);
+            const bool ex = psi_contains(f.psi, lo, hi);
             uint32_t c = 0;
             if (!ex) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
-                const double den = f.E0 - diag_value(J, K, hd, n, f.ecore, a, b);
+                const double den = f.E0 - diag_value(J, X, hd, n, f.ecore, a, b);
                 double sum = 0.0;
                 uint32_t kept = 0;
                 for (uint32_t r = 0; r < sg.size; ++r) {
@@ -498,6 +481,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         uint32_t rrank[IT];
 #pragma unroll
         for (int q = 0; q < IT; ++q) {
+            if ((uint32_t)wv * 64 * IT + (uint32_t)q * 64 >= size) break;  // whole wave past the end
             const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
             const bool valid = li < size;
             const uint64_t lo = valid ? S.klo[cur][li] : 0ull;
@@ -565,20 +549,11 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         if (tid == 0) {
             head[base] = (uint16_t)min(size, (uint32_t)CAP);
             S.nruns = base;
-            S.psi_range[0] = f.psi_range[2 * sidx];
-            S.psi_range[1] = f.psi_range[2 * sidx + 1];
-        }
-        __syncthreads();
-        const uint32_t pa = S.psi_range[0], pb = min(S.psi_range[1], S.psi_range[0] + 256u);
-        for (uint32_t t = tid; t < pb - pa; t += NT) {
-            S.psi_lo[t] = f.plo[pa + t];
-            if (W == 2) S.psi_hi[t] = f.phi[pa + t];
         }
         __syncthreads();
     }
     // one thread per run: sum, exclusion, diagonal, score; compacted writes
-    const uint32_t nruns = S.nruns, npl = S.psi_range[1] - S.psi_range[0];
-    const bool psi_overflow = npl > 256u;
+    const uint32_t nruns = S.nruns;
     uint32_t written = 0;
     for (uint32_t u0 = 0; u0 < nruns; u0 += NT) {
         const uint32_t u = u0 + tid;
@@ -589,18 +564,10 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             const uint32_t j0 = head[u], j1 = head[u + 1];
             lo = S.klo[cur][j0];
             hi = W == 2 ? S.khi[cur][j0] : 0ull;
-            uint32_t at;
-            bool ex;
-            if (!psi_overflow) {
-                at = psi_lower<W>(S.psi_lo, S.psi_hi, 0u, npl, lo, hi);
-                ex = at < npl && S.psi_lo[at] == lo && (W == 1 || S.psi_hi[at] == hi);
-            } else {
-                at = psi_lower<W>(f.plo, f.phi, S.psi_range[0], S.psi_range[1], lo, hi);
-                ex = at < f.npsi && f.plo[at] == lo && (W == 1 || f.phi[at] == hi);
-            }
+            const bool ex = psi_contains(f.psi, lo, hi);
             if (!ex) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
-                const double den = f.E0 - diag_value(J, K, hd, n, f.ecore, a, b);
+                const double den = f.E0 - diag_value(J, X, hd, n, f.ecore, a, b);
                 if (f.eps > 0.0) {
                     // Alg. 2's threshold, per pair, in record (ascending core) order
                     for (uint32_t j = j0; j < j1; ++j) {
@@ -642,67 +609,22 @@ __global__ __launch_bounds__(NT) void k_finish(FinishArgs f)
     double *tab = reinterpret_cast<double *>(smem_raw + ((sizeof(L) + 15) & ~size_t(15)));
     const int n = f.n;
     const int tid = threadIdx.x;
-    const double *J, *K, *hd;
+    const double *J, *X, *hd;
     if (f.tab_in_lds) {
         for (int t = tid; t < 2 * n * n; t += NT) tab[t] = f.jk[t];
         for (int t = tid; t < n; t += NT) tab[2 * n * n + t] = f.h[(size_t)t * n + t];
         J = tab;
-        K = tab + n * n;
+        X = tab + n * n;
         hd = tab + 2 * n * n;
     } else {
         J = f.jk;
-        K = f.jk + n * n;
+        X = f.jk + n * n;
         hd = f.jk + 2 * n * n;
     }
     for (uint32_t sidx = blockIdx.x; sidx < f.nfinal; sidx += gridDim.x) {
         __syncthreads();
-        finish_segment<W, CAP, NT>(f, S, J, K, hd, sidx);
+        finish_segment<W, CAP, NT>(f, S, J, X, hd, sidx);
     }
-}
-
-// input keys inside every final segment's key range (its constant prefix above
-// `top`, any bits below): two binary searches per segment, one thread each
-template <int W>
-__global__ __launch_bounds__(256) void k_psi_ranges(const Seg *__restrict__ finals, uint32_t nf,
-                                                    uint64_t *const *__restrict__ klo_,
-                                                    uint64_t *const *__restrict__ khi_, int n,
-                                                    const uint64_t *__restrict__ plo, const uint64_t *__restrict__ phi,
-                                                    uint32_t npsi, uint32_t *__restrict__ range)
-{
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= nf) return;
-    const Seg sg = finals[j];
-    const uint32_t buf = seg_buf(sg);
-    const uint64_t *klo = klo_[buf];
-    const uint64_t *khi = khi_[buf];
-    const uint64_t lo = klo[sg.start], hi = W == 2 ? khi[sg.start] : 0ull;
-    const int top = (int)seg_top(sg);
-    uint64_t llo, lhi, ulo, uhi;
-    if (W == 1) {
-        const uint64_t m = top >= 64 ? ~0ull : ((1ull << top) - 1ull);
-        llo = lo & ~m;
-        ulo = lo | m;
-        lhi = uhi = 0ull;
-    } else {
-        // virtual bits [0, n) are the lo word, [n, 2n) the hi word
-        const int tlo = top < n ? top : n, thi = top > n ? top - n : 0;
-        const uint64_t mlo = tlo >= 64 ? ~0ull : ((1ull << tlo) - 1ull);
-        const uint64_t mhi = thi >= 64 ? ~0ull : ((1ull << thi) - 1ull);
-        llo = lo & ~mlo;
-        ulo = lo | mlo;
-        lhi = hi & ~mhi;
-        uhi = hi | mhi;
-    }
-    const uint32_t a = psi_lower<W>(plo, phi, 0u, npsi, llo, lhi);
-    // first input key greater than the upper bound
-    uint32_t L = a, R = npsi;
-    while (L < R) {
-        const uint32_t m = (L + R) >> 1;
-        if (!key_less<W>(ulo, uhi, plo[m], W == 2 ? phi[m] : 0ull)) L = m + 1;
-        else R = m;
-    }
-    range[2 * j] = a;
-    range[2 * j + 1] = L;
 }
 
 // ---------------------------------------------------------------- collect
@@ -915,19 +837,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     b.nfinal = nf;
     b.levels = (uint32_t)lev;
     uint32_t *cnt = ar.take<uint32_t>(nf + 1);
-    uint32_t *prange = ar.take<uint32_t>(2 * (size_t)nf + 2);
-    uint64_t **bufptr = ar.take<uint64_t *>(4);
     if (nf) {
-        uint64_t *hb[4] = {b.klo[0], b.klo[1], b.khi[0], b.khi[1]};
-        uint64_t **hstage = (uint64_t **)((char *)hs.ptr + 64);
-        for (int i = 0; i < 4; ++i) hstage[i] = hb[i];
-        ASCI_HIP(hipMemcpyAsync(bufptr, hstage, 4 * sizeof(uint64_t *), hipMemcpyHostToDevice, s));
-        {
-            ProfScope ps(prof, "psi_ranges", 0.0, s);
-            k_psi_ranges<W><<<(nf + 255) / 256, 256, 0, s>>>(finals, nf, bufptr, bufptr + 2, b.n, b.plo, b.phi,
-                                                             b.npsi, prange);
-            ASCI_LAUNCH_CHECK();
-        }
         FinishArgs fa;
         fa.finals = finals;
         fa.klo[0] = b.klo[0];
@@ -937,9 +847,6 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.val[0] = b.val[0];
         fa.val[1] = b.val[1];
         fa.n = b.n;
-        fa.plo = b.plo;
-        fa.phi = b.phi;
-        fa.npsi = b.npsi;
         fa.jk = b.jk;
         fa.h = b.h;
         fa.ecore = b.ecore;
@@ -951,7 +858,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.cscore = b.cscore;
         fa.cnt = cnt;
         fa.nfinal = nf;
-        fa.psi_range = prange;
+        fa.psi = b.psi;
         if constexpr (W == 1) {
             if (CAP == 4096) launch_finish<1, 4096, 512>(fa, b, nf, s, prof);
             else if (CAP == 2048) launch_finish<1, 2048, 256>(fa, b, nf, s, prof);
@@ -997,6 +904,52 @@ void bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof)
                                          b.cscore, b.pool_lo, b.pool_hi, b.pool_num, b.pool_score, b.pool_base,
                                          b.pool_cap);
     ASCI_LAUNCH_CHECK();
+}
+
+// sum of N_a * A_a over the batch's candidates: per final segment in key
+// order (sequential inside a segment), then a fixed-order tree over segments
+__global__ __launch_bounds__(256) void k_pt2_segments(const Seg *__restrict__ finals, uint32_t nf,
+                                                      const uint32_t *__restrict__ order,
+                                                      const uint32_t *__restrict__ cnt_sorted,
+                                                      const double *__restrict__ cnum,
+                                                      const double *__restrict__ cscore, double *__restrict__ part)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nf) return;
+    const Seg sg = finals[order[j]];
+    double e = 0.0;
+    for (uint32_t t = 0; t < cnt_sorted[j]; ++t) e = e + cnum[sg.start + t] * cscore[sg.start + t];
+    part[j] = e;
+}
+
+__global__ __launch_bounds__(1024) void k_sum_fixed(const double *__restrict__ x, uint32_t n, double *__restrict__ out)
+{
+    __shared__ double sh[1024];
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += 1024) acc = acc + x[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs)
+{
+    if (b.nfinal == 0) return 0.0;
+    double *part = ar.take<double>(b.nfinal);
+    double *tot = ar.take<double>(1);
+    k_pt2_segments<<<(b.nfinal + 255) / 256, 256, 0, s>>>((const Seg *)b.finals, b.nfinal, b.order, b.cnt_sorted,
+                                                          b.cnum, b.cscore, part);
+    ASCI_LAUNCH_CHECK();
+    k_sum_fixed<<<1, 1024, 0, s>>>(part, b.nfinal, tot);
+    ASCI_LAUNCH_CHECK();
+    double *h = (double *)((char *)hs.ptr + 128);
+    ASCI_HIP(hipMemcpyAsync(h, tot, sizeof(double), hipMemcpyDeviceToHost, s));
+    ASCI_HIP(hipStreamSynchronize(s));
+    return *h;
 }
 
 template void bucket_accumulate<1>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);

@@ -60,34 +60,40 @@ __device__ __forceinline__ double double_opp_value(const double *__restrict__ er
     return sg * eri4(eri, n, q, p, s, r);
 }
 
-// H_aa from a J/K table (J[p*n+q] = (pp|qq), K[p*n+q] = (pq|qp)) and the
-// diagonal of h, in this order: ecore, alpha h_pp, beta h_pp, alpha pairs
-// p<q of (J-K), beta pairs, then alpha x beta J.
-__device__ __forceinline__ double diag_value(const double *J, const double *K, const double *hd, int n,
-                                             double ecore, uint64_t a, uint64_t b)
+// H_aa from a table of J[p*n+q] = (pp|qq), X[p*n+q] = (pp|qq) - (pq|qp) and
+// the diagonal of h, in this order: ecore, alpha h_pp, beta h_pp, alpha pairs
+// p<q of X, beta pairs, then alpha x beta J.  M is the string word type: a
+// 32-bit word when every orbital fits in it (half the bit arithmetic).
+__device__ __forceinline__ int tz(uint32_t m) { return __builtin_ctz(m); }
+__device__ __forceinline__ int tz(uint64_t m) { return __builtin_ctzll(m); }
+
+template <typename M>
+__device__ __forceinline__ double diag_value_m(const double *J, const double *X, const double *hd, int n,
+                                               double ecore, M a, M b)
 {
     double e = ecore;
-    for (uint64_t m = a; m; m &= m - 1ull) e = e + hd[lowbit(m)];
-    for (uint64_t m = b; m; m &= m - 1ull) e = e + hd[lowbit(m)];
-    for (uint64_t m = a; m; m &= m - 1ull) {
-        const int p = lowbit(m);
-        for (uint64_t m2 = m & (m - 1ull); m2; m2 &= m2 - 1ull) {
-            const int q = lowbit(m2);
-            e = e + (J[p * n + q] - K[p * n + q]);
-        }
+    for (M m = a; m; m &= m - 1) e = e + hd[tz(m)];
+    for (M m = b; m; m &= m - 1) e = e + hd[tz(m)];
+    for (M m = a; m; m &= m - 1) {
+        const double *row = X + tz(m) * n;
+        for (M m2 = m & (m - 1); m2; m2 &= m2 - 1) e = e + row[tz(m2)];
     }
-    for (uint64_t m = b; m; m &= m - 1ull) {
-        const int p = lowbit(m);
-        for (uint64_t m2 = m & (m - 1ull); m2; m2 &= m2 - 1ull) {
-            const int q = lowbit(m2);
-            e = e + (J[p * n + q] - K[p * n + q]);
-        }
+    for (M m = b; m; m &= m - 1) {
+        const double *row = X + tz(m) * n;
+        for (M m2 = m & (m - 1); m2; m2 &= m2 - 1) e = e + row[tz(m2)];
     }
-    for (uint64_t m = a; m; m &= m - 1ull) {
-        const int p = lowbit(m);
-        for (uint64_t m2 = b; m2; m2 &= m2 - 1ull) e = e + J[p * n + lowbit(m2)];
+    for (M m = a; m; m &= m - 1) {
+        const double *row = J + tz(m) * n;
+        for (M m2 = b; m2; m2 &= m2 - 1) e = e + row[tz(m2)];
     }
     return e;
+}
+
+__device__ __forceinline__ double diag_value(const double *J, const double *X, const double *hd, int n,
+                                             double ecore, uint64_t a, uint64_t b)
+{
+    if (n <= 32) return diag_value_m<uint32_t>(J, X, hd, n, ecore, (uint32_t)a, (uint32_t)b);
+    return diag_value_m<uint64_t>(J, X, hd, n, ecore, a, b);
 }
 
 }  // namespace asci

@@ -112,24 +112,49 @@ __device__ __forceinline__ void put_key(uint64_t *klo, uint64_t *khi, size_t j, 
     }
 }
 
-// class index of an alpha string: the rank of its top-L occupied orbitals
-// among all admissible L-subsets in ascending mask order (combinatorial number
-// system on x = orbital - L0, L0 = n_alpha - L); equals the position of the
-// class in make_classes()
-__device__ __forceinline__ uint32_t class_index(uint64_t a, int L, int L0)
+// C(x, k) for k <= 6 and x < 64 (exact: every partial product is a binomial)
+__device__ __forceinline__ uint32_t choose_le6(uint32_t x, int k)
 {
-    if (L == 0) return 0u;
-    const int o1 = 63 - __clzll((long long)a);
-    a &= ~(1ull << o1);
-    const uint32_t x1 = (uint32_t)(o1 - L0);
-    if (L == 1) return x1;
-    const int o2 = 63 - __clzll((long long)a);
-    a &= ~(1ull << o2);
-    const uint32_t x2 = (uint32_t)(o2 - L0);
-    if (L == 2) return x1 * (x1 - 1u) / 2u + x2;
-    const int o3 = 63 - __clzll((long long)a);
-    const uint32_t x3 = (uint32_t)(o3 - L0);
-    return x1 * (x1 - 1u) * (x1 - 2u) / 6u + x2 * (x2 - 1u) / 2u + x3;
+    if ((int)x < k) return 0u;
+    uint32_t r = 1u;
+    for (int i = 0; i < k; ++i) r = r * (x - (uint32_t)i) / (uint32_t)(i + 1);
+    return r;
+}
+
+// The class of an alpha string.  Root classes are the sets of its top Lr
+// occupied orbitals, ranked among all admissible Lr-subsets in ascending mask
+// order (combinatorial number system on x = orbital - (n_alpha - Lr)).  A root
+// class that was split (a heavy class, refined by one more highest occupied
+// orbital per level) is followed through `tree`: an entry with the top bit set
+// is the base of its children, indexed by the next orbital's rank
+// o - (n_alpha - level); any other entry is the final class number.  Class
+// numbers follow ascending mask order, i.e. key order.
+struct ClassMap {
+    int Lr;                // root level (0: a single class)
+    int na;
+    const uint32_t *tree;  // null when no class is split
+};
+
+__device__ __forceinline__ uint32_t class_of(uint64_t a, const ClassMap &m)
+{
+    if (m.Lr == 0) return 0u;
+    const int L0 = m.na - m.Lr;
+    uint32_t idx = 0u;
+    for (int j = 0; j < m.Lr; ++j) {
+        const int o = 63 - __clzll((long long)a);
+        a &= ~(1ull << o);
+        idx += choose_le6((uint32_t)(o - L0), m.Lr - j);
+    }
+    if (!m.tree) return idx;
+    uint32_t e = m.tree[idx];
+    int level = m.Lr;
+    while (e & 0x80000000u) {
+        const int o = 63 - __clzll((long long)a);
+        a &= ~(1ull << o);
+        ++level;
+        e = m.tree[(e & 0x7FFFFFFFu) + (uint32_t)(o - (m.na - level))];
+    }
+    return e;
 }
 
 // lanes of the wave whose (active, key) equal this lane's, key < 2^nbits
@@ -152,7 +177,8 @@ struct GenArgs {
     int nbits;                // bits of nc - 1
     const uint32_t *offsets;  // [nc][nq] start of every (class, core) item
     const double *h, *eri;
-    int n, na, nb, L, L0;
+    int n, na, nb;
+    ClassMap cmap;
     uint64_t full;
     uint32_t nas, nbs, f0, f1, pva2, npa2, pvb2;  // table sizes and block sizes
     uint64_t *klo, *khi;
@@ -233,7 +259,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     for (uint32_t u = lane; u < g.nas; u += 64) {
         const int p = occA[u / va], q = virA[u % va];
         const uint64_t a2 = (a & ~(1ull << p)) | (1ull << q);
-        const uint32_t c = class_index(a2, g.L, g.L0);
+        const uint32_t c = class_of(a2, g.cmap);
         asA[u] = a2;
         asV[u] = single_value(g.h, g.eri, n, a, b, p, q);
         asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u);
@@ -245,7 +271,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         bsB[t] = (b & ~(1ull << r)) | (1ull << s);
         bsX[t] = (uint32_t)r | ((uint32_t)s << 8) | (between_sign(b, r, s) < 0 ? (1u << 16) : 0u);
     }
-    const uint32_t cs = class_index(a, g.L, g.L0);
+    const uint32_t cs = class_of(a, g.cmap);
     const bool self_in = cs >= g.c0 && cs < g.c0 + g.nc;
     if (lane == 0 && self_in) cur[cs - g.c0] = g.f0;
     __syncthreads();
@@ -329,7 +355,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
                 holes = (1ull << occA[i1]) | (1ull << occA[j1]);
                 parts = (1ull << virA[i2]) | (1ull << virA[j2]);
                 a2 = (a & ~holes) | parts;
-                c = class_index(a2, g.L, g.L0);
+                c = class_of(a2, g.cmap);
             }
             const bool act = c >= g.c0 && c < g.c0 + g.nc;
             const uint32_t key = act ? c - g.c0 : 0u;
@@ -468,6 +494,27 @@ __global__ __launch_bounds__(kBlock) void k_pack_keys(const uint64_t *__restrict
     idx[j] = (uint32_t)j;
 }
 
+// insert every input key into the hash set (keys as (lo, hi) words)
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_psi_insert(const uint64_t *__restrict__ dets, size_t nd, int n,
+                                                       uint64_t *__restrict__ tlo, uint64_t *__restrict__ thi,
+                                                       uint32_t *__restrict__ state, uint32_t mask)
+{
+    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nd) return;
+    const uint64_t a = dets[2 * j], b = dets[2 * j + 1];
+    const uint64_t lo = W == 1 ? ((a << n) | b) : b, hi = W == 1 ? 0ull : a;
+    uint32_t s = psi_hash(lo, hi, mask);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        if (atomicCAS(&state[s], 0u, 1u) == 0u) {
+            tlo[s] = lo;
+            thi[s] = hi;
+            return;
+        }
+        s = (s + 1u) & mask;
+    }
+}
+
 // bit 1 of err: two equal input determinants (keys sorted)
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_check_dups(const uint64_t *__restrict__ klo,
@@ -510,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_core(const uint64_t *__restri
     qc[j] = c[i];
 }
 
-// J_pq = (pp|qq), K_pq = (pq|qp), then h_pp: the tables of the diagonal H_aa
+// J_pq = (pp|qq), X_pq = (pp|qq) - (pq|qp), then h_pp: the tables of the diagonal H_aa
 __global__ __launch_bounds__(kBlock) void k_jk(const double *__restrict__ eri, const double *__restrict__ h, int n,
                                                double *__restrict__ jk)
 {
@@ -518,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_jk(const double *__restrict__ eri, c
     if (t >= n * n) return;
     const int p = t / n, q = t % n;
     jk[t] = eri4(eri, n, p, p, q, q);
-    jk[n * n + t] = eri4(eri, n, p, q, q, p);
+    jk[n * n + t] = eri4(eri, n, p, p, q, q) - eri4(eri, n, p, q, q, p);
     if (q == 0) jk[2 * n * n + p] = h[(size_t)p * n + p];
 }
 
@@ -532,22 +579,19 @@ inline uint64_t choose_u64(uint64_t x, int k)
     return r;
 }
 
-// the constraint classes in ascending mask order: the sets of the three
+// the constraint classes of level L in ascending mask order: the sets of the L
 // highest occupied alpha orbitals that a string with na electrons can have
-// (all na orbitals when na < 3)
-std::vector<uint64_t> make_classes(int n, int na)
+// (all na orbitals when na < L)
+std::vector<uint64_t> make_classes(int n, int na, int L)
 {
     std::vector<uint64_t> out;
-    const int L = na < 3 ? na : 3;
+    L = std::min(L, na);
     if (L == 0) {
         out.push_back(0ull);
         return out;
     }
-    std::vector<int> c(L);
     // all L-subsets o_1 > ... > o_L with o_L >= na - L
-    std::function<void(int, int, uint64_t)> rec;
-    for (int i = 0; i < L; ++i) c[i] = 0;
-    rec = [&](int depth, int below, uint64_t mask) {
+    std::function<void(int, int, uint64_t)> rec = [&](int depth, int below, uint64_t mask) {
         if (depth == L) {
             out.push_back(mask);
             return;
@@ -587,8 +631,121 @@ struct Prepared {
     double *q_c = nullptr;
     uint64_t *d_cls = nullptr;
     double *d_jk = nullptr;
-    std::vector<uint64_t> cls, totals;
+    std::vector<uint64_t> cls, totals;  // final classes (ascending mask) and their pair counts
+    int Lr = 0;                         // level of the root classes
+    uint32_t *d_tree = nullptr;         // split tree (null when no class is split)
+    PsiSet psi;
+    ClassMap cmap(int na) const { return ClassMap{Lr, na, d_tree}; }
 };
+
+// pair totals of a list of classes (step 4 without the matrix), on the host
+static void count_classes(const uint64_t *q_a, uint32_t nq, const std::vector<uint64_t> &masks, uint64_t *d_cls,
+                          unsigned long long *d_tot, uint64_t full, const BetaFactors &bf, HostStage &hs,
+                          std::vector<uint64_t> &tot, hipStream_t s)
+{
+    const size_t m = masks.size();
+    tot.assign(m, 0);
+    if (m == 0) return;
+    ASCI_HIP(hipMemcpyAsync(d_cls, masks.data(), m * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    ASCI_HIP(hipMemsetAsync(d_tot, 0, m * sizeof(unsigned long long), s));
+    for (size_t c0 = 0; c0 < m; c0 += 65535) {
+        const unsigned ny = (unsigned)std::min<size_t>(65535, m - c0);
+        dim3 g((unsigned)((nq + kBlock - 1) / kBlock), ny);
+        k_count<<<g, kBlock, 0, s>>>(q_a, nq, d_cls, (uint32_t)c0, full, bf, nullptr, d_tot);
+        ASCI_LAUNCH_CHECK();
+    }
+    hs.reserve(m * sizeof(uint64_t));
+    ASCI_HIP(hipMemcpyAsync(hs.ptr, d_tot, m * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    ASCI_HIP(hipStreamSynchronize(s));
+    std::memcpy(tot.data(), hs.ptr, m * sizeof(uint64_t));
+}
+
+// Classes of the search (Sec. II.B, Alg. 3).  Uniform (split_pairs == 0): every
+// class at level L.  Adaptive (split_pairs > 0): the classes start at level
+// min(L, 3) and a class with more than split_pairs pairs is replaced by the
+// classes of the next level (one more highest occupied orbital) up to level L.
+// Either way a class with more than `fit` pairs (the pair buffer) is split
+// further, up to level 6, so that it fits.  The split classes partition the
+// targets exactly like the classes they replace.
+constexpr size_t kMaxClasses = (size_t)1 << 20;
+
+static void plan_classes(int n, int na, int L, int64_t split_pairs, uint64_t fit, const uint64_t *q_a,
+                         uint32_t nq, uint64_t *d_cls, unsigned long long *d_tot, uint64_t full,
+                         const BetaFactors &bf, HostStage &hs, std::vector<uint64_t> &cls,
+                         std::vector<uint64_t> &totals, std::vector<uint32_t> &tree, int &Lr, hipStream_t s)
+{
+    Lr = std::min(split_pairs > 0 ? std::min(L, 3) : L, na);
+    require(choose_u64((uint64_t)(n - na + Lr), Lr) <= kMaxClasses, ASCI_EINVAL,
+            "too many constraint classes at this level");
+    std::vector<uint64_t> roots = make_classes(n, na, Lr);
+    std::vector<uint64_t> rt;
+    count_classes(q_a, nq, roots, d_cls, d_tot, full, bf, hs, rt, s);
+    struct Node {
+        uint64_t mask, total;
+        int level;
+        int64_t child0;
+        uint32_t nchild;
+    };
+    std::vector<Node> nodes;
+    for (size_t r = 0; r < roots.size(); ++r) nodes.push_back({roots[r], rt[r], Lr, -1, 0});
+    std::vector<size_t> frontier(roots.size());
+    for (size_t r = 0; r < roots.size(); ++r) frontier[r] = r;
+    bool split_any = false;
+    while (!frontier.empty()) {
+        std::vector<uint64_t> kids;
+        for (size_t v : frontier) {
+            Node &nd = nodes[v];
+            const int lim = nd.total > fit ? 6 : (split_pairs > 0 ? L : 0);
+            const bool heavy = nd.total > fit || (split_pairs > 0 && nd.total > (uint64_t)split_pairs);
+            if (!heavy || nd.level >= lim || nd.level >= na || nd.mask == 0) continue;
+            const int o_lo = na - nd.level - 1, o_hi = __builtin_ctzll(nd.mask);
+            if (o_hi <= o_lo) continue;
+            nd.child0 = (int64_t)(nodes.size() + kids.size());
+            nd.nchild = (uint32_t)(o_hi - o_lo);
+            for (int o = o_lo; o < o_hi; ++o) kids.push_back(nd.mask | (1ull << o));
+        }
+        if (kids.empty()) break;
+        split_any = true;
+        require(nodes.size() + kids.size() <= kMaxClasses, ASCI_ENOMEM, "too many split constraint classes");
+        std::vector<uint64_t> kt;
+        count_classes(q_a, nq, kids, d_cls, d_tot, full, bf, hs, kt, s);
+        std::vector<size_t> next;
+        const size_t base = nodes.size();
+        for (size_t c = 0; c < kids.size(); ++c) {
+            // the level of a child is its parent's plus one; kids are grouped by parent
+            next.push_back(base + c);
+            nodes.push_back({kids[c], kt[c], 0, -1, 0});
+        }
+        for (size_t v : frontier)
+            if (nodes[v].child0 >= 0)
+                for (uint32_t c = 0; c < nodes[v].nchild; ++c) nodes[(size_t)nodes[v].child0 + c].level = nodes[v].level + 1;
+        frontier.swap(next);
+    }
+    cls.clear();
+    totals.clear();
+    tree.clear();
+    if (!split_any) {
+        cls = roots;
+        totals = rt;
+        return;
+    }
+    // leaves in depth-first order, children ascending: ascending masks
+    tree.resize(roots.size());
+    std::function<void(size_t, size_t)> place = [&](size_t v, size_t slot) {
+        const Node nd = nodes[v];
+        if (nd.child0 < 0) {
+            tree[slot] = (uint32_t)cls.size();
+            cls.push_back(nd.mask);
+            totals.push_back(nd.total);
+            return;
+        }
+        const size_t base = tree.size();
+        tree.resize(base + nd.nchild);
+        tree[slot] = 0x80000000u | (uint32_t)base;
+        for (uint32_t c = 0; c < nd.nchild; ++c) place((size_t)nd.child0 + c, base + c);
+    };
+    for (size_t r = 0; r < roots.size(); ++r) place(r, r);
+}
 
 static std::vector<Digit> full_key_digits(int n, int W)
 {
@@ -606,28 +763,27 @@ static std::vector<Digit> full_key_digits(int n, int W)
 // pairs of every constraint class.  All buffers live in ctx->setup.
 template <int W>
 static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n, int na, int nb, const uint64_t *dets,
-                    const double *coeffs, int64_t ndets, int64_t ncore, bool need_psi, Prepared<W> &pp,
-                    hipStream_t s)
+                    const double *coeffs, int64_t ndets, const asci_options &opt, uint64_t fit, bool need_psi,
+                    Prepared<W> &pp, hipStream_t s)
 {
     const size_t nd = (size_t)ndets;
     const uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
     const BetaFactors bf = beta_factors(n, nb);
+    const int64_t ncore = opt.ncore;
     pp.nd = nd;
     pp.nq = (ncore > 0 && (size_t)ncore < nd) ? (size_t)ncore : nd;
     const size_t nq = pp.nq;
-    pp.cls = make_classes(n, na);
-    const uint32_t ncls = (uint32_t)pp.cls.size();
-    require(ncls <= 65535, ASCI_EINVAL, "too many constraint classes");
 
     Arena &ar = ctx->setup;
     const size_t hist_bytes = ((nd + kScanTile - 1) / kScanTile) * 256 * 4 * 2 + (1 << 16);
     ar.reset();
-    ar.reserve(nd * (8 * 2 * W + 4 * 2) + nd * (8 * 2 + 4 * 2) + nq * 8 * 4 + (size_t)ncls * 16 +
-               (size_t)2 * n * n * 8 + 2 * hist_bytes + 64 * 256);
+    ar.reserve(nd * (8 * 2 * W + 4 * 2) + nd * (8 * 2 + 4 * 2) + nq * 8 * 4 + kMaxClasses * 20 +
+               (size_t)2 * n * n * 8 + 2 * hist_bytes + 64 * 256 + (nd * 8 + 1024) * 20);
     ar.reset();
     unsigned int *d_err = ar.take<unsigned int>(16);
-    pp.d_cls = ar.take<uint64_t>(ncls);
-    unsigned long long *d_tot = ar.take<unsigned long long>(ncls);
+    pp.d_cls = ar.take<uint64_t>(kMaxClasses);
+    unsigned long long *d_tot = ar.take<unsigned long long>(kMaxClasses);
+    uint32_t *d_tree = ar.take<uint32_t>(kMaxClasses);
     pp.d_jk = ar.take<double>((size_t)2 * n * n + n);
     uint64_t *psi_lo[2] = {ar.take<uint64_t>(nd), ar.take<uint64_t>(nd)};
     uint64_t *psi_hi[2] = {W == 2 ? ar.take<uint64_t>(nd) : nullptr, W == 2 ? ar.take<uint64_t>(nd) : nullptr};
@@ -635,10 +791,16 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     pp.q_a = ar.take<uint64_t>(nq);
     pp.q_b = ar.take<uint64_t>(nq);
     pp.q_c = ar.take<double>(nq);
+    uint32_t tsize = 1024;
+    while (tsize < 4 * nd) tsize <<= 1;
+    uint64_t *t_lo = ar.take<uint64_t>(tsize), *t_hi = ar.take<uint64_t>(tsize);
+    uint32_t *t_state = ar.take<uint32_t>(tsize);
+    pp.psi.lo = t_lo;
+    pp.psi.hi = t_hi;
+    pp.psi.state = t_state;
+    pp.psi.mask = tsize - 1;
 
     ASCI_HIP(hipMemsetAsync(d_err, 0, 16 * sizeof(unsigned int), s));
-    ASCI_HIP(hipMemsetAsync(d_tot, 0, ncls * sizeof(unsigned long long), s));
-    ASCI_HIP(hipMemcpyAsync(pp.d_cls, pp.cls.data(), ncls * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     k_validate<<<grid_for(nd), kBlock, 0, s>>>(dets, nd, full, na, nb, d_err);
     ASCI_LAUNCH_CHECK();
     if (d_eri && d_h) {
@@ -646,6 +808,9 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
         ASCI_LAUNCH_CHECK();
     }
     if (need_psi) {
+        ASCI_HIP(hipMemsetAsync(t_state, 0, (size_t)tsize * sizeof(uint32_t), s));
+        k_psi_insert<W><<<grid_for(nd), kBlock, 0, s>>>(dets, nd, n, t_lo, t_hi, t_state, tsize - 1);
+        ASCI_LAUNCH_CHECK();
         k_pack_keys<W><<<grid_for(nd), kBlock, 0, s>>>(dets, nd, n, psi_lo[0], psi_hi[0], psi_idx[0]);
         ASCI_LAUNCH_CHECK();
         const int pc = radix_sort<uint32_t>(psi_lo, psi_hi, psi_idx, nd, W, full_key_digits(n, W), ar, s);
@@ -677,22 +842,24 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
         k_gather_core<<<grid_for(nq), kBlock, 0, s>>>(dets, coeffs, nullptr, nq, pp.q_a, pp.q_b, pp.q_c);
     }
     ASCI_LAUNCH_CHECK();
-    // step 4, totals per class
-    {
-        dim3 g((unsigned)((nq + kBlock - 1) / kBlock), ncls);
-        k_count<<<g, kBlock, 0, s>>>(pp.q_a, (uint32_t)nq, pp.d_cls, 0, full, bf, nullptr, d_tot);
-        ASCI_LAUNCH_CHECK();
-    }
     HostStage &hs = ctx->stage;
-    hs.reserve(256 + ncls * sizeof(uint64_t));
+    hs.reserve(256);
     unsigned int *h_err = (unsigned int *)hs.ptr;
-    uint64_t *h_tot = (uint64_t *)((char *)hs.ptr + 256);
     ASCI_HIP(hipMemcpyAsync(h_err, d_err, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-    ASCI_HIP(hipMemcpyAsync(h_tot, d_tot, ncls * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     ASCI_HIP(hipStreamSynchronize(s));
     if (h_err[0] & 1u) throw Error{ASCI_EINVAL, "input determinant with wrong electron count or orbital >= norb"};
     if (h_err[0] & 2u) throw Error{ASCI_EINVAL, "duplicate input determinants"};
-    pp.totals.assign(h_tot, h_tot + ncls);
+    // step 4, totals per class (and the split of heavy classes)
+    std::vector<uint32_t> tree;
+    plan_classes(n, na, opt.constraint_level, opt.split_pairs, fit, pp.q_a, (uint32_t)nq, pp.d_cls, d_tot, full, bf,
+                 hs, pp.cls, pp.totals, tree, pp.Lr, s);
+    ASCI_HIP(hipMemcpyAsync(pp.d_cls, pp.cls.data(), pp.cls.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    if (!tree.empty()) {
+        ASCI_HIP(hipMemcpyAsync(d_tree, tree.data(), tree.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        pp.d_tree = d_tree;
+    }
+    // the host vectors are read by the copies above: finish them before returning
+    ASCI_HIP(hipStreamSynchronize(s));
 }
 
 template <int W>
@@ -704,12 +871,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     const bool topk = out.k > 0;
 
     Profiler *prof = &ctx->prof;
-    Prepared<W> pp;
-    prepare<W>(ctx, in.h, in.eri, n, in.na, in.nb, in.dets, in.coeffs, in.ndets, in.opt.ncore, true, pp, s);
-    const size_t nd = pp.nd, nq = pp.nq;
-    const uint32_t ncls = (uint32_t)pp.cls.size();
-
-    // ---- batch plan: consecutive classes up to the pair-buffer capacity
+    // ---- pair-buffer capacity (records of one class batch)
     const size_t rec_bytes = 2 * (8 * W + 8);  // ping-pong keys + values
     uint64_t cap;
     if (in.opt.pair_buffer_bytes > 0) {
@@ -721,6 +883,13 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         cap = std::min<uint64_t>((uint64_t)1 << 30, (uint64_t)(fr / 2) / (rec_bytes + 3 * 4 + 8 * W + 20));
     }
     cap = std::max<uint64_t>(cap, 1);
+
+    Prepared<W> pp;
+    prepare<W>(ctx, in.h, in.eri, n, in.na, in.nb, in.dets, in.coeffs, in.ndets, in.opt, cap, true, pp, s);
+    const size_t nd = pp.nd, nq = pp.nq;
+    const uint32_t ncls = (uint32_t)pp.cls.size();
+
+    // ---- batch plan: consecutive classes up to the pair-buffer capacity
     std::vector<std::pair<uint32_t, uint32_t>> batches;
     uint64_t max_batch = 0, max_entries = 0, total = 0;
     for (uint32_t c = 0; c < ncls;) {
@@ -742,7 +911,8 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     const size_t Pb = std::max<uint64_t>(max_batch, 1);
     const size_t E = std::max<uint64_t>(max_entries, 1);
     size_t pool_cap;
-    if (topk) pool_cap = (size_t)std::min<uint64_t>(total + 1, std::max<uint64_t>(4 * (uint64_t)out.k, Pb) + (uint64_t)out.k);
+    if (out.pt2) pool_cap = 1;
+    else if (topk) pool_cap = (size_t)std::min<uint64_t>(total + 1, std::max<uint64_t>(4 * (uint64_t)out.k, Pb) + (uint64_t)out.k);
     else pool_cap = total + 1;
     require(pool_cap < (1ull << 32), ASCI_ENOMEM, "candidate pool too large");
     const size_t scan_tmp = ((std::max<size_t>(Pb, E) + kScanTile - 1) / kScanTile) * 4 + 4096;
@@ -839,8 +1009,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.n = n;
             ga.na = in.na;
             ga.nb = in.nb;
-            ga.L = in.na < 3 ? in.na : 3;
-            ga.L0 = in.na - ga.L;
+            ga.cmap = pp.cmap(in.na);
             ga.full = full;
             const uint32_t va = (uint32_t)(n - in.na), vb = (uint32_t)(n - in.nb);
             ga.nas = (uint32_t)in.na * va;
@@ -878,6 +1047,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.plo = pp.plo;
         ba.phi = pp.phi;
         ba.npsi = (uint32_t)nd;
+        ba.psi = pp.psi;
         ba.jk = pp.d_jk;
         ba.h = in.h;
         ba.ecore = in.opt.ecore;
@@ -889,6 +1059,11 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.cnum = c_num;
         ba.cscore = c_score;
         bucket_accumulate<W>(ba, ar, s, prof, hs);
+        if (out.pt2) {
+            out.pt2_energy = out.pt2_energy + bucket_pt2(ba, ar, s, hs);
+            out.count += ba.V;
+            continue;
+        }
         const uint32_t V = ba.V;
         ctx->last_finals += ba.nfinal;
         ctx->last_levels = std::max<int64_t>(ctx->last_levels, ba.levels);
@@ -911,6 +1086,10 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
 
     ar.reset();
     (void)ar.take<char>(loop_mark);
+    if (out.pt2) {
+        ASCI_HIP(hipStreamSynchronize(s));
+        return;
+    }
     if (!topk) {
         out.count = (int64_t)pool_n;
         if (pool_n > (size_t)out.capacity) return;  // the caller reports ENOMEM
@@ -975,7 +1154,7 @@ void validate_dets(asci_ctx *ctx, const uint64_t *dets, int64_t ndets, int n, in
 }
 
 void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *dets, const double *coeffs,
-                         int64_t ndets, int64_t ncore, std::vector<uint64_t> &masks,
+                         int64_t ndets, const asci_options &opt, std::vector<uint64_t> &masks,
                          std::vector<uint64_t> &counts, hipStream_t s)
 {
     masks.clear();
@@ -987,13 +1166,14 @@ void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *d
                 counts.push_back(tot[c]);
             }
     };
+    const uint64_t no_fit = ~0ull;
     if (n <= 32) {
         Prepared<1> pp;
-        prepare<1>(ctx, nullptr, nullptr, n, na, nb, dets, coeffs, ndets, ncore, false, pp, s);
+        prepare<1>(ctx, nullptr, nullptr, n, na, nb, dets, coeffs, ndets, opt, no_fit, false, pp, s);
         collect(pp.cls, pp.totals);
     } else {
         Prepared<2> pp;
-        prepare<2>(ctx, nullptr, nullptr, n, na, nb, dets, coeffs, ndets, ncore, false, pp, s);
+        prepare<2>(ctx, nullptr, nullptr, n, na, nb, dets, coeffs, ndets, opt, no_fit, false, pp, s);
         collect(pp.cls, pp.totals);
     }
 }

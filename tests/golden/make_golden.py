@@ -4,8 +4,10 @@ For each named workload this stores E0 = <C|H|C> (oracle double loop) and, when
 the oracle can run the whole search in a few minutes, the exact facts of its
 result (Alg. 2 with the score of Eq. (1)): number of pairs, number of
 candidates, SHA-256 of the candidate keys / numerators / scores in ascending
-key order, SHA-256 of the top-k keys and scores in selection order, and the
-first entries of the top-k as hex floats.
+key order, SHA-256 of the top-k keys and scores in selection order, the
+first entries of the top-k as hex floats, and the second-order energy
+sum_a N_a^2 / (E0 - H_aa) over the candidates (compensated sum) with the sum
+of the absolute values of its terms.
 
     python tests/golden/make_golden.py 8e12o 16e20o 24e30o
 """
@@ -62,6 +64,9 @@ def main(names):
                 "topk_head": [[int(a), int(b), float(s).hex()] for (a, b), s in zip(tk[:16], ts[:16])],
                 "kth_abs_score": float(abs(ts[-1])).hex(),
             })
+            e2, ncand, s2 = oracle.pt2(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, with_abs=True)
+            out["pt2"] = e2.hex()
+            out["pt2_abs_terms"] = s2.hex()
         out["oracle_seconds"] = round(time.time() - t0, 1)
         with open(os.path.join(HERE, "search_%s.json" % name), "w") as f:
             json.dump(out, f, indent=1)

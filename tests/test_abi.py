@@ -29,6 +29,8 @@ def built_lib():
         mod = importlib.util.module_from_spec(spec)
         spec.loader.exec_module(mod)
         mod.build()
+    import torch  # noqa: F401  (torch's HIP runtime first: the library binds to it, see the package)
+
     return ctypes.CDLL(LIB)
 
 

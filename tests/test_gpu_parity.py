@@ -43,13 +43,15 @@ def _sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def _all_parity(asci, oracle_lib, c, E0, ncore=0, pair_buffer_bytes=0, eps=0.0):
+def _all_parity(asci, oracle_lib, c, E0, ncore=0, pair_buffer_bytes=0, eps=0.0, constraint_level=3, split_pairs=0):
     d = to_dev(c)
     n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
-    print("case n=%d na=%d nb=%d ndets=%d seed=%s ncore=%d buf=%d eps=%g" % (
-        n, na, nb, len(c["coeffs"]), c["seed"], ncore, pair_buffer_bytes, eps), flush=True)
+    print("case n=%d na=%d nb=%d ndets=%d seed=%s ncore=%d buf=%d eps=%g level=%d split=%d" % (
+        n, na, nb, len(c["coeffs"]), c["seed"], ncore, pair_buffer_bytes, eps, constraint_level, split_pairs),
+        flush=True)
     keys, num, score = asci.candidates(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, ncore=ncore,
-                                       pair_buffer_bytes=pair_buffer_bytes, eps=eps)
+                                       pair_buffer_bytes=pair_buffer_bytes, eps=eps,
+                                       constraint_level=constraint_level, split_pairs=split_pairs)
     want = oracle_lib.search_all(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, ncore=ncore, eps=eps)
     gk = host(keys)
     assert gk.shape == want["keys"].shape
@@ -272,6 +274,85 @@ def test_full_size_16e20o(asci, oracle_lib):
     assert (order == np.arange(len(gk))).all()
 
 
+LEVEL_CASES = [(12, 4, 4, 150, 31), (16, 6, 6, 300, 32), (34, 3, 2, 12, 33), (9, 2, 3, 30, 34), (14, 7, 1, 80, 35)]
+
+
+@pytest.mark.parametrize("level,split", [(1, 0), (2, 0), (4, 0), (5, 0), (6, 0), (6, 300), (5, 5000), (4, 1)])
+def test_constraint_levels_same_candidates(asci, oracle_lib, level, split):
+    """The classes only partition the targets (Sec. II.B): any level, uniform or
+    with only the heavy classes split, gives the oracle's candidates exactly."""
+    for n, na, nb, nd, seed in LEVEL_CASES:
+        c = _case(n, na, nb, nd, seed=seed, sampler="level")
+        E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+        _all_parity(asci, oracle_lib, c, E0, constraint_level=level, split_pairs=split)
+
+
+@pytest.mark.parametrize("level", [1, 2, 3, 4, 5, 6])
+def test_class_counts_by_level(asci, oracle_lib, level):
+    """Pair counts of the level-L classes (closed form on the GPU) equal the
+    oracle's enumeration."""
+    for n, na, nb, nd, seed in LEVEL_CASES[:3]:
+        c = _case(n, na, nb, nd, seed=seed, sampler="level")
+        d = to_dev(c)
+        gm, gc = asci.class_counts(n, na, nb, d["dets"], d["coeffs"], constraint_level=level)
+        wm, wc = oracle_lib.class_counts(n, na, nb, c["dets"], c["coeffs"], level=level)
+        assert (gm == wm).all() and (gc == wc).all()
+
+
+def test_heavy_classes_split_adaptively(asci, oracle_lib):
+    """split_pairs > 0: classes start as triplets and only the heavy ones are
+    refined, up to the maximum level; every final class has the oracle's count
+    at its own level, and a class left unsplit below the maximum is light."""
+    n, na, nb, nd, seed = LEVEL_CASES[1]
+    c = _case(n, na, nb, nd, seed=seed, sampler="level")
+    d = to_dev(c)
+    split = 4000
+    gm, gc = asci.class_counts(n, na, nb, d["dets"], d["coeffs"], constraint_level=6, split_pairs=split)
+    assert gc.sum() == nd * oracle_lib.sd_count(n, na, nb)
+    assert (np.diff(gm.astype(np.float64)) > 0).all()
+    want = {lv: dict(zip(*[a.tolist() for a in oracle_lib.class_counts(n, na, nb, c["dets"], c["coeffs"],
+                                                                      level=lv)])) for lv in range(3, 7)}
+    levels = set()
+    for m, k in zip(gm.tolist(), gc.tolist()):
+        lv = bin(m).count("1")
+        levels.add(lv)
+        assert want[lv][m] == k
+        if lv < 6:
+            assert k <= split
+    assert levels == {3, 4, 5, 6}
+    # refining never makes the partition coarser (the paper's Fig. 3 trend); the
+    # heaviest class here is a single alpha string, which no constraint divides
+    st3 = asci.class_skew(asci.class_counts(n, na, nb, d["dets"], d["coeffs"])[1], npes=(64,))
+    sta = asci.class_skew(gc, npes=(64,))
+    assert sta["classes"] > st3["classes"]
+    assert sta["largest_share"] <= st3["largest_share"]
+    assert sta["imbalance"][64] <= st3["imbalance"][64]
+
+
+def test_class_larger_than_pair_buffer_is_split(asci, oracle_lib):
+    """A triplet class bigger than the whole pair buffer is split further
+    automatically; the candidates do not change."""
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    m, k = oracle_lib.class_counts(12, 4, 4, c["dets"], c["coeffs"])
+    big = int(k.max())
+    _all_parity(asci, oracle_lib, c, E0, pair_buffer_bytes=32 * (big // 3))
+
+
+@pytest.mark.parametrize("level,split", [(6, 0), (6, 1 << 18)])
+def test_full_size_16e20o_levels(asci, level, split):
+    """The bench workload with hextuplet classes (18,564 of them, about ten
+    class batches) and with only the heavy triplets split: same candidates."""
+    c = syn.workload("16e20o")
+    g = _golden("16e20o")
+    d = to_dev(c)
+    keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], float.fromhex(g["E0"]),
+                                       constraint_level=level, split_pairs=split)
+    assert _sha(host(keys)) == g["cand_keys_sha256"]
+    assert _sha(host(num)) == g["cand_num_sha256"]
+    assert _sha(host(score)) == g["cand_score_sha256"]
+
+
 def test_full_size_16e20o_multi_batch(asci, oracle_lib):
     """The bench workload split into about five class batches (a forced pair
     buffer of 1 GiB): the top-k must not change."""
@@ -333,3 +414,50 @@ def test_one_target_from_more_cores_than_fit_in_lds(asci, oracle_lib):
     gk, gs = asci.search(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, 1000)
     order = np.lexsort((host(gk)[:, 1], host(gk)[:, 0], -np.abs(host(gs))))
     assert (order == np.arange(len(order))).all()
+
+
+def _pt2_case(asci, oracle_lib, c, E0, **kw):
+    d = to_dev(c)
+    n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
+    e, cnt = asci.pt2(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, **kw)
+    we, wc, sabs = oracle_lib.pt2(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, with_abs=True,
+                                  **{k: v for k, v in kw.items() if k != "pair_buffer_bytes"})
+    assert cnt == wc
+    assert abs(e - we) <= pt2_tol(we, sabs)
+    return e, pt2_tol(we, sabs)
+
+
+def pt2_tol(exact, sabs):
+    """The terms N_a * A_a are bit-identical on both sides; the GPU adds them in
+    segments of at most 4096 candidates, then adds the segment sums (a few per
+    thread, then a 1024-wide tree, then the batches), so its error is at most
+    about (4096 + 2048) u S with S the sum of |terms| (Higham, ch. 4); the
+    oracle's compensated sum is exact to 2u|E|."""
+    u = 2.0 ** -53
+    return 6144 * u * sabs + 2 * u * abs(exact)
+
+
+def test_pt2_energy(asci, oracle_lib):
+    """E_PT2 = sum_a N_a^2 / (E0 - H_aa): the candidates and every term are
+    exact, only the order of the additions differs (bound in pt2_tol)."""
+    c = syn.workload("8e12o")
+    E0 = float.fromhex(_golden("8e12o")["E0"])
+    e1, tol = _pt2_case(asci, oracle_lib, c, E0)
+    e2, _ = _pt2_case(asci, oracle_lib, c, E0, pair_buffer_bytes=1 << 18)
+    assert abs(e1 - e2) <= 2 * tol
+    _pt2_case(asci, oracle_lib, c, E0, eps=1e-4)
+    _pt2_case(asci, oracle_lib, c, E0, ncore=40)
+    for (n, na, nb, nd) in [(6, 3, 3, 12), (9, 4, 2, 30), (34, 3, 2, 10)]:
+        cc = _case(n, na, nb, nd, seed=900 + n)
+        E0 = oracle_lib.energy(cc["h"], cc["eri"], cc["dets"], cc["coeffs"])
+        _pt2_case(asci, oracle_lib, cc, E0)
+
+
+def test_pt2_energy_16e20o(asci):
+    c = syn.workload("16e20o")
+    g = _golden("16e20o")
+    d = to_dev(c)
+    e, cnt = asci.pt2(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], float.fromhex(g["E0"]))
+    assert cnt == g["ncandidates"]
+    want = float.fromhex(g["pt2"])
+    assert abs(e - want) <= pt2_tol(want, float.fromhex(g["pt2_abs_terms"]))

@@ -208,26 +208,52 @@ def test_topk_equals_library_sort(oracle_lib):
     assert len(oracle_lib.topk_index(keys, score, 0)) == 0
 
 
-def test_class_counts_match_classification(oracle_lib):
+@pytest.mark.parametrize("level", [1, 2, 3, 4, 5, 6])
+def test_class_counts_match_classification(oracle_lib, level):
+    """Every pair lands in the class of its target's top-`level` alpha orbitals;
+    the classes are disjoint and cover all pairs (Sec. II.B)."""
     n, na, nb = 9, 4, 3
     rng = np.random.default_rng(21)
     dets = [syn.aufbau(n, na, nb)] + syn.uniform_dets(n, na, nb, 30, rng, exclude=(syn.aufbau(n, na, nb),))
     dets = np.array(dets, dtype=np.uint64)
     C = syn.coefficients(len(dets), 5.0, rng)
 
-    def top3(a):
-        bits = [p for p in range(63, -1, -1) if (a >> p) & 1][:3]
+    def top(a):
+        bits = [p for p in range(63, -1, -1) if (a >> p) & 1][:level]
         return sum(1 << p for p in bits)
 
     from collections import Counter
     want = Counter()
     for a, b in dets.tolist():
         for t in oracle_lib.sd_targets(n, a, b).tolist():
-            want[top3(t[0])] += 1
-    masks, counts = oracle_lib.class_counts(n, na, nb, dets, C)
+            want[top(t[0])] += 1
+    masks, counts = oracle_lib.class_counts(n, na, nb, dets, C, level=level)
     assert list(masks) == sorted(want)
     assert [want[m] for m in masks.tolist()] == list(counts)
     assert counts.sum() == len(dets) * oracle_lib.sd_count(n, na, nb)
+
+
+def test_higher_level_classes_refine_lower_ones(oracle_lib):
+    """A level-(L+1) class lies inside the level-L class of its top L orbitals,
+    so its counts add up to the parent's (the split of a heavy class)."""
+    c = syn.workload("8e12o")
+    prev = None
+    for level in range(1, 7):
+        masks, counts = oracle_lib.class_counts(12, 4, 4, c["dets"], c["coeffs"], level=level)
+        assert (np.diff(masks.astype(np.float64)) > 0).all()
+        if prev is not None:
+            pm, pc = prev
+            parent = {}
+            for m, k in zip(masks.tolist(), counts.tolist()):
+                bits = [p for p in range(63, -1, -1) if (m >> p) & 1][:level - 1]
+                key = sum(1 << p for p in bits)
+                parent[key] = parent.get(key, 0) + k
+            assert parent == dict(zip(pm.tolist(), pc.tolist()))
+        prev = (masks, counts)
+    # level >= n_alpha: one class per alpha string, the strings targets reach
+    from math import comb
+
+    assert len(prev[0]) <= comb(12, 4)
 
 
 def test_eps_screening_matches_dense_filter(oracle_lib):
@@ -270,3 +296,62 @@ def test_invalid_inputs_rejected(oracle_lib):
     out_of_range[1, 1] = (1 << 5) | 1
     with pytest.raises(ValueError):
         oracle_lib.search_all(h, eri, 5, 2, 2, out_of_range, C, 0.0)
+
+
+@pytest.mark.parametrize("n,na,nb,ndets", [(5, 2, 2, 6), (6, 3, 3, 15), (6, 2, 3, 10)])
+def test_pt2_equals_dense_epstein_nesbet(oracle_lib, n, na, nb, ndets):
+    """E_PT2 = sum_{a not in psi} (H C)_a^2 / (E0 - H_aa), from the dense H."""
+    h, eri, dets, C = _tiny_case(n, na, nb, ndets, seed=70 + n + ndets)
+    space, H = bf.dense_h(h, eri, n, na, nb)
+    index = {d: i for i, d in enumerate(space)}
+    psi = [index[(int(a), int(b))] for a, b in dets]
+    v = np.zeros(len(space))
+    v[psi] = C
+    E0 = float(v @ H @ v)
+    sigma = H @ v
+    mask = np.ones(len(space), bool)
+    mask[psi] = False
+    conn = np.abs(H[:, psi]).sum(axis=1) > 0
+    sel = mask & conn
+    want = float(np.sum(sigma[sel] ** 2 / (E0 - np.diag(H)[sel])))
+    got, cnt = oracle_lib.pt2(h, eri, n, na, nb, dets, C, E0)
+    assert got == pytest.approx(want, rel=1e-11, abs=1e-13)
+    assert cnt == len(oracle_lib.search_all(h, eri, n, na, nb, dets, C, E0)["keys"])
+
+
+def test_pt2_compensated_sum_is_the_exact_sum(oracle_lib):
+    """The oracle's compensated PT2 sum equals the correctly rounded sum of its
+    terms (math.fsum) to within 2u|E|, and S is the sum of their magnitudes."""
+    import math
+
+    c = syn.workload("8e12o")
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    r = oracle_lib.search_all(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0)
+    terms = r["num"] * r["score"]
+    e, cnt, sabs = oracle_lib.pt2(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, with_abs=True)
+    exact = math.fsum(terms.tolist())
+    assert cnt == len(terms)
+    assert abs(e - exact) <= 2.3e-16 * abs(exact)
+    assert sabs == pytest.approx(math.fsum(np.abs(terms).tolist()), rel=1e-12)
+
+
+@pytest.mark.parametrize("npe", [1, 3, 8, 64])
+def test_balance_invariants(oracle_lib, npe):
+    """Alg. 3 (greedy list scheduling): work is conserved, the first npe
+    non-empty classes land on distinct elements, and the largest load obeys
+    Graham's bound max <= total/npe + max class (a missing load update, an
+    arg-max or a dropped class breaks one of these)."""
+    rng = np.random.default_rng(npe)
+    counts = rng.integers(0, 1000, 300) * (rng.random(300) < 0.8)
+    counts[5] = 50_000  # one heavy class
+    owner, work = oracle_lib.balance(counts, npe)
+    nz = counts > 0
+    assert (owner[~nz] == -1).all() and (owner[nz] >= 0).all() and (owner < npe).all()
+    assert work.sum() == counts.sum()
+    assert (np.bincount(owner[nz], weights=counts[nz], minlength=npe) == work).all()
+    first = owner[nz][:npe]
+    assert len(set(first.tolist())) == len(first)
+    assert work.max() <= counts.sum() / npe + counts.max()
+    # the heavy class is indivisible: with many elements it sets the maximum
+    if npe >= 64:
+        assert work.max() == 50_000

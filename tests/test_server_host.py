@@ -78,3 +78,27 @@ def test_fifo_admission_order():
     srv.close()
     lat = [r.latency_ms for r in res]
     assert lat == sorted(lat)
+
+
+def test_balance_equals_oracle(oracle_lib):
+    """The library's Alg. 3 (heap arg-min) equals the oracle's linear scan."""
+    import numpy as np
+
+    rng = np.random.default_rng(3)
+    for npe in (1, 2, 7, 64, 1000):
+        counts = rng.integers(0, 50, 500) * (rng.random(500) < 0.7)
+        counts[rng.integers(0, 500, 20)] = 7  # ties in the loads
+        got_o, got_w = asci.balance_classes(counts, npe)
+        want_o, want_w = oracle_lib.balance(counts, npe)
+        assert (got_o == want_o).all() and (got_w == want_w).all()
+    with pytest.raises(asci.AsciError):
+        asci.balance_classes([1, -1], 2)
+
+
+def test_class_skew_statistics():
+    counts = [0, 10, 10, 10, 70]
+    st = asci.class_skew(counts, npes=(1, 2, 4))
+    assert st["classes"] == 4 and st["pairs"] == 100
+    assert st["largest_share"] == 0.7
+    assert st["imbalance"][1] == 1.0
+    assert st["imbalance"][4] == 70 / 25
