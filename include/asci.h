@@ -214,6 +214,93 @@ int asci_energy_device(asci_ctx *ctx, const double *d_h, const double *d_eri, in
                        int64_t ndets, double ecore, double *out_energy, void *stream);
 
 /* ------------------------------------------------------------------------
+ * The variational step and the ASCI loop (Alg. 1, Sec. II.C).
+ * ------------------------------------------------------------------------ */
+
+/* Hamiltonian over a determinant set, built by the double loop over
+ * determinant pairs (Sec. II.C) and stored as CSR on the device: row i is
+ * determinant i of the set, columns ascending, both triangles and the
+ * diagonal stored; H_ij = <D_i|H|D_j> by the Slater-Condon rules with the
+ * phase convention of the search, H_ii including ecore.  The object owns its
+ * device memory until asci_hmat_destroy. */
+typedef struct asci_hmat asci_hmat;
+
+/* d_h, d_eri, d_dets: device.  Errors: ASCI_EINVAL (bad sizes, invalid
+ * determinants), ASCI_ENOMEM, ASCI_EDEVICE.  The set should hold distinct
+ * determinants (a repeated one gives repeated rows). */
+int asci_hmat_build_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha,
+                           int nbeta, const uint64_t *d_dets, int64_t ndets, double ecore, asci_hmat **out,
+                           void *stream);
+int asci_hmat_info(const asci_hmat *H, int64_t *nrows, int64_t *nnz);
+/* Copy the CSR arrays into caller-owned device buffers (nrows + 1, nnz, nnz). */
+int asci_hmat_export(const asci_hmat *H, int64_t *d_rowptr, int32_t *d_cols, double *d_vals, void *stream);
+/* d_y = H d_x (device vectors of length nrows). */
+int asci_hmat_matvec_device(const asci_hmat *H, const double *d_x, double *d_y, void *stream);
+void asci_hmat_destroy(asci_hmat *H);
+
+/* Lowest eigenpair of H by the Davidson method of Alg. 5 with the
+ * shifted-Jacobi preconditioner (D - theta)^-1 (D = diag H).  d_guess: device
+ * start vector (NULL = the unit vector of the lowest diagonal element).  A full
+ * subspace (max_subspace in [2, 48]) restarts from the current Ritz vector.
+ * Stops when |H u - theta u| <= tol or after max_iter iterations.  Writes the
+ * Ritz value, the unit Ritz vector d_vec (device, nrows), the residual norm
+ * and the iterations used. */
+int asci_davidson_device(asci_ctx *ctx, const asci_hmat *H, const double *d_guess, int32_t max_subspace,
+                         int32_t max_iter, double tol, double *out_energy, double *d_vec, double *out_resid,
+                         int32_t *out_iters, void *stream);
+
+typedef struct asci_loop_options {
+    int64_t ncore;              /* N_cdets: core determinants of every search (0 = all of psi_k) */
+    int64_t ntdets;             /* N_tdets: size of the next determinant set               */
+    int32_t max_iter;           /* outer iterations of Alg. 1                              */
+    double e_tol;               /* stop when |E_{k+1} - E_k| < e_tol                       */
+    int32_t davidson_subspace;  /* largest Davidson subspace, in [2, 48]                   */
+    int32_t davidson_max_iter;  /* Davidson iterations per solve                           */
+    double davidson_tol;        /* residual norm of a converged Ritz pair                  */
+    int32_t pt2;                /* 1: final PT2 step on the last set (exact, eps = 0)      */
+    asci_options search;        /* eps, constraint classes, ecore, pair buffer; its ncore is
+                                   replaced by the field above                             */
+} asci_loop_options;
+
+/* One outer iteration: sizes, energy and the host wall time of each phase. */
+typedef struct asci_loop_iter {
+    int64_t ndets;       /* size of psi_{k+1}                */
+    int64_t candidates;  /* candidates of the search         */
+    int64_t nnz;         /* nonzeros of H over psi_{k+1}     */
+    double energy;       /* E_{k+1}, lowest Ritz value       */
+    double davidson_resid;
+    int32_t davidson_iters;
+    double search_ms, select_ms, hbuild_ms, davidson_ms;
+} asci_loop_iter;
+
+/* Defaults: ncore 0, ntdets 1000, max_iter 10, e_tol 1e-6, Davidson subspace
+ * 24, 200 iterations, tol 1e-8, pt2 0, search options as asci_options_default. */
+void asci_loop_options_default(asci_loop_options *opt);
+
+/* One iteration of Alg. 1 from psi_k = (d_dets, d_coeffs) with energy Ek:
+ * search (top N_tdets new determinants by |A|), selection of psi_{k+1} = the
+ * N_tdets entries of largest score among psi_k (score |C_i|) and the new ones
+ * (score |A_a|), ties by key ascending, stored in that order; H over psi_{k+1}
+ * and Davidson (guess: C_k on the kept determinants, zero elsewhere).  Outputs
+ * (device, capacity ntdets): the set, its coefficients; *out_ndets and *info
+ * (host).  C_k should be normalised. */
+int asci_loop_step_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                          const uint64_t *d_dets, const double *d_coeffs, int64_t ndets, double Ek,
+                          const asci_loop_options *opt, uint64_t *d_out_dets, double *d_out_coeffs,
+                          int64_t *out_ndets, asci_loop_iter *info, void *stream);
+
+/* Alg. 1 from a starting set (e.g. the Hartree-Fock determinant with C = 1):
+ * E_0 = <C|H|C>, then iterations until |E_{k+1} - E_k| < e_tol or max_iter,
+ * then the optional PT2 step.  Outputs: the final set and coefficients (device,
+ * capacity max(ntdets, n0)), *out_ndets, *out_energy, *out_pt2 (0 without the
+ * PT2 step), per-iteration records iters[0 .. *out_iters) (host, capacity
+ * max_iter). */
+int asci_run_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                    const uint64_t *d_dets0, const double *d_coeffs0, int64_t ndets0, const asci_loop_options *opt,
+                    uint64_t *d_out_dets, double *d_out_coeffs, int64_t *out_ndets, double *out_energy,
+                    double *out_pt2, asci_loop_iter *iters, int32_t *out_iters, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched and served searches.
  *
  * A request names device buffers that stay resident (integrals, determinant

@@ -78,6 +78,8 @@ def lib():
         L.oracle_target_numerators.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_double, up, dp,
                                                C.c_int64, C.c_int64, up, C.c_int64, dp, dp,
                                                C.POINTER(C.c_int), ip]
+        L.oracle_hmat_dense.restype = C.c_int
+        L.oracle_hmat_dense.argtypes = [dp, dp, C.c_int, C.c_double, up, C.c_int64, dp]
         L.oracle_balance.restype = C.c_int
         L.oracle_balance.argtypes = [ip, C.c_int64, C.c_int, C.POINTER(C.c_int), ip]
         _lib = L
@@ -258,3 +260,59 @@ def balance(counts, npe):
     if rc != 0:
         raise ValueError("oracle_balance failed with code %d" % rc)
     return owner, work
+
+
+# ---------------------------------------------------------------- the ASCI loop (Alg. 1)
+
+def hamiltonian(h, eri, dets, ecore=0.0):
+    """Dense H over a determinant set by the plain double loop (Sec. II.C):
+    <D_i|H|D_j> where the two differ by at most a double excitation, else 0."""
+    keep, hp, ep, n = _ham(h, eri)
+    d, dp = _u(dets)
+    nd = len(d)
+    out = np.zeros((nd, nd))
+    lib().oracle_hmat_dense(hp, ep, n, float(ecore), dp, nd, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out
+
+
+def lowest(H):
+    """Lowest eigenpair of a dense symmetric matrix (LAPACK through numpy)."""
+    w, v = np.linalg.eigh(H)
+    return float(w[0]), v[:, 0]
+
+
+def select_next(dets, coeffs, cand, cand_scores, ntdets):
+    """Alg. 1's selection: the ntdets entries of largest score over psi_k
+    (score |C_i|) and the new determinants (score |A_a|), ties by (alpha, beta)
+    ascending, in that order.  Returns (dets, guess coefficients) where the
+    guess is C_i on kept determinants and 0 on new ones."""
+    dets = np.asarray(dets, dtype=np.uint64).reshape(-1, 2)
+    cand = np.asarray(cand, dtype=np.uint64).reshape(-1, 2)
+    allk = np.concatenate([dets, cand])
+    score = np.concatenate([np.abs(np.asarray(coeffs, float)), np.abs(np.asarray(cand_scores, float))])
+    guess = np.concatenate([np.asarray(coeffs, float), np.zeros(len(cand))])
+    # compare |score| by its IEEE bits, as the selection of the search does
+    ordkey = score.view(np.uint64)
+    order = np.lexsort((allk[:, 1], allk[:, 0], ~ordkey))[:ntdets]
+    return allk[order], guess[order]
+
+
+def asci_loop(h, eri, norb, nalpha, nbeta, dets0, coeffs0, ntdets, ncore=0, max_iter=10, e_tol=1e-6, eps=0.0,
+              ecore=0.0):
+    """Alg. 1 with the oracle search, the double-loop H and a dense
+    eigensolver: returns the list of (dets, coeffs, energy) per iteration,
+    starting with the input set and E_0 = <C|H|C>."""
+    dets = np.asarray(dets0, dtype=np.uint64).reshape(-1, 2)
+    C = np.asarray(coeffs0, dtype=float)
+    E = energy(h, eri, dets, C, ecore)
+    hist = [(dets, C, E)]
+    for _ in range(max_iter):
+        cand, sc = search(h, eri, norb, nalpha, nbeta, dets, C, E, ntdets, ncore=ncore, eps=eps, ecore=ecore)
+        nd, guess = select_next(dets, C, cand, sc, ntdets)
+        Enew, Cnew = lowest(hamiltonian(h, eri, nd, ecore))
+        hist.append((nd, Cnew, Enew))
+        done = abs(Enew - E) < e_tol
+        dets, C, E = nd, Cnew, Enew
+        if done:
+            break
+    return hist

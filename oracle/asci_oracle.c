@@ -651,3 +651,20 @@ int oracle_balance(const int64_t *counts, int64_t nclasses, int npe, int *owner,
     }
     return ORACLE_OK;
 }
+
+/* ---- Hamiltonian over a determinant set by the double loop (Sec. II.C) ----
+ * out (nd x nd, row-major) gets <D_i|H|D_j> for every pair that differs by at
+ * most a double excitation and 0 elsewhere; H_ii includes ecore. */
+int oracle_hmat_dense(const double *h, const double *eri, int n, double ecore, const uint64_t *dets, int64_t nd,
+                      double *out)
+{
+    for (int64_t i = 0; i < nd; ++i)
+        for (int64_t j = 0; j < nd; ++j) {
+            uint64_t da = dets[2 * i] ^ dets[2 * j], db = dets[2 * i + 1] ^ dets[2 * j + 1];
+            out[i * nd + j] = (popc(da) + popc(db) > 4)
+                                  ? 0.0
+                                  : oracle_helem(h, eri, n, ecore, dets[2 * i], dets[2 * i + 1], dets[2 * j],
+                                                 dets[2 * j + 1]);
+        }
+    return ORACLE_OK;
+}

@@ -36,6 +36,21 @@ class Options(C.Structure):
                 ("ecore", C.c_double), ("pair_buffer_bytes", C.c_int64), ("split_pairs", C.c_int64)]
 
 
+class LoopOptions(C.Structure):
+    _fields_ = [("ncore", C.c_int64), ("ntdets", C.c_int64), ("max_iter", C.c_int32), ("e_tol", C.c_double),
+                ("davidson_subspace", C.c_int32), ("davidson_max_iter", C.c_int32), ("davidson_tol", C.c_double),
+                ("pt2", C.c_int32), ("search", Options)]
+
+
+class LoopIter(C.Structure):
+    _fields_ = [("ndets", C.c_int64), ("candidates", C.c_int64), ("nnz", C.c_int64), ("energy", C.c_double),
+                ("davidson_resid", C.c_double), ("davidson_iters", C.c_int32), ("search_ms", C.c_double),
+                ("select_ms", C.c_double), ("hbuild_ms", C.c_double), ("davidson_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Request(C.Structure):
     _fields_ = [("h", C.c_void_p), ("eri", C.c_void_p), ("norb", C.c_int), ("nalpha", C.c_int),
                 ("nbeta", C.c_int), ("dets", C.c_void_p), ("coeffs", C.c_void_p), ("ndets", C.c_int64),
@@ -81,6 +96,22 @@ _lib.asci_pt2_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, 
 _lib.asci_energy_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
                                     _dp, _vp]
 _lib.asci_balance_classes.argtypes = [_ip, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _ip]
+_lib.asci_hmat_build_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, C.c_int64, C.c_double,
+                                        C.POINTER(C.c_void_p), _vp]
+_lib.asci_hmat_info.argtypes = [_vp, _ip, _ip]
+_lib.asci_hmat_export.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.asci_hmat_matvec_device.argtypes = [_vp, _vp, _vp, _vp]
+_lib.asci_hmat_destroy.restype = None
+_lib.asci_hmat_destroy.argtypes = [_vp]
+_lib.asci_davidson_device.argtypes = [_vp, _vp, _vp, C.c_int32, C.c_int32, C.c_double, _dp, _vp, _dp,
+                                      C.POINTER(C.c_int32), _vp]
+_lib.asci_loop_options_default.restype = None
+_lib.asci_loop_options_default.argtypes = [C.POINTER(LoopOptions)]
+_lib.asci_loop_step_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
+                                       C.POINTER(LoopOptions), _vp, _vp, _ip, C.POINTER(LoopIter), _vp]
+_lib.asci_run_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64,
+                                 C.POINTER(LoopOptions), _vp, _vp, _ip, _dp, _dp, C.POINTER(LoopIter),
+                                 C.POINTER(C.c_int32), _vp]
 
 _lib.asci_ctx_set_profiling.argtypes = [_vp, C.c_int]
 _lib.asci_ctx_set_param.argtypes = [_vp, C.c_char_p, C.c_int64]
@@ -105,7 +136,9 @@ EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_def
            "asci_ctx_destroy", "asci_ctx_set_param", "asci_ctx_get_param", "asci_ctx_set_profiling",
            "asci_ctx_profile_entry", "asci_search",
            "asci_search_device", "asci_candidates_device", "asci_pt2_device", "asci_class_counts_device",
-           "asci_energy_device", "asci_balance_classes",
+           "asci_energy_device", "asci_balance_classes", "asci_hmat_build_device", "asci_hmat_info",
+           "asci_hmat_export", "asci_hmat_matvec_device", "asci_hmat_destroy", "asci_davidson_device",
+           "asci_loop_options_default", "asci_loop_step_device", "asci_run_device",
            "asci_request_footprint", "asci_search_batch", "asci_autotune", "asci_server_create",
            "asci_server_create_fake", "asci_server_submit", "asci_server_footprint", "asci_server_poll",
            "asci_server_wait",
@@ -454,3 +487,112 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- variational step and the ASCI loop
+
+
+class HMat:
+    """H over a determinant set (device CSR built by the double loop)."""
+
+    def __init__(self, h, eri, norb, nalpha, nbeta, dets, ecore=0.0, ctx=None):
+        torch = _torch()
+        dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+        self.ctx = ctx or Context.get(dev)
+        self.device = h.device
+        self._dev = dev
+        dets = _dets_tensor(dets)
+        self.ptr = C.c_void_p()
+        _check(_lib.asci_hmat_build_device(self.ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb,
+                                           nalpha, nbeta, _dev(dets, torch.uint64), dets.shape[0], float(ecore),
+                                           C.byref(self.ptr), _stream(dev)))
+        nr, nz = C.c_int64(), C.c_int64()
+        _check(_lib.asci_hmat_info(self.ptr, C.byref(nr), C.byref(nz)))
+        self.nrows, self.nnz = nr.value, nz.value
+
+    def export(self):
+        """(rowptr int64[n+1], cols int32[nnz], vals float64[nnz]) device tensors."""
+        torch = _torch()
+        rp = torch.empty(self.nrows + 1, dtype=torch.int64, device=self.device)
+        cols = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        vals = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.device)
+        _check(_lib.asci_hmat_export(self.ptr, rp.data_ptr(), cols.data_ptr(), vals.data_ptr(), _stream(self._dev)))
+        return rp, cols[: self.nnz], vals[: self.nnz]
+
+    def matvec(self, x):
+        torch = _torch()
+        y = torch.empty(self.nrows, dtype=torch.float64, device=self.device)
+        _check(_lib.asci_hmat_matvec_device(self.ptr, _dev(x, torch.float64), y.data_ptr(), _stream(self._dev)))
+        return y
+
+    def close(self):
+        if self.ptr:
+            _lib.asci_hmat_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def davidson(H, guess=None, max_subspace=24, max_iter=200, tol=1e-8):
+    """Lowest eigenpair of an HMat (Alg. 5, shifted-Jacobi preconditioner):
+    (energy, vector tensor, residual norm, iterations)."""
+    torch = _torch()
+    vec = torch.empty(H.nrows, dtype=torch.float64, device=H.device)
+    e, r, it = C.c_double(), C.c_double(), C.c_int32()
+    g = _dev(guess, torch.float64) if guess is not None else None
+    _check(_lib.asci_davidson_device(H.ctx.ptr, H.ptr, g, int(max_subspace), int(max_iter), float(tol), C.byref(e),
+                                     vec.data_ptr(), C.byref(r), C.byref(it), _stream(H._dev)))
+    return e.value, vec, r.value, it.value
+
+
+def loop_options(ntdets, ncore=0, max_iter=10, e_tol=1e-6, davidson_subspace=24, davidson_max_iter=200,
+                 davidson_tol=1e-8, pt2=False, eps=0.0, ecore=0.0, constraint_level=3, split_pairs=0,
+                 pair_buffer_bytes=0):
+    o = LoopOptions()
+    _lib.asci_loop_options_default(C.byref(o))
+    o.ncore, o.ntdets, o.max_iter, o.e_tol = int(ncore), int(ntdets), int(max_iter), float(e_tol)
+    o.davidson_subspace, o.davidson_max_iter = int(davidson_subspace), int(davidson_max_iter)
+    o.davidson_tol, o.pt2 = float(davidson_tol), int(bool(pt2))
+    o.search = options(0, eps, ecore, pair_buffer_bytes, constraint_level, split_pairs)
+    return o
+
+
+def loop_step(h, eri, norb, nalpha, nbeta, dets, coeffs, Ek, opts, ctx=None):
+    """One iteration of Alg. 1: (dets, coeffs, info dict) of psi_{k+1}."""
+    torch = _torch()
+    dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or Context.get(dev)
+    dets = _dets_tensor(dets)
+    out_d = torch.empty((opts.ntdets, 2), dtype=torch.uint64, device=h.device)
+    out_c = torch.empty(opts.ntdets, dtype=torch.float64, device=h.device)
+    nn = C.c_int64()
+    info = LoopIter()
+    _check(_lib.asci_loop_step_device(ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha,
+                                      nbeta, _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0],
+                                      float(Ek), C.byref(opts), out_d.data_ptr(), out_c.data_ptr(), C.byref(nn),
+                                      C.byref(info), _stream(dev)))
+    return out_d[: nn.value], out_c[: nn.value], info.as_dict()
+
+
+def run(h, eri, norb, nalpha, nbeta, dets0, coeffs0, opts, ctx=None):
+    """Alg. 1 from (dets0, coeffs0): dict with dets, coeffs (device), energy,
+    pt2 and the per-iteration records."""
+    torch = _torch()
+    dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or Context.get(dev)
+    dets0 = _dets_tensor(dets0)
+    cap = max(int(opts.ntdets), dets0.shape[0])
+    out_d = torch.empty((cap, 2), dtype=torch.uint64, device=h.device)
+    out_c = torch.empty(cap, dtype=torch.float64, device=h.device)
+    nn, e, p, ni = C.c_int64(), C.c_double(), C.c_double(), C.c_int32()
+    recs = (LoopIter * max(1, int(opts.max_iter)))()
+    _check(_lib.asci_run_device(ctx.ptr, _dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
+                                _dev(dets0, torch.uint64), _dev(coeffs0, torch.float64), dets0.shape[0],
+                                C.byref(opts), out_d.data_ptr(), out_c.data_ptr(), C.byref(nn), C.byref(e),
+                                C.byref(p), recs, C.byref(ni), _stream(dev)))
+    return {"dets": out_d[: nn.value], "coeffs": out_c[: nn.value], "energy": e.value, "pt2": p.value,
+            "iterations": [recs[i].as_dict() for i in range(ni.value)]}

@@ -299,6 +299,185 @@ int asci_pt2_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     }
 }
 
+// ---------------------------------------------------------------- variational step and loop
+struct asci_hmat {
+    asci::HMat H;
+};
+
+int asci_hmat_build_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha,
+                           int nbeta, const uint64_t *d_dets, int64_t ndets, double ecore, asci_hmat **out,
+                           void *stream)
+{
+    try {
+        require(ctx && d_h && d_eri && d_dets && out, ASCI_EINVAL, "null pointer argument");
+        check_common(norb, nalpha, nbeta, ndets);
+        ASCI_HIP(hipSetDevice(ctx->device));
+        std::unique_ptr<asci_hmat> m(new asci_hmat);
+        hmat_build(ctx, d_h, d_eri, norb, nalpha, nbeta, d_dets, ndets, ecore, m->H, (hipStream_t)stream);
+        *out = m.release();
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_hmat_info(const asci_hmat *H, int64_t *nrows, int64_t *nnz)
+{
+    try {
+        require(H && nrows && nnz, ASCI_EINVAL, "null pointer argument");
+        *nrows = H->H.nrows;
+        *nnz = H->H.nnz;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_hmat_export(const asci_hmat *H, int64_t *d_rowptr, int32_t *d_cols, double *d_vals, void *stream)
+{
+    try {
+        require(H && d_rowptr && d_cols && d_vals, ASCI_EINVAL, "null pointer argument");
+        ASCI_HIP(hipSetDevice(H->H.device));
+        const hipStream_t s = (hipStream_t)stream;
+        ASCI_HIP(hipMemcpyAsync(d_rowptr, H->H.rowptr, (size_t)(H->H.nrows + 1) * sizeof(int64_t),
+                                hipMemcpyDeviceToDevice, s));
+        if (H->H.nnz) {
+            ASCI_HIP(hipMemcpyAsync(d_cols, H->H.cols, (size_t)H->H.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            ASCI_HIP(hipMemcpyAsync(d_vals, H->H.vals, (size_t)H->H.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        ASCI_HIP(hipStreamSynchronize(s));
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_hmat_matvec_device(const asci_hmat *H, const double *d_x, double *d_y, void *stream)
+{
+    try {
+        require(H && d_x && d_y, ASCI_EINVAL, "null pointer argument");
+        ASCI_HIP(hipSetDevice(H->H.device));
+        hmat_matvec(H->H, d_x, d_y, (hipStream_t)stream);
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+void asci_hmat_destroy(asci_hmat *H) { delete H; }
+
+int asci_davidson_device(asci_ctx *ctx, const asci_hmat *H, const double *d_guess, int32_t max_subspace,
+                         int32_t max_iter, double tol, double *out_energy, double *d_vec, double *out_resid,
+                         int32_t *out_iters, void *stream)
+{
+    try {
+        require(ctx && H && out_energy && d_vec && out_resid && out_iters, ASCI_EINVAL, "null pointer argument");
+        require(max_subspace >= 2 && max_subspace <= 48, ASCI_EINVAL, "max_subspace must be in [2, 48]");
+        require(max_iter >= 1 && tol >= 0.0, ASCI_EINVAL, "max_iter must be >= 1 and tol >= 0");
+        require(H->H.device == ctx->device, ASCI_EINVAL, "matrix and context on different devices");
+        ASCI_HIP(hipSetDevice(ctx->device));
+        DavidsonOpts o;
+        o.max_subspace = max_subspace;
+        o.max_iter = max_iter;
+        o.tol = tol;
+        const DavidsonOut r = davidson(ctx, H->H, d_guess, o, d_vec, (hipStream_t)stream);
+        *out_energy = r.energy;
+        *out_resid = r.resid;
+        *out_iters = r.iters;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+void asci_loop_options_default(asci_loop_options *opt)
+{
+    if (!opt) return;
+    opt->ncore = 0;
+    opt->ntdets = 1000;
+    opt->max_iter = 10;
+    opt->e_tol = 1e-6;
+    opt->davidson_subspace = 24;
+    opt->davidson_max_iter = 200;
+    opt->davidson_tol = 1e-8;
+    opt->pt2 = 0;
+    asci_options_default(&opt->search);
+}
+
+static LoopArgs loop_args(const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                          const asci_loop_options *opt)
+{
+    LoopArgs a;
+    a.h = d_h;
+    a.eri = d_eri;
+    a.n = norb;
+    a.na = nalpha;
+    a.nb = nbeta;
+    asci_loop_options_default(&a.opt);
+    if (opt) a.opt = *opt;
+    a.opt.search = resolve(&a.opt.search);
+    require(a.opt.ntdets >= 1 && a.opt.ntdets < ((int64_t)1 << 31), ASCI_EINVAL, "ntdets must be in [1, 2^31)");
+    require(a.opt.ncore >= 0 && a.opt.max_iter >= 1 && a.opt.e_tol >= 0.0, ASCI_EINVAL,
+            "ncore >= 0, max_iter >= 1 and e_tol >= 0 required");
+    require(a.opt.davidson_subspace >= 2 && a.opt.davidson_subspace <= 48 && a.opt.davidson_max_iter >= 1 &&
+                a.opt.davidson_tol >= 0.0,
+            ASCI_EINVAL, "Davidson options out of range");
+    a.dav.max_subspace = a.opt.davidson_subspace;
+    a.dav.max_iter = a.opt.davidson_max_iter;
+    a.dav.tol = a.opt.davidson_tol;
+    return a;
+}
+
+int asci_loop_step_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                          const uint64_t *d_dets, const double *d_coeffs, int64_t ndets, double Ek,
+                          const asci_loop_options *opt, uint64_t *d_out_dets, double *d_out_coeffs,
+                          int64_t *out_ndets, asci_loop_iter *info, void *stream)
+{
+    try {
+        require(ctx && d_h && d_eri && d_dets && d_coeffs && d_out_dets && d_out_coeffs && out_ndets && info,
+                ASCI_EINVAL, "null pointer argument");
+        check_common(norb, nalpha, nbeta, ndets);
+        ASCI_HIP(hipSetDevice(ctx->device));
+        const LoopArgs a = loop_args(d_h, d_eri, norb, nalpha, nbeta, opt);
+        LoopIter it{};
+        int64_t nn = 0;
+        loop_step(ctx, a, d_dets, d_coeffs, ndets, Ek, d_out_dets, d_out_coeffs, nn, it, (hipStream_t)stream);
+        *out_ndets = nn;
+        *info = it;
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
+int asci_run_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                    const uint64_t *d_dets0, const double *d_coeffs0, int64_t ndets0, const asci_loop_options *opt,
+                    uint64_t *d_out_dets, double *d_out_coeffs, int64_t *out_ndets, double *out_energy,
+                    double *out_pt2, asci_loop_iter *iters, int32_t *out_iters, void *stream)
+{
+    try {
+        require(ctx && d_h && d_eri && d_dets0 && d_coeffs0 && d_out_dets && d_out_coeffs && out_ndets &&
+                    out_energy && out_pt2 && iters && out_iters,
+                ASCI_EINVAL, "null pointer argument");
+        check_common(norb, nalpha, nbeta, ndets0);
+        ASCI_HIP(hipSetDevice(ctx->device));
+        const LoopArgs a = loop_args(d_h, d_eri, norb, nalpha, nbeta, opt);
+        validate_dets(ctx, d_dets0, ndets0, norb, nalpha, nbeta, (hipStream_t)stream);
+        std::vector<LoopIter> rec;
+        int64_t nn = 0;
+        double e = 0.0, p = 0.0;
+        loop_run(ctx, a, d_dets0, d_coeffs0, ndets0, d_out_dets, d_out_coeffs, nn, e, p, rec, (hipStream_t)stream);
+        *out_ndets = nn;
+        *out_energy = e;
+        *out_pt2 = p;
+        *out_iters = (int32_t)rec.size();
+        for (size_t i = 0; i < rec.size(); ++i) iters[i] = rec[i];
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
 int asci_class_counts_device(asci_ctx *ctx, int norb, int nalpha, int nbeta, const uint64_t *d_dets,
                              const double *d_coeffs, int64_t ndets, const asci_options *opt, int64_t capacity,
                              uint64_t *h_masks, int64_t *h_counts, int64_t *out_nclasses, void *stream)

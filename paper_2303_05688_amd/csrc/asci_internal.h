@@ -322,6 +322,53 @@ int64_t request_footprint(const asci_request &r, uint64_t cap_records);
 
 // throws ASCI_EINVAL unless every determinant has na/nb electrons inside norb orbitals
 void validate_dets(asci_ctx *ctx, const uint64_t *dets, int64_t ndets, int n, int na, int nb, hipStream_t s);
+
+// ---------------------------------------------------------------- variational step (eigen.hip)
+// H over a determinant set in CSR: rows in set order, columns ascending, both
+// triangles and the diagonal; device memory owned by the object.
+struct HMat {
+    int device = 0;
+    int64_t nrows = 0, nnz = 0;
+    int64_t *rowptr = nullptr;
+    int32_t *cols = nullptr;
+    double *vals = nullptr;
+    double *diag = nullptr;
+    HMat() = default;
+    HMat(const HMat &) = delete;
+    HMat &operator=(const HMat &) = delete;
+    ~HMat();
+    void release();
+};
+void hmat_build(asci_ctx *ctx, const double *h, const double *eri, int n, int na, int nb, const uint64_t *dets,
+                int64_t ndets, double ecore, HMat &H, hipStream_t s);
+void hmat_matvec(const HMat &H, const double *x, double *y, hipStream_t s, Profiler *prof = nullptr);
+
+struct DavidsonOpts {
+    int max_subspace = 24;
+    int max_iter = 200;
+    double tol = 1e-8;  // residual norm of the Ritz pair
+};
+struct DavidsonOut {
+    double energy, resid;
+    int iters;
+    bool converged;
+};
+DavidsonOut davidson(asci_ctx *ctx, const HMat &H, const double *guess, const DavidsonOpts &o, double *vec,
+                     hipStream_t s);
+
+// ---------------------------------------------------------------- the ASCI loop (loop.hip)
+struct LoopArgs {
+    const double *h, *eri;  // device
+    int n, na, nb;
+    asci_loop_options opt;
+    DavidsonOpts dav;
+};
+using LoopIter = asci_loop_iter;
+void loop_step(asci_ctx *ctx, const LoopArgs &a, const uint64_t *dets, const double *coeffs, int64_t nd, double Ek,
+               uint64_t *out_dets, double *out_coeffs, int64_t &out_nd, LoopIter &info, hipStream_t s);
+void loop_run(asci_ctx *ctx, const LoopArgs &a, const uint64_t *dets0, const double *c0, int64_t n0,
+              uint64_t *out_dets, double *out_coeffs, int64_t &out_nd, double &energy, double &pt2,
+              std::vector<LoopIter> &iters, hipStream_t s);
 double energy_device(asci_ctx *ctx, const double *h, const double *eri, int n, const uint64_t *dets,
                      const double *coeffs, int64_t ndets, double ecore, hipStream_t s);
 
