@@ -49,6 +49,189 @@ def cpu_baseline(case, E0, budget_s=12.0):
                           m, len(case["coeffs"]), case["name"], case["k"], dt)}
 
 
+def _dev_case(case, torch, dev):
+    import numpy as np
+
+    return (torch.from_numpy(case["h"]).to(dev), torch.from_numpy(case["eri"]).to(dev),
+            torch.from_numpy(np.ascontiguousarray(case["dets"]).view(np.int64)).to(dev).view(torch.uint64),
+            torch.from_numpy(case["coeffs"]).to(dev))
+
+
+def mode_levels(args, asci, syn, torch):
+    """Search time and class skew by constraint level (the single-GPU analogue
+    of the strong-scaling and per-element pair-count study by level)."""
+    case = syn.workload(args.workload)
+    n, na, nb, k = case["norb"], case["nalpha"], case["nbeta"], case["k"]
+    dev = torch.device("cuda", 0)
+    h, eri, dets, coeffs = _dev_case(case, torch, dev)
+    ctx = asci.Context.get(0)
+    E0 = asci.energy(h, eri, n, na, nb, dets, coeffs, ctx=ctx)
+    P = len(case["coeffs"]) * sd_per_det(n, na, nb)
+    rows = []
+    configs = [(3, 0), (4, 0), (5, 0), (6, 0), (6, max(1, P // 4096)), (6, max(1, P // 65536))]
+    for level, split in configs:
+        m, counts = asci.class_counts(n, na, nb, dets, coeffs, constraint_level=level, split_pairs=split)
+        st = asci.class_skew(counts, npes=(8, 64, 256, 1024, 4096))
+        asci.search(h, eri, n, na, nb, dets, coeffs, E0, k, constraint_level=level, split_pairs=split, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = asci.search(h, eri, n, na, nb, dets, coeffs, E0, k, constraint_level=level, split_pairs=split,
+                              ctx=ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        rows.append({"level": level, "split_pairs": split, "search_ms": round(ms, 3),
+                     "contributions_per_s": P / (ms * 1e-3), "batches": ctx.get_param("last_batches"),
+                     "selected": int(out[0].shape[0]), **st})
+        print("level %d split %d: %.2f ms, %d classes" % (level, split, ms, st["classes"]), file=sys.stderr,
+              flush=True)
+    return {"metric": "search wall time and class skew by constraint level", "workload": args.workload,
+            "contributions": P, "steps": args.steps, "levels": rows}
+
+
+def mode_loop(args, asci, syn, torch):
+    """The ASCI loop (Alg. 1) from the Hartree-Fock determinant on the
+    workload's integrals: per-iteration search / selection / H / Davidson."""
+    import numpy as np
+
+    case = syn.workload(args.workload)
+    n, na, nb = case["norb"], case["nalpha"], case["nbeta"]
+    dev = torch.device("cuda", 0)
+    h = torch.from_numpy(case["h"]).to(dev)
+    eri = torch.from_numpy(case["eri"]).to(dev)
+    hf = np.array([syn.aufbau(n, na, nb)], dtype=np.uint64)
+    d0 = torch.from_numpy(hf.view(np.int64)).to(dev).view(torch.uint64)
+    c0 = torch.ones(1, dtype=torch.float64, device=dev)
+    opts = asci.loop_options(ntdets=args.ntdets, ncore=args.ncore, max_iter=args.iters, e_tol=0.0, pt2=True,
+                             davidson_tol=1e-6)
+    t0 = time.perf_counter()
+    r = asci.run(h, eri, n, na, nb, d0, c0, opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"metric": "ASCI loop wall time by phase", "workload": args.workload, "ntdets": args.ntdets,
+            "ncore": args.ncore, "wall_s": round(wall, 3), "energy": r["energy"], "pt2": r["pt2"],
+            "iterations": r["iterations"]}
+
+
+def _requests(asci, syn, torch, specs, dev):
+    reqs, pairs = [], 0
+    for sp in specs:
+        c = syn.make_case(sp["n"], sp["na"], sp["nb"], sp["ndets"], sp["seed"], sampler=sp["sampler"],
+                          tau=sp["tau"], k=sp["k"])
+        h, eri, dets, coeffs = _dev_case(c, torch, dev)
+        E0 = asci.energy(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs)
+        reqs.append(asci.SearchRequest(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, E0, sp["k"]))
+        pairs += sp["ndets"] * sd_per_det(sp["n"], sp["na"], sp["nb"])
+    return reqs, pairs
+
+
+def mode_batch(args, asci, syn, torch):
+    """64 uneven searches: one batched call against the same searches one by one."""
+    dev = torch.device("cuda", 0)
+    specs = syn.batch_specs(args.batch_count, seed=64)
+    reqs, P = _requests(asci, syn, torch, specs, dev)
+    print("batch inputs ready: %d searches, %.3g pairs" % (len(reqs), P), file=sys.stderr, flush=True)
+    ctx = asci.Context.get(0)
+    asci.search_batch(reqs[:2], ctx=ctx)
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for r, sp in zip(reqs, specs):
+        t1 = time.perf_counter()
+        asci.search_batch([r], ctx=ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        pairs = sp["ndets"] * sd_per_det(sp["n"], sp["na"], sp["nb"])
+        per.append({"norb": sp["n"], "nalpha": sp["na"], "ndets": sp["ndets"], "pairs": pairs,
+                    "ms": round(dt * 1e3, 3), "contributions_per_s": pairs / dt})
+    single = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = asci.search_batch(reqs, ctx=ctx)
+    torch.cuda.synchronize()
+    batch = time.perf_counter() - t0
+    return {"metric": "batched vs single searches", "searches": len(reqs), "contributions": P,
+            "single_s": round(single, 3), "batch_s": round(batch, 3),
+            "single_contributions_per_s": P / single, "batch_contributions_per_s": P / batch,
+            "speedup": single / batch, "batch_slots": ctx.get_param("batch_slots"),
+            "all_ok": all(r.status == 0 for r in res), "per_search": per}
+
+
+SERVE_MIX = [(0.70, dict(n=20, na=8, nb=8, ndets=1_000)), (0.25, dict(n=26, na=10, nb=10, ndets=10_000)),
+             (0.05, dict(n=30, na=12, nb=12, ndets=100_000))]
+
+
+def mode_serve(args, asci, syn, torch):
+    """Poisson arrivals of a 70/25/5 mix of (16e,20o)/10^3, (20e,26o)/10^4 and
+    (24e,30o)/10^5 searches (k = 10 x cores) against the request server:
+    saturated throughput, then latency p50/p99 at fractions of it."""
+    import numpy as np
+
+    dev = torch.device("cuda", 0)
+    pools = []
+    for frac, base in SERVE_MIX:
+        npool = 4 if base["ndets"] <= 1000 else (2 if base["ndets"] <= 10_000 else 1)
+        specs = [dict(base, seed=500 + 10 * len(pools) + j, sampler="level", tau=base["ndets"] / 10.0,
+                      k=10 * base["ndets"]) for j in range(npool)]
+        reqs, P = _requests(asci, syn, torch, specs, dev)
+        pools.append((frac, reqs, P / len(reqs)))
+    print("serve pools ready", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(55)
+
+    def draw(count):
+        out = []
+        for _ in range(count):
+            u, acc = rng.random(), 0.0
+            for frac, reqs, per in pools:
+                acc += frac
+                if u <= acc:
+                    out.append((reqs[int(rng.integers(len(reqs)))], per))
+                    break
+            else:
+                out.append((pools[-1][1][0], pools[-1][2]))
+        return out
+
+    srv = asci.Server(device=0, slots=args.slots)
+    # saturated: everything queued at once
+    batch = draw(args.requests)
+    t0 = time.perf_counter()
+    tickets = [srv.submit(r) for r, _ in batch]
+    for t in tickets:
+        srv.wait(t)
+    sat_s = time.perf_counter() - t0
+    sat_qps = len(batch) / sat_s
+    sat_cps = sum(per for _, per in batch) / sat_s
+    points = []
+    for f in (0.25, 0.5, 0.75, 0.9):
+        qps = f * sat_qps
+        batch = draw(args.requests)
+        gaps = rng.exponential(1.0 / qps, len(batch))
+        lat = []
+        t_start = time.perf_counter()
+        due = t_start
+        sent = []
+        for (r, _), g in zip(batch, gaps):
+            due += g
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            sent.append((srv.submit(r), time.perf_counter()))
+        for t, ts in sent:
+            srv.wait(t)
+        st = srv.stats()
+        res = [srv.poll(t) for t, _ in sent]
+        lat = sorted(x.latency_ms for x in res if x is not None)
+        points.append({"load": f, "qps": round(qps, 3), "requests": len(batch),
+                       "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                       "max_running": st["max_running"]})
+        print("load %.2f: p50 %.1f ms p99 %.1f ms" % (f, points[-1]["p50_ms"], points[-1]["p99_ms"]),
+              file=sys.stderr, flush=True)
+    srv.close()
+    return {"metric": "served searches: saturated throughput and latency under Poisson load",
+            "mix": "70% (16e,20o)/1e3, 25% (20e,26o)/1e4, 5% (24e,30o)/1e5; k = 10 x cores",
+            "requests_per_point": args.requests, "slots": args.slots, "saturated_qps": sat_qps,
+            "saturated_contributions_per_s": sat_cps, "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +240,14 @@ def main():
     ap.add_argument("--workload", default="16e20o")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--finish-cap", type=int, default=0, help="records per LDS bucket (tuning parameter)")
+    ap.add_argument("--mode", default="search", choices=["search", "levels", "loop", "batch", "serve"],
+                    help="search: the benchmark line; the others print their own measurement")
+    ap.add_argument("--ntdets", type=int, default=10_000, help="loop mode: N_tdets")
+    ap.add_argument("--ncore", type=int, default=0, help="loop mode: N_cdets (0 = all)")
+    ap.add_argument("--iters", type=int, default=4, help="loop mode: outer iterations")
+    ap.add_argument("--batch-count", type=int, default=64, help="batch mode: searches")
+    ap.add_argument("--requests", type=int, default=200, help="serve mode: requests per load point")
+    ap.add_argument("--slots", type=int, default=4, help="serve mode: server worker slots")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the search shards by "
@@ -68,6 +259,11 @@ def main():
 
     import asci_synth as syn
     import paper_2303_05688_amd as asci
+
+    if args.mode != "search":
+        fn = {"levels": mode_levels, "loop": mode_loop, "batch": mode_batch, "serve": mode_serve}[args.mode]
+        print(json.dumps(fn(args, asci, syn, torch)), flush=True)
+        return
 
     case = syn.workload(args.workload)
     n, na, nb = case["norb"], case["nalpha"], case["nbeta"]
