@@ -95,31 +95,41 @@ static int first_bit(uint64_t x)
     return -1;
 }
 
+/* energy of one spin string s on its own: sum_{p in s} h_pp + sum_{p<q in s}
+ * [(pp|qq) - (pq|qp)], one running sum from 0, ascending */
+static double spin_energy(const ham_t *H, uint64_t s)
+{
+    const int n = H->n;
+    double e = 0.0;
+    for (int p = 0; p < n; ++p)
+        if ((s >> p) & 1ull)
+            e = e + H1(H, p, p);
+    for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q)
+            if (((s >> p) & 1ull) && ((s >> q) & 1ull))
+                e = e + (V(H, p, p, q, q) - V(H, p, q, q, p));
+    return e;
+}
+
+/* H_aa = ((ecore + E_alpha) + E_beta) + E_alphabeta: the energies of the two
+ * spin strings on their own, then the opposite-spin Coulomb term
+ * sum_{q in beta} (sum_{p in alpha} (pp|qq)), every sum ascending from 0 */
 double oracle_hdiag(const double *h, const double *eri, int n, double ecore,
                     uint64_t alpha, uint64_t beta)
 {
     ham_t Hs = {n, h, eri, ecore};
     const ham_t *H = &Hs;
-    double e = ecore;
-    for (int p = 0; p < n; ++p)
-        if ((alpha >> p) & 1ull)
-            e = e + H1(H, p, p);
-    for (int p = 0; p < n; ++p)
-        if ((beta >> p) & 1ull)
-            e = e + H1(H, p, p);
-    for (int p = 0; p < n; ++p)
-        for (int q = p + 1; q < n; ++q)
-            if (((alpha >> p) & 1ull) && ((alpha >> q) & 1ull))
-                e = e + (V(H, p, p, q, q) - V(H, p, q, q, p));
-    for (int p = 0; p < n; ++p)
-        for (int q = p + 1; q < n; ++q)
-            if (((beta >> p) & 1ull) && ((beta >> q) & 1ull))
-                e = e + (V(H, p, p, q, q) - V(H, p, q, q, p));
-    for (int p = 0; p < n; ++p)
-        for (int q = 0; q < n; ++q)
-            if (((alpha >> p) & 1ull) && ((beta >> q) & 1ull))
-                e = e + V(H, p, p, q, q);
-    return e;
+    double cross = 0.0;
+    for (int q = 0; q < n; ++q) {
+        if (!((beta >> q) & 1ull))
+            continue;
+        double c = 0.0;
+        for (int p = 0; p < n; ++p)
+            if ((alpha >> p) & 1ull)
+                c = c + V(H, p, p, q, q);
+        cross = cross + c;
+    }
+    return ((ecore + spin_energy(H, alpha)) + spin_energy(H, beta)) + cross;
 }
 
 /* single excitation p -> q in the string `same` (spin s) of determinant i,

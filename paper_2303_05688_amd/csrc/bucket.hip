@@ -4,11 +4,15 @@
 //   segments: contiguous record ranges whose keys agree on every bit at or
 //             above `top`; the classes of the batch are the first segments
 //             (the generator lays records out class by class).
-//   split   : a segment larger than the LDS capacity is split, stably, on the
-//             8 key bits just below `top` (per-tile digit histograms laid out
-//             segment by segment, one global exclusive scan, ranked scatter
-//             into the other buffer).  A segment whose digit is constant only
-//             lowers `top`.  Repeat level by level.
+//   split   : a segment larger than the LDS capacity is split, stably, into
+//             up to 256 key ranges bounded by splitters sampled from it
+//             (sample sort: the ranges are balanced however skewed the keys
+//             are, and they keep key order), with per-tile histograms laid out
+//             segment by segment, one global exclusive scan and a ranked
+//             scatter into the other buffer.  A segment the splitters cannot
+//             divide (its keys lie in one range) is split at the next level
+//             on the 8 key bits just below `top` instead, which always lowers
+//             `top`.  Repeat level by level.
 //   finish  : one workgroup per final segment sorts it in LDS (stable LSD on
 //             bits below `top`), sums every run of equal keys in record order
 //             (record order is ascending core index), drops input
@@ -32,16 +36,21 @@ constexpr int kTileItems = 16;
 constexpr int kTileN = kTileT * kTileItems;  // 4096 records per tile
 
 struct Seg {
-    uint32_t start, size, meta;  // meta: top (bits 0-7) | buf (bit 8) | single key (bit 9)
+    // meta: top (bits 0-7) | buf (bit 8) | single key (bit 9) | split on key bits (bit 10)
+    uint32_t start, size, meta;
 };
 
 __host__ __device__ __forceinline__ uint32_t seg_top(const Seg &s) { return s.meta & 0xFFu; }
 __host__ __device__ __forceinline__ uint32_t seg_buf(const Seg &s) { return (s.meta >> 8) & 1u; }
 __host__ __device__ __forceinline__ bool seg_single(const Seg &s) { return (s.meta >> 9) & 1u; }
-__host__ __device__ __forceinline__ uint32_t make_meta(uint32_t top, uint32_t buf, bool single)
+__host__ __device__ __forceinline__ bool seg_bits(const Seg &s) { return (s.meta >> 10) & 1u; }
+__host__ __device__ __forceinline__ uint32_t make_meta(uint32_t top, uint32_t buf, bool single, bool bits = false)
 {
-    return top | (buf << 8) | (single ? 512u : 0u);
+    return top | (buf << 8) | (single ? 512u : 0u) | (bits ? 1024u : 0u);
 }
+
+constexpr int kMaxSplit = 256;       // ranges per split
+constexpr int kSplitSample = 16;     // samples per range
 
 // bits [sh, sh + w) of the 2n-bit key, w <= 8
 template <int W>
@@ -108,10 +117,13 @@ struct SplitArgs {
     double *val[2];
     int n;
     uint32_t cap;
+    const uint64_t *spl_lo, *spl_hi;  // splitters: kMaxSplit - 1 per segment
+    unsigned long long *kor, *kand;   // per segment: OR and AND of its keys (2 words each)
 };
 
-// digit of a split: the w bits just below `top`, with w the smallest width
-// (at most 8) whose 2^w children average at most half the LDS capacity
+// digit of a split on key bits: the w bits just below `top`, with w the
+// smallest width (at most 8) whose 2^w children average at most half the LDS
+// capacity
 __device__ __forceinline__ void split_digit(const Seg &s, uint32_t cap, int &sh, int &w)
 {
     const int top = (int)seg_top(s);
@@ -119,6 +131,131 @@ __device__ __forceinline__ void split_digit(const Seg &s, uint32_t cap, int &sh,
     while (want < 8 && ((uint64_t)s.size << 1) > ((uint64_t)cap << want)) ++want;
     w = want < top ? want : top;
     sh = top - w;
+}
+
+// ranges of a splitter split: about half the LDS capacity each, 2 to 256
+__host__ __device__ __forceinline__ uint32_t split_ranges(uint32_t size, uint32_t cap)
+{
+    const uint64_t want = ((uint64_t)size * 2 + cap - 1) / cap;
+    return (uint32_t)(want < 2 ? 2 : (want > (uint64_t)kMaxSplit ? (uint64_t)kMaxSplit : want));
+}
+
+// How one split level divides a segment: by splitters (nb ranges, the
+// splitters of segment s staged in LDS by the caller) or by key bits.
+struct SplitRule {
+    bool bits;
+    int sh, w;
+    uint32_t nb;  // digits in use
+};
+
+__device__ __forceinline__ SplitRule split_rule(const Seg &sg, uint32_t cap)
+{
+    SplitRule r;
+    r.bits = seg_bits(sg);
+    if (r.bits) {
+        // the fallback: the 8 bits below top (top is the highest varying bit + 1)
+        const int top = (int)seg_top(sg);
+        r.w = top < 8 ? top : 8;
+        r.sh = top - r.w;
+        r.nb = 1u << r.w;
+    } else {
+        r.sh = r.w = 0;
+        r.nb = split_ranges(sg.size, cap);
+    }
+    return r;
+}
+
+// the digit of a key: its range (number of splitters <= key) or its key bits
+template <int W>
+__device__ __forceinline__ uint32_t split_key_digit(const SplitRule &r, const uint64_t *spl_lo,
+                                                   const uint64_t *spl_hi, uint64_t lo, uint64_t hi, int n)
+{
+    if (r.bits) return vdigit<W>(lo, hi, n, r.sh, r.w);
+    uint32_t a = 0, b = r.nb - 1u;
+    while (a < b) {
+        const uint32_t m = (a + b) >> 1;
+        const bool le = W == 1 ? spl_lo[m] <= lo : (spl_hi[m] < hi || (spl_hi[m] == hi && spl_lo[m] <= lo));
+        if (le) a = m + 1u;
+        else b = m;
+    }
+    return a;
+}
+
+// stage the splitters of segment s in LDS (every thread of the block calls it)
+template <int W>
+__device__ __forceinline__ void load_splitters(const SplitRule &r, const uint64_t *__restrict__ g_lo,
+                                               const uint64_t *__restrict__ g_hi, uint32_t s, uint64_t *spl_lo,
+                                               uint64_t *spl_hi)
+{
+    if (!r.bits)
+        for (uint32_t j = threadIdx.x; j + 1u < r.nb; j += blockDim.x) {
+            spl_lo[j] = g_lo[(size_t)s * (kMaxSplit - 1) + j];
+            if (W == 2) spl_hi[j] = g_hi[(size_t)s * (kMaxSplit - 1) + j];
+        }
+    __syncthreads();
+}
+
+// Splitters of every large segment that splits by ranges: kSplitSample
+// records per range, taken at even strides (the records are in generation
+// order, not key order, so a strided pick is a fair sample), sorted in LDS by
+// a bitonic network; the splitters are the sample's quantiles.
+struct KeyBufs {
+    const uint64_t *lo[2], *hi[2];
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void k_seg_splitters(const Seg *__restrict__ segs, uint32_t cap, KeyBufs kb,
+                                                       uint64_t *__restrict__ g_lo, uint64_t *__restrict__ g_hi)
+{
+    constexpr int kMaxSample = kMaxSplit * kSplitSample;  // 4096
+    __shared__ uint64_t x_lo[kMaxSample];
+    __shared__ uint64_t x_hi[W == 2 ? kMaxSample : 1];
+    const uint32_t s = blockIdx.x;
+    const Seg sg = segs[s];
+    if (seg_bits(sg)) return;
+    const uint32_t nb = split_ranges(sg.size, cap);
+    const uint32_t m = min(sg.size, nb * (uint32_t)kSplitSample);
+    uint32_t p = 1;
+    while (p < m) p <<= 1;
+    const uint64_t *klo = kb.lo[seg_buf(sg)], *khi = kb.hi[seg_buf(sg)];
+    for (uint32_t i = threadIdx.x; i < p; i += 256) {
+        if (i < m) {
+            const size_t j = (size_t)sg.start + (size_t)(((uint64_t)2 * i + 1) * sg.size / (2 * (uint64_t)m));
+            x_lo[i] = klo[j];
+            if (W == 2) x_hi[i] = khi[j];
+        } else {
+            x_lo[i] = ~0ull;
+            if (W == 2) x_hi[i] = ~0ull;
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= p; k <<= 1) {
+        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = threadIdx.x; i < p; i += 256) {
+                const uint32_t o = i ^ jj;
+                if (o > i) {
+                    const bool up = (i & k) == 0;
+                    const uint64_t al = x_lo[i], bl = x_lo[o];
+                    const uint64_t ah = W == 2 ? x_hi[i] : 0ull, bh = W == 2 ? x_hi[o] : 0ull;
+                    const bool gt = key_less<W>(bl, bh, al, ah);
+                    if (gt == up) {
+                        x_lo[i] = bl;
+                        x_lo[o] = al;
+                        if (W == 2) {
+                            x_hi[i] = bh;
+                            x_hi[o] = ah;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t j = threadIdx.x; j + 1u < nb; j += 256) {
+        const uint32_t q = (uint32_t)(((uint64_t)(j + 1) * m) / nb);
+        g_lo[(size_t)s * (kMaxSplit - 1) + j] = x_lo[q];
+        if (W == 2) g_hi[(size_t)s * (kMaxSplit - 1) + j] = x_hi[q];
+    }
 }
 
 // per segment: number of tiles
@@ -143,22 +280,43 @@ template <int W>
 __global__ __launch_bounds__(kTileT) void k_split_hist(SplitArgs a)
 {
     __shared__ uint32_t h[kTileT / 64][256];
+    __shared__ uint64_t spl_lo[kMaxSplit - 1];
+    __shared__ uint64_t spl_hi[W == 2 ? kMaxSplit - 1 : 1];
     const uint32_t t = blockIdx.x;
     const uint32_t s = a.tile_seg[t];
     const Seg sg = a.segs[s];
     const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
-    int sh, w;
-    split_digit(sg, a.cap, sh, w);
+    const SplitRule rule = split_rule(sg, a.cap);
     const uint32_t buf = seg_buf(sg);
     for (int i = threadIdx.x; i < (kTileT / 64) * 256; i += kTileT) (&h[0][0])[i] = 0u;
-    __syncthreads();
+    load_splitters<W>(rule, a.spl_lo, a.spl_hi, s, spl_lo, spl_hi);
     const uint32_t r0 = tl * kTileN, r1 = min(sg.size, r0 + kTileN);
     const int wv = threadIdx.x >> 6;
+    uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
     for (uint32_t r = r0 + threadIdx.x; r < r1; r += kTileT) {
         const size_t j = (size_t)sg.start + r;
         const uint64_t lo = a.klo[buf][j];
         const uint64_t hi = W == 2 ? a.khi[buf][j] : 0ull;
-        atomicAdd(&h[wv][vdigit<W>(lo, hi, a.n, sh, w)], 1u);
+        o0 |= lo;
+        a0 &= lo;
+        o1 |= hi;
+        a1 &= hi;
+        atomicAdd(&h[wv][split_key_digit<W>(rule, spl_lo, spl_hi, lo, hi, a.n)], 1u);
+    }
+    // which key bits vary inside the segment (for segments the split cannot divide)
+    for (int dd = 32; dd >= 1; dd >>= 1) {
+        o0 |= __shfl_xor(o0, dd, 64);
+        a0 &= __shfl_xor(a0, dd, 64);
+        o1 |= __shfl_xor(o1, dd, 64);
+        a1 &= __shfl_xor(a1, dd, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicOr(&a.kor[2 * s], (unsigned long long)o0);
+        atomicAnd(&a.kand[2 * s], (unsigned long long)a0);
+        if (W == 2) {
+            atomicOr(&a.kor[2 * s + 1], (unsigned long long)o1);
+            atomicAnd(&a.kand[2 * s + 1], (unsigned long long)a1);
+        }
     }
     __syncthreads();
     const int d = threadIdx.x;
@@ -189,29 +347,45 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
                                                         uint32_t *__restrict__ skip, Seg *__restrict__ finals,
                                                         uint32_t *__restrict__ nfinal, uint32_t finals_cap,
                                                         Seg *__restrict__ next, uint32_t *__restrict__ nnext,
-                                                        uint32_t next_cap, uint32_t *__restrict__ overflow)
+                                                        uint32_t next_cap, uint32_t *__restrict__ overflow,
+                                                        const unsigned long long *__restrict__ kor,
+                                                        const unsigned long long *__restrict__ kand, int n)
 {
     __shared__ uint32_t s_cnt[256], s_off[256];
     const uint32_t s = blockIdx.x;
     const Seg sg = segs[s];
     const uint32_t tb = tile_base[s], nt = (sg.size + kTileN - 1) / kTileN;
-    int sh, w;
-    split_digit(sg, cap, sh, w);
+    const SplitRule rule = split_rule(sg, cap);
     const uint32_t d = threadIdx.x;
     const size_t b0 = (size_t)tb * 256;
     const uint32_t base = scan[b0];
     const uint32_t off = scan[b0 + (size_t)d * nt] - base;
     const uint32_t end = (d + 1 < 256u) ? scan[b0 + (size_t)(d + 1) * nt] - base : sg.size;
-    s_cnt[d] = (d < (1u << w)) ? end - off : 0u;
+    s_cnt[d] = (d < rule.nb) ? end - off : 0u;
     s_off[d] = off;
     __syncthreads();
     if (d != 0) return;
-    const uint32_t top = (uint32_t)sh, ptop = seg_top(sg);
-    for (uint32_t x = 0; x < (1u << w); ++x) {
+    // the children of a range split keep the parent's top (their keys share at
+    // least its prefix); those of a bit split share bits down to sh
+    const uint32_t ptop = seg_top(sg), top = rule.bits ? (uint32_t)rule.sh : ptop;
+    for (uint32_t x = 0; x < rule.nb; ++x) {
         if (s_cnt[x] == sg.size) {  // one digit holds everything: relabel, do not move
             skip[s] = 1u;
             Seg c{sg.start, sg.size, 0u};
-            if (sg.size <= cap || top == 0) {
+            // highest key bit that varies inside the segment, + 1 (0: one key)
+            const uint64_t v0 = kor[2 * s] ^ kand[2 * s], v1 = W == 2 ? (kor[2 * s + 1] ^ kand[2 * s + 1]) : 0ull;
+            const uint32_t vtop = W == 1 ? (v0 ? 64u - (uint32_t)__clzll((long long)v0) : 0u)
+                                         : (v1 ? (uint32_t)n + 64u - (uint32_t)__clzll((long long)v1)
+                                               : (v0 ? 64u - (uint32_t)__clzll((long long)v0) : 0u));
+            if (vtop == 0) {
+                // a single key: one final segment, summed in record order
+                c.meta = make_meta(0u, seg_buf(sg), sg.size > cap);
+                push_seg(finals, nfinal, finals_cap, c, overflow);
+            } else if (!rule.bits) {
+                // the splitters cannot divide it: split on its top varying bits next
+                c.meta = make_meta(vtop, seg_buf(sg), false, true);
+                push_seg(next, nnext, next_cap, c, overflow);
+            } else if (sg.size <= cap || top == 0) {
                 c.meta = make_meta(top, seg_buf(sg), sg.size > cap);
                 push_seg(finals, nfinal, finals_cap, c, overflow);
             } else {
@@ -231,7 +405,7 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
         g_size = 0;
         g_digits = 0;
     };
-    for (uint32_t x = 0; x < (1u << w); ++x) {
+    for (uint32_t x = 0; x < rule.nb; ++x) {
         const uint32_t c = s_cnt[x];
         if (c == 0) continue;
         if (c > cap) {
@@ -266,22 +440,24 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     __shared__ uint32_t s_dbase[256];
     __shared__ uint32_t s_gbase[256];
     __shared__ uint32_t s_tmp[NW];
+    __shared__ uint8_t s_dg[kTileN];
+    __shared__ uint64_t spl_lo[kMaxSplit - 1];
+    __shared__ uint64_t spl_hi[W == 2 ? kMaxSplit - 1 : 1];
 
     const uint32_t t = blockIdx.x;
     const uint32_t s = a.tile_seg[t];
     if (skip[s]) return;  // uniform per block
     const Seg sg = a.segs[s];
     const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
-    int sh, w;
-    split_digit(sg, a.cap, sh, w);
+    const SplitRule rule = split_rule(sg, a.cap);
     const uint32_t ib = seg_buf(sg), ob = ib ^ 1u;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int i = tid; i < NW * 256; i += kTileT) (&s_wcnt[0][0])[i] = 0u;
-    __syncthreads();
+    load_splitters<W>(rule, a.spl_lo, a.spl_hi, s, spl_lo, spl_hi);
     const uint32_t r0 = tl * kTileN, rn = min(sg.size - r0, (uint32_t)kTileN);
     uint64_t rlo[kTileItems], rhi[kTileItems];
     double rv[kTileItems];
-    uint32_t rrank[kTileItems];
+    uint32_t rrank[kTileItems], rd[kTileItems];
     const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int q = 0; q < kTileItems; ++q) {
@@ -291,7 +467,8 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
         rlo[q] = valid ? a.klo[ib][j] : 0ull;
         rhi[q] = (W == 2 && valid) ? a.khi[ib][j] : 0ull;
         rv[q] = valid ? a.val[ib][j] : 0.0;
-        const uint32_t d = vdigit<W>(rlo[q], rhi[q], a.n, sh, w);
+        const uint32_t d = valid ? split_key_digit<W>(rule, spl_lo, spl_hi, rlo[q], rhi[q], a.n) : 0u;
+        rd[q] = d;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -322,11 +499,12 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     for (int q = 0; q < kTileItems; ++q) {
         const uint32_t li = (uint32_t)wv * 64 * kTileItems + (uint32_t)q * 64 + lane;
         if (li < rn) {
-            const uint32_t d = vdigit<W>(rlo[q], rhi[q], a.n, sh, w);
+            const uint32_t d = rd[q];
             const uint32_t p = min(s_dbase[d] + s_wcnt[wv][d] + rrank[q], (uint32_t)kTileN - 1u);
             s_lo[p] = rlo[q];
             if (W == 2) s_hi[p] = rhi[q];
             s_val[p] = rv[q];
+            s_dg[p] = (uint8_t)d;
         }
     }
     __syncthreads();
@@ -334,7 +512,7 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     for (uint32_t i = tid; i < rn; i += kTileT) {
         const uint64_t lo = s_lo[i];
         const uint64_t hi = W == 2 ? s_hi[i] : 0ull;
-        const uint32_t d = vdigit<W>(lo, hi, a.n, sh, w);
+        const uint32_t d = s_dg[i];
         const uint32_t g = s_gbase[d] + (i - s_dbase[d]);
         if (g >= sg.start && g < seg_end) {
             a.klo[ob][g] = lo;
@@ -552,8 +730,52 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         }
         __syncthreads();
     }
-    // one thread per run: sum, exclusion, diagonal, score; compacted writes
     const uint32_t nruns = S.nruns;
+    // The distinct alpha strings of the runs (the keys are sorted alpha-major):
+    // E(alpha) and c_q(alpha) of H_aa once per string, kept in the buffers the
+    // sort no longer needs; with more strings than fit, H_aa is evaluated per
+    // run instead (the same arithmetic).
+    constexpr uint32_t kAlistCap = (uint32_t)((CAP * 4 - 64) / 16);
+    uint16_t *aidx = head + CAP + 8;
+    uint64_t *alist = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(&S.klo[cur ^ 1][0]) + CAP * 4 + 64);
+    double *ealpha = reinterpret_cast<double *>(alist + kAlistCap);
+    double *colsum = &S.val[cur ^ 1][0];
+    const uint32_t amax = min(kAlistCap, (uint32_t)CAP / (uint32_t)n);
+    uint32_t nalpha = 0;
+    for (uint32_t u0 = 0; u0 < nruns; u0 += NT) {
+        const uint32_t u = u0 + tid;
+        bool nw = false;
+        uint64_t al = 0ull;
+        if (u < nruns) {
+            const uint32_t j0 = head[u];
+            al = W == 1 ? (S.klo[cur][j0] >> n) : S.khi[cur][j0];
+            if (u == 0) {
+                nw = true;
+            } else {
+                const uint32_t jp = head[u - 1];
+                nw = al != (W == 1 ? (S.klo[cur][jp] >> n) : S.khi[cur][jp]);
+            }
+        }
+        uint32_t tot;
+        const uint32_t e = block_scan<NW>(nw ? 1u : 0u, S.tmp, tot);
+        if (u < nruns) {
+            const uint32_t ai = nalpha + e + (nw ? 1u : 0u) - 1u;
+            aidx[u] = (uint16_t)min(ai, 65535u);
+            if (nw && ai < amax) alist[ai] = al;
+        }
+        nalpha += tot;
+    }
+    const bool cached = nalpha <= amax;
+    if (cached) {
+        __syncthreads();
+        for (uint32_t t = tid; t < nalpha * (uint32_t)n; t += NT) {
+            const uint32_t ai = t / (uint32_t)n, q = t - ai * (uint32_t)n;
+            colsum[t] = cross_col(J, n, alist[ai], (int)q);
+        }
+        for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_energy(X, hd, n, alist[t]);
+        __syncthreads();
+    }
+    // one thread per run: sum, exclusion, diagonal, score; compacted writes
     uint32_t written = 0;
     for (uint32_t u0 = 0; u0 < nruns; u0 += NT) {
         const uint32_t u = u0 + tid;
@@ -567,7 +789,17 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             const bool ex = psi_contains(f.psi, lo, hi);
             if (!ex) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
-                const double den = f.E0 - diag_value(J, X, hd, n, f.ecore, a, b);
+                double haa;
+                if (cached) {
+                    const uint32_t ai = aidx[u];
+                    const double *cs = colsum + (size_t)ai * n;
+                    double cross = 0.0;
+                    for (uint64_t m = b; m; m &= m - 1ull) cross = cross + cs[lowbit(m)];
+                    haa = ((f.ecore + ealpha[ai]) + spin_energy(X, hd, n, b)) + cross;
+                } else {
+                    haa = diag_value(J, X, hd, n, f.ecore, a, b);
+                }
+                const double den = f.E0 - haa;
                 if (f.eps > 0.0) {
                     // Alg. 2's threshold, per pair, in record (ascending core) order
                     for (uint32_t j = j0; j < j1; ++j) {
@@ -732,7 +964,8 @@ size_t bucket_workspace_bytes(size_t P, size_t nc, int W)
     const size_t finals = nc + P / 8 + 65536, level = P / cap + nc + 16;
     const size_t tiles = (P + kTileN - 1) / kTileN + level;
     return finals * sizeof(Seg) + 2 * level * sizeof(Seg) + level * 16 + tiles * (256 * 8 + 8) +
-           finals * (8 * 2 + 4 * 4 + 8) + (finals + tiles * 256) / 1024 + (4 << 20);
+           level * ((kMaxSplit - 1) * 8 * W + 32) + finals * (8 * 2 + 4 * 4 + 8) + (finals + tiles * 256) / 1024 +
+           (4 << 20);
 }
 
 template <int W, int CAP, int NT>
@@ -775,7 +1008,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     while (nlarge > 0) {
         ar.reset();
         (void)ar.take<char>(mark);
-        require(lev < 16, ASCI_EDEVICE, "bucket split did not converge");
+        require(lev < 64, ASCI_EDEVICE, "bucket split did not converge");
         Seg *segs = lv[lev & 1], *next = lv[(lev & 1) ^ 1];
         uint32_t *nnext = ctr + 1 + ((lev & 1) ^ 1);
         ASCI_HIP(hipMemsetAsync(nnext, 0, sizeof(uint32_t), s));
@@ -793,8 +1026,20 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         uint32_t *tseg = ar.take<uint32_t>(ntiles + 1);
         uint32_t *hist = ar.take<uint32_t>((size_t)ntiles * 256 + 1);
         uint32_t *hscan = ar.take<uint32_t>((size_t)ntiles * 256 + 1);
+        uint64_t *spl_lo = ar.take<uint64_t>((size_t)nlarge * (kMaxSplit - 1));
+        uint64_t *spl_hi = W == 2 ? ar.take<uint64_t>((size_t)nlarge * (kMaxSplit - 1)) : nullptr;
+        unsigned long long *kor = ar.take<unsigned long long>(2 * (size_t)nlarge);
+        unsigned long long *kand = ar.take<unsigned long long>(2 * (size_t)nlarge);
+        ASCI_HIP(hipMemsetAsync(kor, 0, 2 * (size_t)nlarge * sizeof(unsigned long long), s));
+        ASCI_HIP(hipMemsetAsync(kand, 0xFF, 2 * (size_t)nlarge * sizeof(unsigned long long), s));
         k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg);
         ASCI_LAUNCH_CHECK();
+        {
+            ProfScope ps(prof, "split_sample", 0.0, s);
+            const KeyBufs kb{{b.klo[0], b.klo[1]}, {b.khi[0], b.khi[1]}};
+            k_seg_splitters<W><<<nlarge, 256, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi);
+            ASCI_LAUNCH_CHECK();
+        }
         SplitArgs sa;
         sa.segs = segs;
         sa.nseg = nlarge;
@@ -810,6 +1055,10 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         sa.val[1] = b.val[1];
         sa.n = b.n;
         sa.cap = (uint32_t)CAP;
+        sa.spl_lo = spl_lo;
+        sa.spl_hi = spl_hi;
+        sa.kor = kor;
+        sa.kand = kand;
         {
             ProfScope ps(prof, "split_hist", (8.0 * W) * (double)ntiles * kTileN, s);
             k_split_hist<W><<<ntiles, kTileT, 0, s>>>(sa);
@@ -817,7 +1066,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         }
         scan_u32(hist, hscan, (size_t)ntiles * 256, nullptr, ar, s, prof);
         k_split_children<W><<<nlarge, 256, 0, s>>>(segs, nlarge, tbase, hscan, (uint32_t)CAP, skip, finals, ctr,
-                                                   finals_cap, next, nnext, level_cap, ctr + 3);
+                                                   finals_cap, next, nnext, level_cap, ctr + 3, kor, kand, b.n);
         ASCI_LAUNCH_CHECK();
         sa.hist = hscan;
         {

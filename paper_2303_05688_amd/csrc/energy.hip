@@ -17,31 +17,7 @@ __device__ double pair_value(const double *__restrict__ h, const double *__restr
 {
     const uint64_t da = aa ^ ia, db = ab ^ ib;
     const int ea = popc64(da) >> 1, eb = popc64(db) >> 1;
-    if (ea + eb == 0) {
-        double e = ecore;
-        for (uint64_t m = aa; m; m &= m - 1ull) { const int p = lowbit(m); e = e + h[(size_t)p * n + p]; }
-        for (uint64_t m = ab; m; m &= m - 1ull) { const int p = lowbit(m); e = e + h[(size_t)p * n + p]; }
-        const double *J = jk, *K = jk + n * n;
-        for (uint64_t m = aa; m; m &= m - 1ull) {
-            const int p = lowbit(m);
-            for (uint64_t m2 = m & (m - 1ull); m2; m2 &= m2 - 1ull) {
-                const int q = lowbit(m2);
-                e = e + (J[p * n + q] - K[p * n + q]);
-            }
-        }
-        for (uint64_t m = ab; m; m &= m - 1ull) {
-            const int p = lowbit(m);
-            for (uint64_t m2 = m & (m - 1ull); m2; m2 &= m2 - 1ull) {
-                const int q = lowbit(m2);
-                e = e + (J[p * n + q] - K[p * n + q]);
-            }
-        }
-        for (uint64_t m = aa; m; m &= m - 1ull) {
-            const int p = lowbit(m);
-            for (uint64_t m2 = ab; m2; m2 &= m2 - 1ull) e = e + J[p * n + lowbit(m2)];
-        }
-        return e;
-    }
+    if (ea + eb == 0) return diag_value(jk, jk + n * n, jk + 2 * n * n, n, ecore, aa, ab);
     if (ea + eb > 2) return 0.0;
     if (ea == 1 && eb == 0) return single_value(h, eri, n, ia, ib, lowbit(ia & ~aa), lowbit(aa & ~ia));
     if (ea == 0 && eb == 1) return single_value(h, eri, n, ib, ia, lowbit(ib & ~ab), lowbit(ab & ~ib));
@@ -101,13 +77,16 @@ __global__ __launch_bounds__(1024) void k_sum(const double *__restrict__ x, uint
     if (threadIdx.x == 0) *out = s[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_jk_table(const double *__restrict__ eri, int n, double *__restrict__ jk)
+// J_pq = (pp|qq), X_pq = (pp|qq) - (pq|qp), h_pp: the tables of H_aa
+__global__ __launch_bounds__(kBlock) void k_jk_table(const double *__restrict__ eri, const double *__restrict__ h,
+                                                     int n, double *__restrict__ jk)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= n * n) return;
     const int p = t / n, q = t % n;
     jk[t] = eri4(eri, n, p, p, q, q);
-    jk[n * n + t] = eri4(eri, n, p, q, q, p);
+    jk[n * n + t] = eri4(eri, n, p, p, q, q) - eri4(eri, n, p, q, q, p);
+    if (q == 0) jk[2 * n * n + p] = h[(size_t)p * n + p];
 }
 
 }  // namespace
@@ -119,12 +98,12 @@ double energy_device(asci_ctx *ctx, const double *h, const double *eri, int n, c
     const uint32_t nd = (uint32_t)ndets;
     Arena &ar = ctx->main;
     ar.reset();
-    ar.reserve((size_t)nd * 8 + (size_t)2 * n * n * 8 + 4096);
+    ar.reserve((size_t)nd * 8 + ((size_t)2 * n * n + n) * 8 + 4096);
     ar.reset();
     double *row = ar.take<double>(nd);
-    double *jk = ar.take<double>((size_t)2 * n * n);
+    double *jk = ar.take<double>((size_t)2 * n * n + n);
     double *out = ar.take<double>(1);
-    k_jk_table<<<(unsigned)((n * n + kBlock - 1) / kBlock), kBlock, 0, s>>>(eri, n, jk);
+    k_jk_table<<<(unsigned)((n * n + kBlock - 1) / kBlock), kBlock, 0, s>>>(eri, h, n, jk);
     ASCI_LAUNCH_CHECK();
     k_energy_rows<<<(nd + kBlock - 1) / kBlock, kBlock, 0, s>>>(dets, coeffs, nd, h, eri, jk, n, ecore, row);
     ASCI_LAUNCH_CHECK();

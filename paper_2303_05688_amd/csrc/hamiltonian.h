@@ -60,33 +60,43 @@ __device__ __forceinline__ double double_opp_value(const double *__restrict__ er
     return sg * eri4(eri, n, q, p, s, r);
 }
 
-// H_aa from a table of J[p*n+q] = (pp|qq), X[p*n+q] = (pp|qq) - (pq|qp) and
-// the diagonal of h, in this order: ecore, alpha h_pp, beta h_pp, alpha pairs
-// p<q of X, beta pairs, then alpha x beta J.  M is the string word type: a
-// 32-bit word when every orbital fits in it (half the bit arithmetic).
+// H_aa from the tables J[p*n+q] = (pp|qq), X[p*n+q] = (pp|qq) - (pq|qp) and
+// hd[p] = h_pp, as ((ecore + E(alpha)) + E(beta)) + E(alpha, beta):
+//   E(s)           = sum_{p in s} h_pp + sum_{p<q in s} X_pq (one running sum from 0)
+//   E(alpha, beta) = sum_{q in beta} c_q(alpha),  c_q(alpha) = sum_{p in alpha} J_pq
+// every sum ascending.  Grouping the opposite-spin term by beta orbital lets
+// c_q(alpha) be computed once per alpha string and reused.  M is the string
+// word type: a 32-bit word when every orbital fits in it.
 __device__ __forceinline__ int tz(uint32_t m) { return __builtin_ctz(m); }
 __device__ __forceinline__ int tz(uint64_t m) { return __builtin_ctzll(m); }
+
+template <typename M>
+__device__ __forceinline__ double spin_energy_m(const double *X, const double *hd, int n, M s)
+{
+    double e = 0.0;
+    for (M m = s; m; m &= m - 1) e = e + hd[tz(m)];
+    for (M m = s; m; m &= m - 1) {
+        const double *row = X + tz(m) * n;
+        for (M m2 = m & (m - 1); m2; m2 &= m2 - 1) e = e + row[tz(m2)];
+    }
+    return e;
+}
+
+template <typename M>
+__device__ __forceinline__ double cross_col_m(const double *J, int n, M a, int q)
+{
+    double c = 0.0;
+    for (M m = a; m; m &= m - 1) c = c + J[tz(m) * n + q];
+    return c;
+}
 
 template <typename M>
 __device__ __forceinline__ double diag_value_m(const double *J, const double *X, const double *hd, int n,
                                                double ecore, M a, M b)
 {
-    double e = ecore;
-    for (M m = a; m; m &= m - 1) e = e + hd[tz(m)];
-    for (M m = b; m; m &= m - 1) e = e + hd[tz(m)];
-    for (M m = a; m; m &= m - 1) {
-        const double *row = X + tz(m) * n;
-        for (M m2 = m & (m - 1); m2; m2 &= m2 - 1) e = e + row[tz(m2)];
-    }
-    for (M m = b; m; m &= m - 1) {
-        const double *row = X + tz(m) * n;
-        for (M m2 = m & (m - 1); m2; m2 &= m2 - 1) e = e + row[tz(m2)];
-    }
-    for (M m = a; m; m &= m - 1) {
-        const double *row = J + tz(m) * n;
-        for (M m2 = b; m2; m2 &= m2 - 1) e = e + row[tz(m2)];
-    }
-    return e;
+    double cross = 0.0;
+    for (M m = b; m; m &= m - 1) cross = cross + cross_col_m<M>(J, n, a, tz(m));
+    return ((ecore + spin_energy_m<M>(X, hd, n, a)) + spin_energy_m<M>(X, hd, n, b)) + cross;
 }
 
 __device__ __forceinline__ double diag_value(const double *J, const double *X, const double *hd, int n,
@@ -94,6 +104,18 @@ __device__ __forceinline__ double diag_value(const double *J, const double *X, c
 {
     if (n <= 32) return diag_value_m<uint32_t>(J, X, hd, n, ecore, (uint32_t)a, (uint32_t)b);
     return diag_value_m<uint64_t>(J, X, hd, n, ecore, a, b);
+}
+
+__device__ __forceinline__ double spin_energy(const double *X, const double *hd, int n, uint64_t s)
+{
+    if (n <= 32) return spin_energy_m<uint32_t>(X, hd, n, (uint32_t)s);
+    return spin_energy_m<uint64_t>(X, hd, n, s);
+}
+
+__device__ __forceinline__ double cross_col(const double *J, int n, uint64_t a, int q)
+{
+    if (n <= 32) return cross_col_m<uint32_t>(J, n, (uint32_t)a, q);
+    return cross_col_m<uint64_t>(J, n, a, q);
 }
 
 }  // namespace asci
