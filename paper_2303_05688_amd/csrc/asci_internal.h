@@ -227,8 +227,16 @@ struct SelectState {
     uint64_t krem;  // after the passes: number of entries equal to t to take
     uint32_t hist[256];
 };
+// optional workspace: after two digit passes the entries that still match the
+// selected prefix are copied to tmp (capacity n) and the remaining passes run
+// on the copy; d_count (device) and h_count (pinned host) hold its length
+struct SelectWork {
+    double *tmp;
+    unsigned int *d_count;
+    unsigned int *h_count;
+};
 void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_state,
-                      hipStream_t s, Profiler *prof = nullptr);
+                      hipStream_t s, Profiler *prof = nullptr, const SelectWork *work = nullptr);
 
 // ---------------------------------------------------------------- input-determinant set
 // Open-addressing hash set of the input keys (linear probing; a slot is taken

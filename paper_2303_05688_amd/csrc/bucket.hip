@@ -1109,11 +1109,12 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.nfinal = nf;
         fa.psi = b.psi;
         if constexpr (W == 1) {
-            if (CAP == 4096) launch_finish<1, 4096, 512>(fa, b, nf, s, prof);
-            else if (CAP == 2048) launch_finish<1, 2048, 256>(fa, b, nf, s, prof);
+            // four records per thread: the more wavefronts, the more LDS latency is hidden
+            if (CAP == 4096) launch_finish<1, 4096, 1024>(fa, b, nf, s, prof);
+            else if (CAP == 2048) launch_finish<1, 2048, 512>(fa, b, nf, s, prof);
             else launch_finish<1, 1024, 256>(fa, b, nf, s, prof);
         } else {
-            if (CAP == 2048) launch_finish<2, 2048, 256>(fa, b, nf, s, prof);
+            if (CAP == 2048) launch_finish<2, 2048, 512>(fa, b, nf, s, prof);
             else launch_finish<2, 1024, 256>(fa, b, nf, s, prof);
         }
     }

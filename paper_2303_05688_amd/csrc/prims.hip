@@ -247,6 +247,28 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const double *__restrict_
     if (c) atomicAdd(&st->hist[threadIdx.x], c);
 }
 
+// the entries that still match the selected prefix, copied (in any order:
+// only their count per digit matters) to a smaller array
+__global__ __launch_bounds__(kThreads) void k_sel_compact(const double *__restrict__ score, size_t n,
+                                                          const SelectState *__restrict__ st, double *__restrict__ out,
+                                                          unsigned int *__restrict__ count)
+{
+    const uint64_t prefix = st->prefix, mask = st->mask;
+    const size_t base = (size_t)blockIdx.x * kTile;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int i = threadIdx.x; i < kTile; i += kThreads) {
+        const size_t j = base + i;
+        const double v = j < n ? score[j] : 0.0;
+        const bool keep = j < n && (abs_order(v) & mask) == prefix;
+        const uint64_t b = __ballot(keep);
+        unsigned int at = 0;
+        if (lane == 0 && b) at = atomicAdd(count, (unsigned int)__popcll(b));
+        at = __shfl(at, 0, 64);
+        if (keep) out[at + __popcll(b & lt)] = v;
+    }
+}
+
 __global__ void k_sel_pick(SelectState *st, int shift)
 {
     if (threadIdx.x != 0) return;
@@ -392,16 +414,34 @@ void Profiler::reset()
 }
 
 void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_state, hipStream_t s,
-                      Profiler *prof)
+                      Profiler *prof, const SelectWork *work)
 {
     require(k >= 1 && k <= n, ASCI_EINVAL, "radix select: k out of range");
     size_t nb = (n + kTile - 1) / kTile;
     k_sel_init<<<1, kThreads, 0, s>>>(d_state, k);
     ASCI_LAUNCH_CHECK();
+    const double *x = score;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        ProfScope ps(prof, "select_hist", 8.0 * n, s);
-        k_sel_hist<<<(unsigned)nb, kThreads, 0, s>>>(score, n, shift, d_state);
-        ASCI_LAUNCH_CHECK();
+        if (shift == 40 && work) {
+            // after 16 bits only the entries of the selected prefix matter:
+            // copy them out and run the remaining passes on the copy
+            ASCI_HIP(hipMemsetAsync(work->d_count, 0, sizeof(unsigned int), s));
+            {
+                ProfScope ps(prof, "select_compact", 8.0 * n, s);
+                k_sel_compact<<<(unsigned)nb, kThreads, 0, s>>>(x, n, d_state, work->tmp, work->d_count);
+                ASCI_LAUNCH_CHECK();
+            }
+            ASCI_HIP(hipMemcpyAsync(work->h_count, work->d_count, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+            ASCI_HIP(hipStreamSynchronize(s));
+            x = work->tmp;
+            n = *work->h_count;
+            nb = (n + kTile - 1) / kTile;
+        }
+        if (nb) {
+            ProfScope ps(prof, "select_hist", 8.0 * n, s);
+            k_sel_hist<<<(unsigned)nb, kThreads, 0, s>>>(x, n, shift, d_state);
+            ASCI_LAUNCH_CHECK();
+        }
         k_sel_pick<<<1, 64, 0, s>>>(d_state, shift);
         ASCI_LAUNCH_CHECK();
     }

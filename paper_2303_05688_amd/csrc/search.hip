@@ -955,7 +955,8 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     // keep the pool's keepk entries of largest |score|, in ascending key order
     auto prune = [&](size_t keepk) {
         const size_t entry_mark = ar.used();
-        radix_select_abs(p_score[pcur], pool_n, keepk, d_sel, s, prof);
+        const SelectWork sw{p_score[pcur ^ 1], d_cnt + 8, (unsigned int *)((char *)hs.ptr + 192)};
+        radix_select_abs(p_score[pcur], pool_n, keepk, d_sel, s, prof, &sw);
         k_flag_equal<<<grid_for(pool_n), kBlock, 0, s>>>(p_score[pcur], pool_n, d_sel, pflag);
         ASCI_LAUNCH_CHECK();
         scan_u32(pflag, prank, pool_n, nullptr, ar, s);
