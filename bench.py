@@ -23,6 +23,30 @@ METRIC = "H_ai·C_i contributions/sec + search wall-time; batched/served vs sing
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "%s_16e20o_pmc.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if not parts or parts[0] != "traffic_record":
+            continue
+        rec = dict(p.split("=", 1) for p in parts[1:])
+        h = hashlib.sha256()
+        for f in rec["sources"].split(","):
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["sha256"]:
+            return None
+        return 1024.0 * (float(rec["fetch_kib"]) * float(rec["fetch_scale"]) +
+                         float(rec["write_kib"]) * float(rec["write_scale"]))
+    return None
+
+
 def sd_per_det(n, na, nb):
     va, vb = n - na, n - nb
     return na * va + nb * vb + comb(na, 2) * comb(va, 2) + comb(nb, 2) * comb(vb, 2) + na * va * nb * vb
@@ -232,6 +256,22 @@ def mode_serve(args, asci, syn, torch):
             "saturated_contributions_per_s": sat_cps, "points": points}
 
 
+def mode_copy(args, asci, syn, torch):
+    """A plain device-to-device copy of known size: the reference for scaling
+    the FETCH_SIZE / WRITE_SIZE counters of the search kernels."""
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return {"metric": "device copy (counter reference)", "bytes_read": nbytes, "bytes_written": nbytes,
+            "copies": args.steps, "ms_per_copy": round(dt * 1e3, 4), "GB/s": 2 * nbytes / dt / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,7 +280,7 @@ def main():
     ap.add_argument("--workload", default="16e20o")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--finish-cap", type=int, default=0, help="records per LDS bucket (tuning parameter)")
-    ap.add_argument("--mode", default="search", choices=["search", "levels", "loop", "batch", "serve"],
+    ap.add_argument("--mode", default="search", choices=["search", "levels", "loop", "batch", "serve", "copy"],
                     help="search: the benchmark line; the others print their own measurement")
     ap.add_argument("--ntdets", type=int, default=10_000, help="loop mode: N_tdets")
     ap.add_argument("--ncore", type=int, default=0, help="loop mode: N_cdets (0 = all)")
@@ -261,7 +301,8 @@ def main():
     import paper_2303_05688_amd as asci
 
     if args.mode != "search":
-        fn = {"levels": mode_levels, "loop": mode_loop, "batch": mode_batch, "serve": mode_serve}[args.mode]
+        fn = {"levels": mode_levels, "loop": mode_loop, "batch": mode_batch, "serve": mode_serve,
+              "copy": mode_copy}[args.mode]
         print(json.dumps(fn(args, asci, syn, torch)), flush=True)
         return
 
@@ -302,8 +343,9 @@ def main():
     name, (kms, launches, kbytes) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_ms = kms / max(launches, 1)
     achieved = (kbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(name) if args.workload == "16e20o" else None
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches / args.steps}
     phases = {kname: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps,
                       "GB/s": round((v[2] / max(v[0], 1e-9)) / 1e6, 1)} for kname, v in sorted(prof.items())}
