@@ -708,29 +708,38 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         cur ^= 1;
     }
     // runs of equal keys (record order inside a run is the input order); the
-    // run heads live in the key buffer the sort no longer needs
+    // run heads live in the key buffer the sort no longer needs.  Every thread
+    // owns IT consecutive records, later up to IT consecutive runs, so each
+    // phase needs a single block-wide scan.
     uint16_t *head = reinterpret_cast<uint16_t *>(&S.klo[cur ^ 1][0]);
     {
-        uint32_t base = 0;
-        for (uint32_t r0 = 0; r0 < size; r0 += NT) {
-            const uint32_t r = r0 + tid;
-            bool hd_ = false;
-            if (r < size) {
-                hd_ = r == 0 || S.klo[cur][r] != S.klo[cur][r - 1] ||
-                      (W == 2 && S.khi[cur][r] != S.khi[cur][r - 1]);
-            }
-            uint32_t tot;
-            const uint32_t e = block_scan<NW>(hd_ ? 1u : 0u, S.tmp, tot);
-            if (hd_) head[base + e] = (uint16_t)r;
-            base += tot;
+        const uint32_t r0 = (uint32_t)tid * IT;
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t r = r0 + i;
+            if (r < size && (r == 0 || S.klo[cur][r] != S.klo[cur][r - 1] ||
+                             (W == 2 && S.khi[cur][r] != S.khi[cur][r - 1])))
+                ++c;
+        }
+        uint32_t tot;
+        uint32_t at = block_scan<NW>(c, S.tmp, tot);
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t r = r0 + i;
+            if (r < size && (r == 0 || S.klo[cur][r] != S.klo[cur][r - 1] ||
+                             (W == 2 && S.khi[cur][r] != S.khi[cur][r - 1])))
+                head[at++] = (uint16_t)r;
         }
         if (tid == 0) {
-            head[base] = (uint16_t)min(size, (uint32_t)CAP);
-            S.nruns = base;
+            head[tot] = (uint16_t)min(size, (uint32_t)CAP);
+            S.nruns = tot;
         }
         __syncthreads();
     }
     const uint32_t nruns = S.nruns;
+    const uint32_t rpt = (nruns + NT - 1) / NT;  // runs per thread, <= IT
+    const uint32_t u0 = (uint32_t)tid * rpt, u1 = min(u0 + rpt, nruns);
     // The distinct alpha strings of the runs (the keys are sorted alpha-major):
     // E(alpha) and c_q(alpha) of H_aa once per string, kept in the buffers the
     // sort no longer needs; with more strings than fit, H_aa is evaluated per
@@ -741,29 +750,24 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     double *ealpha = reinterpret_cast<double *>(alist + kAlistCap);
     double *colsum = &S.val[cur ^ 1][0];
     const uint32_t amax = min(kAlistCap, (uint32_t)CAP / (uint32_t)n);
-    uint32_t nalpha = 0;
-    for (uint32_t u0 = 0; u0 < nruns; u0 += NT) {
-        const uint32_t u = u0 + tid;
-        bool nw = false;
-        uint64_t al = 0ull;
-        if (u < nruns) {
-            const uint32_t j0 = head[u];
-            al = W == 1 ? (S.klo[cur][j0] >> n) : S.khi[cur][j0];
-            if (u == 0) {
-                nw = true;
-            } else {
-                const uint32_t jp = head[u - 1];
-                nw = al != (W == 1 ? (S.klo[cur][jp] >> n) : S.khi[cur][jp]);
+    auto alpha_of = [&](uint32_t u) -> uint64_t {
+        const uint32_t j = head[u];
+        return W == 1 ? (S.klo[cur][j] >> n) : S.khi[cur][j];
+    };
+    uint32_t nalpha;
+    {
+        uint32_t c = 0;
+        for (uint32_t u = u0; u < u1; ++u)
+            if (u == 0 || alpha_of(u) != alpha_of(u - 1)) ++c;
+        uint32_t at = block_scan<NW>(c, S.tmp, nalpha);
+        for (uint32_t u = u0; u < u1; ++u) {
+            const uint64_t al = alpha_of(u);
+            if (u == 0 || al != alpha_of(u - 1)) {
+                if (at < amax) alist[at] = al;
+                ++at;
             }
+            aidx[u] = (uint16_t)min(at - 1u, 65535u);
         }
-        uint32_t tot;
-        const uint32_t e = block_scan<NW>(nw ? 1u : 0u, S.tmp, tot);
-        if (u < nruns) {
-            const uint32_t ai = nalpha + e + (nw ? 1u : 0u) - 1u;
-            aidx[u] = (uint16_t)min(ai, 65535u);
-            if (nw && ai < amax) alist[ai] = al;
-        }
-        nalpha += tot;
     }
     const bool cached = nalpha <= amax;
     if (cached) {
@@ -775,19 +779,25 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_energy(X, hd, n, alist[t]);
         __syncthreads();
     }
-    // one thread per run: sum, exclusion, diagonal, score; compacted writes
-    uint32_t written = 0;
-    for (uint32_t u0 = 0; u0 < nruns; u0 += NT) {
-        const uint32_t u = u0 + tid;
-        bool keep = false;
-        double sum = 0.0, score = 0.0;
-        uint64_t lo = 0ull, hi = 0ull;
-        if (u < nruns) {
+    // a thread's runs: sum, exclusion, diagonal, score; one scan places the
+    // surviving candidates, compacted, in run order
+    uint64_t olo[IT], ohi[IT];
+    double osum[IT], oscore[IT];
+    bool okeep[IT];
+    uint32_t kept = 0;
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const uint32_t u = u0 + (uint32_t)i;
+        okeep[i] = false;
+        osum[i] = oscore[i] = 0.0;
+        olo[i] = ohi[i] = 0ull;
+        if (u < u1) {
             const uint32_t j0 = head[u], j1 = head[u + 1];
-            lo = S.klo[cur][j0];
-            hi = W == 2 ? S.khi[cur][j0] : 0ull;
-            const bool ex = psi_contains(f.psi, lo, hi);
-            if (!ex) {
+            const uint64_t lo = S.klo[cur][j0];
+            const uint64_t hi = W == 2 ? S.khi[cur][j0] : 0ull;
+            olo[i] = lo;
+            ohi[i] = hi;
+            if (!psi_contains(f.psi, lo, hi)) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
                 double haa;
                 if (cached) {
@@ -800,6 +810,8 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     haa = diag_value(J, X, hd, n, f.ecore, a, b);
                 }
                 const double den = f.E0 - haa;
+                double sum = 0.0;
+                bool keep = false;
                 if (f.eps > 0.0) {
                     // Alg. 2's threshold, per pair, in record (ascending core) order
                     for (uint32_t j = j0; j < j1; ++j) {
@@ -813,19 +825,25 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     for (uint32_t j = j0; j < j1; ++j) sum = sum + S.val[cur][j];
                     keep = true;
                 }
-                score = sum / den;
+                okeep[i] = keep;
+                osum[i] = sum;
+                oscore[i] = sum / den;
+                kept += keep ? 1u : 0u;
             }
         }
-        uint32_t tot;
-        const uint32_t e = block_scan<NW>(keep ? 1u : 0u, S.tmp, tot);
-        if (keep) {
-            const size_t d = (size_t)sg.start + written + e;
-            f.clo[d] = lo;
-            if (W == 2) f.chi[d] = hi;
-            if (f.cnum) f.cnum[d] = sum;
-            f.cscore[d] = score;
+    }
+    uint32_t written;
+    uint32_t at = block_scan<NW>(kept, S.tmp, written);
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        if (okeep[i]) {
+            const size_t d = (size_t)sg.start + at;
+            f.clo[d] = olo[i];
+            if (W == 2) f.chi[d] = ohi[i];
+            if (f.cnum) f.cnum[d] = osum[i];
+            f.cscore[d] = oscore[i];
+            ++at;
         }
-        written += tot;
     }
     if (tid == 0) f.cnt[sidx] = written;
 }
