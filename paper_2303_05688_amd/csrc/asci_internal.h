@@ -273,8 +273,6 @@ struct BucketArgs {
     const uint32_t *total;          // device: records of the batch
     uint64_t *klo[2], *khi[2];      // record buffers (ping-pong)
     double *val[2];
-    const uint64_t *plo, *phi;      // sorted input keys
-    uint32_t npsi;
     PsiSet psi;                     // the same keys as a hash set
     const double *jk, *h;
     double ecore, E0, eps;

@@ -332,14 +332,6 @@ __global__ __launch_bounds__(kTileT) void k_split_hist(SplitArgs a)
 // digits are coalesced into final segments of at most `cap` records, so the
 // finish never sees fragments.  A segment whose records all share the digit
 // is not moved: skip[s] = 1 and its child keeps its buffer.
-__device__ __forceinline__ void push_seg(Seg *list, uint32_t *count, uint32_t capacity, const Seg &c,
-                                         uint32_t *overflow)
-{
-    const uint32_t at = atomicAdd(count, 1u);
-    if (at < capacity) list[at] = c;
-    else atomicOr(overflow, 1u);
-}
-
 template <int W>
 __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ segs, uint32_t nseg,
                                                         const uint32_t *__restrict__ tile_base,
@@ -352,6 +344,8 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
                                                         const unsigned long long *__restrict__ kand, int n)
 {
     __shared__ uint32_t s_cnt[256], s_off[256];
+    __shared__ Seg s_fin[256], s_nxt[256];
+    __shared__ uint32_t s_nf, s_nn, s_bf, s_bn;
     const uint32_t s = blockIdx.x;
     const Seg sg = segs[s];
     const uint32_t tb = tile_base[s], nt = (sg.size + kTileN - 1) / kTileN;
@@ -364,12 +358,18 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
     s_cnt[d] = (d < rule.nb) ? end - off : 0u;
     s_off[d] = off;
     __syncthreads();
-    if (d != 0) return;
+    // thread 0 lays out the children in LDS (no global atomics in the loop)
+    if (d == 0) {
+    uint32_t nf = 0, nn = 0;
+    auto push_fin = [&](const Seg &c) { s_fin[nf++] = c; };
+    auto push_nxt = [&](const Seg &c) { s_nxt[nn++] = c; };
     // the children of a range split keep the parent's top (their keys share at
     // least its prefix); those of a bit split share bits down to sh
     const uint32_t ptop = seg_top(sg), top = rule.bits ? (uint32_t)rule.sh : ptop;
+    bool whole = false;
     for (uint32_t x = 0; x < rule.nb; ++x) {
         if (s_cnt[x] == sg.size) {  // one digit holds everything: relabel, do not move
+            whole = true;
             skip[s] = 1u;
             Seg c{sg.start, sg.size, 0u};
             // highest key bit that varies inside the segment, + 1 (0: one key)
@@ -380,19 +380,19 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
             if (vtop == 0) {
                 // a single key: one final segment, summed in record order
                 c.meta = make_meta(0u, seg_buf(sg), sg.size > cap);
-                push_seg(finals, nfinal, finals_cap, c, overflow);
+                push_fin(c);
             } else if (!rule.bits) {
                 // the splitters cannot divide it: split on its top varying bits next
                 c.meta = make_meta(vtop, seg_buf(sg), false, true);
-                push_seg(next, nnext, next_cap, c, overflow);
+                push_nxt(c);
             } else if (sg.size <= cap || top == 0) {
                 c.meta = make_meta(top, seg_buf(sg), sg.size > cap);
-                push_seg(finals, nfinal, finals_cap, c, overflow);
+                push_fin(c);
             } else {
                 c.meta = make_meta(top, seg_buf(sg), false);
-                push_seg(next, nnext, next_cap, c, overflow);
+                push_nxt(c);
             }
-            return;
+            break;
         }
     }
     const uint32_t buf = seg_buf(sg) ^ 1u;
@@ -400,12 +400,12 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
     auto flush = [&]() {
         if (g_size) {
             Seg c{sg.start + g_start, g_size, make_meta(g_digits == 1 ? top : ptop, buf, false)};
-            push_seg(finals, nfinal, finals_cap, c, overflow);
+            push_fin(c);
         }
         g_size = 0;
         g_digits = 0;
     };
-    for (uint32_t x = 0; x < rule.nb; ++x) {
+    for (uint32_t x = 0; x < (whole ? 0u : rule.nb); ++x) {
         const uint32_t c = s_cnt[x];
         if (c == 0) continue;
         if (c > cap) {
@@ -413,10 +413,10 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
             Seg L{sg.start + s_off[x], c, 0u};
             if (top == 0) {
                 L.meta = make_meta(0u, buf, true);
-                push_seg(finals, nfinal, finals_cap, L, overflow);
+                push_fin(L);
             } else {
                 L.meta = make_meta(top, buf, false);
-                push_seg(next, nnext, next_cap, L, overflow);
+                push_nxt(L);
             }
             continue;
         }
@@ -426,6 +426,22 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
         ++g_digits;
     }
     flush();
+    s_nf = nf;
+    s_nn = nn;
+    s_bf = nf ? atomicAdd(nfinal, nf) : 0u;
+    s_bn = nn ? atomicAdd(nnext, nn) : 0u;
+    }
+    __syncthreads();
+    // every thread copies its share of the children out
+    const uint32_t nf = s_nf, nn = s_nn, bf = s_bf, bn = s_bn;
+    for (uint32_t i = d; i < nf; i += 256) {
+        if (bf + i < finals_cap) finals[bf + i] = s_fin[i];
+        else atomicOr(overflow, 1u);
+    }
+    for (uint32_t i = d; i < nn; i += 256) {
+        if (bn + i < next_cap) next[bn + i] = s_nxt[i];
+        else atomicOr(overflow, 1u);
+    }
 }
 
 template <int W>
@@ -921,18 +937,32 @@ __global__ __launch_bounds__(256) void k_collect(const Seg *__restrict__ finals,
     }
 }
 
-__global__ void k_class_segs(const uint64_t *__restrict__ cls, uint32_t c0, uint32_t nc, uint32_t nq,
-                             const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ total, int n,
-                             uint32_t cap, Seg *__restrict__ large, uint32_t *__restrict__ nlarge,
-                             Seg *__restrict__ finals, uint32_t *__restrict__ nfinal)
+constexpr uint32_t kMaxClassSegs = 2048;  // classes of one batch
+
+__global__ __launch_bounds__(256) void k_class_segs(const uint64_t *__restrict__ cls, uint32_t c0, uint32_t nc,
+                                                    uint32_t nq, const uint32_t *__restrict__ offsets,
+                                                    const uint32_t *__restrict__ total, int n, uint32_t cap,
+                                                    Seg *__restrict__ large, uint32_t *__restrict__ nlarge,
+                                                    Seg *__restrict__ finals, uint32_t *__restrict__ nfinal)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // class bounds and masks staged in LDS in parallel; one thread then walks
+    // the classes (the counters start at zero and this kernel is their only writer)
+    __shared__ uint32_t s_start[kMaxClassSegs + 1];
+    __shared__ uint64_t s_cls[kMaxClassSegs];
+    for (uint32_t c = threadIdx.x; c < nc; c += 256) {
+        s_start[c] = offsets[(size_t)c * nq];
+        s_cls[c] = cls[c0 + c];
+    }
+    if (threadIdx.x == 0) s_start[nc] = *total;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    uint32_t nf = 0, nl = 0;
     // a class's keys share every bit at or above n + (lowest bit of its mask);
     // a run of classes shares the bits above the highest bit where its first
     // lower bound and last upper bound differ
     uint32_t g_start = 0, g_size = 0, g_first = 0, g_last = 0;
     auto top_of = [&](uint32_t cf, uint32_t cl) -> uint32_t {
-        const uint64_t Tf = cls[c0 + cf], Tl = cls[c0 + cl];
+        const uint64_t Tf = s_cls[cf], Tl = s_cls[cl];
         const int of = Tf ? __ffsll((unsigned long long)Tf) - 1 : 0;
         const int ol = Tl ? __ffsll((unsigned long long)Tl) - 1 : 0;
         if (cf == cl) return (uint32_t)(n + of);
@@ -942,17 +972,16 @@ __global__ void k_class_segs(const uint64_t *__restrict__ cls, uint32_t c0, uint
         return (uint32_t)n + (diff ? (uint32_t)(64 - __clzll((long long)diff)) : 0u);
     };
     auto flush = [&]() {
-        if (g_size) finals[(*nfinal)++] = Seg{g_start, g_size, make_meta(top_of(g_first, g_last), 0u, false)};
+        if (g_size) finals[nf++] = Seg{g_start, g_size, make_meta(top_of(g_first, g_last), 0u, false)};
         g_size = 0;
     };
     for (uint32_t c = 0; c < nc; ++c) {
-        const uint32_t start = offsets[(size_t)c * nq];
-        const uint32_t end = (c + 1 < nc) ? offsets[(size_t)(c + 1) * nq] : *total;
+        const uint32_t start = s_start[c], end = s_start[c + 1];
         if (end <= start) continue;
         const uint32_t size = end - start;
         if (size > cap) {
             flush();
-            large[(*nlarge)++] = Seg{start, size, make_meta(top_of(c, c), 0u, false)};
+            large[nl++] = Seg{start, size, make_meta(top_of(c, c), 0u, false)};
             continue;
         }
         if (g_size + size > cap) flush();
@@ -964,6 +993,8 @@ __global__ void k_class_segs(const uint64_t *__restrict__ cls, uint32_t c0, uint
         g_last = c;
     }
     flush();
+    *nfinal = nf;
+    *nlarge = nl;
 }
 
 }  // namespace
@@ -1015,8 +1046,9 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     uint32_t *ctr = ar.take<uint32_t>(8);  // 0: finals, 1/2: large segments per level parity, 3: overflow
     uint32_t *hcnt = (uint32_t *)hs.ptr;
     ASCI_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(uint32_t), s));
-    k_class_segs<<<1, 64, 0, s>>>(b.cls, b.c0, b.nc, b.nq, b.offsets, b.total, b.n, (uint32_t)CAP, lv[0], ctr + 1,
-                                  finals, ctr);
+    require(b.nc <= kMaxClassSegs, ASCI_EINVAL, "too many classes in one batch");
+    k_class_segs<<<1, 256, 0, s>>>(b.cls, b.c0, b.nc, b.nq, b.offsets, b.total, b.n, (uint32_t)CAP, lv[0], ctr + 1,
+                                   finals, ctr);
     ASCI_LAUNCH_CHECK();
     ASCI_HIP(hipMemcpyAsync(hcnt, ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     ASCI_HIP(hipStreamSynchronize(s));

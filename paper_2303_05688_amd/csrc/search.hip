@@ -389,45 +389,141 @@ __global__ void k_init_or_and(unsigned long long *p)
     if (threadIdx.x < 4) p[threadIdx.x] = (threadIdx.x & 1) ? ~0ull : 0ull;
 }
 
-// ---------------------------------------------------------------- selection helpers
-__global__ __launch_bounds__(kBlock) void k_flag_equal(const double *__restrict__ score, size_t n,
-                                                       const SelectState *__restrict__ st,
-                                                       uint32_t *__restrict__ flag)
+// ---- stable compaction of the pool to its keepk largest |score| entries:
+// keep ord > t, plus the first krem entries with ord == t in pool order.
+// Tiles of kKeepTile entries: per-tile counts, one pass over the tiles for
+// their bases, then an in-order scatter (no per-entry flag or rank arrays).
+constexpr int kKeepItems = 16;
+constexpr int kKeepTile = kBlock * kKeepItems;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, uint32_t &total)
 {
-    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j < n) flag[j] = abs_order(score[j]) == st->prefix ? 1u : 0u;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        base += i < w ? s_w[i] : 0u;
+        tot += s_w[i];
+    }
+    __syncthreads();
+    total = tot;
+    return base + x - v;
 }
 
-// keep[j] = ord > t, or ord == t among the first krem such entries
-__global__ __launch_bounds__(kBlock) void k_flag_keep(const double *__restrict__ score, size_t n,
-                                                      const SelectState *__restrict__ st,
-                                                      const uint32_t *__restrict__ eq_rank,
-                                                      uint32_t *__restrict__ flag)
+__global__ __launch_bounds__(kBlock) void k_keep_count(const double *__restrict__ score, size_t n,
+                                                       const SelectState *__restrict__ st, uint32_t *__restrict__ tgt,
+                                                       uint32_t *__restrict__ teq)
 {
-    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    const uint64_t o = abs_order(score[j]), t = st->prefix;
-    flag[j] = (o > t || (o == t && eq_rank[j] < st->krem)) ? 1u : 0u;
+    __shared__ uint32_t s_w[kBlock / 64];
+    const uint64_t t = st->prefix;
+    const size_t base = (size_t)blockIdx.x * kKeepTile;
+    uint32_t gt = 0, eq = 0;
+#pragma unroll
+    for (int i = 0; i < kKeepItems; ++i) {
+        const size_t j = base + (size_t)i * kBlock + threadIdx.x;
+        if (j < n) {
+            const uint64_t o = abs_order(score[j]);
+            gt += o > t ? 1u : 0u;
+            eq += o == t ? 1u : 0u;
+        }
+    }
+    uint32_t tg, te;
+    (void)block_excl_scan(gt, s_w, tg);
+    (void)block_excl_scan(eq, s_w, te);
+    if (threadIdx.x == 0) {
+        tgt[blockIdx.x] = tg;
+        teq[blockIdx.x] = te;
+    }
+}
+
+// one block walks the tiles: equal-entry bases and output bases
+__global__ __launch_bounds__(1024) void k_keep_bases(const uint32_t *__restrict__ tgt, const uint32_t *__restrict__ teq,
+                                                     uint32_t nt, const SelectState *__restrict__ st,
+                                                     uint32_t *__restrict__ eqbase, uint32_t *__restrict__ keptbase)
+{
+    __shared__ uint32_t s_w[16];
+    const uint64_t krem = st->krem;
+    uint32_t eq_run = 0, kept_run = 0;
+    for (uint32_t c0 = 0; c0 < nt; c0 += 1024) {
+        const uint32_t i = c0 + threadIdx.x;
+        const uint32_t e = i < nt ? teq[i] : 0u, g = i < nt ? tgt[i] : 0u;
+        uint32_t etot, ktot;
+        const uint32_t eb = eq_run + block_excl_scan(e, s_w, etot);
+        const uint64_t left = krem > eb ? krem - eb : 0ull;
+        const uint32_t kept = g + (uint32_t)(left < e ? left : e);
+        const uint32_t kb = kept_run + block_excl_scan(kept, s_w, ktot);
+        if (i < nt) {
+            eqbase[i] = eb;
+            keptbase[i] = kb;
+        }
+        eq_run += etot;
+        kept_run += ktot;
+    }
 }
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_compact(const uint64_t *__restrict__ ilo,
-                                                    const uint64_t *__restrict__ ihi,
-                                                    const double *__restrict__ inum,
-                                                    const double *__restrict__ iscore, size_t n,
-                                                    const uint32_t *__restrict__ flag,
-                                                    const uint32_t *__restrict__ pos, uint64_t *__restrict__ olo,
-                                                    uint64_t *__restrict__ ohi, double *__restrict__ onum,
-                                                    double *__restrict__ oscore)
+__global__ __launch_bounds__(kBlock) void k_keep_scatter(const uint64_t *__restrict__ ilo,
+                                                         const uint64_t *__restrict__ ihi,
+                                                         const double *__restrict__ iscore, size_t n,
+                                                         const SelectState *__restrict__ st,
+                                                         const uint32_t *__restrict__ eqbase,
+                                                         const uint32_t *__restrict__ keptbase,
+                                                         uint64_t *__restrict__ olo, uint64_t *__restrict__ ohi,
+                                                         double *__restrict__ oscore, size_t cap)
 {
-    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n || !flag[j]) return;
-    const uint32_t d = pos[j];
-    if (d >= n) return;
-    olo[d] = ilo[j];
-    if (W == 2) ohi[d] = ihi[j];
-    if (onum) onum[d] = inum[j];
-    oscore[d] = iscore[j];
+    __shared__ uint32_t s_w[kBlock / 64];
+    const uint64_t t = st->prefix, krem = st->krem;
+    // thread-contiguous entries keep the pool order inside the tile
+    const size_t base = (size_t)blockIdx.x * kKeepTile + (size_t)threadIdx.x * kKeepItems;
+    uint64_t o[kKeepItems];
+    uint32_t eq = 0;
+#pragma unroll
+    for (int i = 0; i < kKeepItems; ++i) {
+        const size_t j = base + i;
+        o[i] = j < n ? abs_order(iscore[j]) : 0ull;
+        eq += (j < n && o[i] == t) ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t erank = eqbase[blockIdx.x] + block_excl_scan(eq, s_w, tot);
+    uint32_t kept = 0;
+    uint32_t keepmask = 0;
+#pragma unroll
+    for (int i = 0; i < kKeepItems; ++i) {
+        const size_t j = base + i;
+        bool k = false;
+        if (j < n) {
+            if (o[i] > t) {
+                k = true;
+            } else if (o[i] == t) {
+                k = erank < krem;
+                ++erank;
+            }
+        }
+        if (k) {
+            keepmask |= 1u << i;
+            ++kept;
+        }
+    }
+    uint32_t at = keptbase[blockIdx.x] + block_excl_scan(kept, s_w, tot);
+#pragma unroll
+    for (int i = 0; i < kKeepItems; ++i) {
+        if ((keepmask >> i) & 1u) {
+            const size_t j = base + i;
+            if (at < cap) {
+                olo[at] = ilo[j];
+                if (W == 2) ohi[at] = ihi[j];
+                oscore[at] = iscore[j];
+            }
+            ++at;
+        }
+    }
 }
 
 // sort key for the final order: ~|score| bits so that ascending = descending |score|
@@ -483,17 +579,6 @@ __global__ __launch_bounds__(kBlock) void k_validate(const uint64_t *__restrict_
     if ((a & ~full) || (b & ~full) || popc64(a) != na || popc64(b) != nb) atomicOr(err, 1u);
 }
 
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_pack_keys(const uint64_t *__restrict__ dets, size_t nd, int n,
-                                                      uint64_t *__restrict__ klo, uint64_t *__restrict__ khi,
-                                                      uint32_t *__restrict__ idx)
-{
-    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= nd) return;
-    put_key<W>(klo, khi, j, dets[2 * j], dets[2 * j + 1], n);
-    idx[j] = (uint32_t)j;
-}
-
 // insert every input key into the hash set (keys as (lo, hi) words)
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_psi_insert(const uint64_t *__restrict__ dets, size_t nd, int n,
@@ -515,15 +600,22 @@ __global__ __launch_bounds__(kBlock) void k_psi_insert(const uint64_t *__restric
     }
 }
 
-// bit 1 of err: two equal input determinants (keys sorted)
+// bit 1 of err: an input determinant stored twice in the hash set (every insert
+// has finished: this runs as a kernel of its own)
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_check_dups(const uint64_t *__restrict__ klo,
-                                                       const uint64_t *__restrict__ khi, size_t n,
-                                                       unsigned int *__restrict__ err)
+__global__ __launch_bounds__(kBlock) void k_psi_dups(const uint64_t *__restrict__ dets, size_t nd, int n, PsiSet t,
+                                                     unsigned int *__restrict__ err)
 {
     const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j == 0 || j >= n) return;
-    if (klo[j] == klo[j - 1] && (W == 1 || khi[j] == khi[j - 1])) atomicOr(err, 2u);
+    if (j >= nd) return;
+    const uint64_t a = dets[2 * j], b = dets[2 * j + 1];
+    const uint64_t lo = W == 1 ? ((a << n) | b) : b, hi = W == 1 ? 0ull : a;
+    uint32_t sl = psi_hash(lo, hi, t.mask), seen = 0;
+    for (uint32_t probe = 0; probe <= t.mask && t.state[sl]; ++probe) {
+        if (t.lo[sl] == lo && t.hi[sl] == hi) ++seen;
+        sl = (sl + 1u) & t.mask;
+    }
+    if (seen > 1) atomicOr(err, 2u);
 }
 
 // core-selection sort key: ~|C| bits, so ascending order is |C| descending
@@ -626,7 +718,6 @@ static BetaFactors beta_factors(int n, int nb)
 template <int W>
 struct Prepared {
     size_t nd = 0, nq = 0;
-    const uint64_t *plo = nullptr, *phi = nullptr;  // sorted keys of every input determinant
     uint64_t *q_a = nullptr, *q_b = nullptr;         // core set, ascending input index
     double *q_c = nullptr;
     uint64_t *d_cls = nullptr;
@@ -747,18 +838,6 @@ static void plan_classes(int n, int na, int L, int64_t split_pairs, uint64_t fit
     for (size_t r = 0; r < roots.size(); ++r) place(r, r);
 }
 
-static std::vector<Digit> full_key_digits(int n, int W)
-{
-    std::vector<Digit> d;
-    if (W == 1) {
-        for (int sh = 0; sh < 2 * n; sh += 8) d.push_back({0, sh});
-    } else {
-        for (int sh = 0; sh < n; sh += 8) d.push_back({0, sh});
-        for (int sh = 0; sh < n; sh += 8) d.push_back({1, sh});
-    }
-    return d;
-}
-
 // Validate the determinants, sort their keys, pick the core set and count the
 // pairs of every constraint class.  All buffers live in ctx->setup.
 template <int W>
@@ -785,9 +864,6 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     unsigned long long *d_tot = ar.take<unsigned long long>(kMaxClasses);
     uint32_t *d_tree = ar.take<uint32_t>(kMaxClasses);
     pp.d_jk = ar.take<double>((size_t)2 * n * n + n);
-    uint64_t *psi_lo[2] = {ar.take<uint64_t>(nd), ar.take<uint64_t>(nd)};
-    uint64_t *psi_hi[2] = {W == 2 ? ar.take<uint64_t>(nd) : nullptr, W == 2 ? ar.take<uint64_t>(nd) : nullptr};
-    uint32_t *psi_idx[2] = {ar.take<uint32_t>(nd), ar.take<uint32_t>(nd)};
     pp.q_a = ar.take<uint64_t>(nq);
     pp.q_b = ar.take<uint64_t>(nq);
     pp.q_c = ar.take<double>(nq);
@@ -811,12 +887,7 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
         ASCI_HIP(hipMemsetAsync(t_state, 0, (size_t)tsize * sizeof(uint32_t), s));
         k_psi_insert<W><<<grid_for(nd), kBlock, 0, s>>>(dets, nd, n, t_lo, t_hi, t_state, tsize - 1);
         ASCI_LAUNCH_CHECK();
-        k_pack_keys<W><<<grid_for(nd), kBlock, 0, s>>>(dets, nd, n, psi_lo[0], psi_hi[0], psi_idx[0]);
-        ASCI_LAUNCH_CHECK();
-        const int pc = radix_sort<uint32_t>(psi_lo, psi_hi, psi_idx, nd, W, full_key_digits(n, W), ar, s);
-        pp.plo = psi_lo[pc];
-        pp.phi = psi_hi[pc];
-        k_check_dups<W><<<grid_for(nd), kBlock, 0, s>>>(psi_lo[pc], psi_hi[pc], nd, d_err);
+        k_psi_dups<W><<<grid_for(nd), kBlock, 0, s>>>(dets, nd, n, pp.psi, d_err);
         ASCI_LAUNCH_CHECK();
     }
     // core set: the nq inputs of largest |C| (ties: lower index), ascending index
@@ -922,7 +993,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     Arena &ar = ctx->main;
     ar.reset();
     ar.reserve(E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, max_nc, W) +
-               pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 12) + kk_max * 24 + 64 * 256 + (1 << 16));
+               pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 1) + kk_max * 24 + 64 * 256 + (1 << 16));
     ar.reset();
     uint32_t *counts = ar.take<uint32_t>(E);
     uint32_t *offs = ar.take<uint32_t>(E);
@@ -937,9 +1008,6 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     uint64_t *p_hi[2] = {W == 2 ? ar.take<uint64_t>(pool_cap) : nullptr, W == 2 ? ar.take<uint64_t>(pool_cap) : nullptr};
     double *p_num = topk ? nullptr : ar.take<double>(pool_cap);
     double *p_score[2] = {ar.take<double>(pool_cap), ar.take<double>(pool_cap)};
-    uint32_t *pflag = ar.take<uint32_t>(pool_cap);
-    uint32_t *ppos = ar.take<uint32_t>(pool_cap);
-    uint32_t *prank = ar.take<uint32_t>(pool_cap);
     SelectState *d_sel = ar.take<SelectState>(1);
     uint32_t *d_cnt = ar.take<uint32_t>(16);
     unsigned long long *d_misc = ar.take<unsigned long long>(16);
@@ -957,16 +1025,20 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         const size_t entry_mark = ar.used();
         const SelectWork sw{p_score[pcur ^ 1], d_cnt + 8, (unsigned int *)((char *)hs.ptr + 192)};
         radix_select_abs(p_score[pcur], pool_n, keepk, d_sel, s, prof, &sw);
-        k_flag_equal<<<grid_for(pool_n), kBlock, 0, s>>>(p_score[pcur], pool_n, d_sel, pflag);
-        ASCI_LAUNCH_CHECK();
-        scan_u32(pflag, prank, pool_n, nullptr, ar, s);
-        k_flag_keep<<<grid_for(pool_n), kBlock, 0, s>>>(p_score[pcur], pool_n, d_sel, prank, pflag);
-        ASCI_LAUNCH_CHECK();
-        scan_u32(pflag, ppos, pool_n, nullptr, ar, s);
+        const uint32_t ntile = (uint32_t)((pool_n + kKeepTile - 1) / kKeepTile);
+        uint32_t *tgt = ar.take<uint32_t>(ntile), *teq = ar.take<uint32_t>(ntile);
+        uint32_t *eqb = ar.take<uint32_t>(ntile), *kb = ar.take<uint32_t>(ntile);
         const int o = pcur ^ 1;
-        k_compact<W><<<grid_for(pool_n), kBlock, 0, s>>>(p_lo[pcur], p_hi[pcur], nullptr, p_score[pcur], pool_n,
-                                                         pflag, ppos, p_lo[o], p_hi[o], nullptr, p_score[o]);
-        ASCI_LAUNCH_CHECK();
+        {
+            ProfScope ps(prof, "keep", 2.0 * 8.0 * pool_n + (8.0 * W + 8.0) * 2.0 * keepk, s);
+            k_keep_count<<<ntile, kBlock, 0, s>>>(p_score[pcur], pool_n, d_sel, tgt, teq);
+            ASCI_LAUNCH_CHECK();
+            k_keep_bases<<<1, 1024, 0, s>>>(tgt, teq, ntile, d_sel, eqb, kb);
+            ASCI_LAUNCH_CHECK();
+            k_keep_scatter<W><<<ntile, kBlock, 0, s>>>(p_lo[pcur], p_hi[pcur], p_score[pcur], pool_n, d_sel, eqb, kb,
+                                                       p_lo[o], p_hi[o], p_score[o], keepk);
+            ASCI_LAUNCH_CHECK();
+        }
         pcur = o;
         pool_n = keepk;
         ar.reset();
@@ -1045,9 +1117,6 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.khi[1] = k_hi[1];
         ba.val[0] = v[0];
         ba.val[1] = v[1];
-        ba.plo = pp.plo;
-        ba.phi = pp.phi;
-        ba.npsi = (uint32_t)nd;
         ba.psi = pp.psi;
         ba.jk = pp.d_jk;
         ba.h = in.h;
