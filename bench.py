@@ -150,19 +150,25 @@ def _requests(asci, syn, torch, specs, dev):
 
 
 def mode_batch(args, asci, syn, torch):
-    """64 uneven searches: one batched call against the same searches one by one."""
+    """64 uneven searches: one batched call (after a warm-up call that sizes the
+    worker workspaces) against the same searches one by one on one context."""
     dev = torch.device("cuda", 0)
     specs = syn.batch_specs(args.batch_count, seed=64)
     reqs, P = _requests(asci, syn, torch, specs, dev)
     print("batch inputs ready: %d searches, %.3g pairs" % (len(reqs), P), file=sys.stderr, flush=True)
     ctx = asci.Context.get(0)
-    asci.search_batch(reqs[:2], ctx=ctx)
+    asci.search_batch(reqs, ctx=ctx)
+    torch.cuda.synchronize()
+    for r, sp in zip(reqs, specs):  # warm-up: size the context's workspace
+        h, eri, dets, coeffs = r.keep
+        asci.search(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, r.c.E0, sp["k"], ctx=ctx)
     torch.cuda.synchronize()
     per = []
     t0 = time.perf_counter()
     for r, sp in zip(reqs, specs):
         t1 = time.perf_counter()
-        asci.search_batch([r], ctx=ctx)
+        h, eri, dets, coeffs = r.keep
+        asci.search(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, r.c.E0, sp["k"], ctx=ctx)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         pairs = sp["ndets"] * sd_per_det(sp["n"], sp["na"], sp["nb"])
@@ -256,6 +262,23 @@ def mode_serve(args, asci, syn, torch):
             "saturated_contributions_per_s": sat_cps, "points": points}
 
 
+def mode_host(args, asci, syn, torch):
+    """The host-buffer entry point (asci_search): inputs uploaded and results
+    downloaded inside the timed call (PCIe included)."""
+    case = syn.workload(args.workload)
+    n, na, nb, k = case["norb"], case["nalpha"], case["nbeta"], case["k"]
+    h, eri, dets, coeffs = _dev_case(case, torch, torch.device("cuda", 0))
+    E0 = asci.energy(h, eri, n, na, nb, dets, coeffs)
+    asci.search_host(case["h"], case["eri"], n, na, nb, case["dets"], case["coeffs"], E0, k)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        asci.search_host(case["h"], case["eri"], n, na, nb, case["dets"], case["coeffs"], E0, k)
+    dt = (time.perf_counter() - t0) / args.steps
+    P = len(case["coeffs"]) * sd_per_det(n, na, nb)
+    return {"metric": "host-buffer search (PCIe inclusive)", "workload": args.workload, "ms": round(dt * 1e3, 3),
+            "contributions_per_s": P / dt}
+
+
 def mode_copy(args, asci, syn, torch):
     """A plain device-to-device copy of known size: the reference for scaling
     the FETCH_SIZE / WRITE_SIZE counters of the search kernels."""
@@ -280,7 +303,7 @@ def main():
     ap.add_argument("--workload", default="16e20o")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--finish-cap", type=int, default=0, help="records per LDS bucket (tuning parameter)")
-    ap.add_argument("--mode", default="search", choices=["search", "levels", "loop", "batch", "serve", "copy"],
+    ap.add_argument("--mode", default="search", choices=["search", "levels", "loop", "batch", "serve", "copy", "host"],
                     help="search: the benchmark line; the others print their own measurement")
     ap.add_argument("--ntdets", type=int, default=10_000, help="loop mode: N_tdets")
     ap.add_argument("--ncore", type=int, default=0, help="loop mode: N_cdets (0 = all)")
@@ -302,7 +325,7 @@ def main():
 
     if args.mode != "search":
         fn = {"levels": mode_levels, "loop": mode_loop, "batch": mode_batch, "serve": mode_serve,
-              "copy": mode_copy}[args.mode]
+              "copy": mode_copy, "host": mode_host}[args.mode]
         print(json.dumps(fn(args, asci, syn, torch)), flush=True)
         return
 

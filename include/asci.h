@@ -96,6 +96,8 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *                 1024, 2048 or 4096 (default 4096; two-word keys use at most
  *                 2048).  Smaller buckets let two workgroups share a CU.
  *   "batch_slots": concurrent searches of asci_search_batch, 1..8 (default 2).
+ *   "release_workspace" (value 1): free the context's device workspaces and
+ *                 the batch workers (they are allocated again on demand).
  * Read-only diagnostics of the last search on ctx (asci_ctx_get_param):
  *   "last_batches" (class batches), "last_finals" (LDS buckets),
  *   "last_levels" (deepest bucket split), "last_candidates" (candidates).
@@ -335,7 +337,9 @@ int64_t asci_request_footprint(const asci_request *req);
  * Run nreq searches as one batch on ctx's device: the requests are ordered by
  * estimated cost (largest first) and run concurrently on `slots` worker
  * streams (ctx parameter "batch_slots", default 2; see asci_autotune), each
- * with its own workspace.  Work already queued on `stream` completes first;
+ * with its own workspace.  The workers and their workspaces stay with ctx
+ * between calls (until "release_workspace", a change of "batch_slots" or
+ * "finish_cap", or asci_ctx_destroy).  Work already queued on `stream` completes first;
  * the call returns when every result is written.  res[i] is request i's
  * result; the return value is ASCI_OK when every request succeeded, else the
  * first error code.

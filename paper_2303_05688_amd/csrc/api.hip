@@ -13,16 +13,23 @@ namespace asci {
 void Arena::reserve(size_t bytes)
 {
     if (bytes <= cap_) return;
+    const size_t grown = cap_ + cap_ / 4;  // grow by a quarter at least: fewer reallocations
     release();
-    bytes = (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+    auto round = [](size_t b) { return (b + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1); };
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    size_t got = round(std::max(bytes, grown));
+    hipError_t e = hipMalloc(&p, got);
+    if (e != hipSuccess && got > round(bytes)) {
+        (void)hipGetLastError();
+        got = round(bytes);
+        e = hipMalloc(&p, got);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         throw Error{ASCI_ENOMEM, "hipMalloc of the workspace failed"};
     }
     base_ = (char *)p;
-    cap_ = bytes;
+    cap_ = got;
     used_ = 0;
 }
 
@@ -166,6 +173,17 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
         if (key == "batch_slots") {
             require(value >= 1 && value <= 8, ASCI_EINVAL, "batch_slots must be in [1, 8]");
             ctx->batch_slots = (int)value;
+            return ASCI_OK;
+        }
+        if (key == "release_workspace") {
+            require(value == 1, ASCI_EINVAL, "release_workspace takes the value 1");
+            ASCI_HIP(hipSetDevice(ctx->device));
+            ASCI_HIP(hipDeviceSynchronize());
+            if (ctx->batch_pool) ctx->batch_pool_free(ctx->batch_pool);
+            ctx->batch_pool = nullptr;
+            ctx->batch_pool_slots = ctx->batch_pool_cap = 0;
+            ctx->setup.release();
+            ctx->main.release();
             return ASCI_OK;
         }
         throw Error{ASCI_EINVAL, "unknown parameter: " + key};

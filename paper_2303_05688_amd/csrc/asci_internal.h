@@ -122,9 +122,21 @@ struct asci_ctx {
     // diagnostics of the last search
     int64_t last_batches = 0, last_finals = 0, last_levels = 0, last_candidates = 0;
     asci::Profiler prof;
-    asci::Arena setup;  // inputs, sorted psi keys, core set, class totals
+    asci::Arena setup;  // inputs, psi hash set, core set, class totals
     asci::Arena main;   // per-batch pair buffers, candidate pool, selection
     asci::HostStage stage;
+    // worker pool of asci_search_batch, kept between calls so that its
+    // workspaces stay allocated (rebuilt when batch_slots or finish_cap change)
+    void *batch_pool = nullptr;
+    void (*batch_pool_free)(void *) = nullptr;
+    int batch_pool_slots = 0, batch_pool_cap = 0;
+    asci_ctx() = default;
+    asci_ctx(const asci_ctx &) = delete;
+    asci_ctx &operator=(const asci_ctx &) = delete;
+    ~asci_ctx()
+    {
+        if (batch_pool && batch_pool_free) batch_pool_free(batch_pool);
+    }
 };
 
 namespace asci {

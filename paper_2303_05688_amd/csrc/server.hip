@@ -83,18 +83,11 @@ struct WorkerState {
 
 class Pool {
   public:
-    Pool(int device, int64_t budget, int slots, bool fake, double ns_per_byte, int finish_cap,
-         hipStream_t after = nullptr)
+    Pool(int device, int64_t budget, int slots, bool fake, double ns_per_byte, int finish_cap)
         : device_(device), budget_(budget), fake_(fake), ns_per_byte_(ns_per_byte)
     {
         slots = std::max(1, std::min(slots, 16));
         cap_records_ = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(1ll << 30, budget / slots / 160));
-        hipEvent_t ready = nullptr;
-        if (!fake_ && after) {
-            ASCI_HIP(hipSetDevice(device_));
-            ASCI_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-            ASCI_HIP(hipEventRecord(ready, after));
-        }
         ws_.resize((size_t)slots);
         for (auto &w : ws_) {
             w = std::make_unique<WorkerState>();
@@ -104,11 +97,29 @@ class Pool {
                 w->ctx->device = device_;
                 w->ctx->finish_cap = finish_cap;
                 ASCI_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
-                if (ready) ASCI_HIP(hipStreamWaitEvent(w->stream, ready, 0));
             }
         }
-        if (ready) ASCI_HIP(hipEventDestroy(ready));
         for (size_t i = 0; i < ws_.size(); ++i) ws_[i]->th = std::thread([this, i] { loop((int)i); });
+    }
+
+    // work queued on `after` before this call completes before any worker
+    // starts what is submitted next (the pool must be idle)
+    void order_after(hipStream_t after)
+    {
+        if (fake_ || !after) return;
+        ASCI_HIP(hipSetDevice(device_));
+        hipEvent_t ready = nullptr;
+        ASCI_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        ASCI_HIP(hipEventRecord(ready, after));
+        for (auto &w : ws_) ASCI_HIP(hipStreamWaitEvent(w->stream, ready, 0));
+        ASCI_HIP(hipEventDestroy(ready));
+    }
+
+    // forget the results of finished tickets (a batch's bookkeeping)
+    void forget(const std::vector<uint64_t> &tickets)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        for (uint64_t t : tickets) done_.erase(t);
     }
 
     ~Pool()
@@ -436,24 +447,33 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
         require(ctx != nullptr && (nreq == 0 || (reqs && res)), ASCI_EINVAL, "null argument");
         require(nreq >= 0, ASCI_EINVAL, "nreq must be >= 0");
         if (nreq == 0) return ASCI_OK;
-        const int64_t budget = device_budget(ctx->device);
+        if (!ctx->batch_pool || ctx->batch_pool_slots != ctx->batch_slots ||
+            ctx->batch_pool_cap != ctx->finish_cap) {
+            if (ctx->batch_pool) ctx->batch_pool_free(ctx->batch_pool);
+            ctx->batch_pool = nullptr;
+            const int64_t budget = device_budget(ctx->device);
+            ctx->batch_pool = new Pool(ctx->device, budget, ctx->batch_slots, false, 0.0, ctx->finish_cap);
+            ctx->batch_pool_free = [](void *p) { delete static_cast<Pool *>(p); };
+            ctx->batch_pool_slots = ctx->batch_slots;
+            ctx->batch_pool_cap = ctx->finish_cap;
+        }
+        Pool &pool = *static_cast<Pool *>(ctx->batch_pool);
+        pool.order_after((hipStream_t)stream);
         std::vector<int> order((size_t)nreq);
         for (int i = 0; i < nreq; ++i) order[(size_t)i] = i;
         std::stable_sort(order.begin(), order.end(),
                          [&](int a, int b) { return request_pairs(reqs[a]) > request_pairs(reqs[b]); });
         std::vector<uint64_t> tickets((size_t)nreq, 0);
         int rc = ASCI_OK;
-        {
-            Pool pool(ctx->device, budget, ctx->batch_slots, false, 0.0, ctx->finish_cap, (hipStream_t)stream);
-            for (int i : order) {
-                const int r = pool.submit(reqs[i], &tickets[(size_t)i]);
-                if (r != ASCI_OK && rc == ASCI_OK) rc = r;
-            }
-            for (int i = 0; i < nreq; ++i) {
-                pool.poll(tickets[(size_t)i], &res[i], true);
-                if (res[i].status != ASCI_OK && rc == ASCI_OK) rc = res[i].status;
-            }
+        for (int i : order) {
+            const int r = pool.submit(reqs[i], &tickets[(size_t)i]);
+            if (r != ASCI_OK && rc == ASCI_OK) rc = r;
         }
+        for (int i = 0; i < nreq; ++i) {
+            pool.poll(tickets[(size_t)i], &res[i], true);
+            if (res[i].status != ASCI_OK && rc == ASCI_OK) rc = res[i].status;
+        }
+        pool.forget(tickets);
         return rc;
     } catch (const Error &e) {
         return srv_fail(e);

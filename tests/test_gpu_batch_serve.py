@@ -107,3 +107,23 @@ def test_autotune_keeps_results(setup):
     finally:
         ctx.set_param("batch_slots", old[0])
         ctx.set_param("finish_cap", old[1])
+
+
+def test_batch_reuses_workers_and_release(setup):
+    """Two batches in a row reuse the context's workers; after releasing the
+    workspaces the results are still the same."""
+    asci, cases, alone = setup
+    ctx = asci.Context.get(0)
+    for _ in range(2):
+        reqs = _requests(asci, cases)
+        res = asci.search_batch(reqs, ctx=ctx)
+        assert all(_same(q, r, w) for r, q, w in zip(res, reqs, alone))
+    ctx.set_param("release_workspace", 1)
+    reqs = _requests(asci, cases[:3])
+    res = asci.search_batch(reqs, ctx=ctx)
+    assert all(_same(q, r, w) for r, q, w in zip(res, reqs, alone[:3]))
+    c = cases[0]
+    d = c["dev"]
+    k, s = asci.search(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], c["E0"],
+                       c["kk"], ctx=ctx)
+    assert (host(k) == alone[0][0]).all() and (host(s) == alone[0][1]).all()
