@@ -119,6 +119,7 @@ struct SplitArgs {
     uint32_t cap;
     const uint64_t *spl_lo, *spl_hi;  // splitters: kMaxSplit - 1 per segment
     unsigned long long *kor, *kand;   // per segment: OR and AND of its keys (2 words each)
+    uint8_t *dig;                     // per record: its digit, from the histogram pass
 };
 
 // digit of a split on key bits: the w bits just below `top`, with w the
@@ -301,7 +302,9 @@ __global__ __launch_bounds__(kTileT) void k_split_hist(SplitArgs a)
         a0 &= lo;
         o1 |= hi;
         a1 &= hi;
-        atomicAdd(&h[wv][split_key_digit<W>(rule, spl_lo, spl_hi, lo, hi, a.n)], 1u);
+        const uint32_t dg = split_key_digit<W>(rule, spl_lo, spl_hi, lo, hi, a.n);
+        a.dig[j] = (uint8_t)dg;
+        atomicAdd(&h[wv][dg], 1u);
     }
     // which key bits vary inside the segment (for segments the split cannot divide)
     for (int dd = 32; dd >= 1; dd >>= 1) {
@@ -457,8 +460,6 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     __shared__ uint32_t s_gbase[256];
     __shared__ uint32_t s_tmp[NW];
     __shared__ uint8_t s_dg[kTileN];
-    __shared__ uint64_t spl_lo[kMaxSplit - 1];
-    __shared__ uint64_t spl_hi[W == 2 ? kMaxSplit - 1 : 1];
 
     const uint32_t t = blockIdx.x;
     const uint32_t s = a.tile_seg[t];
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     const uint32_t ib = seg_buf(sg), ob = ib ^ 1u;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int i = tid; i < NW * 256; i += kTileT) (&s_wcnt[0][0])[i] = 0u;
-    load_splitters<W>(rule, a.spl_lo, a.spl_hi, s, spl_lo, spl_hi);
+    __syncthreads();
     const uint32_t r0 = tl * kTileN, rn = min(sg.size - r0, (uint32_t)kTileN);
     uint64_t rlo[kTileItems], rhi[kTileItems];
     double rv[kTileItems];
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
         rlo[q] = valid ? a.klo[ib][j] : 0ull;
         rhi[q] = (W == 2 && valid) ? a.khi[ib][j] : 0ull;
         rv[q] = valid ? a.val[ib][j] : 0.0;
-        const uint32_t d = valid ? split_key_digit<W>(rule, spl_lo, spl_hi, rlo[q], rhi[q], a.n) : 0u;
+        const uint32_t d = valid ? (uint32_t)a.dig[j] : 0u;
         rd[q] = d;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -1013,7 +1014,7 @@ size_t bucket_workspace_bytes(size_t P, size_t nc, int W)
     const size_t finals = nc + P / 8 + 65536, level = P / cap + nc + 16;
     const size_t tiles = (P + kTileN - 1) / kTileN + level;
     return finals * sizeof(Seg) + 2 * level * sizeof(Seg) + level * 16 + tiles * (256 * 8 + 8) +
-           level * ((kMaxSplit - 1) * 8 * W + 32) + finals * (8 * 2 + 4 * 4 + 8) + (finals + tiles * 256) / 1024 +
+           level * ((kMaxSplit - 1) * 8 * W + 32) + P + 256 + finals * (8 * 2 + 4 * 4 + 8) + (finals + tiles * 256) / 1024 +
            (4 << 20);
 }
 
@@ -1054,6 +1055,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     ASCI_HIP(hipStreamSynchronize(s));
     uint32_t nlarge = hcnt[1];
     int lev = 0;
+    uint8_t *dig = ar.take<uint8_t>(P + 1);
     const size_t mark = ar.used();
     while (nlarge > 0) {
         ar.reset();
@@ -1109,6 +1111,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         sa.spl_hi = spl_hi;
         sa.kor = kor;
         sa.kand = kand;
+        sa.dig = dig;
         {
             ProfScope ps(prof, "split_hist", (8.0 * W) * (double)ntiles * kTileN, s);
             k_split_hist<W><<<ntiles, kTileT, 0, s>>>(sa);
