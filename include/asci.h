@@ -96,6 +96,11 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *                 1024, 2048 or 4096 (default 4096; two-word keys use at most
  *                 2048).  Smaller buckets let two workgroups share a CU.
  *   "batch_slots": concurrent searches of asci_search_batch, 1..8 (default 2).
+ *   "spin_tables": 1 (default) tabulates E(s) of every alpha and beta string
+ *                 (at most 2^27 strings per spin, and only when the search
+ *                 has at least four pairs per string) so the diagonal element
+ *                 looks them up by string rank; 0 evaluates them directly.
+ *                 Both give the same bits (same summation order).
  *   "release_workspace" (value 1): free the context's device workspaces and
  *                 the batch workers (they are allocated again on demand).
  * Read-only diagnostics of the last search on ctx (asci_ctx_get_param):

@@ -175,6 +175,11 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
             ctx->batch_slots = (int)value;
             return ASCI_OK;
         }
+        if (key == "spin_tables") {
+            require(value == 0 || value == 1, ASCI_EINVAL, "spin_tables must be 0 or 1");
+            ctx->spin_tables = (int)value;
+            return ASCI_OK;
+        }
         if (key == "release_workspace") {
             require(value == 1, ASCI_EINVAL, "release_workspace takes the value 1");
             ASCI_HIP(hipSetDevice(ctx->device));
@@ -184,6 +189,7 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
             ctx->batch_pool_slots = ctx->batch_pool_cap = 0;
             ctx->setup.release();
             ctx->main.release();
+            ctx->tables.release();
             return ASCI_OK;
         }
         throw Error{ASCI_EINVAL, "unknown parameter: " + key};
@@ -199,6 +205,7 @@ int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value)
         const std::string key(name);
         if (key == "finish_cap") *value = ctx->finish_cap;
         else if (key == "batch_slots") *value = ctx->batch_slots;
+        else if (key == "spin_tables") *value = ctx->spin_tables;
         else if (key == "last_batches") *value = ctx->last_batches;
         else if (key == "last_finals") *value = ctx->last_finals;
         else if (key == "last_levels") *value = ctx->last_levels;

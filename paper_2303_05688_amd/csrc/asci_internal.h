@@ -119,11 +119,13 @@ struct asci_ctx {
     int device = 0;
     int finish_cap = 4096;  // tunable: records per LDS bucket (see asci_ctx_set_param)
     int batch_slots = 2;    // tunable: concurrent searches of a batch
+    int spin_tables = 1;    // tunable: 1 = spin-string energy tables when they pay, 0 = never
     // diagnostics of the last search
     int64_t last_batches = 0, last_finals = 0, last_levels = 0, last_candidates = 0;
     asci::Profiler prof;
     asci::Arena setup;  // inputs, psi hash set, core set, class totals
     asci::Arena main;   // per-batch pair buffers, candidate pool, selection
+    asci::Arena tables; // spin-string energy tables of the current integrals
     asci::HostStage stage;
     // worker pool of asci_search_batch, kept between calls so that its
     // workspaces stay allocated (rebuilt when batch_slots or finish_cap change)
@@ -275,6 +277,26 @@ __device__ __forceinline__ bool psi_contains(const PsiSet &t, uint64_t lo, uint6
     return false;
 }
 
+// Energies E(s) of every spin string with a given electron count, indexed by
+// the combinatorial rank of the string (sum over its set bits p_1 < p_2 < ...
+// of C(p_j, j)); binom[k * (n + 1) + p] = C(p, k).  e[0] covers the alpha
+// strings, e[1] the beta strings (null: no table, evaluate directly).
+struct SpinTables {
+    const double *e[2] = {nullptr, nullptr};
+    const uint32_t *binom = nullptr;
+};
+
+// Which tables a search builds: count[i] strings (0 = none) for alpha (0) and
+// beta (1); share when both spins have the same electron count.
+constexpr uint64_t kSpinTableMax = (uint64_t)1 << 27;
+struct SpinTablePlan {
+    uint64_t count[2] = {0, 0};
+    bool share = false;
+    int kmax = 0;
+    size_t bytes = 0;
+};
+SpinTablePlan spin_table_plan(int n, int na, int nb, uint64_t pairs, bool enabled);
+
 // ---------------------------------------------------------------- buckets (bucket.hip)
 struct BucketArgs {
     size_t P;                       // records of the batch
@@ -287,6 +309,7 @@ struct BucketArgs {
     double *val[2];
     PsiSet psi;                     // the same keys as a hash set
     const double *jk, *h;
+    SpinTables st;                  // tabulated E(alpha), E(beta) (optional)
     double ecore, E0, eps;
     int finish_cap = 4096;          // LDS capacity of a final segment (tunable)
     uint64_t *clo, *chi;            // candidate slots (P)

@@ -547,6 +547,7 @@ struct FinishArgs {
     double *val[2];
     int n;
     const double *jk, *h;       // J, J-K (n^2 each), h_pp (n); h (n^2)
+    SpinTables st;              // E(alpha), E(beta) by string rank (optional)
     double ecore, E0, eps;      // eps > 0: keep a pair only if |H_ai C_i / (E0 - H_aa)| > eps
     uint64_t *clo, *chi;        // slot arrays (batch positions)
     double *cnum, *cscore;
@@ -555,6 +556,21 @@ struct FinishArgs {
     PsiSet psi;                 // input determinants (exclusion)
     int tab_in_lds;             // J, J-K, h_pp staged in LDS (else read from jk)
 };
+
+// E(s) of one spin string (0 = alpha, 1 = beta): looked up when tabulated
+__device__ __forceinline__ double spin_e(const SpinTables &st, int spin, const double *X, const double *hd, int n,
+                                         uint64_t str)
+{
+    const double *t = st.e[spin];
+    return t ? t[spin_rank(st.binom, n, str)] : spin_energy(X, hd, n, str);
+}
+
+// H_aa = ((ecore + E(alpha)) + E(beta)) + E(alpha, beta)
+__device__ __forceinline__ double diag_tab(const SpinTables &st, const double *J, const double *X, const double *hd,
+                                           int n, double ecore, uint64_t a, uint64_t b)
+{
+    return ((ecore + spin_e(st, 0, X, hd, n, a)) + spin_e(st, 1, X, hd, n, b)) + cross_energy(J, n, a, b);
+}
 
 template <int W, int CAP, int NT>
 struct FinishLds {
@@ -595,7 +611,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             uint32_t c = 0;
             if (!ex) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
-                const double den = f.E0 - diag_value(J, X, hd, n, f.ecore, a, b);
+                const double den = f.E0 - diag_tab(f.st, J, X, hd, n, f.ecore, a, b);
                 double sum = 0.0;
                 uint32_t kept = 0;
                 for (uint32_t r = 0; r < sg.size; ++r) {
@@ -793,7 +809,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             const uint32_t ai = t / (uint32_t)n, q = t - ai * (uint32_t)n;
             colsum[t] = cross_col(J, n, alist[ai], (int)q);
         }
-        for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_energy(X, hd, n, alist[t]);
+        for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_e(f.st, 0, X, hd, n, alist[t]);
         __syncthreads();
     }
     // a thread's runs: sum, exclusion, diagonal, score; one scan places the
@@ -822,9 +838,9 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     const double *cs = colsum + (size_t)ai * n;
                     double cross = 0.0;
                     for (uint64_t m = b; m; m &= m - 1ull) cross = cross + cs[lowbit(m)];
-                    haa = ((f.ecore + ealpha[ai]) + spin_energy(X, hd, n, b)) + cross;
+                    haa = ((f.ecore + ealpha[ai]) + spin_e(f.st, 1, X, hd, n, b)) + cross;
                 } else {
-                    haa = diag_value(J, X, hd, n, f.ecore, a, b);
+                    haa = diag_tab(f.st, J, X, hd, n, f.ecore, a, b);
                 }
                 const double den = f.E0 - haa;
                 double sum = 0.0;
@@ -1151,6 +1167,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.n = b.n;
         fa.jk = b.jk;
         fa.h = b.h;
+        fa.st = b.st;
         fa.ecore = b.ecore;
         fa.E0 = b.E0;
         fa.eps = b.eps;

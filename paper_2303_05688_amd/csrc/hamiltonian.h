@@ -112,6 +112,33 @@ __device__ __forceinline__ double spin_energy(const double *X, const double *hd,
     return spin_energy_m<uint64_t>(X, hd, n, s);
 }
 
+// E(alpha, beta) of the diagonal element: sum over q in beta of c_q(alpha)
+__device__ __forceinline__ double cross_energy(const double *J, int n, uint64_t a, uint64_t b)
+{
+    if (n <= 32) {
+        double cross = 0.0;
+        for (uint32_t m = (uint32_t)b; m; m &= m - 1) cross = cross + cross_col_m<uint32_t>(J, n, (uint32_t)a, tz(m));
+        return cross;
+    }
+    double cross = 0.0;
+    for (uint64_t m = b; m; m &= m - 1) cross = cross + cross_col_m<uint64_t>(J, n, a, tz(m));
+    return cross;
+}
+
+// combinatorial rank of a spin string: sum over its set bits p_1 < p_2 < ...
+// of C(p_j, j), with binom[k * (n + 1) + p] = C(p, k)
+__device__ __forceinline__ uint32_t spin_rank(const uint32_t *binom, int n, uint64_t s)
+{
+    uint32_t r = 0;
+    const uint32_t *row = binom + (n + 1);
+    if (n <= 32) {
+        for (uint32_t m = (uint32_t)s; m; m &= m - 1, row += n + 1) r += row[tz(m)];
+    } else {
+        for (uint64_t m = s; m; m &= m - 1, row += n + 1) r += row[tz(m)];
+    }
+    return r;
+}
+
 __device__ __forceinline__ double cross_col(const double *J, int n, uint64_t a, int q)
 {
     if (n <= 32) return cross_col_m<uint32_t>(J, n, (uint32_t)a, q);

@@ -697,6 +697,29 @@ std::vector<uint64_t> make_classes(int n, int na, int L)
     return out;
 }
 
+// E(s) of every string of ne electrons in n orbitals, by rank: the string is
+// unranked in the combinatorial number system (highest bit first: the largest
+// p with C(p, j) <= remaining rank, for j = ne, ..., 1) and evaluated by the
+// same routine as the direct path, so a looked-up value equals a computed one
+__global__ __launch_bounds__(kBlock) void k_spin_table(const double *__restrict__ jk, int n, int ne,
+                                                      const uint32_t *__restrict__ binom, uint32_t count,
+                                                      double *__restrict__ out)
+{
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= count) return;
+    uint32_t rem = r;
+    uint64_t str = 0;
+    int p = n - 1;
+    for (int j = ne; j >= 1; --j) {
+        const uint32_t *row = binom + (size_t)j * (n + 1);
+        while (p > 0 && row[p] > rem) --p;  // C(p, j) = 0 <= rem once p < j
+        str |= 1ull << p;
+        rem -= row[p];
+        --p;
+    }
+    out[r] = spin_energy(jk + n * n, jk + 2 * n * n, n, str);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host driver
@@ -712,6 +735,75 @@ static BetaFactors beta_factors(int n, int nb)
     bf.vb = vb;
     bf.pairs_vb = pvb;
     return bf;
+}
+
+// ---- spin-string energy tables (E(alpha), E(beta) looked up by rank)
+static uint64_t binom_sat(int n, int k)
+{
+    if (k < 0 || k > n) return 0;
+    k = std::min(k, n - k);
+    unsigned __int128 c = 1;
+    for (int i = 1; i <= k; ++i) {
+        c = c * (unsigned)(n - k + i) / (unsigned)i;
+        if (c > (unsigned __int128)UINT64_MAX) return UINT64_MAX;
+    }
+    return (uint64_t)c;
+}
+
+SpinTablePlan spin_table_plan(int n, int na, int nb, uint64_t pairs, bool enabled)
+{
+    SpinTablePlan pl;
+    const int ne[2] = {na, nb};
+    for (int i = 0; i < 2; ++i) {
+        const uint64_t c = binom_sat(n, ne[i]);
+        // a table pays when it is small next to the search that reads it
+        pl.count[i] = (enabled && c <= kSpinTableMax && (c <= (1u << 16) || 4 * c <= pairs)) ? c : 0;
+    }
+    pl.share = na == nb;
+    if (pl.share) pl.count[1] = pl.count[0];
+    if (pl.count[0] == 0 && pl.count[1] == 0) return pl;
+    pl.kmax = std::max(pl.count[0] ? na : 0, pl.count[1] ? nb : 0);
+    const size_t tab = (size_t)(pl.count[0] + (pl.share ? 0 : pl.count[1])) * 8;
+    pl.bytes = tab + (size_t)(pl.kmax + 1) * (n + 1) * 4 + 1024;
+    return pl;
+}
+
+// Build the tables of `pl` for the integrals' J / J-K / h_pp table `jk`.
+static SpinTables build_spin_tables(asci_ctx *ctx, const SpinTablePlan &pl, const double *jk, int n, int na, int nb,
+                                    hipStream_t s)
+{
+    SpinTables st;
+    if (pl.bytes == 0) return st;
+    Arena &ar = ctx->tables;
+    ar.reset();
+    ar.reserve(pl.bytes);
+    ar.reset();
+    std::vector<uint32_t> hb((size_t)(pl.kmax + 1) * (n + 1));
+    for (int k = 0; k <= pl.kmax; ++k)
+        for (int p = 0; p <= n; ++p)
+            hb[(size_t)k * (n + 1) + p] = (uint32_t)std::min<uint64_t>(binom_sat(p, k), UINT32_MAX);
+    uint32_t *d_binom = ar.take<uint32_t>(hb.size());
+    HostStage &hs = ctx->stage;
+    hs.reserve(hb.size() * 4);
+    std::memcpy(hs.ptr, hb.data(), hb.size() * 4);
+    ASCI_HIP(hipMemcpyAsync(d_binom, hs.ptr, hb.size() * 4, hipMemcpyHostToDevice, s));
+    st.binom = d_binom;
+    const int ne[2] = {na, nb};
+    for (int i = 0; i < 2; ++i) {
+        if (pl.count[i] == 0) continue;
+        if (i == 1 && pl.share) {
+            st.e[1] = st.e[0];
+            continue;
+        }
+        double *t = ar.take<double>(pl.count[i]);
+        k_spin_table<<<(unsigned)((pl.count[i] + kBlock - 1) / kBlock), kBlock, 0, s>>>(jk, n, ne[i], d_binom,
+                                                                                    (uint32_t)pl.count[i], t);
+        ASCI_LAUNCH_CHECK();
+        st.e[i] = t;
+    }
+    // the staged binomials are read by the copy above
+    ASCI_HIP(hipStreamSynchronize(s));
+    return st;
 }
 
 // inputs shared by the search entry points: validated, keyed and core-selected
@@ -959,6 +1051,10 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     prepare<W>(ctx, in.h, in.eri, n, in.na, in.nb, in.dets, in.coeffs, in.ndets, in.opt, cap, true, pp, s);
     const size_t nd = pp.nd, nq = pp.nq;
     const uint32_t ncls = (uint32_t)pp.cls.size();
+    uint64_t all_pairs = 0;
+    for (uint64_t t : pp.totals) all_pairs += t;
+    const SpinTables st = build_spin_tables(ctx, spin_table_plan(n, in.na, in.nb, all_pairs, ctx->spin_tables != 0),
+                                            pp.d_jk, n, in.na, in.nb, s);
 
     // ---- batch plan: consecutive classes up to the pair-buffer capacity
     std::vector<std::pair<uint32_t, uint32_t>> batches;
@@ -1120,6 +1216,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.psi = pp.psi;
         ba.jk = pp.d_jk;
         ba.h = in.h;
+        ba.st = st;
         ba.ecore = in.opt.ecore;
         ba.E0 = in.E0;
         ba.eps = in.opt.eps;

@@ -60,7 +60,8 @@ int64_t request_footprint(const asci_request &r, uint64_t cap_records)
                            (uint64_t)(2 * r.norb * r.norb + r.norb) * 8 + (1 << 20);
     const uint64_t main = E * 8 + Pb * (2 * (8 * W + 8)) + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, nc, W) +
                           pool * ((8 * W + 8) * 2 + 12) + std::min(k, pool) * 24 + (1 << 20);
-    return (int64_t)(setup + main);
+    const uint64_t tables = spin_table_plan(r.norb, r.nalpha, r.nbeta, P, true).bytes;
+    return (int64_t)(setup + main + tables);
 }
 
 // ---------------------------------------------------------------- the pool
@@ -234,6 +235,7 @@ class Pool {
             (void)hipSetDevice(device_);
             w.ctx->setup.release();
             w.ctx->main.release();
+            w.ctx->tables.release();
         }
         w.resident = 0;
     }
@@ -304,7 +306,8 @@ class Pool {
                 me.busy = false;
                 me.reserved = 0;
                 me.resident = fake_ ? std::max(me.resident, j.footprint)
-                                    : (int64_t)(me.ctx->setup.capacity() + me.ctx->main.capacity());
+                                    : (int64_t)(me.ctx->setup.capacity() + me.ctx->main.capacity() +
+                                                me.ctx->tables.capacity());
                 --running_;
                 done_[j.ticket] = res;
                 if (res.status == ASCI_OK) {

@@ -274,6 +274,39 @@ def test_full_size_16e20o(asci, oracle_lib):
     assert (order == np.arange(len(gk))).all()
 
 
+SPIN_TABLE_CASES = [(12, 6, 6, 150, 41), (9, 5, 2, 60, 42), (34, 3, 2, 12, 43), (14, 7, 1, 80, 44), (6, 0, 3, 6, 45)]
+
+
+def test_spin_tables_change_no_bit(asci, oracle_lib):
+    """E(alpha) and E(beta) looked up from the rank-indexed tables or evaluated
+    directly give the same bits (one summation order); both match the oracle."""
+    ctx = asci.Context.get(0)
+    try:
+        for n, na, nb, nd, seed in SPIN_TABLE_CASES:
+            c = _case(n, na, nb, nd, seed=seed, sampler="level")
+            E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+            d = to_dev(c)
+            got = []
+            for flag in (1, 0):
+                ctx.set_param("spin_tables", flag)
+                _all_parity(asci, oracle_lib, c, E0)
+                got.append([host(t) for t in asci.candidates(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"],
+                                                             E0)])
+            for a, b in zip(*got):
+                assert a.shape == b.shape and a.tobytes() == b.tobytes()
+        # the full-size workload, direct evaluation: the stored hashes still hold
+        ctx.set_param("spin_tables", 0)
+        c = syn.workload("16e20o")
+        g = _golden("16e20o")
+        d = to_dev(c)
+        keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"],
+                                           float.fromhex(g["E0"]))
+        assert _sha(host(keys)) == g["cand_keys_sha256"]
+        assert _sha(host(score)) == g["cand_score_sha256"]
+    finally:
+        ctx.set_param("spin_tables", 1)
+
+
 LEVEL_CASES = [(12, 4, 4, 150, 31), (16, 6, 6, 300, 32), (34, 3, 2, 12, 33), (9, 2, 3, 30, 34), (14, 7, 1, 80, 35)]
 
 
