@@ -323,7 +323,7 @@ struct BucketArgs {
     double *pool_num = nullptr, *pool_score = nullptr;
     size_t pool_base = 0, pool_cap = 0;
 };
-size_t bucket_workspace_bytes(size_t P, size_t nc, int W);
+size_t bucket_workspace_bytes(size_t P, size_t nc, int W, int finish_cap);
 template <int W>
 void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, HostStage &hs);
 template <int W>
@@ -359,7 +359,7 @@ void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *d
                          std::vector<uint64_t> &counts, hipStream_t s);
 // closed-form pair count and workspace estimate of a request (server.hip)
 int64_t request_pairs(const asci_request &r);
-int64_t request_footprint(const asci_request &r, uint64_t cap_records);
+int64_t request_footprint(const asci_request &r, uint64_t cap_records, int finish_cap = 4096);
 
 // throws ASCI_EINVAL unless every determinant has na/nb electrons inside norb orbitals
 void validate_dets(asci_ctx *ctx, const uint64_t *dets, int64_t ndets, int n, int na, int nb, hipStream_t s);

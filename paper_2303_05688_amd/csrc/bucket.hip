@@ -122,18 +122,6 @@ struct SplitArgs {
     uint8_t *dig;                     // per record: its digit, from the histogram pass
 };
 
-// digit of a split on key bits: the w bits just below `top`, with w the
-// smallest width (at most 8) whose 2^w children average at most half the LDS
-// capacity
-__device__ __forceinline__ void split_digit(const Seg &s, uint32_t cap, int &sh, int &w)
-{
-    const int top = (int)seg_top(s);
-    int want = 1;
-    while (want < 8 && ((uint64_t)s.size << 1) > ((uint64_t)cap << want)) ++want;
-    w = want < top ? want : top;
-    sh = top - w;
-}
-
 // ranges of a splitter split: about half the LDS capacity each, 2 to 256
 __host__ __device__ __forceinline__ uint32_t split_ranges(uint32_t size, uint32_t cap)
 {
@@ -466,7 +454,6 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     if (skip[s]) return;  // uniform per block
     const Seg sg = a.segs[s];
     const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
-    const SplitRule rule = split_rule(sg, a.cap);
     const uint32_t ib = seg_buf(sg), ob = ib ^ 1u;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int i = tid; i < NW * 256; i += kTileT) (&s_wcnt[0][0])[i] = 0u;
@@ -572,16 +559,51 @@ __device__ __forceinline__ double diag_tab(const SpinTables &st, const double *J
     return ((ecore + spin_e(st, 0, X, hd, n, a)) + spin_e(st, 1, X, hd, n, b)) + cross_energy(J, n, a, b);
 }
 
+// The key as one 2n-bit value (alpha << n) | beta.  Bits [o, o + 32) of it:
+template <int W>
+__device__ __forceinline__ uint32_t key_window(uint64_t lo, uint64_t hi, int n, int o)
+{
+    if (W == 1) return o < 64 ? (uint32_t)(lo >> o) : 0u;
+    if (o >= n) return (uint32_t)(hi >> (o - n));
+    uint64_t x = lo >> o;
+    if (n - o < 32) x |= hi << (n - o);
+    return (uint32_t)x;
+}
+
+// lowest varying key bit (-1: none) and one past the highest
+template <int W>
+__device__ __forceinline__ int key_low(uint64_t vlo, uint64_t vhi, int n)
+{
+    if (vlo) return __builtin_ctzll(vlo);
+    if (W == 2 && vhi) return n + __builtin_ctzll(vhi);
+    return -1;
+}
+template <int W>
+__device__ __forceinline__ int key_top(uint64_t vlo, uint64_t vhi, int n)
+{
+    if (W == 2 && vhi) return n + 64 - __builtin_clzll(vhi);
+    if (vlo) return 64 - __builtin_clzll(vlo);
+    return 0;
+}
+
+// LDS of one workgroup.  Records stay where they were loaded (values in
+// input order); the sort permutes 16-bit record indices, ranking them by a
+// 32-bit window of each key that holds its varying bits.  After the sort the
+// buffers are reused: ix[cur ^ 1] holds the run heads, `ck` the per-alpha
+// cache, `aidx` (over the digit counters) each run's alpha slot.
 template <int W, int CAP, int NT>
 struct FinishLds {
     static constexpr int NW = NT / 64;
-    uint64_t klo[2][CAP];
-    uint64_t khi[2][W == 2 ? CAP : 1];
-    double val[2][CAP];
-    uint32_t wcnt[NW][256];
+    uint32_t ck[CAP];
+    uint16_t ix[2][CAP + 8];
+    double val[CAP];
+    union {
+        uint16_t wcnt[NW][256];
+        uint8_t aidx[CAP];
+    };
     uint32_t dbase[256];
     uint32_t tmp[NW];
-    uint32_t nruns;
+    uint32_t nruns, nalpha;
     uint64_t red[4][NW];  // per-wave OR / AND of the key words
 };
 
@@ -593,6 +615,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     using L = FinishLds<W, CAP, NT>;
     constexpr int NW = L::NW;
     constexpr int IT = CAP / NT;
+    static_assert(CAP % NT == 0 && NW * 256 * 2 >= CAP, "aidx must fit over the digit counters");
     const int n = f.n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -600,13 +623,15 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     const Seg sg = f.finals[sidx];
     const uint32_t buf = seg_buf(sg);
     const uint64_t nmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+    const uint64_t *gk = f.klo[buf] + sg.start;
+    const uint64_t *gh = f.khi[buf] + sg.start;
+    const double *gv = f.val[buf] + sg.start;
 
     if (seg_single(sg)) {
         // more records than fit in LDS, all with one key: sum in record order
         __syncthreads();
         if (tid == 0) {
-            const size_t j0 = sg.start;
-            const uint64_t lo = f.klo[buf][j0], hi = W == 2 ? f.khi[buf][j0] : 0ull;
+            const uint64_t lo = gk[0], hi = W == 2 ? gh[0] : 0ull;
             const bool ex = psi_contains(f.psi, lo, hi);
             uint32_t c = 0;
             if (!ex) {
@@ -615,12 +640,13 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                 double sum = 0.0;
                 uint32_t kept = 0;
                 for (uint32_t r = 0; r < sg.size; ++r) {
-                    const double v = f.val[buf][j0 + r];
+                    const double v = gv[r];
                     if (f.eps > 0.0 && !(fabs(v / den) > f.eps)) continue;
                     sum = sum + v;
                     ++kept;
                 }
                 if (kept) {
+                    const size_t j0 = sg.start;
                     f.clo[j0] = lo;
                     if (W == 2) f.chi[j0] = hi;
                     f.cnum[j0] = sum;
@@ -634,23 +660,20 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     }
 
     const uint32_t size = sg.size;
-    const int top = (int)seg_top(sg);
-    // load
-    for (uint32_t r = tid; r < size; r += NT) {
-        const size_t j = (size_t)sg.start + r;
-        S.klo[0][r] = f.klo[buf][j];
-        if (W == 2) S.khi[0][r] = f.khi[buf][j];
-        S.val[0][r] = f.val[buf][j];
-    }
-    // bits that vary inside the segment: digits without any are not sorted
+    // load: values to LDS, identity order; OR / AND of the keys give the bits
+    // that vary inside the segment (the keys are read again, from cache, for
+    // their windows)
     {
         uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
-        for (uint32_t r = tid; r < size; r += NT) {
-            const uint64_t lo = S.klo[0][r];
-            o0 |= lo;
-            a0 &= lo;
-            if (W == 2) {
-                const uint64_t hi = S.khi[0][r];
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
+            if (r < size) {
+                const uint64_t lo = gk[r], hi = W == 2 ? gh[r] : 0ull;
+                S.val[r] = gv[r];
+                S.ix[0][r] = (uint16_t)r;
+                o0 |= lo;
+                a0 &= lo;
                 o1 |= hi;
                 a1 &= hi;
             }
@@ -669,7 +692,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         }
     }
     __syncthreads();
-    uint64_t var_lo = 0ull, var_hi = 0ull;
+    uint64_t var_lo, var_hi;
     {
         uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
 #pragma unroll
@@ -682,129 +705,153 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         var_lo = o0 ^ a0;
         var_hi = W == 2 ? (o1 ^ a1) : 0ull;
     }
-    // stable LSD radix sort in LDS on the varying digits below `top`
+    const int low = key_low<W>(var_lo, var_hi, n);
+    const int span = low < 0 ? 0 : key_top<W>(var_lo, var_hi, n) - low;
+    const int nwin = (span + 31) / 32;  // 32-bit windows holding the varying bits
+
+    // stable LSD radix sort of the record indices, one window at a time
     int cur = 0;
-    for (int sh = 0; sh < top; sh += 8) {
-        const int w = (top - sh) < 8 ? (top - sh) : 8;
-        if (vdigit<W>(var_lo, var_hi, n, sh, w) == 0u) continue;  // uniform: constant digit
-        for (int i = tid; i < NW * 256; i += NT) (&S.wcnt[0][0])[i] = 0u;
+    for (int win = 0; win < nwin; ++win) {
+        const int o = low + 32 * win;
+        const uint32_t vwin = key_window<W>(var_lo, var_hi, n, o);
+        for (uint32_t r = tid; r < size; r += NT) S.ck[r] = key_window<W>(gk[r], W == 2 ? gh[r] : 0ull, n, o);
         __syncthreads();
-        uint32_t rrank[IT];
+        for (int sh = 0; sh < 32; sh += 8) {
+            const uint32_t dv = (vwin >> sh) & 0xFFu;
+            if (dv == 0u) continue;  // no record differs in these bits
+            const int w = 32 - __builtin_clz(dv);  // up to the highest varying bit
+            const uint32_t dmask = (1u << w) - 1u;
+            for (int i = lane; i < (1 << w); i += 64) S.wcnt[wv][i] = 0;
+            static_assert(CAP <= 4096, "rank and record index take 12 bits each");
+            uint32_t item[IT];  // rank | record << 12 | digit << 24
 #pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            if ((uint32_t)wv * 64 * IT + (uint32_t)q * 64 >= size) break;  // whole wave past the end
-            const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
-            const bool valid = li < size;
-            const uint64_t lo = valid ? S.klo[cur][li] : 0ull;
-            const uint64_t hi = (W == 2 && valid) ? S.khi[cur][li] : 0ull;
-            const uint32_t d = vdigit<W>(lo, hi, n, sh, w);
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const uint64_t bb = __ballot((d >> b) & 1u);
-                peers &= ((d >> b) & 1u) ? bb : ~bb;
+            for (int q = 0; q < IT; ++q) {
+                item[q] = 0u;
+                if ((uint32_t)wv * 64 * IT + (uint32_t)q * 64 >= size) continue;  // whole wave past the end
+                const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+                const bool valid = li < size;
+                const uint32_t r = valid ? S.ix[cur][li] : 0u;
+                const uint32_t d = valid ? (S.ck[r] >> sh) & dmask : 0u;
+                uint64_t peers = __ballot(valid);
+                for (int b = 0; b < w; ++b) {
+                    const uint64_t bb = __ballot((d >> b) & 1u);
+                    peers &= ((d >> b) & 1u) ? bb : ~bb;
+                }
+                const uint32_t before = S.wcnt[wv][d];
+                item[q] = (before + (uint32_t)__popcll(peers & lt)) | (r << 12) | (d << 24);
+                if (valid && (peers & lt) == 0ull) S.wcnt[wv][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
             }
-            const uint32_t before = S.wcnt[wv][d];
-            rrank[q] = before + (uint32_t)__popcll(peers & lt);
-            if (valid && (peers & lt) == 0ull) S.wcnt[wv][d] = before + (uint32_t)__popcll(peers);
-        }
-        __syncthreads();
-        {
-            uint32_t run = 0;
-            if (tid < 256) {
+            __syncthreads();
+            {
+                uint32_t run = 0;
+                if (tid < (1 << w)) {
 #pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    const uint32_t c = S.wcnt[i][tid];
-                    S.wcnt[i][tid] = run;
-                    run += c;
+                    for (int i = 0; i < NW; ++i) {
+                        const uint32_t c = S.wcnt[i][tid];
+                        S.wcnt[i][tid] = (uint16_t)run;
+                        run += c;
+                    }
+                }
+                uint32_t tot;
+                const uint32_t e = block_scan<NW>(tid < (1 << w) ? run : 0u, S.tmp, tot);
+                if (tid < (1 << w)) S.dbase[tid] = e;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < IT; ++q) {
+                const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+                if (li < size) {
+                    const uint32_t d = item[q] >> 24;
+                    const uint32_t p = min(S.dbase[d] + (uint32_t)S.wcnt[wv][d] + (item[q] & 0xFFFu), (uint32_t)CAP - 1u);
+                    S.ix[cur ^ 1][p] = (uint16_t)((item[q] >> 12) & 0xFFFu);
                 }
             }
-            uint32_t tot;
-            const uint32_t e = block_scan<NW>(tid < 256 ? run : 0u, S.tmp, tot);
-            if (tid < 256) S.dbase[tid] = e;
+            __syncthreads();
+            cur ^= 1;
         }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < IT; ++q) {
-            const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
-            if (li < size) {
-                const uint64_t lo = S.klo[cur][li];
-                const uint64_t hi = W == 2 ? S.khi[cur][li] : 0ull;
-                const uint32_t d = vdigit<W>(lo, hi, n, sh, w);
-                const uint32_t p = min(S.dbase[d] + S.wcnt[wv][d] + rrank[q], (uint32_t)CAP - 1u);
-                S.klo[cur ^ 1][p] = lo;
-                if (W == 2) S.khi[cur ^ 1][p] = hi;
-                S.val[cur ^ 1][p] = S.val[cur][li];
+    }
+    // runs of equal keys and the alpha strings among them.  Each thread owns IT
+    // consecutive sorted records; one scan of packed counts (runs low, alpha
+    // heads high) places both.  With one window the window decides equality,
+    // else the keys are read back from the segment.
+    uint16_t *head = &S.ix[cur ^ 1][0];
+    const uint16_t *perm = &S.ix[cur][0];
+    const int aw = n - low;  // window bits at or above this one are alpha bits (one-word keys: also two-word)
+    constexpr uint32_t kAlistBytes = CAP * 4;
+    const uint32_t amax = min(255u, kAlistBytes / (8u * (uint32_t)(n + 2)));
+    uint32_t nalpha, nruns;
+    {
+        const uint32_t j0 = (uint32_t)tid * IT;
+        uint32_t flags = 0;  // bit i: run head, bit 16 + i: alpha head
+        uint64_t prev_lo = 0ull, prev_hi = 0ull;
+        uint32_t prev_c = 0;
+        if (j0 > 0 && j0 < size) {
+            const uint32_t r = perm[j0 - 1];
+            if (nwin >= 2) {
+                prev_lo = gk[r];
+                prev_hi = W == 2 ? gh[r] : 0ull;
+            } else {
+                prev_c = nwin ? S.ck[r] : 0u;
             }
         }
-        __syncthreads();
-        cur ^= 1;
-    }
-    // runs of equal keys (record order inside a run is the input order); the
-    // run heads live in the key buffer the sort no longer needs.  Every thread
-    // owns IT consecutive records, later up to IT consecutive runs, so each
-    // phase needs a single block-wide scan.
-    uint16_t *head = reinterpret_cast<uint16_t *>(&S.klo[cur ^ 1][0]);
-    {
-        const uint32_t r0 = (uint32_t)tid * IT;
-        uint32_t c = 0;
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
-            const uint32_t r = r0 + i;
-            if (r < size && (r == 0 || S.klo[cur][r] != S.klo[cur][r - 1] ||
-                             (W == 2 && S.khi[cur][r] != S.khi[cur][r - 1])))
-                ++c;
+            const uint32_t j = j0 + i;
+            if (j >= size) continue;
+            const uint32_t r = perm[j];
+            bool rh, ah;
+            if (nwin >= 2) {
+                const uint64_t klo = gk[r], khi = W == 2 ? gh[r] : 0ull;
+                rh = j == 0 || klo != prev_lo || khi != prev_hi;
+                ah = j == 0 || (W == 1 ? (klo >> n) != (prev_lo >> n) : khi != prev_hi);
+                prev_lo = klo;
+                prev_hi = khi;
+            } else {
+                const uint32_t c = nwin ? S.ck[r] : 0u;
+                const uint32_t x = c ^ prev_c;
+                rh = j == 0 || x != 0u;
+                ah = j == 0 || (aw < 32 && (x >> max(aw, 0)) != 0u);
+                prev_c = c;
+            }
+            flags |= (rh ? 1u : 0u) << i;
+            flags |= (ah ? 1u : 0u) << (16 + i);
         }
+        const uint32_t cnt = (uint32_t)__popc(flags & 0xFFFFu) | ((uint32_t)__popc(flags >> 16) << 16);
         uint32_t tot;
-        uint32_t at = block_scan<NW>(c, S.tmp, tot);
+        const uint32_t at = block_scan<NW>(cnt, S.tmp, tot);
+        nruns = tot & 0xFFFFu;
+        nalpha = tot >> 16;
+        // counts are below 2^16 (size <= CAP <= 4096), so the packed scan is exact
+        uint32_t rb = at & 0xFFFFu, ab = at >> 16;
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
-            const uint32_t r = r0 + i;
-            if (r < size && (r == 0 || S.klo[cur][r] != S.klo[cur][r - 1] ||
-                             (W == 2 && S.khi[cur][r] != S.khi[cur][r - 1])))
-                head[at++] = (uint16_t)r;
+            if ((flags >> (16 + i)) & 1u) ++ab;
+            if ((flags >> i) & 1u) {
+                head[rb] = (uint16_t)(j0 + i);
+                S.aidx[rb] = (uint8_t)min(ab - 1u, 255u);
+                ++rb;
+            }
         }
-        if (tid == 0) {
-            head[tot] = (uint16_t)min(size, (uint32_t)CAP);
-            S.nruns = tot;
+        if (tid == 0) head[nruns] = (uint16_t)size;
+        __syncthreads();  // every read of the key windows is done
+        // alpha cache in the window buffer: strings, E(alpha), c_q(alpha)
+        if (nalpha <= amax) {
+            uint32_t a2 = at >> 16;
+            uint64_t *alist = reinterpret_cast<uint64_t *>(&S.ck[0]);
+#pragma unroll
+            for (int i = 0; i < IT; ++i)
+                if ((flags >> (16 + i)) & 1u) {
+                    const uint32_t r = perm[j0 + i];
+                    alist[a2++] = W == 1 ? (gk[r] >> n) : gh[r];
+                }
         }
         __syncthreads();
-    }
-    const uint32_t nruns = S.nruns;
-    const uint32_t rpt = (nruns + NT - 1) / NT;  // runs per thread, <= IT
-    const uint32_t u0 = (uint32_t)tid * rpt, u1 = min(u0 + rpt, nruns);
-    // The distinct alpha strings of the runs (the keys are sorted alpha-major):
-    // E(alpha) and c_q(alpha) of H_aa once per string, kept in the buffers the
-    // sort no longer needs; with more strings than fit, H_aa is evaluated per
-    // run instead (the same arithmetic).
-    constexpr uint32_t kAlistCap = (uint32_t)((CAP * 4 - 64) / 16);
-    uint16_t *aidx = head + CAP + 8;
-    uint64_t *alist = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(&S.klo[cur ^ 1][0]) + CAP * 4 + 64);
-    double *ealpha = reinterpret_cast<double *>(alist + kAlistCap);
-    double *colsum = &S.val[cur ^ 1][0];
-    const uint32_t amax = min(kAlistCap, (uint32_t)CAP / (uint32_t)n);
-    auto alpha_of = [&](uint32_t u) -> uint64_t {
-        const uint32_t j = head[u];
-        return W == 1 ? (S.klo[cur][j] >> n) : S.khi[cur][j];
-    };
-    uint32_t nalpha;
-    {
-        uint32_t c = 0;
-        for (uint32_t u = u0; u < u1; ++u)
-            if (u == 0 || alpha_of(u) != alpha_of(u - 1)) ++c;
-        uint32_t at = block_scan<NW>(c, S.tmp, nalpha);
-        for (uint32_t u = u0; u < u1; ++u) {
-            const uint64_t al = alpha_of(u);
-            if (u == 0 || al != alpha_of(u - 1)) {
-                if (at < amax) alist[at] = al;
-                ++at;
-            }
-            aidx[u] = (uint16_t)min(at - 1u, 65535u);
-        }
     }
     const bool cached = nalpha <= amax;
+    uint64_t *alist = reinterpret_cast<uint64_t *>(&S.ck[0]);
+    double *ealpha = reinterpret_cast<double *>(alist + amax);
+    double *colsum = ealpha + amax;
     if (cached) {
-        __syncthreads();
         for (uint32_t t = tid; t < nalpha * (uint32_t)n; t += NT) {
             const uint32_t ai = t / (uint32_t)n, q = t - ai * (uint32_t)n;
             colsum[t] = cross_col(J, n, alist[ai], (int)q);
@@ -812,29 +859,25 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_e(f.st, 0, X, hd, n, alist[t]);
         __syncthreads();
     }
-    // a thread's runs: sum, exclusion, diagonal, score; one scan places the
+    // runs, NT at a time: key (read back from the segment), exclusion,
+    // diagonal, sum in record order, score; one scan per round places the
     // surviving candidates, compacted, in run order
-    uint64_t olo[IT], ohi[IT];
-    double osum[IT], oscore[IT];
-    bool okeep[IT];
-    uint32_t kept = 0;
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const uint32_t u = u0 + (uint32_t)i;
-        okeep[i] = false;
-        osum[i] = oscore[i] = 0.0;
-        olo[i] = ohi[i] = 0ull;
-        if (u < u1) {
+    uint32_t written = 0;
+    for (uint32_t base = 0; base < nruns; base += NT) {
+        const uint32_t u = base + (uint32_t)tid;
+        bool keep = false;
+        uint64_t lo = 0ull, hi = 0ull;
+        double sum = 0.0, score = 0.0;
+        if (u < nruns) {
             const uint32_t j0 = head[u], j1 = head[u + 1];
-            const uint64_t lo = S.klo[cur][j0];
-            const uint64_t hi = W == 2 ? S.khi[cur][j0] : 0ull;
-            olo[i] = lo;
-            ohi[i] = hi;
+            const uint32_t r0 = perm[j0];
+            lo = gk[r0];
+            hi = W == 2 ? gh[r0] : 0ull;
             if (!psi_contains(f.psi, lo, hi)) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
                 double haa;
+                const uint32_t ai = S.aidx[u];
                 if (cached) {
-                    const uint32_t ai = aidx[u];
                     const double *cs = colsum + (size_t)ai * n;
                     double cross = 0.0;
                     for (uint64_t m = b; m; m &= m - 1ull) cross = cross + cs[lowbit(m)];
@@ -843,40 +886,32 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     haa = diag_tab(f.st, J, X, hd, n, f.ecore, a, b);
                 }
                 const double den = f.E0 - haa;
-                double sum = 0.0;
-                bool keep = false;
                 if (f.eps > 0.0) {
                     // Alg. 2's threshold, per pair, in record (ascending core) order
                     for (uint32_t j = j0; j < j1; ++j) {
-                        const double v = S.val[cur][j];
+                        const double v = S.val[perm[j]];
                         if (fabs(v / den) > f.eps) {
                             sum = sum + v;
                             keep = true;
                         }
                     }
                 } else {
-                    for (uint32_t j = j0; j < j1; ++j) sum = sum + S.val[cur][j];
+                    for (uint32_t j = j0; j < j1; ++j) sum = sum + S.val[perm[j]];
                     keep = true;
                 }
-                okeep[i] = keep;
-                osum[i] = sum;
-                oscore[i] = sum / den;
-                kept += keep ? 1u : 0u;
+                score = sum / den;
             }
         }
-    }
-    uint32_t written;
-    uint32_t at = block_scan<NW>(kept, S.tmp, written);
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        if (okeep[i]) {
-            const size_t d = (size_t)sg.start + at;
-            f.clo[d] = olo[i];
-            if (W == 2) f.chi[d] = ohi[i];
-            if (f.cnum) f.cnum[d] = osum[i];
-            f.cscore[d] = oscore[i];
-            ++at;
+        uint32_t tot;
+        const uint32_t at = block_scan<NW>(keep ? 1u : 0u, S.tmp, tot);
+        if (keep) {
+            const size_t d = (size_t)sg.start + written + at;
+            f.clo[d] = lo;
+            if (W == 2) f.chi[d] = hi;
+            if (f.cnum) f.cnum[d] = sum;
+            f.cscore[d] = score;
         }
+        written += tot;
     }
     if (tid == 0) f.cnt[sidx] = written;
 }
@@ -884,7 +919,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
 // persistent workgroups loop over the final segments (a grid of one
 // workgroup per segment could exceed the 2^32 work-item limit of a dispatch)
 template <int W, int CAP, int NT>
-__global__ __launch_bounds__(NT) void k_finish(FinishArgs f)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_finish(FinishArgs f)
 {
     using L = FinishLds<W, CAP, NT>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1017,16 +1052,9 @@ __global__ __launch_bounds__(256) void k_class_segs(const uint64_t *__restrict__
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-template <int W, int CAP, int NT>
-static constexpr size_t lds_max()
+size_t bucket_workspace_bytes(size_t P, size_t nc, int W, int finish_cap)
 {
-    return 160 * 1024;
-}
-
-
-size_t bucket_workspace_bytes(size_t P, size_t nc, int W)
-{
-    const size_t cap = W == 1 ? 4096 : 2048;
+    const size_t cap = finish_cap >= 4096 ? 4096 : (finish_cap >= 2048 ? 2048 : 1024);
     const size_t finals = nc + P / 8 + 65536, level = P / cap + nc + 16;
     const size_t tiles = (P + kTileN - 1) / kTileN + level;
     return finals * sizeof(Seg) + 2 * level * sizeof(Seg) + level * 16 + tiles * (256 * 8 + 8) +
@@ -1034,27 +1062,35 @@ size_t bucket_workspace_bytes(size_t P, size_t nc, int W)
            (4 << 20);
 }
 
+// LDS per workgroup: the table of J, J-K and h_pp is staged when the whole
+// still lets two workgroups share a CU (their barriers then overlap)
+constexpr size_t kFinishLdsBudget = 80 * 1024;
+
 template <int W, int CAP, int NT>
 static void launch_finish(FinishArgs &fa, const BucketArgs &b, uint32_t nf, hipStream_t s, Profiler *prof)
 {
     const size_t base_lds = (sizeof(FinishLds<W, CAP, NT>) + 15) & ~size_t(15);
     const size_t tab_lds = ((size_t)2 * b.n * b.n + b.n) * 8;
-    fa.tab_in_lds = base_lds + tab_lds <= lds_max<W, CAP, NT>() ? 1 : 0;
+    fa.tab_in_lds = base_lds + tab_lds <= kFinishLdsBudget ? 1 : 0;
     const size_t lds = base_lds + (fa.tab_in_lds ? tab_lds : 0);
-    ASCI_HIP(hipFuncSetAttribute((const void *)k_finish<W, CAP, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds_max<W, CAP, NT>()));
+    const void *fn = (const void *)k_finish<W, CAP, NT>;
+    ASCI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int dev = 0, ncu = 0, per_cu = 0;
+    ASCI_HIP(hipGetDevice(&dev));
+    ASCI_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    ASCI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds));
+    // one resident grid: every workgroup strides over the segments
+    const uint32_t grid = std::min<uint32_t>(nf, (uint32_t)std::max(1, ncu * std::max(per_cu, 1)));
     ProfScope ps(prof, "finish", (8.0 * W + 8.0) * (double)b.P, s);
-    k_finish<W, CAP, NT><<<std::min<uint32_t>(nf, 4096u), NT, lds, s>>>(fa);
+    k_finish<W, CAP, NT><<<grid, NT, lds, s>>>(fa);
     ASCI_LAUNCH_CHECK();
 }
 
 template <int W>
 void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, HostStage &hs)
 {
-    // LDS capacity of a final segment: 4096 or 2048 records (one-word keys),
-    // 2048 or 1024 (two-word keys)
-    const int CAP = W == 1 ? (b.finish_cap >= 4096 ? 4096 : (b.finish_cap >= 2048 ? 2048 : 1024))
-                           : (b.finish_cap >= 2048 ? 2048 : 1024);
+    // LDS capacity of a final segment: 4096, 2048 or 1024 records
+    const int CAP = b.finish_cap >= 4096 ? 4096 : (b.finish_cap >= 2048 ? 2048 : 1024);
     const size_t P = b.P;
     const uint32_t finals_cap = (uint32_t)std::min<size_t>(b.nc + P / 8 + 65536, 0xFFFFFFF0u);
     const uint32_t level_cap = (uint32_t)(P / CAP + b.nc + 16);
@@ -1178,15 +1214,10 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.cnt = cnt;
         fa.nfinal = nf;
         fa.psi = b.psi;
-        if constexpr (W == 1) {
-            // four records per thread: the more wavefronts, the more LDS latency is hidden
-            if (CAP == 4096) launch_finish<1, 4096, 1024>(fa, b, nf, s, prof);
-            else if (CAP == 2048) launch_finish<1, 2048, 512>(fa, b, nf, s, prof);
-            else launch_finish<1, 1024, 256>(fa, b, nf, s, prof);
-        } else {
-            if (CAP == 2048) launch_finish<2, 2048, 512>(fa, b, nf, s, prof);
-            else launch_finish<2, 1024, 256>(fa, b, nf, s, prof);
-        }
+        // eight records per thread
+        if (CAP == 4096) launch_finish<W, 4096, 512>(fa, b, nf, s, prof);
+        else if (CAP == 2048) launch_finish<W, 2048, 256>(fa, b, nf, s, prof);
+        else launch_finish<W, 1024, 128>(fa, b, nf, s, prof);
     }
     // candidates in key order: final segments by start, counts scanned
     uint64_t *sk[2] = {ar.take<uint64_t>(nf + 1), ar.take<uint64_t>(nf + 1)};

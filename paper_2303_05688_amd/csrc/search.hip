@@ -1088,7 +1088,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     for (const auto &bt : batches) max_nc = std::max<uint32_t>(max_nc, bt.second - bt.first);
     Arena &ar = ctx->main;
     ar.reset();
-    ar.reserve(E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, max_nc, W) +
+    ar.reserve(E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, max_nc, W, ctx->finish_cap) +
                pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 1) + kk_max * 24 + 64 * 256 + (1 << 16));
     ar.reset();
     uint32_t *counts = ar.take<uint32_t>(E);

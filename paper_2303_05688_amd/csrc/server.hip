@@ -40,7 +40,7 @@ int64_t request_pairs(const asci_request &r)
     return nq * per;
 }
 
-int64_t request_footprint(const asci_request &r, uint64_t cap_records)
+int64_t request_footprint(const asci_request &r, uint64_t cap_records, int finish_cap)
 {
     const int W = r.norb <= 32 ? 1 : 2;
     const int L = r.nalpha < 3 ? r.nalpha : 3;
@@ -58,7 +58,7 @@ int64_t request_footprint(const asci_request &r, uint64_t cap_records)
     const uint64_t pool = std::min<uint64_t>(P + 1, std::max<uint64_t>(4 * k, Pb) + k);
     const uint64_t setup = (uint64_t)r.ndets * 128 + (uint64_t)nq * 64 + (uint64_t)ncls * 16 +
                            (uint64_t)(2 * r.norb * r.norb + r.norb) * 8 + (1 << 20);
-    const uint64_t main = E * 8 + Pb * (2 * (8 * W + 8)) + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, nc, W) +
+    const uint64_t main = E * 8 + Pb * (2 * (8 * W + 8)) + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, nc, W, finish_cap) +
                           pool * ((8 * W + 8) * 2 + 12) + std::min(k, pool) * 24 + (1 << 20);
     const uint64_t tables = spin_table_plan(r.norb, r.nalpha, r.nbeta, P, true).bytes;
     return (int64_t)(setup + main + tables);
@@ -85,7 +85,7 @@ struct WorkerState {
 class Pool {
   public:
     Pool(int device, int64_t budget, int slots, bool fake, double ns_per_byte, int finish_cap)
-        : device_(device), budget_(budget), fake_(fake), ns_per_byte_(ns_per_byte)
+        : device_(device), budget_(budget), fake_(fake), ns_per_byte_(ns_per_byte), finish_cap_(finish_cap)
     {
         slots = std::max(1, std::min(slots, 16));
         cap_records_ = (uint64_t)std::max<int64_t>(1 << 20, std::min<int64_t>(1ll << 30, budget / slots / 160));
@@ -145,14 +145,14 @@ class Pool {
         return q;
     }
 
-    int64_t footprint(const asci_request &r) const { return request_footprint(shaped(r), cap_records_); }
+    int64_t footprint(const asci_request &r) const { return request_footprint(shaped(r), cap_records_, finish_cap_); }
 
     int submit(const asci_request &r, uint64_t *ticket)
     {
         Job j;
         j.req = shaped(r);
         j.pairs = request_pairs(r);
-        j.footprint = request_footprint(j.req, cap_records_);
+        j.footprint = request_footprint(j.req, cap_records_, finish_cap_);
         std::unique_lock<std::mutex> lk(mu_);
         j.ticket = next_ticket_++;
         *ticket = j.ticket;
@@ -329,6 +329,7 @@ class Pool {
     bool fake_;
     double ns_per_byte_;
     uint64_t cap_records_ = 1 << 26;
+    int finish_cap_ = 4096;
     std::vector<std::unique_ptr<WorkerState>> ws_;
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_;
