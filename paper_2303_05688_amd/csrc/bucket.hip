@@ -31,8 +31,9 @@ namespace asci {
 
 namespace {
 
-constexpr int kTileT = 256;           // threads of tile kernels
-constexpr int kTileItems = 16;
+constexpr int kTileT = 512;           // threads of the scatter (two workgroups per CU)
+constexpr int kTileItems = 8;
+constexpr int kHistT = 256;           // threads of the histogram pass
 constexpr int kTileN = kTileT * kTileItems;  // 4096 records per tile
 
 struct Seg {
@@ -266,9 +267,9 @@ __global__ __launch_bounds__(256) void k_seg_expand(const Seg *__restrict__ segs
 }
 
 template <int W>
-__global__ __launch_bounds__(kTileT) void k_split_hist(SplitArgs a)
+__global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
 {
-    __shared__ uint32_t h[kTileT / 64][256];
+    __shared__ uint32_t h[kHistT / 64][256];
     __shared__ uint64_t spl_lo[kMaxSplit - 1];
     __shared__ uint64_t spl_hi[W == 2 ? kMaxSplit - 1 : 1];
     const uint32_t t = blockIdx.x;
@@ -277,12 +278,12 @@ __global__ __launch_bounds__(kTileT) void k_split_hist(SplitArgs a)
     const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
     const SplitRule rule = split_rule(sg, a.cap);
     const uint32_t buf = seg_buf(sg);
-    for (int i = threadIdx.x; i < (kTileT / 64) * 256; i += kTileT) (&h[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < (kHistT / 64) * 256; i += kHistT) (&h[0][0])[i] = 0u;
     load_splitters<W>(rule, a.spl_lo, a.spl_hi, s, spl_lo, spl_hi);
     const uint32_t r0 = tl * kTileN, r1 = min(sg.size, r0 + kTileN);
     const int wv = threadIdx.x >> 6;
     uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kTileT) {
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kHistT) {
         const size_t j = (size_t)sg.start + r;
         const uint64_t lo = a.klo[buf][j];
         const uint64_t hi = W == 2 ? a.khi[buf][j] : 0ull;
@@ -311,10 +312,12 @@ __global__ __launch_bounds__(kTileT) void k_split_hist(SplitArgs a)
     }
     __syncthreads();
     const int d = threadIdx.x;
-    uint32_t c = 0;
+    if (d < 256) {
+        uint32_t c = 0;
 #pragma unroll
-    for (int i = 0; i < kTileT / 64; ++i) c += h[i][d];
-    a.hist[(size_t)tb * 256 + (size_t)d * nt + tl] = c;
+        for (int i = 0; i < kHistT / 64; ++i) c += h[i][d];
+        a.hist[(size_t)tb * 256 + (size_t)d * nt + tl] = c;
+    }
 }
 
 // children of every large segment (one block of 256 threads per segment).
@@ -487,16 +490,21 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     {
         const int d = tid;
         uint32_t run = 0;
+        if (d < 256) {
 #pragma unroll
-        for (int i = 0; i < NW; ++i) {
-            const uint32_t c = s_wcnt[i][d];
-            s_wcnt[i][d] = run;
-            run += c;
+            for (int i = 0; i < NW; ++i) {
+                const uint32_t c = s_wcnt[i][d];
+                s_wcnt[i][d] = run;
+                run += c;
+            }
         }
         uint32_t tot;
-        s_dbase[d] = block_scan<NW>(run, s_tmp, tot);
-        const size_t b0 = (size_t)tb * 256;
-        s_gbase[d] = sg.start + (a.hist[b0 + (size_t)d * nt + tl] - a.hist[b0]);
+        const uint32_t e = block_scan<NW>(d < 256 ? run : 0u, s_tmp, tot);
+        if (d < 256) {
+            s_dbase[d] = e;
+            const size_t b0 = (size_t)tb * 256;
+            s_gbase[d] = sg.start + (a.hist[b0 + (size_t)d * nt + tl] - a.hist[b0]);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -1166,7 +1174,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         sa.dig = dig;
         {
             ProfScope ps(prof, "split_hist", (8.0 * W) * (double)ntiles * kTileN, s);
-            k_split_hist<W><<<ntiles, kTileT, 0, s>>>(sa);
+            k_split_hist<W><<<ntiles, kHistT, 0, s>>>(sa);
             ASCI_LAUNCH_CHECK();
         }
         scan_u32(hist, hscan, (size_t)ntiles * 256, nullptr, ar, s, prof);
