@@ -578,6 +578,23 @@ __device__ __forceinline__ uint32_t key_window(uint64_t lo, uint64_t hi, int n, 
     return (uint32_t)x;
 }
 
+// OR a 32-bit window c into bits [o, o + 32) of the key (bits past 2n are 0 in c)
+template <int W>
+__device__ __forceinline__ void key_put(uint32_t c, int o, int n, uint64_t &lo, uint64_t &hi)
+{
+    if (W == 1) {
+        lo |= (uint64_t)c << o;
+        return;
+    }
+    if (o >= n) {
+        hi |= (uint64_t)c << (o - n);
+        return;
+    }
+    const uint64_t nmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+    lo |= ((uint64_t)c << o) & nmask;
+    if (n - o < 32) hi |= (uint64_t)c >> (n - o);
+}
+
 // lowest varying key bit (-1: none) and one past the highest
 template <int W>
 __device__ __forceinline__ int key_low(uint64_t vlo, uint64_t vhi, int n)
@@ -594,17 +611,20 @@ __device__ __forceinline__ int key_top(uint64_t vlo, uint64_t vhi, int n)
     return 0;
 }
 
-// LDS of one workgroup.  Records stay where they were loaded (values in
-// input order); the sort permutes 16-bit record indices, ranking them by a
-// 32-bit window of each key that holds its varying bits.  After the sort the
-// buffers are reused: ix[cur ^ 1] holds the run heads, `ck` the per-alpha
-// cache, `aidx` (over the digit counters) each run's alpha slot.
+// LDS of one workgroup.  Values stay where they were loaded (input order);
+// the sort permutes 16-bit record indices, ranking them by a 32-bit window of
+// each key that holds its varying bits (a key is rebuilt from its window and
+// the segment's constant bits).  After the sort ix[cur ^ 1] holds the run
+// heads, `aidx` (over the digit counters) each run's alpha slot, and `acache`
+// the strings, E(alpha) and c_q(alpha) of up to a few dozen alpha strings.
 template <int W, int CAP, int NT>
 struct FinishLds {
     static constexpr int NW = NT / 64;
+    static constexpr uint32_t kAcacheBytes = CAP;
     uint32_t ck[CAP];
     uint16_t ix[2][CAP + 8];
     double val[CAP];
+    uint64_t acache[kAcacheBytes / 8];
     union {
         uint16_t wcnt[NW][256];
         uint8_t aidx[CAP];
@@ -700,7 +720,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         }
     }
     __syncthreads();
-    uint64_t var_lo, var_hi;
+    uint64_t var_lo, var_hi, and_lo, and_hi;
     {
         uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
 #pragma unroll
@@ -712,6 +732,8 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         }
         var_lo = o0 ^ a0;
         var_hi = W == 2 ? (o1 ^ a1) : 0ull;
+        and_lo = a0;
+        and_hi = W == 2 ? a1 : 0ull;
     }
     const int low = key_low<W>(var_lo, var_hi, n);
     const int span = low < 0 ? 0 : key_top<W>(var_lo, var_hi, n) - low;
@@ -785,8 +807,10 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     uint16_t *head = &S.ix[cur ^ 1][0];
     const uint16_t *perm = &S.ix[cur][0];
     const int aw = n - low;  // window bits at or above this one are alpha bits (one-word keys: also two-word)
-    constexpr uint32_t kAlistBytes = CAP * 4;
-    const uint32_t amax = min(255u, kAlistBytes / (8u * (uint32_t)(n + 2)));
+    const uint32_t amax = min(255u, L::kAcacheBytes / (8u * (uint32_t)(n + 2)));
+    uint64_t *alist = &S.acache[0];
+    double *ealpha = reinterpret_cast<double *>(alist + amax);
+    double *colsum = ealpha + amax;
     uint32_t nalpha, nruns;
     {
         const uint32_t j0 = (uint32_t)tid * IT;
@@ -841,24 +865,26 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             }
         }
         if (tid == 0) head[nruns] = (uint16_t)size;
-        __syncthreads();  // every read of the key windows is done
-        // alpha cache in the window buffer: strings, E(alpha), c_q(alpha)
+        // the alpha strings, in order
         if (nalpha <= amax) {
             uint32_t a2 = at >> 16;
-            uint64_t *alist = reinterpret_cast<uint64_t *>(&S.ck[0]);
 #pragma unroll
             for (int i = 0; i < IT; ++i)
                 if ((flags >> (16 + i)) & 1u) {
                     const uint32_t r = perm[j0 + i];
-                    alist[a2++] = W == 1 ? (gk[r] >> n) : gh[r];
+                    uint64_t klo = and_lo, khi = and_hi;
+                    if (nwin >= 2) {
+                        klo = gk[r];
+                        khi = W == 2 ? gh[r] : 0ull;
+                    } else if (nwin == 1) {
+                        key_put<W>(S.ck[r], low, n, klo, khi);
+                    }
+                    alist[a2++] = W == 1 ? (klo >> n) : khi;
                 }
         }
         __syncthreads();
     }
     const bool cached = nalpha <= amax;
-    uint64_t *alist = reinterpret_cast<uint64_t *>(&S.ck[0]);
-    double *ealpha = reinterpret_cast<double *>(alist + amax);
-    double *colsum = ealpha + amax;
     if (cached) {
         for (uint32_t t = tid; t < nalpha * (uint32_t)n; t += NT) {
             const uint32_t ai = t / (uint32_t)n, q = t - ai * (uint32_t)n;
@@ -879,8 +905,14 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
         if (u < nruns) {
             const uint32_t j0 = head[u], j1 = head[u + 1];
             const uint32_t r0 = perm[j0];
-            lo = gk[r0];
-            hi = W == 2 ? gh[r0] : 0ull;
+            lo = and_lo;
+            hi = and_hi;
+            if (nwin >= 2) {
+                lo = gk[r0];
+                hi = W == 2 ? gh[r0] : 0ull;
+            } else if (nwin == 1) {
+                key_put<W>(S.ck[r0], low, n, lo, hi);
+            }
             if (!psi_contains(f.psi, lo, hi)) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
                 double haa;
