@@ -147,6 +147,23 @@ namespace asci {
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ int lowbit(uint64_t x) { return __ffsll((unsigned long long)x) - 1; }
 
+// Lanes of the wavefront whose (active, key) equal this lane's, key < 2^nbits:
+// one ballot per key bit.  The bit is taken sign-extended (0 or all ones), so
+// folding a ballot into the mask is a single three-input logic op per half.
+__device__ __forceinline__ uint64_t wave_match(uint32_t key, bool active, int nbits)
+{
+    const uint64_t act = __builtin_amdgcn_ballot_w64(active);
+    uint32_t plo = (uint32_t)act, phi = (uint32_t)(act >> 32);
+#pragma nounroll
+    for (int b = 0; b < nbits; ++b) {
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)key, b, 1);
+        const uint64_t bb = __builtin_amdgcn_ballot_w64(m != 0u);
+        plo &= ~((uint32_t)bb ^ m);
+        phi &= ~((uint32_t)(bb >> 32) ^ m);
+    }
+    return ((uint64_t)phi << 32) | plo;
+}
+
 // index of the k-th (0-based) set bit of x; requires k < popc64(x)
 __device__ __forceinline__ int select_bit(uint64_t x, int k)
 {

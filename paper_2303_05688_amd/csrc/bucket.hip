@@ -476,12 +476,7 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
         rv[q] = valid ? a.val[ib][j] : 0.0;
         const uint32_t d = valid ? (uint32_t)a.dig[j] : 0u;
         rd[q] = d;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bb = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bb : ~bb;
-        }
+        const uint64_t peers = wave_match(d, valid, 8);
         const uint32_t before = s_wcnt[wv][d];
         rrank[q] = before + (uint32_t)__popcll(peers & lt);
         if (valid && (peers & lt) == 0ull) s_wcnt[wv][d] = before + (uint32_t)__popcll(peers);
@@ -762,29 +757,42 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                 const bool valid = li < size;
                 const uint32_t r = valid ? S.ix[cur][li] : 0u;
                 const uint32_t d = valid ? (S.ck[r] >> sh) & dmask : 0u;
-                uint64_t peers = __ballot(valid);
-                for (int b = 0; b < w; ++b) {
-                    const uint64_t bb = __ballot((d >> b) & 1u);
-                    peers &= ((d >> b) & 1u) ? bb : ~bb;
-                }
+                const uint64_t peers = wave_match(d, valid, w);
                 const uint32_t before = S.wcnt[wv][d];
                 item[q] = (before + (uint32_t)__popcll(peers & lt)) | (r << 12) | (d << 24);
                 if (valid && (peers & lt) == 0ull) S.wcnt[wv][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
             }
             __syncthreads();
-            {
-                uint32_t run = 0;
-                if (tid < (1 << w)) {
+            if (wv == 0) {
+                // one wavefront scans the (digit, wave) counts: each lane takes up
+                // to four consecutive digits, then one scan across the lanes
+                const int nd = 1 << w, dpl = (nd + 63) >> 6;
+                uint32_t dsum[4], lane_tot = 0;
 #pragma unroll
-                    for (int i = 0; i < NW; ++i) {
-                        const uint32_t c = S.wcnt[i][tid];
-                        S.wcnt[i][tid] = (uint16_t)run;
-                        run += c;
+                for (int k = 0; k < 4; ++k) {
+                    dsum[k] = 0;
+                    const int dg = lane * dpl + k;
+                    if (k < dpl && dg < nd) {
+                        uint32_t run = 0;
+#pragma unroll
+                        for (int i = 0; i < NW; ++i) {
+                            const uint32_t c = S.wcnt[i][dg];
+                            S.wcnt[i][dg] = (uint16_t)run;
+                            run += c;
+                        }
+                        dsum[k] = run;
+                        lane_tot += run;
                     }
                 }
-                uint32_t tot;
-                const uint32_t e = block_scan<NW>(tid < (1 << w) ? run : 0u, S.tmp, tot);
-                if (tid < (1 << w)) S.dbase[tid] = e;
+                uint32_t base = wave_incl_scan(lane_tot) - lane_tot;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int dg = lane * dpl + k;
+                    if (k < dpl && dg < nd) {
+                        S.dbase[dg] = base;
+                        base += dsum[k];
+                    }
+                }
             }
             __syncthreads();
 #pragma unroll

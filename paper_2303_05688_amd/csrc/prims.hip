@@ -167,12 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(
         rhi[s] = (W == 2 && valid) ? ihi[j] : 0ull;
         rv[s] = valid ? ival[j] : V(0);
         uint32_t d = digit_of<W>(rlo[s], rhi[s], word, shift);
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            uint64_t bb = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bb : ~bb;
-        }
+        const uint64_t peers = wave_match(d, valid, 8);
         uint32_t before = s_wcnt[w][d];
         rrank[s] = before + (uint32_t)__popcll(peers & lt);
         if (valid && (peers & lt) == 0ull) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);

@@ -157,18 +157,6 @@ __device__ __forceinline__ uint32_t class_of(uint64_t a, const ClassMap &m)
     return e;
 }
 
-// lanes of the wave whose (active, key) equal this lane's, key < 2^nbits
-__device__ __forceinline__ uint64_t match_peers(uint32_t key, bool active, int nbits)
-{
-    uint64_t peers = __ballot(active);
-    for (int b = 0; b < nbits; ++b) {
-        const bool bit = (key >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        peers &= bit ? bb : ~bb;
-    }
-    return peers;
-}
-
 struct GenArgs {
     const uint64_t *core_a, *core_b;
     const double *core_c;
@@ -309,7 +297,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const uint32_t lc = u < g.nas ? asP[u] : ~0u;
         const bool act = lc != ~0u;
         const uint32_t key = act ? lc : 0u;
-        const uint64_t peers = match_peers(key, act, g.nbits);
+        const uint64_t peers = wave_match(key, act, g.nbits);
         const uint32_t before = cur[key];
         const uint64_t sel = __ballot(act);
         const uint32_t nsel0 = s_nsel;
@@ -359,7 +347,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             }
             const bool act = c >= g.c0 && c < g.c0 + g.nc;
             const uint32_t key = act ? c - g.c0 : 0u;
-            const uint64_t peers = match_peers(key, act, g.nbits);
+            const uint64_t peers = wave_match(key, act, g.nbits);
             const uint32_t before = cur[key];
             if (act) {
                 const size_t dst = (size_t)g.offsets[(size_t)key * g.nq + i] + before + (uint32_t)__popcll(peers & lt);
