@@ -749,17 +749,33 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             for (int i = lane; i < (1 << w); i += 64) S.wcnt[wv][i] = 0;
             static_assert(CAP <= 4096, "rank and record index take 12 bits each");
             uint32_t item[IT];  // rank | record << 12 | digit << 24
+            // records and digits of all items first, so their loads overlap (the
+            // loads are unconditional and in bounds; past the segment's end the
+            // values are ignored)
+            static_assert((CAP & (CAP - 1)) == 0, "CAP must be a power of two");
 #pragma unroll
             for (int q = 0; q < IT; ++q) {
-                item[q] = 0u;
-                if ((uint32_t)wv * 64 * IT + (uint32_t)q * 64 >= size) continue;  // whole wave past the end
+                const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+                item[q] = (uint32_t)S.ix[cur][li] & (uint32_t)(CAP - 1);
+            }
+            uint32_t cw[IT];
+#pragma unroll
+            for (int q = 0; q < IT; ++q) cw[q] = S.ck[item[q]];
+#pragma unroll
+            for (int q = 0; q < IT; ++q) {
+                const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+                const uint32_t v = (item[q] << 12) | (((cw[q] >> sh) & dmask) << 24);
+                item[q] = li < size ? v : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < IT; ++q) {
+                if ((uint32_t)wv * 64 * IT + (uint32_t)q * 64 >= size) break;  // whole wave past the end
                 const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
                 const bool valid = li < size;
-                const uint32_t r = valid ? S.ix[cur][li] : 0u;
-                const uint32_t d = valid ? (S.ck[r] >> sh) & dmask : 0u;
+                const uint32_t d = item[q] >> 24;
                 const uint64_t peers = wave_match(d, valid, w);
                 const uint32_t before = S.wcnt[wv][d];
-                item[q] = (before + (uint32_t)__popcll(peers & lt)) | (r << 12) | (d << 24);
+                item[q] |= before + (uint32_t)__popcll(peers & lt);
                 if (valid && (peers & lt) == 0ull) S.wcnt[wv][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
             }
             __syncthreads();
@@ -921,7 +937,11 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             } else if (nwin == 1) {
                 key_put<W>(S.ck[r0], low, n, lo, hi);
             }
-            if (!psi_contains(f.psi, lo, hi)) {
+            // the first probe of the exclusion test is issued before H_aa and
+            // the sum are formed, so its latency overlaps theirs
+            const uint32_t slot = psi_hash(lo, hi, f.psi.mask);
+            const uint32_t st0 = f.psi.state[slot];
+            {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
                 double haa;
                 const uint32_t ai = S.aidx[u];
@@ -948,6 +968,19 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     keep = true;
                 }
                 score = sum / den;
+            }
+            // an input determinant is not a candidate (rare: finish the probe)
+            if (st0 != 0u && keep) {
+                uint32_t sl = slot;
+                bool found = false;
+                for (uint32_t st = st0; st != 0u; st = f.psi.state[sl]) {
+                    if (f.psi.lo[sl] == lo && f.psi.hi[sl] == hi) {
+                        found = true;
+                        break;
+                    }
+                    sl = (sl + 1u) & f.psi.mask;
+                }
+                keep = !found;
             }
         }
         uint32_t tot;

@@ -127,16 +127,32 @@ __device__ __forceinline__ double cross_energy(const double *J, int n, uint64_t 
 
 // combinatorial rank of a spin string: sum over its set bits p_1 < p_2 < ...
 // of C(p_j, j), with binom[k * (n + 1) + p] = C(p, k)
-__device__ __forceinline__ uint32_t spin_rank(const uint32_t *binom, int n, uint64_t s)
+// (four table loads in flight at a time; integer sums need no order)
+template <typename M>
+__device__ __forceinline__ uint32_t spin_rank_m(const uint32_t *binom, int n, M m)
 {
     uint32_t r = 0;
     const uint32_t *row = binom + (n + 1);
-    if (n <= 32) {
-        for (uint32_t m = (uint32_t)s; m; m &= m - 1, row += n + 1) r += row[tz(m)];
-    } else {
-        for (uint64_t m = s; m; m &= m - 1, row += n + 1) r += row[tz(m)];
+    while (m) {
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = 0u;
+            if (m) {
+                v[k] = row[k * (n + 1) + tz(m)];
+                m &= m - 1;
+            }
+        }
+        r += (v[0] + v[1]) + (v[2] + v[3]);
+        row += 4 * (n + 1);
     }
     return r;
+}
+
+__device__ __forceinline__ uint32_t spin_rank(const uint32_t *binom, int n, uint64_t s)
+{
+    if (n <= 32) return spin_rank_m<uint32_t>(binom, n, (uint32_t)s);
+    return spin_rank_m<uint64_t>(binom, n, s);
 }
 
 __device__ __forceinline__ double cross_col(const double *J, int n, uint64_t a, int q)
