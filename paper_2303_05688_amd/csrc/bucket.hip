@@ -606,10 +606,10 @@ __device__ __forceinline__ int key_top(uint64_t vlo, uint64_t vhi, int n)
     return 0;
 }
 
-// LDS of one workgroup.  Values stay where they were loaded (input order);
-// the sort permutes 16-bit record indices, ranking them by a 32-bit window of
-// each key that holds its varying bits (a key is rebuilt from its window and
-// the segment's constant bits).  After the sort ix[cur ^ 1] holds the run
+// LDS of one workgroup.  The sort permutes 16-bit record indices, ranking
+// them by a 32-bit window of each key that holds its varying bits (a key is
+// rebuilt from its window and the segment's constant bits); the values are
+// then gathered from the segment in sorted order.  After the sort ix[cur ^ 1] holds the run
 // heads, `aidx` (over the digit counters) each run's alpha slot, and `acache`
 // the strings, E(alpha) and c_q(alpha) of up to a few dozen alpha strings.
 template <int W, int CAP, int NT>
@@ -683,9 +683,9 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     }
 
     const uint32_t size = sg.size;
-    // load: values to LDS, identity order; OR / AND of the keys give the bits
-    // that vary inside the segment (the keys are read again, from cache, for
-    // their windows)
+    // identity order; OR / AND of the keys give the bits that vary inside the
+    // segment (the keys are read again, from cache, for their windows; the
+    // values are gathered in sorted order once the sort is done)
     {
         uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
 #pragma unroll
@@ -693,7 +693,6 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
             if (r < size) {
                 const uint64_t lo = gk[r], hi = W == 2 ? gh[r] : 0ull;
-                S.val[r] = gv[r];
                 S.ix[0][r] = (uint16_t)r;
                 o0 |= lo;
                 a0 &= lo;
@@ -830,6 +829,17 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     // else the keys are read back from the segment.
     uint16_t *head = &S.ix[cur ^ 1][0];
     const uint16_t *perm = &S.ix[cur][0];
+    // values in sorted order: each thread gathers the IT consecutive positions
+    // it owns below (all loads in flight together; the segment is in cache)
+    {
+        const uint32_t j0 = (uint32_t)tid * IT;
+        double v[IT];
+#pragma unroll
+        for (int i = 0; i < IT; ++i) v[i] = j0 + i < size ? gv[perm[j0 + i]] : 0.0;
+#pragma unroll
+        for (int i = 0; i < IT; ++i)
+            if (j0 + i < size) S.val[j0 + i] = v[i];
+    }
     const int aw = n - low;  // window bits at or above this one are alpha bits (one-word keys: also two-word)
     const uint32_t amax = min(255u, L::kAcacheBytes / (8u * (uint32_t)(n + 2)));
     uint64_t *alist = &S.acache[0];
@@ -954,17 +964,18 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     haa = diag_tab(f.st, J, X, hd, n, f.ecore, a, b);
                 }
                 const double den = f.E0 - haa;
+                // the run's values, in sorted (= record, ascending core) order
                 if (f.eps > 0.0) {
-                    // Alg. 2's threshold, per pair, in record (ascending core) order
+                    // Alg. 2's threshold, per pair
                     for (uint32_t j = j0; j < j1; ++j) {
-                        const double v = S.val[perm[j]];
+                        const double v = S.val[j];
                         if (fabs(v / den) > f.eps) {
                             sum = sum + v;
                             keep = true;
                         }
                     }
                 } else {
-                    for (uint32_t j = j0; j < j1; ++j) sum = sum + S.val[perm[j]];
+                    for (uint32_t j = j0; j < j1; ++j) sum = sum + S.val[j];
                     keep = true;
                 }
                 score = sum / den;
