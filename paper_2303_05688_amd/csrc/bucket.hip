@@ -830,15 +830,13 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     uint16_t *head = &S.ix[cur ^ 1][0];
     const uint16_t *perm = &S.ix[cur][0];
     // values in sorted order: each thread gathers the IT consecutive positions
-    // it owns below (all loads in flight together; the segment is in cache)
+    // it owns below (all loads in flight together, stored at the end of the
+    // run-head pass so that their latency overlaps it)
+    double gval[IT];
     {
         const uint32_t j0 = (uint32_t)tid * IT;
-        double v[IT];
 #pragma unroll
-        for (int i = 0; i < IT; ++i) v[i] = j0 + i < size ? gv[perm[j0 + i]] : 0.0;
-#pragma unroll
-        for (int i = 0; i < IT; ++i)
-            if (j0 + i < size) S.val[j0 + i] = v[i];
+        for (int i = 0; i < IT; ++i) gval[i] = j0 + i < size ? gv[perm[j0 + i]] : 0.0;
     }
     const int aw = n - low;  // window bits at or above this one are alpha bits (one-word keys: also two-word)
     const uint32_t amax = min(255u, L::kAcacheBytes / (8u * (uint32_t)(n + 2)));
@@ -916,6 +914,9 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     alist[a2++] = W == 1 ? (klo >> n) : khi;
                 }
         }
+#pragma unroll
+        for (int i = 0; i < IT; ++i)
+            if (j0 + i < size) S.val[j0 + i] = gval[i];
         __syncthreads();
     }
     const bool cached = nalpha <= amax;
