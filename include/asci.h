@@ -121,6 +121,12 @@ int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value);
  * once index is past the last entry; name receives at most name_cap - 1 chars.
  */
 int asci_ctx_set_profiling(asci_ctx *ctx, int enable);
+/*
+ * Restrict profiling to the launches of one kernel name (null or "" = every
+ * timed kernel), so that the events bracket only that kernel; set before
+ * asci_ctx_set_profiling.
+ */
+int asci_ctx_profile_only(asci_ctx *ctx, const char *kernel);
 int asci_ctx_profile_entry(asci_ctx *ctx, int index, char *name, int name_cap, double *total_ms,
                            int64_t *launches, double *bytes);
 

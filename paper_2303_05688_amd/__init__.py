@@ -114,6 +114,7 @@ _lib.asci_run_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, 
                                  C.POINTER(C.c_int32), _vp]
 
 _lib.asci_ctx_set_profiling.argtypes = [_vp, C.c_int]
+_lib.asci_ctx_profile_only.argtypes = [_vp, C.c_char_p]
 _lib.asci_ctx_set_param.argtypes = [_vp, C.c_char_p, C.c_int64]
 _lib.asci_ctx_get_param.argtypes = [_vp, C.c_char_p, _ip]
 _lib.asci_ctx_profile_entry.argtypes = [_vp, C.c_int, C.c_char_p, C.c_int, _dp, _ip, _dp]
@@ -134,7 +135,7 @@ _lib.asci_server_destroy.argtypes = [_vp]
 
 EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_default", "asci_ctx_create",
            "asci_ctx_destroy", "asci_ctx_set_param", "asci_ctx_get_param", "asci_ctx_set_profiling",
-           "asci_ctx_profile_entry", "asci_search",
+           "asci_ctx_profile_only", "asci_ctx_profile_entry", "asci_search",
            "asci_search_device", "asci_candidates_device", "asci_pt2_device", "asci_class_counts_device",
            "asci_energy_device", "asci_balance_classes", "asci_hmat_build_device", "asci_hmat_info",
            "asci_hmat_export", "asci_hmat_matvec_device", "asci_hmat_destroy", "asci_davidson_device",
@@ -187,7 +188,9 @@ class Context:
         _check(_lib.asci_ctx_get_param(self.ptr, name.encode(), C.byref(v)))
         return v.value
 
-    def set_profiling(self, enable=True):
+    def set_profiling(self, enable=True, only=None):
+        """Per-kernel timing; `only` restricts the events to one kernel name."""
+        _check(_lib.asci_ctx_profile_only(self.ptr, (only or "").encode()))
         _check(_lib.asci_ctx_set_profiling(self.ptr, int(bool(enable))))
 
     def profile(self):

@@ -230,6 +230,17 @@ int asci_ctx_set_profiling(asci_ctx *ctx, int enable)
     }
 }
 
+int asci_ctx_profile_only(asci_ctx *ctx, const char *kernel)
+{
+    try {
+        require(ctx != nullptr, ASCI_EINVAL, "null context");
+        ctx->prof.only = kernel ? std::string(kernel) : std::string();
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    }
+}
+
 int asci_ctx_profile_entry(asci_ctx *ctx, int index, char *name, int name_cap, double *total_ms,
                            int64_t *launches, double *bytes)
 {

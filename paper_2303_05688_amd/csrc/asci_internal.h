@@ -81,6 +81,7 @@ class Profiler {
   public:
     ~Profiler();
     bool on = false;
+    std::string only;  // non-empty: time only launches of this name
     std::vector<ProfEntry> entries;
     int begin(const char *name, double bytes, hipStream_t s);  // -1 when off
     void end(int token, hipStream_t s);
@@ -105,7 +106,7 @@ struct ProfScope {
     hipStream_t s;
     ProfScope(Profiler *p_, const char *name, double bytes, hipStream_t s_) : p(p_), tok(-1), s(s_)
     {
-        if (p && p->on) tok = p->begin(name, bytes, s);
+        if (p && p->on && (p->only.empty() || p->only == name)) tok = p->begin(name, bytes, s);
     }
     ~ProfScope()
     {
