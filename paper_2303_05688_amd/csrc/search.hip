@@ -168,7 +168,7 @@ struct GenArgs {
     int n, na, nb;
     ClassMap cmap;
     uint64_t full;
-    uint32_t nas, nbs, f0, f1, pva2, npa2, pvb2;  // table sizes and block sizes
+    uint32_t nas, nbs, f0, f1, pva2, npa2, pvb2, npb2;  // table sizes and block sizes
     uint64_t *klo, *khi;
     double *vals;
     size_t cap;
@@ -227,6 +227,8 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     uint32_t *bsX = asL + g.nas;                      // nbs: r | s << 8 | (sign < 0) << 16
     uint32_t *cur = bsX + g.nbs;                      // nc cursors
     uint8_t *occA = (uint8_t *)(cur + g.nc), *virA = occA + 64, *occB = occA + 128, *virB = occA + 192;
+    // orbital pairs in the order unrank_pair enumerates them: lo | hi << 8
+    uint16_t *pOA = (uint16_t *)(occA + 256), *pVA = pOA + g.npa2, *pOB = pVA + g.pva2, *pVB = pOB + g.npb2;
     __shared__ uint32_t s_nsel;
 
     const uint64_t a = g.core_a[i], b = g.core_b[i];
@@ -253,6 +255,21 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u);
         asP[u] = (c >= g.c0 && c < g.c0 + g.nc) ? c - g.c0 : ~0u;
     }
+    // occupied and virtual orbital pairs of both spins (hole and particle pairs
+    // of the doubles)
+    {
+        auto fill = [&](uint16_t *tab, uint32_t cnt, const uint8_t *orb) {
+            for (uint32_t t = lane; t < cnt; t += 64) {
+                int i1, j1;
+                unrank_pair(t, i1, j1);
+                tab[t] = (uint16_t)(orb[i1] | ((uint32_t)orb[j1] << 8));
+            }
+        };
+        fill(pOA, g.npa2, occA);
+        fill(pVA, g.pva2, virA);
+        fill(pOB, g.npb2, occB);
+        fill(pVB, g.pvb2, virB);
+    }
     // beta singles: target, orbitals, sign
     for (uint32_t t = lane; t < g.nbs; t += 64) {
         const int r = occB[t / vb], s = virB[t % vb];
@@ -268,25 +285,32 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // f0 block: the alpha string is unchanged
     if (self_in && g.f0) {
         const size_t base = g.offsets[(size_t)(cs - g.c0) * g.nq + i];
-        for (uint32_t t = lane; t < g.f0; t += 64) {
-            uint64_t b2;
-            double hv;
-            if (t < g.nbs) {
-                const uint32_t x = bsX[t];
-                b2 = bsB[t];
-                hv = single_value(g.h, g.eri, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
-            } else {
-                const uint32_t y = t - g.nbs;
-                const uint32_t hp = y / g.pvb2, pp = y - hp * g.pvb2;
-                int i1, j1, i2, j2;
-                unrank_pair(hp, i1, j1);
-                unrank_pair(pp, i2, j2);
-                const uint64_t hb = (1ull << occB[i1]) | (1ull << occB[j1]);
-                const uint64_t pb = (1ull << virB[i2]) | (1ull << virB[j2]);
-                b2 = (b & ~hb) | pb;
-                hv = double_same_value(g.eri, n, b, hb, pb);
+        const uint32_t ns1 = min(g.nbs, g.f0);
+        for (uint32_t t = lane; t < ns1; t += 64) {
+            const uint32_t x = bsX[t];
+            const double hv = single_value(g.h, g.eri, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
+            emit<W>(g, base + t, a, bsB[t], hv * ci, or0, and0, or1, and1);
+        }
+        // beta-beta doubles y = hole pair * pvb2 + particle pair, the pair
+        // indices advanced by the 64 records a lane strides over
+        const uint32_t nd2 = g.f0 - ns1;
+        if (nd2) {
+            const uint32_t q64 = 64u / g.pvb2, r64 = 64u % g.pvb2;
+            uint32_t hp = (uint32_t)lane / g.pvb2, pp = (uint32_t)lane % g.pvb2;
+            for (uint32_t y = lane; y < nd2; y += 64) {
+                const uint32_t po = pOB[hp], pv = pVB[pp];
+                const uint64_t hb = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
+                const uint64_t pb = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
+                const uint64_t b2 = (b & ~hb) | pb;
+                emit<W>(g, base + ns1 + y, a, b2, double_same_value(g.eri, n, b, hb, pb) * ci, or0, and0, or1,
+                        and1);
+                pp += r64;
+                hp += q64;
+                if (pp >= g.pvb2) {
+                    pp -= g.pvb2;
+                    ++hp;
+                }
             }
-            emit<W>(g, base + t, a, b2, hv * ci, or0, and0, or1, and1);
         }
     }
     // slots of the alpha-single blocks: rank among equal classes, in u order
@@ -312,8 +336,13 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // alpha-single blocks, flattened over (selected single, record)
     {
         const uint32_t total = s_nsel * g.f1;
-        for (uint32_t t = lane; t < total; t += 64) {
-            const uint32_t k = t / g.f1, j = t - k * g.f1;
+        const uint32_t q64 = 64u / g.f1, r64 = 64u % g.f1;
+        uint32_t k = (uint32_t)lane / g.f1, j = (uint32_t)lane % g.f1;  // t = k * f1 + j
+        for (uint32_t t = lane; t < total; t += 64, j += r64, k += q64) {
+            if (j >= g.f1) {
+                j -= g.f1;
+                ++k;
+            }
             const uint32_t u = asL[k];
             const uint64_t a2 = asA[u];
             const size_t dst = (size_t)asP[u] + j;
@@ -331,19 +360,24 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // alpha-alpha doubles, one record each
     {
         const uint32_t total = g.npa2 * g.pva2;
+        const uint32_t q64 = total ? 64u / g.pva2 : 0u, r64 = total ? 64u % g.pva2 : 0u;
+        uint32_t hp = total ? (uint32_t)lane / g.pva2 : 0u, pp = total ? (uint32_t)lane % g.pva2 : 0u;
         for (uint32_t t0 = 0; t0 < total; t0 += 64) {
-            const uint32_t t = t0 + lane;
+            const uint32_t t = t0 + lane;  // = hp * pva2 + pp
             uint64_t holes = 0ull, parts = 0ull, a2 = a;
             uint32_t c = ~0u;
             if (t < total) {
-                const uint32_t hp = t / g.pva2, pp = t - hp * g.pva2;
-                int i1, j1, i2, j2;
-                unrank_pair(hp, i1, j1);
-                unrank_pair(pp, i2, j2);
-                holes = (1ull << occA[i1]) | (1ull << occA[j1]);
-                parts = (1ull << virA[i2]) | (1ull << virA[j2]);
+                const uint32_t po = pOA[hp], pv = pVA[pp];
+                holes = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
+                parts = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
                 a2 = (a & ~holes) | parts;
                 c = class_of(a2, g.cmap);
+            }
+            pp += r64;
+            hp += q64;
+            if (pp >= g.pva2) {
+                pp -= g.pva2;
+                ++hp;
             }
             const bool act = c >= g.c0 && c < g.c0 + g.nc;
             const uint32_t key = act ? c - g.c0 : 0u;
@@ -1176,12 +1210,14 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.pva2 = va * (va - (va ? 1u : 0u)) / 2u;
             ga.npa2 = (uint32_t)in.na * (uint32_t)(in.na - (in.na ? 1 : 0)) / 2u;
             ga.pvb2 = bf.pairs_vb;
+            ga.npb2 = (uint32_t)in.nb * (uint32_t)(in.nb - (in.nb ? 1 : 0)) / 2u;
             ga.klo = k_lo[0];
             ga.khi = k_hi[0];
             ga.vals = v[0];
             ga.cap = Pb;
             ga.key_or_and = d_misc;
-            const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 + 64;
+            const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 +
+                               2 * ((size_t)ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
             k_generate<W><<<(unsigned)nq, 64, lds, s>>>(ga);
             ASCI_LAUNCH_CHECK();
         }
