@@ -212,7 +212,12 @@ template <int W>
 __global__ __launch_bounds__(64) void k_generate(GenArgs g)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t i = blockIdx.x;
+    // workgroups go to the 8 XCDs in turn: give each XCD a contiguous range of
+    // cores, so that neighbouring cores (which share lines of the offset
+    // matrix) meet in the same L2
+    const uint32_t per = (g.nq + 7u) / 8u;
+    const uint32_t i = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    if (i >= g.nq) return;
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
     const int n = g.n;
@@ -242,7 +247,9 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         else if (inr) virA[__popcll(bva & lt)] = (uint8_t)lane;
         if (ob) occB[__popcll(bob & lt)] = (uint8_t)lane;
         else if (inr) virB[__popcll(bvb & lt)] = (uint8_t)lane;
-        for (uint32_t t = lane; t < g.nc; t += 64) cur[t] = 0u;
+        // cursors start at the (class, core) item starts: one strided read per
+        // class here instead of one per record below
+        for (uint32_t t = lane; t < g.nc; t += 64) cur[t] = g.offsets[(size_t)t * g.nq + i];
     }
     __syncthreads();
     // alpha singles: target, class, H value (the O(n) sums, lane-parallel)
@@ -278,7 +285,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     }
     const uint32_t cs = class_of(a, g.cmap);
     const bool self_in = cs >= g.c0 && cs < g.c0 + g.nc;
-    if (lane == 0 && self_in) cur[cs - g.c0] = g.f0;
+    if (lane == 0 && self_in) cur[cs - g.c0] += g.f0;
     __syncthreads();
 
     uint64_t or0 = 0ull, and0 = ~0ull, or1 = 0ull, and1 = ~0ull;
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const uint64_t sel = __ballot(act);
         const uint32_t nsel0 = s_nsel;
         if (act) {
-            asP[u] = g.offsets[(size_t)lc * g.nq + i] + before + (uint32_t)__popcll(peers & lt) * g.f1;
+            asP[u] = before + (uint32_t)__popcll(peers & lt) * g.f1;
             asL[nsel0 + __popcll(sel & lt)] = u;
             if ((peers & lt) == 0ull) cur[key] = before + (uint32_t)__popcll(peers) * g.f1;
         }
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             const uint64_t peers = wave_match(key, act, g.nbits);
             const uint32_t before = cur[key];
             if (act) {
-                const size_t dst = (size_t)g.offsets[(size_t)key * g.nq + i] + before + (uint32_t)__popcll(peers & lt);
+                const size_t dst = (size_t)before + (uint32_t)__popcll(peers & lt);
                 if ((peers & lt) == 0ull) cur[key] = before + (uint32_t)__popcll(peers);
                 emit<W>(g, dst, a2, b, double_same_value(g.eri, n, a, holes, parts) * ci, or0, and0, or1, and1);
             }
@@ -1218,7 +1225,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.key_or_and = d_misc;
             const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 +
                                2 * ((size_t)ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
-            k_generate<W><<<(unsigned)nq, 64, lds, s>>>(ga);
+            k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
             ASCI_LAUNCH_CHECK();
         }
         // steps 6-9: bucket sort-and-accumulate, exclusion, diagonal, score
