@@ -50,6 +50,16 @@ __host__ __device__ __forceinline__ uint32_t make_meta(uint32_t top, uint32_t bu
     return top | (buf << 8) | (single ? 512u : 0u) | (bits ? 1024u : 0u);
 }
 
+// Workgroups are handed to the 8 XCDs in turn; tile kernels map them so that
+// each XCD takes a contiguous range of tiles (neighbouring tiles write
+// neighbouring parts of the same ranges, whose shared lines then meet in one
+// L2).  The grid is 8 * ceil(ntiles / 8); indices past ntiles exit.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles)
+{
+    const uint32_t per = (ntiles + 7u) / 8u;
+    return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+}
+
 constexpr int kMaxSplit = 256;       // ranges per split
 constexpr int kSplitSample = 16;     // samples per range
 
@@ -272,7 +282,8 @@ __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
     __shared__ uint32_t h[kHistT / 64][256];
     __shared__ uint64_t spl_lo[kMaxSplit - 1];
     __shared__ uint64_t spl_hi[W == 2 ? kMaxSplit - 1 : 1];
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = xcd_tile(a.ntiles);
+    if (t >= a.ntiles) return;
     const uint32_t s = a.tile_seg[t];
     const Seg sg = a.segs[s];
     const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
@@ -452,7 +463,8 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     __shared__ uint32_t s_tmp[NW];
     __shared__ uint8_t s_dg[kTileN];
 
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = xcd_tile(a.ntiles);
+    if (t >= a.ntiles) return;
     const uint32_t s = a.tile_seg[t];
     if (skip[s]) return;  // uniform per block
     const Seg sg = a.segs[s];
@@ -1259,7 +1271,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         sa.dig = dig;
         {
             ProfScope ps(prof, "split_hist", (8.0 * W) * (double)ntiles * kTileN, s);
-            k_split_hist<W><<<ntiles, kHistT, 0, s>>>(sa);
+            k_split_hist<W><<<8 * ((ntiles + 7) / 8), kHistT, 0, s>>>(sa);
             ASCI_LAUNCH_CHECK();
         }
         scan_u32(hist, hscan, (size_t)ntiles * 256, nullptr, ar, s, prof);
@@ -1269,7 +1281,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         sa.hist = hscan;
         {
             ProfScope ps(prof, "split_scatter", 2.0 * (8.0 * W + 8.0) * (double)ntiles * kTileN, s);
-            k_split_scatter<W><<<ntiles, kTileT, 0, s>>>(sa, hscan, skip);
+            k_split_scatter<W><<<8 * ((ntiles + 7) / 8), kTileT, 0, s>>>(sa, hscan, skip);
             ASCI_LAUNCH_CHECK();
         }
         ASCI_HIP(hipMemcpyAsync(hcnt, ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
