@@ -76,6 +76,34 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t *__restrict__ p
     if (threadIdx.x == 0 && d_total) *d_total = carry;
 }
 
+// short inputs (at most kScanSmall elements): one workgroup, one launch,
+// chunks of 4096 scanned in turn with a running carry
+constexpr size_t kScanSmall = 65536;
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_t *out, uint32_t n,
+                                                     uint32_t *__restrict__ d_total)
+{
+    __shared__ uint32_t s_tmp[16];
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < n; c0 += 4096) {
+        const uint32_t j0 = c0 + threadIdx.x * 4u;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[i] = j0 + i < n ? in[j0 + i] : 0u;
+            sum += v[i];
+        }
+        uint32_t tot;
+        uint32_t e = carry + block_excl_scan<16>(sum, s_tmp, tot);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (j0 + i < n) out[j0 + i] = e;
+            e += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && d_total) *d_total = carry;
+}
+
 __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *in, uint32_t *out, size_t n,
                                                         const uint32_t *__restrict__ partial)
 {
@@ -289,11 +317,16 @@ void scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, Ar
         if (d_total) ASCI_HIP(hipMemsetAsync(d_total, 0, sizeof(uint32_t), s));
         return;
     }
+    ProfScope ps(prof, "scan", 8.0 * n, s);
+    if (n <= kScanSmall) {
+        k_scan_small<<<1, 1024, 0, s>>>(in, out, (uint32_t)n, d_total);
+        ASCI_LAUNCH_CHECK();
+        return;
+    }
     size_t nb = (n + kTile - 1) / kTile;
     require(nb <= (1u << 26), ASCI_EINVAL, "scan too long");
     size_t mark = ar.used();
     uint32_t *partial = ar.take<uint32_t>(nb);
-    ProfScope ps(prof, "scan", 8.0 * n, s);
     k_scan_reduce<<<(unsigned)nb, kThreads, 0, s>>>(in, n, partial);
     ASCI_LAUNCH_CHECK();
     k_scan_partials<<<1, 1024, 0, s>>>(partial, (uint32_t)nb, d_total);

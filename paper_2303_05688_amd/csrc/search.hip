@@ -507,51 +507,55 @@ __global__ __launch_bounds__(kBlock) void k_keep_scatter(const uint64_t *__restr
                                                          uint64_t *__restrict__ olo, uint64_t *__restrict__ ohi,
                                                          double *__restrict__ oscore, size_t cap)
 {
-    __shared__ uint32_t s_w[kBlock / 64];
+    constexpr int NW = kBlock / 64;
+    __shared__ uint32_t s_w[NW];
     const uint64_t t = st->prefix, krem = st->krem;
-    // thread-contiguous entries keep the pool order inside the tile
-    const size_t base = (size_t)blockIdx.x * kKeepTile + (size_t)threadIdx.x * kKeepItems;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    // wave-contiguous chunks, lane-strided inside (coalesced loads); the pool
+    // order inside the tile is (wave, item, lane), and ranks follow it
+    const size_t wbase = (size_t)blockIdx.x * kKeepTile + (size_t)wv * 64 * kKeepItems;
     uint64_t o[kKeepItems];
-    uint32_t eq = 0;
+    uint64_t eqm[kKeepItems];
+    uint32_t weq = 0;
 #pragma unroll
     for (int i = 0; i < kKeepItems; ++i) {
-        const size_t j = base + i;
+        const size_t j = wbase + (size_t)i * 64 + lane;
         o[i] = j < n ? abs_order(iscore[j]) : 0ull;
-        eq += (j < n && o[i] == t) ? 1u : 0u;
+        eqm[i] = __ballot(j < n && o[i] == t);
+        weq += (uint32_t)__popcll(eqm[i]);
     }
     uint32_t tot;
-    uint32_t erank = eqbase[blockIdx.x] + block_excl_scan(eq, s_w, tot);
-    uint32_t kept = 0;
-    uint32_t keepmask = 0;
+    uint32_t erank = eqbase[blockIdx.x] + block_excl_scan(lane == 0 ? weq : 0u, s_w, tot);
+    erank = (uint32_t)__shfl((int)erank, 0, 64);
+    uint64_t keptm[kKeepItems];
+    uint32_t wkept = 0;
 #pragma unroll
     for (int i = 0; i < kKeepItems; ++i) {
-        const size_t j = base + i;
+        const size_t j = wbase + (size_t)i * 64 + lane;
         bool k = false;
         if (j < n) {
-            if (o[i] > t) {
-                k = true;
-            } else if (o[i] == t) {
-                k = erank < krem;
-                ++erank;
-            }
+            if (o[i] > t) k = true;
+            else if (o[i] == t) k = erank + (uint32_t)__popcll(eqm[i] & lt) < krem;
         }
-        if (k) {
-            keepmask |= 1u << i;
-            ++kept;
-        }
+        erank += (uint32_t)__popcll(eqm[i]);
+        keptm[i] = __ballot(k);
+        wkept += (uint32_t)__popcll(keptm[i]);
     }
-    uint32_t at = keptbase[blockIdx.x] + block_excl_scan(kept, s_w, tot);
+    uint32_t at = keptbase[blockIdx.x] + block_excl_scan(lane == 0 ? wkept : 0u, s_w, tot);
+    at = (uint32_t)__shfl((int)at, 0, 64);
 #pragma unroll
     for (int i = 0; i < kKeepItems; ++i) {
-        if ((keepmask >> i) & 1u) {
-            const size_t j = base + i;
-            if (at < cap) {
-                olo[at] = ilo[j];
-                if (W == 2) ohi[at] = ihi[j];
-                oscore[at] = iscore[j];
+        if ((keptm[i] >> lane) & 1ull) {
+            const size_t j = wbase + (size_t)i * 64 + lane;
+            const uint32_t d = at + (uint32_t)__popcll(keptm[i] & lt);
+            if (d < cap) {
+                olo[d] = ilo[j];
+                if (W == 2) ohi[d] = ihi[j];
+                oscore[d] = iscore[j];
             }
-            ++at;
         }
+        at += (uint32_t)__popcll(keptm[i]);
     }
 }
 
