@@ -328,6 +328,7 @@ struct BucketArgs {
     PsiSet psi;                     // the same keys as a hash set
     const double *jk, *h;
     SpinTables st;                  // tabulated E(alpha), E(beta) (optional)
+    const uint64_t *thr = nullptr;  // device: drop candidates whose |A| order bits are below (optional)
     double ecore, E0, eps;
     int finish_cap = 4096;          // LDS capacity of a final segment (tunable)
     uint64_t *clo, *chi;            // candidate slots (P)

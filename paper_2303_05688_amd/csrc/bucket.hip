@@ -550,6 +550,7 @@ struct FinishArgs {
     int n;
     const double *jk, *h;       // J, J-K (n^2 each), h_pp (n); h (n^2)
     SpinTables st;              // E(alpha), E(beta) by string rank (optional)
+    const uint64_t *thr;        // candidates with abs_order(A) below *thr cannot enter the top k (optional)
     double ecore, E0, eps;      // eps > 0: keep a pair only if |H_ai C_i / (E0 - H_aa)| > eps
     uint64_t *clo, *chi;        // slot arrays (batch positions)
     double *cnum, *cscore;
@@ -680,7 +681,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     sum = sum + v;
                     ++kept;
                 }
-                if (kept) {
+                if (kept && (!f.thr || abs_order(sum / den) >= *f.thr)) {
                     const size_t j0 = sg.start;
                     f.clo[j0] = lo;
                     if (W == 2) f.chi[j0] = hi;
@@ -943,6 +944,8 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     // runs, NT at a time: key (read back from the segment), exclusion,
     // diagonal, sum in record order, score; one scan per round places the
     // surviving candidates, compacted, in run order
+    // a lower bound of the final k-th |A| from earlier class batches, if any
+    const uint64_t thr = f.thr ? *f.thr : 0ull;
     uint32_t written = 0;
     for (uint32_t base = 0; base < nruns; base += NT) {
         const uint32_t u = base + (uint32_t)tid;
@@ -992,6 +995,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     keep = true;
                 }
                 score = sum / den;
+                keep = keep && abs_order(score) >= thr;
             }
             // an input determinant is not a candidate (rare: finish the probe)
             if (st0 != 0u && keep) {
@@ -1309,6 +1313,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.jk = b.jk;
         fa.h = b.h;
         fa.st = b.st;
+        fa.thr = b.thr;
         fa.ecore = b.ecore;
         fa.E0 = b.E0;
         fa.eps = b.eps;

@@ -1174,7 +1174,12 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         (void)ar.take<char>(entry_mark);
     };
 
-    for (const auto &bt : batches) {
+    // after a class batch the pool is cut to the k best; the k-th |A| then
+    // bounds the final one from below, and later batches (larger keys, so they
+    // lose every tie) drop candidates under it in the finish kernel
+    const uint64_t *d_thr = nullptr;
+    for (size_t bi = 0; bi < batches.size(); ++bi) {
+        const auto &bt = batches[bi];
         const uint32_t c0 = bt.first, nc = bt.second - bt.first;
         uint64_t btotal = 0;
         for (uint32_t c = bt.first; c < bt.second; ++c) btotal += pp.totals[c];
@@ -1252,6 +1257,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.jk = pp.d_jk;
         ba.h = in.h;
         ba.st = st;
+        ba.thr = topk ? d_thr : nullptr;
         ba.ecore = in.opt.ecore;
         ba.E0 = in.E0;
         ba.eps = in.opt.eps;
@@ -1284,6 +1290,10 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.pool_cap = pool_cap;
         bucket_collect<W>(ba, s, prof);
         pool_n += V;
+        if (topk && bi + 1 < batches.size() && pool_n > (uint64_t)out.k) {
+            prune((size_t)out.k);
+            d_thr = &d_sel->prefix;
+        }
     }
 
     ar.reset();
