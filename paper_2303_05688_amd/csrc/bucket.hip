@@ -171,14 +171,17 @@ __device__ __forceinline__ uint32_t split_key_digit(const SplitRule &r, const ui
                                                    const uint64_t *spl_hi, uint64_t lo, uint64_t hi, int n)
 {
     if (r.bits) return vdigit<W>(lo, hi, n, r.sh, r.w);
-    uint32_t a = 0, b = r.nb - 1u;
-    while (a < b) {
-        const uint32_t m = (a + b) >> 1;
+    // count of splitters <= key by binary lifting over the 255 staged entries
+    // (the unused ones hold the largest key): eight steps, no branches, so
+    // the searches of several keys overlap
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t step = 128; step >= 1; step >>= 1) {
+        const uint32_t m = pos + step - 1u;
         const bool le = W == 1 ? spl_lo[m] <= lo : (spl_hi[m] < hi || (spl_hi[m] == hi && spl_lo[m] <= lo));
-        if (le) a = m + 1u;
-        else b = m;
+        pos += le ? step : 0u;
     }
-    return a;
+    return min(pos, r.nb - 1u);
 }
 
 // stage the splitters of segment s in LDS (every thread of the block calls it)
@@ -187,10 +190,12 @@ __device__ __forceinline__ void load_splitters(const SplitRule &r, const uint64_
                                                const uint64_t *__restrict__ g_hi, uint32_t s, uint64_t *spl_lo,
                                                uint64_t *spl_hi)
 {
+    static_assert(kMaxSplit == 256, "binary lifting over 255 splitters");
     if (!r.bits)
-        for (uint32_t j = threadIdx.x; j + 1u < r.nb; j += blockDim.x) {
-            spl_lo[j] = g_lo[(size_t)s * (kMaxSplit - 1) + j];
-            if (W == 2) spl_hi[j] = g_hi[(size_t)s * (kMaxSplit - 1) + j];
+        for (uint32_t j = threadIdx.x; j < kMaxSplit - 1; j += blockDim.x) {
+            const bool used = j + 1u < r.nb;
+            spl_lo[j] = used ? g_lo[(size_t)s * (kMaxSplit - 1) + j] : ~0ull;
+            if (W == 2) spl_hi[j] = used ? g_hi[(size_t)s * (kMaxSplit - 1) + j] : ~0ull;
         }
     __syncthreads();
 }
@@ -294,17 +299,31 @@ __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
     const uint32_t r0 = tl * kTileN, r1 = min(sg.size, r0 + kTileN);
     const int wv = threadIdx.x >> 6;
     uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kHistT) {
-        const size_t j = (size_t)sg.start + r;
-        const uint64_t lo = a.klo[buf][j];
-        const uint64_t hi = W == 2 ? a.khi[buf][j] : 0ull;
-        o0 |= lo;
-        a0 &= lo;
-        o1 |= hi;
-        a1 &= hi;
-        const uint32_t dg = split_key_digit<W>(rule, spl_lo, spl_hi, lo, hi, a.n);
-        a.dig[j] = (uint8_t)dg;
-        atomicAdd(&h[wv][dg], 1u);
+    // four records per step, their searches interleaved
+    for (uint32_t rb = r0 + threadIdx.x; rb < r1; rb += 4 * kHistT) {
+        uint64_t lo[4], hi[4];
+        uint32_t dg[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = rb + (uint32_t)k * kHistT;
+            const size_t j = (size_t)sg.start + (r < r1 ? r : r0);
+            lo[k] = a.klo[buf][j];
+            hi[k] = W == 2 ? a.khi[buf][j] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dg[k] = split_key_digit<W>(rule, spl_lo, spl_hi, lo[k], hi[k], a.n);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = rb + (uint32_t)k * kHistT;
+            if (r < r1) {
+                o0 |= lo[k];
+                a0 &= lo[k];
+                o1 |= hi[k];
+                a1 &= hi[k];
+                a.dig[(size_t)sg.start + r] = (uint8_t)dg[k];
+                atomicAdd(&h[wv][dg[k]], 1u);
+            }
+        }
     }
     // which key bits vary inside the segment (for segments the split cannot divide)
     for (int dd = 32; dd >= 1; dd >>= 1) {
