@@ -208,8 +208,8 @@ struct KeyBufs {
     const uint64_t *lo[2], *hi[2];
 };
 
-template <int W>
-__global__ __launch_bounds__(256) void k_seg_splitters(const Seg *__restrict__ segs, uint32_t cap, KeyBufs kb,
+template <int W, int T>
+__global__ __launch_bounds__(T) void k_seg_splitters(const Seg *__restrict__ segs, uint32_t cap, KeyBufs kb,
                                                        uint64_t *__restrict__ g_lo, uint64_t *__restrict__ g_hi)
 {
     constexpr int kMaxSample = kMaxSplit * kSplitSample;  // 4096
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_seg_splitters(const Seg *__restrict__ s
     uint32_t p = 1;
     while (p < m) p <<= 1;
     const uint64_t *klo = kb.lo[seg_buf(sg)], *khi = kb.hi[seg_buf(sg)];
-    for (uint32_t i = threadIdx.x; i < p; i += 256) {
+    for (uint32_t i = threadIdx.x; i < p; i += T) {
         if (i < m) {
             const size_t j = (size_t)sg.start + (size_t)(((uint64_t)2 * i + 1) * sg.size / (2 * (uint64_t)m));
             x_lo[i] = klo[j];
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void k_seg_splitters(const Seg *__restrict__ s
     __syncthreads();
     for (uint32_t k = 2; k <= p; k <<= 1) {
         for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-            for (uint32_t i = threadIdx.x; i < p; i += 256) {
+            for (uint32_t i = threadIdx.x; i < p; i += T) {
                 const uint32_t o = i ^ jj;
                 if (o > i) {
                     const bool up = (i & k) == 0;
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_seg_splitters(const Seg *__restrict__ s
             __syncthreads();
         }
     }
-    for (uint32_t j = threadIdx.x; j + 1u < nb; j += 256) {
+    for (uint32_t j = threadIdx.x; j + 1u < nb; j += T) {
         const uint32_t q = (uint32_t)(((uint64_t)(j + 1) * m) / nb);
         g_lo[(size_t)s * (kMaxSplit - 1) + j] = x_lo[q];
         if (W == 2) g_hi[(size_t)s * (kMaxSplit - 1) + j] = x_hi[q];
@@ -1269,7 +1269,10 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         {
             ProfScope ps(prof, "split_sample", 0.0, s);
             const KeyBufs kb{{b.klo[0], b.klo[1]}, {b.khi[0], b.khi[1]}};
-            k_seg_splitters<W><<<nlarge, 256, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi);
+            // class-sized segments of the first level sort up to 4096 samples:
+            // more threads per sort; later levels sort a few hundred
+            if (lev == 0) k_seg_splitters<W, 1024><<<nlarge, 1024, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi);
+            else k_seg_splitters<W, 256><<<nlarge, 256, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi);
             ASCI_LAUNCH_CHECK();
         }
         SplitArgs sa;
