@@ -132,6 +132,7 @@ struct asci_ctx {
     // workspaces stay allocated (rebuilt when batch_slots or finish_cap change)
     void *batch_pool = nullptr;
     void (*batch_pool_free)(void *) = nullptr;
+    void (*batch_pool_trim)(void *) = nullptr;  // free the idle workers' workspaces
     int batch_pool_slots = 0, batch_pool_cap = 0;
     asci_ctx() = default;
     asci_ctx(const asci_ctx &) = delete;

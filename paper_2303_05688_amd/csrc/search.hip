@@ -1061,6 +1061,9 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
 template <int W>
 static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s)
 {
+    // a batch pool on this context is idle between batch calls: its workers'
+    // workspaces give way to this search (they grow again in the next batch)
+    if (ctx->batch_pool && ctx->batch_pool_trim) ctx->batch_pool_trim(ctx->batch_pool);
     const int n = in.n;
     const uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
     const BetaFactors bf = beta_factors(n, in.nb);

@@ -193,6 +193,25 @@ class Pool {
         cv_done_.wait(lk, [&] { return queue_.empty() && running_ == 0; });
     }
 
+    // free the workspaces of the idle workers (they grow again on demand)
+    void trim()
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        for (auto &w : ws_)
+            if (!w->busy) release_locked(*w);
+    }
+
+    // the HBM the pool may use: what is free now plus what its workers hold
+    void set_budget(int64_t free_bytes)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        int64_t held = 0;
+        for (auto &w : ws_) held += w->resident;
+        budget_ = free_bytes + held;
+        cap_records_ = (uint64_t)std::max<int64_t>(
+            1 << 20, std::min<int64_t>(1ll << 30, budget_ / (int64_t)ws_.size() / 160));
+    }
+
     void stats(asci_server_stats *st)
     {
         std::unique_lock<std::mutex> lk(mu_);
@@ -458,10 +477,19 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
             const int64_t budget = device_budget(ctx->device);
             ctx->batch_pool = new Pool(ctx->device, budget, ctx->batch_slots, false, 0.0, ctx->finish_cap);
             ctx->batch_pool_free = [](void *p) { delete static_cast<Pool *>(p); };
+            ctx->batch_pool_trim = [](void *p) { static_cast<Pool *>(p)->trim(); };
             ctx->batch_pool_slots = ctx->batch_slots;
             ctx->batch_pool_cap = ctx->finish_cap;
         }
         Pool &pool = *static_cast<Pool *>(ctx->batch_pool);
+        // the context's own workspaces are idle during the batch: give their
+        // HBM to the workers (work queued on `stream` finishes first)
+        ASCI_HIP(hipSetDevice(ctx->device));
+        ASCI_HIP(hipStreamSynchronize((hipStream_t)stream));
+        ctx->setup.release();
+        ctx->main.release();
+        ctx->tables.release();
+        pool.set_budget(device_budget(ctx->device));
         pool.order_after((hipStream_t)stream);
         std::vector<int> order((size_t)nreq);
         for (int i = 0; i < nreq; ++i) order[(size_t)i] = i;
