@@ -93,8 +93,10 @@ int asci_ctx_destroy(asci_ctx *ctx);
 /*
  * Tuning parameters of a context (they change speed, never results):
  *   "finish_cap": records per LDS bucket in the sort-and-accumulate finish,
- *                 1024, 2048 or 4096 (default 4096; two-word keys use at most
- *                 2048).  Smaller buckets let two workgroups share a CU.
+ *                 1024, 2048 or 4096 (default 4096, any key width).  A
+ *                 workgroup of cap / 8 threads takes a bucket; smaller
+ *                 buckets let more workgroups share a CU but need more split
+ *                 passes.
  *   "batch_slots": concurrent searches of asci_search_batch, 1..8 (default 2).
  *   "spin_tables": 1 (default) tabulates E(s) of every alpha and beta string
  *                 (at most 2^27 strings per spin, and only when the search
@@ -348,12 +350,15 @@ int64_t asci_request_footprint(const asci_request *req);
  * Run nreq searches as one batch on ctx's device: the requests are ordered by
  * estimated cost (largest first) and run concurrently on `slots` worker
  * streams (ctx parameter "batch_slots", default 2; see asci_autotune), each
- * with its own workspace.  The workers and their workspaces stay with ctx
- * between calls (until "release_workspace", a change of "batch_slots" or
- * "finish_cap", or asci_ctx_destroy).  Work already queued on `stream` completes first;
- * the call returns when every result is written.  res[i] is request i's
- * result; the return value is ASCI_OK when every request succeeded, else the
- * first error code.
+ * with its own workspace.  The workers stay with ctx between calls (until
+ * "release_workspace", a change of "batch_slots" or "finish_cap", or
+ * asci_ctx_destroy) and keep their workspaces while only batches run; the
+ * context's own workspaces are freed when a batch starts, and a single search
+ * on ctx frees the idle workers' workspaces, so the two never hold HBM at the
+ * same time.  Work already queued on `stream` completes first; the call
+ * returns when every result is written.  res[i] is request i's result; the
+ * return value is ASCI_OK when every request succeeded, else the first error
+ * code.
  */
 int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_result *res, void *stream);
 

@@ -127,3 +127,20 @@ def test_batch_reuses_workers_and_release(setup):
     k, s = asci.search(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], c["E0"],
                        c["kk"], ctx=ctx)
     assert (host(k) == alone[0][0]).all() and (host(s) == alone[0][1]).all()
+
+
+def test_batch_and_single_alternate_on_one_context(setup):
+    """Batches and single searches alternate on one context: each hands the
+    other its HBM (the context's workspaces are freed by a batch, the idle
+    workers' by a single search) and every result stays the same."""
+    asci, cases, alone = setup
+    ctx = asci.Context.get(0)
+    c = cases[0]
+    d = c["dev"]
+    for _ in range(2):
+        reqs = _requests(asci, cases)
+        res = asci.search_batch(reqs, ctx=ctx)
+        assert all(_same(q, r, w) for r, q, w in zip(res, reqs, alone))
+        k, s = asci.search(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], c["E0"],
+                           c["kk"], ctx=ctx)
+        assert (host(k) == alone[0][0]).all() and (host(s) == alone[0][1]).all()
