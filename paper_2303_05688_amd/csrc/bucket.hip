@@ -13,11 +13,15 @@
 //             divide (its keys lie in one range) is split at the next level
 //             on the 8 key bits just below `top` instead, which always lowers
 //             `top`.  Repeat level by level.
-//   finish  : one workgroup per final segment sorts it in LDS (stable LSD on
-//             bits below `top`), sums every run of equal keys in record order
+//   finish  : one workgroup per final segment sorts the segment's record
+//             indices in LDS (stable LSD on a 32-bit window of each key that
+//             holds the bits varying inside the segment), gathers the values
+//             in sorted order, sums every run of equal keys in record order
 //             (record order is ascending core index), drops input
-//             determinants, forms H_aa and A_a, and writes the surviving
-//             candidates, compacted, at the segment's start in slot arrays.
+//             determinants (and, after an earlier class batch, candidates
+//             below the pool's k-th |A|), forms H_aa and A_a, and writes the
+//             surviving candidates, compacted, at the segment's start in slot
+//             arrays.
 //   collect : final segments ordered by start (= key order), their candidate
 //             counts scanned, and the candidates copied to the pool.
 //
