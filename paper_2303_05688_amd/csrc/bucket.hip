@@ -708,7 +708,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     const size_t j0 = sg.start;
                     f.clo[j0] = lo;
                     if (W == 2) f.chi[j0] = hi;
-                    f.cnum[j0] = sum;
+                    if (f.cnum) f.cnum[j0] = sum;
                     f.cscore[j0] = sum / den;
                     c = 1;
                 }

@@ -1124,7 +1124,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     for (const auto &bt : batches) max_nc = std::max<uint32_t>(max_nc, bt.second - bt.first);
     Arena &ar = ctx->main;
     ar.reset();
-    ar.reserve(E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + 16) + bucket_workspace_bytes(Pb, max_nc, W, ctx->finish_cap) +
+    ar.reserve(E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + (topk ? 8 : 16)) + bucket_workspace_bytes(Pb, max_nc, W, ctx->finish_cap) +
                pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 1) + kk_max * 24 + 64 * 256 + (1 << 16));
     ar.reset();
     uint32_t *counts = ar.take<uint32_t>(E);
@@ -1134,7 +1134,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     double *v[2] = {ar.take<double>(Pb), ar.take<double>(Pb)};
     uint64_t *c_lo = ar.take<uint64_t>(Pb);
     uint64_t *c_hi = W == 2 ? ar.take<uint64_t>(Pb) : nullptr;
-    double *c_num = ar.take<double>(Pb);
+    double *c_num = topk ? nullptr : ar.take<double>(Pb);  // N_a is needed only without a top k
     double *c_score = ar.take<double>(Pb);
     uint64_t *p_lo[2] = {ar.take<uint64_t>(pool_cap), ar.take<uint64_t>(pool_cap)};
     uint64_t *p_hi[2] = {W == 2 ? ar.take<uint64_t>(pool_cap) : nullptr, W == 2 ? ar.take<uint64_t>(pool_cap) : nullptr};

@@ -494,3 +494,32 @@ def test_pt2_energy_16e20o(asci):
     assert cnt == g["ncandidates"]
     want = float.fromhex(g["pt2"])
     assert abs(e - want) <= pt2_tol(want, float.fromhex(g["pt2_abs_terms"]))
+
+
+def test_profiler_entries_and_kernel_filter(asci, oracle_lib):
+    """Per-kernel timing: every timed kernel gets an entry with launches and
+    algorithmic bytes; restricted to one name, only that kernel is timed; the
+    results do not change either way."""
+    import torch
+
+    c = _case(12, 6, 6, 150, seed=41, sampler="level")
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    d = to_dev(c)
+    ctx = asci.Context.get(0)
+    base = [host(t) for t in asci.search(d["h"], d["eri"], 12, 6, 6, d["dets"], d["coeffs"], E0, 100, ctx=ctx)]
+    try:
+        ctx.set_profiling(True)
+        got = [host(t) for t in asci.search(d["h"], d["eri"], 12, 6, 6, d["dets"], d["coeffs"], E0, 100, ctx=ctx)]
+        torch.cuda.synchronize()
+        prof = ctx.profile()
+        assert {"generate", "finish", "collect"} <= set(prof)
+        assert all(v[1] >= 1 and v[0] >= 0.0 for v in prof.values())
+        assert prof["finish"][2] > 0.0
+        ctx.set_profiling(True, only="finish")
+        got2 = [host(t) for t in asci.search(d["h"], d["eri"], 12, 6, 6, d["dets"], d["coeffs"], E0, 100, ctx=ctx)]
+        torch.cuda.synchronize()
+        assert set(ctx.profile()) == {"finish"}
+    finally:
+        ctx.set_profiling(False)
+    for a, b, e in zip(base, got, got2):
+        assert a.tobytes() == b.tobytes() == e.tobytes()
