@@ -273,11 +273,15 @@ void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_
 
 // ---------------------------------------------------------------- input-determinant set
 // Open-addressing hash set of the input keys (linear probing; a slot is taken
-// when state != 0): exclusion costs one or two L2-resident probes.
+// when state != 0), fronted by a one-hash bit filter of about 8 bits per key
+// (a clear bit proves a key absent; a set bit sends the lookup to the table):
+// most lookups of non-members cost one read of a small, cache-resident array.
 struct PsiSet {
     const uint64_t *lo = nullptr, *hi = nullptr;
     const uint32_t *state = nullptr;
-    uint32_t mask = 0;  // table size - 1 (a power of two minus one)
+    uint32_t mask = 0;                  // table size - 1 (a power of two minus one)
+    const uint32_t *filter = nullptr;   // filter bits (null: no filter)
+    uint32_t fmask = 0;                 // filter bits - 1
 };
 
 __device__ __forceinline__ uint32_t psi_hash(uint64_t lo, uint64_t hi, uint32_t mask)
@@ -286,8 +290,24 @@ __device__ __forceinline__ uint32_t psi_hash(uint64_t lo, uint64_t hi, uint32_t 
     return (uint32_t)(h >> 32) & mask;
 }
 
+// the filter bit of a key (a hash independent of psi_hash's slot)
+__device__ __forceinline__ uint32_t psi_filter_bit(uint64_t lo, uint64_t hi, uint32_t fmask)
+{
+    const uint64_t h = (lo ^ 0xA0761D6478BD642Full) * 0xE7037ED1A0B428DBull + hi * 0x8EBC6AF09C88C6E3ull;
+    return (uint32_t)((h ^ (h >> 29)) >> 17) & fmask;
+}
+
+// false: the key is certainly not in the set
+__device__ __forceinline__ bool psi_maybe(const PsiSet &t, uint64_t lo, uint64_t hi)
+{
+    if (!t.filter) return true;
+    const uint32_t b = psi_filter_bit(lo, hi, t.fmask);
+    return (t.filter[b >> 5] >> (b & 31u)) & 1u;
+}
+
 __device__ __forceinline__ bool psi_contains(const PsiSet &t, uint64_t lo, uint64_t hi)
 {
+    if (!psi_maybe(t, lo, hi)) return false;
     uint32_t s = psi_hash(lo, hi, t.mask);
     while (t.state[s]) {
         if (t.lo[s] == lo && t.hi[s] == hi) return true;

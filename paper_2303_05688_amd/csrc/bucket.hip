@@ -986,10 +986,10 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             } else if (nwin == 1) {
                 key_put<W>(S.ck[r0], low, n, lo, hi);
             }
-            // the first probe of the exclusion test is issued before H_aa and
-            // the sum are formed, so its latency overlaps theirs
-            const uint32_t slot = psi_hash(lo, hi, f.psi.mask);
-            const uint32_t st0 = f.psi.state[slot];
+            // the exclusion filter is read before H_aa and the sum are formed,
+            // so its latency overlaps theirs; the table is probed only when the
+            // filter bit is set
+            const bool maybe = psi_maybe(f.psi, lo, hi);
             {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
                 double haa;
@@ -1020,11 +1020,11 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                 score = sum / den;
                 keep = keep && abs_order(score) >= thr;
             }
-            // an input determinant is not a candidate (rare: finish the probe)
-            if (st0 != 0u && keep) {
-                uint32_t sl = slot;
+            // an input determinant is not a candidate
+            if (maybe && keep) {
+                uint32_t sl = psi_hash(lo, hi, f.psi.mask);
                 bool found = false;
-                for (uint32_t st = st0; st != 0u; st = f.psi.state[sl]) {
+                for (uint32_t st = f.psi.state[sl]; st != 0u; st = f.psi.state[sl]) {
                     if (f.psi.lo[sl] == lo && f.psi.hi[sl] == hi) {
                         found = true;
                         break;
