@@ -75,7 +75,8 @@ def test_candidates_tiny(asci, oracle_lib, n, na, nb, ndets, ncore):
     _all_parity(asci, oracle_lib, c, E0, ncore=ncore)
 
 
-@pytest.mark.parametrize("n,na,nb,ndets", [(33, 3, 2, 12), (40, 4, 4, 8), (36, 2, 3, 20), (50, 2, 2, 6)])
+@pytest.mark.parametrize("n,na,nb,ndets", [(33, 3, 2, 12), (40, 4, 4, 8), (36, 2, 3, 20), (50, 2, 2, 6),
+                                             (64, 2, 2, 5), (32, 3, 3, 10)])
 def test_candidates_two_word_keys(asci, oracle_lib, n, na, nb, ndets):
     c = _case(n, na, nb, ndets, seed=77 + n)
     E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
