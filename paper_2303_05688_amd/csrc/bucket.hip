@@ -719,17 +719,28 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     }
 
     const uint32_t size = sg.size;
-    // identity order; OR / AND of the keys give the bits that vary inside the
-    // segment (the keys are read again, from cache, for their windows; the
-    // values are gathered in sorted order once the sort is done)
+    // identity order; the values in record order (permuted in LDS once the
+    // sort is done, instead of gathered from memory in sorted order); OR / AND
+    // of the keys give the bits that vary inside the segment.  One-word keys
+    // stay in registers for their windows; two-word keys are read again, from
+    // cache.
+    uint64_t rk[IT];
     {
         uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
+        double rv[IT];
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
+            rk[k] = r < size ? gk[r] : 0ull;
+            rv[k] = r < size ? gv[r] : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
             if (r < size) {
-                const uint64_t lo = gk[r], hi = W == 2 ? gh[r] : 0ull;
+                const uint64_t lo = rk[k], hi = W == 2 ? gh[r] : 0ull;
                 S.ix[0][r] = (uint16_t)r;
+                S.val[r] = rv[k];
                 o0 |= lo;
                 a0 &= lo;
                 o1 |= hi;
@@ -774,7 +785,15 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     for (int win = 0; win < nwin; ++win) {
         const int o = low + 32 * win;
         const uint32_t vwin = key_window<W>(var_lo, var_hi, n, o);
-        for (uint32_t r = tid; r < size; r += NT) S.ck[r] = key_window<W>(gk[r], W == 2 ? gh[r] : 0ull, n, o);
+        if (W == 1) {
+#pragma unroll
+            for (int k = 0; k < IT; ++k) {
+                const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
+                if (r < size) S.ck[r] = key_window<W>(rk[k], 0ull, n, o);
+            }
+        } else {
+            for (uint32_t r = tid; r < size; r += NT) S.ck[r] = key_window<W>(gk[r], W == 2 ? gh[r] : 0ull, n, o);
+        }
         __syncthreads();
         for (int sh = 0; sh < 32; sh += 8) {
             const uint32_t dv = (vwin >> sh) & 0xFFu;
@@ -866,13 +885,14 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
     uint16_t *head = &S.ix[cur ^ 1][0];
     const uint16_t *perm = &S.ix[cur][0];
     // values in sorted order: each thread gathers the IT consecutive positions
-    // it owns below (all loads in flight together, stored at the end of the
-    // run-head pass so that their latency overlaps it)
+    // it owns below from the record-order copy in LDS and stores them back in
+    // sorted order after the scan of the run-head pass (whose barriers order
+    // every read before any write)
     double gval[IT];
     {
         const uint32_t j0 = (uint32_t)tid * IT;
 #pragma unroll
-        for (int i = 0; i < IT; ++i) gval[i] = j0 + i < size ? gv[perm[j0 + i]] : 0.0;
+        for (int i = 0; i < IT; ++i) gval[i] = j0 + i < size ? S.val[perm[j0 + i]] : 0.0;
     }
     const int aw = n - low;  // window bits at or above this one are alpha bits (one-word keys: also two-word)
     const uint32_t amax = min(255u, L::kAcacheBytes / (8u * (uint32_t)(n + 2)));
