@@ -280,8 +280,8 @@ struct PsiSet {
     const uint64_t *lo = nullptr, *hi = nullptr;
     const uint32_t *state = nullptr;
     uint32_t mask = 0;                  // table size - 1 (a power of two minus one)
-    const uint32_t *filter = nullptr;   // filter bits (null: no filter)
-    uint32_t fmask = 0;                 // filter bits - 1
+    const unsigned long long *filter = nullptr;  // filter words (null: no filter)
+    uint32_t fmask = 0;                          // filter words - 1 (a power of two minus one)
 };
 
 __device__ __forceinline__ uint32_t psi_hash(uint64_t lo, uint64_t hi, uint32_t mask)
@@ -290,19 +290,30 @@ __device__ __forceinline__ uint32_t psi_hash(uint64_t lo, uint64_t hi, uint32_t 
     return (uint32_t)(h >> 32) & mask;
 }
 
-// the filter bit of a key (a hash independent of psi_hash's slot)
-__device__ __forceinline__ uint32_t psi_filter_bit(uint64_t lo, uint64_t hi, uint32_t fmask)
+// Blocked Bloom filter in front of the table: a key sets (and is tested
+// against) four bits of one 64-bit word, both drawn from a hash independent of
+// psi_hash's slot.  At 32 filter bits per key about one absent key in a
+// thousand reaches the table.
+__device__ __forceinline__ uint64_t psi_filter_hash(uint64_t lo, uint64_t hi)
 {
-    const uint64_t h = (lo ^ 0xA0761D6478BD642Full) * 0xE7037ED1A0B428DBull + hi * 0x8EBC6AF09C88C6E3ull;
-    return (uint32_t)((h ^ (h >> 29)) >> 17) & fmask;
+    uint64_t h = (lo ^ 0xA0761D6478BD642Full) * 0xE7037ED1A0B428DBull + hi * 0x8EBC6AF09C88C6E3ull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    return h ^ (h >> 32);
+}
+__device__ __forceinline__ uint32_t psi_filter_word(uint64_t h, uint32_t fmask) { return (uint32_t)(h >> 32) & fmask; }
+__device__ __forceinline__ uint64_t psi_filter_bits(uint64_t h)
+{
+    return (1ull << (h & 63u)) | (1ull << ((h >> 6) & 63u)) | (1ull << ((h >> 12) & 63u)) |
+           (1ull << ((h >> 18) & 63u));
 }
 
 // false: the key is certainly not in the set
 __device__ __forceinline__ bool psi_maybe(const PsiSet &t, uint64_t lo, uint64_t hi)
 {
     if (!t.filter) return true;
-    const uint32_t b = psi_filter_bit(lo, hi, t.fmask);
-    return (t.filter[b >> 5] >> (b & 31u)) & 1u;
+    const uint64_t h = psi_filter_hash(lo, hi), m = psi_filter_bits(h);
+    return (t.filter[psi_filter_word(h, t.fmask)] & m) == m;
 }
 
 __device__ __forceinline__ bool psi_contains(const PsiSet &t, uint64_t lo, uint64_t hi)

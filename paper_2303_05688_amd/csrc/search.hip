@@ -617,14 +617,14 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_psi_insert(const uint64_t *__restrict__ dets, size_t nd, int n,
                                                        uint64_t *__restrict__ tlo, uint64_t *__restrict__ thi,
                                                        uint32_t *__restrict__ state, uint32_t mask,
-                                                       uint32_t *__restrict__ filter, uint32_t fmask)
+                                                       unsigned long long *__restrict__ filter, uint32_t fmask)
 {
     const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nd) return;
     const uint64_t a = dets[2 * j], b = dets[2 * j + 1];
     const uint64_t lo = W == 1 ? ((a << n) | b) : b, hi = W == 1 ? 0ull : a;
-    const uint32_t fb = psi_filter_bit(lo, hi, fmask);
-    atomicOr(&filter[fb >> 5], 1u << (fb & 31u));
+    const uint64_t fh = psi_filter_hash(lo, hi);
+    atomicOr(&filter[psi_filter_word(fh, fmask)], (unsigned long long)psi_filter_bits(fh));
     uint32_t s = psi_hash(lo, hi, mask);
     for (uint32_t probe = 0; probe <= mask; ++probe) {
         if (atomicCAS(&state[s], 0u, 1u) == 0u) {
@@ -985,7 +985,7 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     const size_t hist_bytes = ((nd + kScanTile - 1) / kScanTile) * 256 * 4 * 2 + (1 << 16);
     ar.reset();
     ar.reserve(nd * (8 * 2 * W + 4 * 2) + nd * (8 * 2 + 4 * 2) + nq * 8 * 4 + kMaxClasses * 20 +
-               (size_t)2 * n * n * 8 + 2 * hist_bytes + 64 * 256 + (nd * 8 + 1024) * 20 + nd * 2 + (1 << 14));
+               (size_t)2 * n * n * 8 + 2 * hist_bytes + 64 * 256 + (nd * 8 + 1024) * 20 + nd * 8 + (1 << 14));
     ar.reset();
     unsigned int *d_err = ar.take<unsigned int>(16);
     pp.d_cls = ar.take<uint64_t>(kMaxClasses);
@@ -999,15 +999,16 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     while (tsize < 4 * nd) tsize <<= 1;
     uint64_t *t_lo = ar.take<uint64_t>(tsize), *t_hi = ar.take<uint64_t>(tsize);
     uint32_t *t_state = ar.take<uint32_t>(tsize);
-    uint32_t fbits = 1u << 16;
-    while (fbits < 8 * nd && fbits < (1u << 31)) fbits <<= 1;
-    uint32_t *t_filter = ar.take<uint32_t>(fbits / 32);
+    // exclusion filter: 32 bits per input determinant (a power of two, at least 2^16)
+    size_t fbits = (size_t)1 << 16;
+    while (fbits < 32 * nd && fbits < ((size_t)1 << 34)) fbits <<= 1;
+    unsigned long long *t_filter = ar.take<unsigned long long>(fbits / 64);
     pp.psi.lo = t_lo;
     pp.psi.hi = t_hi;
     pp.psi.state = t_state;
     pp.psi.mask = tsize - 1;
     pp.psi.filter = t_filter;
-    pp.psi.fmask = fbits - 1;
+    pp.psi.fmask = (uint32_t)(fbits / 64 - 1);
 
     ASCI_HIP(hipMemsetAsync(d_err, 0, 16 * sizeof(unsigned int), s));
     k_validate<<<grid_for(nd), kBlock, 0, s>>>(dets, nd, full, na, nb, d_err);
@@ -1020,7 +1021,7 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
         ASCI_HIP(hipMemsetAsync(t_state, 0, (size_t)tsize * sizeof(uint32_t), s));
         ASCI_HIP(hipMemsetAsync(t_filter, 0, (size_t)fbits / 8, s));
         k_psi_insert<W><<<grid_for(nd), kBlock, 0, s>>>(dets, nd, n, t_lo, t_hi, t_state, tsize - 1, t_filter,
-                                                        fbits - 1);
+                                                        pp.psi.fmask);
         ASCI_LAUNCH_CHECK();
         k_psi_dups<W><<<grid_for(nd), kBlock, 0, s>>>(dets, nd, n, pp.psi, d_err);
         ASCI_LAUNCH_CHECK();
