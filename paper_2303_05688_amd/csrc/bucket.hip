@@ -1016,8 +1016,8 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                 const uint32_t ai = S.aidx[u];
                 if (cached) {
                     const double *cs = colsum + (size_t)ai * n;
-                    double cross = 0.0;
-                    for (uint64_t m = b; m; m &= m - 1ull) cross = cross + cs[lowbit(m)];
+                    const double cross = n <= 32 ? bit_sum<uint32_t>((uint32_t)b, [&](int q) { return cs[q]; })
+                                                 : bit_sum<uint64_t>(b, [&](int q) { return cs[q]; });
                     haa = ((f.ecore + ealpha[ai]) + spin_e(f.st, 1, X, hd, n, b)) + cross;
                 } else {
                     haa = diag_tab(f.st, J, X, hd, n, f.ecore, a, b);
@@ -1034,7 +1034,14 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                         }
                     }
                 } else {
-                    for (uint32_t j = j0; j < j1; ++j) sum = sum + S.val[j];
+                    // four values in flight at a time, added in order
+                    for (uint32_t j = j0; j < j1; j += 4) {
+                        double v[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) v[k] = S.val[min(j + (uint32_t)k, j1 - 1u)];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) sum = j + (uint32_t)k < j1 ? sum + v[k] : sum;
+                    }
                     keep = true;
                 }
                 score = sum / den;

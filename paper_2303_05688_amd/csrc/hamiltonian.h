@@ -82,12 +82,32 @@ __device__ __forceinline__ double spin_energy_m(const double *X, const double *h
     return e;
 }
 
+// sum over the set bits p of m, ascending, of v(p): the adds run in that order
+// from 0.0; the values are loaded four at a time (a spare slot loads v(0) and
+// is not added), so their latencies overlap
+template <typename M, typename F>
+__device__ __forceinline__ double bit_sum(M m, F v)
+{
+    double s = 0.0;
+    while (m) {
+        double x[4];
+        bool ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            ok[k] = m != 0;
+            x[k] = v(ok[k] ? tz(m) : 0);
+            m &= m - 1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = ok[k] ? s + x[k] : s;
+    }
+    return s;
+}
+
 template <typename M>
 __device__ __forceinline__ double cross_col_m(const double *J, int n, M a, int q)
 {
-    double c = 0.0;
-    for (M m = a; m; m &= m - 1) c = c + J[tz(m) * n + q];
-    return c;
+    return bit_sum<M>(a, [&](int p) { return J[p * n + q]; });
 }
 
 template <typename M>
