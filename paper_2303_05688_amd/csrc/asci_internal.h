@@ -333,7 +333,8 @@ __device__ __forceinline__ bool psi_contains(const PsiSet &t, uint64_t lo, uint6
 // strings, e[1] the beta strings (null: no table, evaluate directly).
 struct SpinTables {
     const double *e[2] = {nullptr, nullptr};
-    const uint32_t *binom = nullptr;
+    const uint32_t *binom = nullptr;  // (kmax + 4) rows of n + 1: C(p, k) for k <= kmax, then zeros
+    int kmax = 0;
 };
 
 // Which tables a search builds: count[i] strings (0 = none) for alpha (0) and

@@ -580,7 +580,7 @@ struct FinishArgs {
     uint32_t *cnt;              // per final segment: candidates written
     uint32_t nfinal;
     PsiSet psi;                 // input determinants (exclusion)
-    int tab_in_lds;             // J, J-K, h_pp staged in LDS (else read from jk)
+    int tab_in_lds;             // staged in LDS: 1 J, J-K, h_pp; 2 J and the binomials; 3 the binomials; 0 none
 };
 
 // E(s) of one spin string (0 = alpha, 1 = beta): looked up when tabulated
@@ -668,8 +668,8 @@ struct FinishLds {
 
 // one final segment, processed by the whole workgroup
 template <int W, int CAP, int NT>
-__device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W, CAP, NT> &S, const double *J,
-                                               const double *X, const double *hd, uint32_t sidx)
+__device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTables &st, FinishLds<W, CAP, NT> &S,
+                                               const double *J, const double *X, const double *hd, uint32_t sidx)
 {
     using L = FinishLds<W, CAP, NT>;
     constexpr int NW = L::NW;
@@ -695,7 +695,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             uint32_t c = 0;
             if (!ex) {
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
-                const double den = f.E0 - diag_tab(f.st, J, X, hd, n, f.ecore, a, b);
+                const double den = f.E0 - diag_tab(st, J, X, hd, n, f.ecore, a, b);
                 double sum = 0.0;
                 uint32_t kept = 0;
                 for (uint32_t r = 0; r < sg.size; ++r) {
@@ -981,7 +981,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
             const uint32_t ai = t / (uint32_t)n, q = t - ai * (uint32_t)n;
             colsum[t] = cross_col(J, n, alist[ai], (int)q);
         }
-        for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_e(f.st, 0, X, hd, n, alist[t]);
+        for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_e(st, 0, X, hd, n, alist[t]);
         __syncthreads();
     }
     // runs, NT at a time: key (read back from the segment), exclusion,
@@ -1018,9 +1018,9 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, FinishLds<W,
                     const double *cs = colsum + (size_t)ai * n;
                     const double cross = n <= 32 ? bit_sum<uint32_t>((uint32_t)b, [&](int q) { return cs[q]; })
                                                  : bit_sum<uint64_t>(b, [&](int q) { return cs[q]; });
-                    haa = ((f.ecore + ealpha[ai]) + spin_e(f.st, 1, X, hd, n, b)) + cross;
+                    haa = ((f.ecore + ealpha[ai]) + spin_e(st, 1, X, hd, n, b)) + cross;
                 } else {
-                    haa = diag_tab(f.st, J, X, hd, n, f.ecore, a, b);
+                    haa = diag_tab(st, J, X, hd, n, f.ecore, a, b);
                 }
                 const double den = f.E0 - haa;
                 // the run's values, in sorted (= record, ascending core) order
@@ -1086,21 +1086,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     double *tab = reinterpret_cast<double *>(smem_raw + ((sizeof(L) + 15) & ~size_t(15)));
     const int n = f.n;
     const int tid = threadIdx.x;
-    const double *J, *X, *hd;
-    if (f.tab_in_lds) {
+    const double *J = f.jk, *X = f.jk + n * n, *hd = f.jk + 2 * n * n;
+    SpinTables st = f.st;
+    if (f.tab_in_lds == 1) {
         for (int t = tid; t < 2 * n * n; t += NT) tab[t] = f.jk[t];
         for (int t = tid; t < n; t += NT) tab[2 * n * n + t] = f.h[(size_t)t * n + t];
         J = tab;
         X = tab + n * n;
         hd = tab + 2 * n * n;
-    } else {
-        J = f.jk;
-        X = f.jk + n * n;
-        hd = f.jk + 2 * n * n;
+    } else if (f.tab_in_lds >= 2) {
+        // with both spin tables only J and the binomials of the string ranks are read
+        const int nj = f.tab_in_lds == 2 ? n * n : 0;
+        for (int t = tid; t < nj; t += NT) tab[t] = f.jk[t];
+        uint32_t *bt = reinterpret_cast<uint32_t *>(tab + nj);
+        for (int t = tid; t < (st.kmax + 4) * (n + 1); t += NT) bt[t] = f.st.binom[t];
+        if (nj) J = tab;
+        st.binom = bt;
     }
     for (uint32_t sidx = blockIdx.x; sidx < f.nfinal; sidx += gridDim.x) {
         __syncthreads();
-        finish_segment<W, CAP, NT>(f, S, J, X, hd, sidx);
+        finish_segment<W, CAP, NT>(f, st, S, J, X, hd, sidx);
     }
 }
 
@@ -1229,9 +1234,24 @@ template <int W, int CAP, int NT>
 static void launch_finish(FinishArgs &fa, const BucketArgs &b, uint32_t nf, hipStream_t s, Profiler *prof)
 {
     const size_t base_lds = (sizeof(FinishLds<W, CAP, NT>) + 15) & ~size_t(15);
-    const size_t tab_lds = ((size_t)2 * b.n * b.n + b.n) * 8;
-    fa.tab_in_lds = base_lds + tab_lds <= kFinishLdsBudget ? 1 : 0;
-    const size_t lds = base_lds + (fa.tab_in_lds ? tab_lds : 0);
+    const size_t n = (size_t)b.n;
+    size_t tab_lds = 0;
+    fa.tab_in_lds = 0;
+    if (b.st.e[0] && b.st.e[1]) {
+        // E(alpha), E(beta) are looked up: stage J and the binomials, else the binomials
+        const size_t bin = (size_t)(b.st.kmax + 4) * (n + 1) * 4;
+        if (base_lds + n * n * 8 + bin <= kFinishLdsBudget) {
+            fa.tab_in_lds = 2;
+            tab_lds = n * n * 8 + bin;
+        } else if (base_lds + bin <= kFinishLdsBudget) {
+            fa.tab_in_lds = 3;
+            tab_lds = bin;
+        }
+    } else if (base_lds + (2 * n * n + n) * 8 <= kFinishLdsBudget) {
+        fa.tab_in_lds = 1;
+        tab_lds = (2 * n * n + n) * 8;
+    }
+    const size_t lds = base_lds + ((tab_lds + 15) & ~size_t(15));
     const void *fn = (const void *)k_finish<W, CAP, NT>;
     ASCI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int dev = 0, ncu = 0, per_cu = 0;

@@ -154,14 +154,13 @@ __device__ __forceinline__ uint32_t spin_rank_m(const uint32_t *binom, int n, M 
     uint32_t r = 0;
     const uint32_t *row = binom + (n + 1);
     while (m) {
+        // unconditional loads (a spare slot reads C(0, k) and adds nothing)
         uint32_t v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            v[k] = 0u;
-            if (m) {
-                v[k] = row[k * (n + 1) + tz(m)];
-                m &= m - 1;
-            }
+            const bool ok = m != 0;
+            v[k] = row[k * (n + 1) + (ok ? tz(m) : 0)] & (ok ? ~0u : 0u);
+            m &= m - 1;
         }
         r += (v[0] + v[1]) + (v[2] + v[3]);
         row += 4 * (n + 1);

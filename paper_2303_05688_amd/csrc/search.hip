@@ -800,7 +800,7 @@ SpinTablePlan spin_table_plan(int n, int na, int nb, uint64_t pairs, bool enable
     if (pl.count[0] == 0 && pl.count[1] == 0) return pl;
     pl.kmax = std::max(pl.count[0] ? na : 0, pl.count[1] ? nb : 0);
     const size_t tab = (size_t)(pl.count[0] + (pl.share ? 0 : pl.count[1])) * 8;
-    pl.bytes = tab + (size_t)(pl.kmax + 1) * (n + 1) * 4 + 1024;
+    pl.bytes = tab + (size_t)(pl.kmax + 4) * (n + 1) * 4 + 1024;
     return pl;
 }
 
@@ -814,7 +814,9 @@ static SpinTables build_spin_tables(asci_ctx *ctx, const SpinTablePlan &pl, cons
     ar.reset();
     ar.reserve(pl.bytes);
     ar.reset();
-    std::vector<uint32_t> hb((size_t)(pl.kmax + 1) * (n + 1));
+    // rows 0..kmax, and three zero rows that the rank's unconditional loads may
+    // touch past the last electron
+    std::vector<uint32_t> hb((size_t)(pl.kmax + 4) * (n + 1), 0u);
     for (int k = 0; k <= pl.kmax; ++k)
         for (int p = 0; p <= n; ++p)
             hb[(size_t)k * (n + 1) + p] = (uint32_t)std::min<uint64_t>(binom_sat(p, k), UINT32_MAX);
@@ -824,6 +826,7 @@ static SpinTables build_spin_tables(asci_ctx *ctx, const SpinTablePlan &pl, cons
     std::memcpy(hs.ptr, hb.data(), hb.size() * 4);
     ASCI_HIP(hipMemcpyAsync(d_binom, hs.ptr, hb.size() * 4, hipMemcpyHostToDevice, s));
     st.binom = d_binom;
+    st.kmax = pl.kmax;
     const int ne[2] = {na, nb};
     for (int i = 0; i < 2; ++i) {
         if (pl.count[i] == 0) continue;
