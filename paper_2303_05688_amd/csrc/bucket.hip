@@ -896,8 +896,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
     }
     const int aw = n - low;  // window bits at or above this one are alpha bits (one-word keys: also two-word)
     const uint32_t amax = min(255u, L::kAcacheBytes / (8u * (uint32_t)(n + 2)));
-    uint64_t *alist = &S.acache[0];
-    double *ealpha = reinterpret_cast<double *>(alist + amax);
+    double *ealpha = reinterpret_cast<double *>(&S.acache[0]);
     double *colsum = ealpha + amax;
     uint32_t nalpha, nruns;
     {
@@ -953,13 +952,18 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
             }
         }
         if (tid == 0) head[nruns] = (uint16_t)size;
-        // the alpha strings, in order
+        // the alpha strings, in order: E(alpha) by the thread that owns the
+        // alpha head, the column sums c_q(alpha) by the lanes of its wavefront
+        // (one alpha head of the wavefront at a time)
         if (nalpha <= amax) {
-            uint32_t a2 = at >> 16;
-#pragma unroll
-            for (int i = 0; i < IT; ++i)
-                if ((flags >> (16 + i)) & 1u) {
-                    const uint32_t r = perm[j0 + i];
+            uint32_t ai_next = at >> 16;
+            uint32_t pend = (flags >> 16) & ((1u << IT) - 1u);
+            for (uint64_t owners = __ballot(pend != 0u); owners; owners = __ballot(pend != 0u)) {
+                const int src = __ffsll((long long)owners) - 1;
+                uint32_t a_lo = 0u, a_hi = 0u, ai = 0u;
+                if (lane == src) {
+                    const int i = __ffs(pend) - 1;
+                    const uint32_t r = perm[j0 + (uint32_t)i];
                     uint64_t klo = and_lo, khi = and_hi;
                     if (nwin >= 2) {
                         klo = gk[r];
@@ -967,8 +971,19 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
                     } else if (nwin == 1) {
                         key_put<W>(S.ck[r], low, n, klo, khi);
                     }
-                    alist[a2++] = W == 1 ? (klo >> n) : khi;
+                    const uint64_t alpha = W == 1 ? (klo >> n) : khi;
+                    ai = ai_next++;
+                    ealpha[ai] = spin_e(st, 0, X, hd, n, alpha);
+                    a_lo = (uint32_t)alpha;
+                    a_hi = (uint32_t)(alpha >> 32);
+                    pend &= pend - 1u;
                 }
+                a_lo = __shfl(a_lo, src, 64);
+                a_hi = __shfl(a_hi, src, 64);
+                ai = __shfl(ai, src, 64);
+                const uint64_t alpha = (uint64_t)a_lo | ((uint64_t)a_hi << 32);
+                for (int q = lane; q < n; q += 64) colsum[(size_t)ai * n + q] = cross_col(J, n, alpha, q);
+            }
         }
 #pragma unroll
         for (int i = 0; i < IT; ++i)
@@ -976,14 +991,6 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
         __syncthreads();
     }
     const bool cached = nalpha <= amax;
-    if (cached) {
-        for (uint32_t t = tid; t < nalpha * (uint32_t)n; t += NT) {
-            const uint32_t ai = t / (uint32_t)n, q = t - ai * (uint32_t)n;
-            colsum[t] = cross_col(J, n, alist[ai], (int)q);
-        }
-        for (uint32_t t = tid; t < nalpha; t += NT) ealpha[t] = spin_e(st, 0, X, hd, n, alist[t]);
-        __syncthreads();
-    }
     // runs, NT at a time: key (read back from the segment), exclusion,
     // diagonal, sum in record order, score; one scan per round places the
     // surviving candidates, compacted, in run order
