@@ -292,20 +292,48 @@ __global__ __launch_bounds__(kThreads) void k_sel_compact(const double *__restri
     }
 }
 
-__global__ void k_sel_pick(SelectState *st, int shift)
+// one wavefront: lane l holds digits 255 - 4l .. 252 - 4l, so a scan across
+// the lanes counts the entries above every digit; the digit taken is the
+// largest d >= 1 with (entries above d) + hist[d] >= krem, else 0
+__global__ __launch_bounds__(64) void k_sel_pick(SelectState *st, int shift)
 {
-    if (threadIdx.x != 0) return;
-    uint64_t need = st->krem, cum = 0;
-    int d = 255;
-    for (; d > 0; --d) {
-        uint64_t c = st->hist[d];
-        if (cum + c >= need) break;
-        cum += c;
+    const int lane = threadIdx.x;
+    uint32_t c[4];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = st->hist[255 - 4 * lane - k];
+        sum += c[k];
     }
-    st->krem = need - cum;
-    st->prefix |= (uint64_t)d << shift;
-    st->mask |= 0xFFull << shift;
-    for (int i = 0; i < 256; ++i) st->hist[i] = 0u;
+    uint64_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t ylo = __shfl_up((uint32_t)incl, d, 64), yhi = __shfl_up((uint32_t)(incl >> 32), d, 64);
+        if (lane >= d) incl += (uint64_t)ylo | ((uint64_t)yhi << 32);
+    }
+    const uint64_t need = st->krem;
+    uint64_t cum = incl - sum, above = 0;
+    int found = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int dg = 255 - 4 * lane - k;
+        if (found < 0 && (dg == 0 || cum + c[k] >= need)) {
+            found = dg;
+            above = cum;
+        }
+        cum += c[k];
+    }
+    const uint64_t bal = __ballot(found >= 0);
+    const int src = __ffsll((long long)bal) - 1;
+    const int d = __shfl(found, src, 64);
+    const uint32_t alo = __shfl((uint32_t)above, src, 64), ahi = __shfl((uint32_t)(above >> 32), src, 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st->hist[4 * lane + k] = 0u;
+    if (lane == 0) {
+        st->krem = need - ((uint64_t)alo | ((uint64_t)ahi << 32));
+        st->prefix |= (uint64_t)d << shift;
+        st->mask |= 0xFFull << shift;
+    }
 }
 
 }  // namespace
