@@ -268,19 +268,30 @@ __global__ __launch_bounds__(T) void k_seg_splitters(const Seg *__restrict__ seg
 }
 
 // per segment: number of tiles
+// tiles per large segment; also clears the level's skip flags and the count of
+// next-level segments (instead of separate fill launches)
 __global__ __launch_bounds__(256) void k_seg_tiles(const Seg *__restrict__ segs, uint32_t nseg,
-                                                   uint32_t *__restrict__ ntile)
+                                                   uint32_t *__restrict__ ntile, uint32_t *__restrict__ skip,
+                                                   uint32_t *__restrict__ nnext)
 {
     const uint32_t s = blockIdx.x * 256 + threadIdx.x;
     if (s < nseg) ntile[s] = (segs[s].size + kTileN - 1) / kTileN;
+    if (s <= nseg) skip[s] = 0u;
+    if (s == 0) *nnext = 0u;
 }
 
+// the segment of every tile; also starts the OR / AND of every segment's keys
 __global__ __launch_bounds__(256) void k_seg_expand(const Seg *__restrict__ segs, uint32_t nseg,
                                                     const uint32_t *__restrict__ tile_base,
-                                                    uint32_t *__restrict__ tile_seg)
+                                                    uint32_t *__restrict__ tile_seg, unsigned long long *__restrict__ kor,
+                                                    unsigned long long *__restrict__ kand)
 {
     const uint32_t s = blockIdx.x * 256 + threadIdx.x;
     if (s >= nseg) return;
+    kor[2 * s] = 0ull;
+    kor[2 * s + 1] = 0ull;
+    kand[2 * s] = ~0ull;
+    kand[2 * s + 1] = ~0ull;
     const uint32_t nt = (segs[s].size + kTileN - 1) / kTileN, tb = tile_base[s];
     for (uint32_t t = 0; t < nt; ++t) tile_seg[tb + t] = s;
 }
@@ -1183,37 +1194,57 @@ __global__ __launch_bounds__(256) void k_class_segs(const uint64_t *__restrict__
     // a class's keys share every bit at or above n + (lowest bit of its mask);
     // a run of classes shares the bits above the highest bit where its first
     // lower bound and last upper bound differ
-    uint32_t g_start = 0, g_size = 0, g_first = 0, g_last = 0;
-    auto top_of = [&](uint32_t cf, uint32_t cl) -> uint32_t {
-        const uint64_t Tf = s_cls[cf], Tl = s_cls[cl];
+    uint32_t g_start = 0, g_size = 0;
+    uint64_t g_first = 0, g_last = 0;  // masks of the run's first and last class
+    bool g_one = true;                 // the run holds one class
+    auto top_of = [&](uint64_t Tf, uint64_t Tl, bool one) -> uint32_t {
         const int of = Tf ? __ffsll((unsigned long long)Tf) - 1 : 0;
         const int ol = Tl ? __ffsll((unsigned long long)Tl) - 1 : 0;
-        if (cf == cl) return (uint32_t)(n + of);
+        if (one) return (uint32_t)(n + of);
         // alpha range [Tf, Tl | (2^ol - 1)]
         const uint64_t lo = Tf, hi = Tl | ((1ull << ol) - 1ull);
         const uint64_t diff = lo ^ hi;
         return (uint32_t)n + (diff ? (uint32_t)(64 - __clzll((long long)diff)) : 0u);
     };
     auto flush = [&]() {
-        if (g_size) finals[nf++] = Seg{g_start, g_size, make_meta(top_of(g_first, g_last), 0u, false)};
+        if (g_size) finals[nf++] = Seg{g_start, g_size, make_meta(top_of(g_first, g_last, g_one), 0u, false)};
         g_size = 0;
     };
-    for (uint32_t c = 0; c < nc; ++c) {
-        const uint32_t start = s_start[c], end = s_start[c + 1];
-        if (end <= start) continue;
-        const uint32_t size = end - start;
-        if (size > cap) {
-            flush();
-            large[nl++] = Seg{start, size, make_meta(top_of(c, c), 0u, false)};
-            continue;
+    // eight classes' bounds and masks are read at a time, so the walk waits on
+    // LDS once per eight classes
+    uint32_t prev = s_start[0];
+    for (uint32_t cb = 0; cb < nc; cb += 8) {
+        uint32_t e8[8];
+        uint64_t t8[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t c = min(cb + (uint32_t)k, nc - 1u);
+            e8[k] = s_start[c + 1];
+            t8[k] = s_cls[c];
         }
-        if (g_size + size > cap) flush();
-        if (g_size == 0) {
-            g_start = start;
-            g_first = c;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (cb + (uint32_t)k >= nc) break;
+            const uint32_t start = prev, end = e8[k];
+            prev = end;
+            if (end <= start) continue;
+            const uint32_t size = end - start;
+            if (size > cap) {
+                flush();
+                large[nl++] = Seg{start, size, make_meta(top_of(t8[k], t8[k], true), 0u, false)};
+                continue;
+            }
+            if (g_size + size > cap) flush();
+            if (g_size == 0) {
+                g_start = start;
+                g_first = t8[k];
+                g_one = true;
+            } else {
+                g_one = false;
+            }
+            g_size += size;
+            g_last = t8[k];
         }
-        g_size += size;
-        g_last = c;
     }
     flush();
     *nfinal = nf;
@@ -1301,13 +1332,11 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         require(lev < 64, ASCI_EDEVICE, "bucket split did not converge");
         Seg *segs = lv[lev & 1], *next = lv[(lev & 1) ^ 1];
         uint32_t *nnext = ctr + 1 + ((lev & 1) ^ 1);
-        ASCI_HIP(hipMemsetAsync(nnext, 0, sizeof(uint32_t), s));
         uint32_t *ntile = ar.take<uint32_t>(nlarge + 1);
         uint32_t *tbase = ar.take<uint32_t>(nlarge + 1);
         uint32_t *skip = ar.take<uint32_t>(nlarge + 1);
         uint32_t *d_ntiles = ar.take<uint32_t>(4);
-        ASCI_HIP(hipMemsetAsync(skip, 0, (nlarge + 1) * sizeof(uint32_t), s));
-        k_seg_tiles<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, ntile);
+        k_seg_tiles<<<(nlarge + 256) / 256, 256, 0, s>>>(segs, nlarge, ntile, skip, nnext);
         ASCI_LAUNCH_CHECK();
         scan_u32(ntile, tbase, nlarge, d_ntiles, ar, s, prof);
         ASCI_HIP(hipMemcpyAsync(hcnt + 4, d_ntiles, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -1320,9 +1349,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         uint64_t *spl_hi = W == 2 ? ar.take<uint64_t>((size_t)nlarge * (kMaxSplit - 1)) : nullptr;
         unsigned long long *kor = ar.take<unsigned long long>(2 * (size_t)nlarge);
         unsigned long long *kand = ar.take<unsigned long long>(2 * (size_t)nlarge);
-        ASCI_HIP(hipMemsetAsync(kor, 0, 2 * (size_t)nlarge * sizeof(unsigned long long), s));
-        ASCI_HIP(hipMemsetAsync(kand, 0xFF, 2 * (size_t)nlarge * sizeof(unsigned long long), s));
-        k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg);
+        k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg, kor, kand);
         ASCI_LAUNCH_CHECK();
         {
             ProfScope ps(prof, "split_sample", 0.0, s);
