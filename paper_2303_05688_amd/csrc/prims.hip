@@ -1,6 +1,7 @@
 // Device primitives for the search: exclusive scan, stable LSD radix sort and
 // radix selection.  Written for 64-wide wavefronts (gfx950): ranking inside a
 // wave uses ballots, blocks are 256 threads (4 waves).
+#include <type_traits>
 #include "asci_internal.h"
 
 namespace asci {
@@ -135,18 +136,21 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t lo, uint64_t hi, int word,
     return (uint32_t)(k >> shift) & 0xFFu;
 }
 
-template <int W>
+// IT records per thread: a tile of kThreads * IT records per workgroup (small
+// sorts take small tiles, so that they still spread over the CUs)
+template <int W, int IT>
 __global__ __launch_bounds__(kThreads) void k_rs_hist(const uint64_t *__restrict__ klo,
                                                       const uint64_t *__restrict__ khi, size_t n,
                                                       int word, int shift,
                                                       uint32_t *__restrict__ hist, uint32_t nblocks)
 {
+    constexpr int TILE = kThreads * IT;
     __shared__ uint32_t h[kWaves][256];
     const int tid = threadIdx.x, w = tid >> 6;
     for (int i = tid; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0u;
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * kTile;
-    for (int i = tid; i < kTile; i += kThreads) {
+    const size_t base = (size_t)blockIdx.x * TILE;
+    for (int i = tid; i < TILE; i += kThreads) {
         size_t j = base + i;
         if (j < n) {
             uint64_t lo = klo[j];
@@ -163,12 +167,13 @@ __global__ __launch_bounds__(kThreads) void k_rs_hist(const uint64_t *__restrict
 
 // Stable scatter of one tile.  Tile order is (wave, slot, lane), which is the
 // input index order, so equal digits keep their input order.
-template <int W, typename V>
+template <int W, typename V, int IT>
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(
     const uint64_t *__restrict__ ilo, const uint64_t *__restrict__ ihi, const V *__restrict__ ival,
     uint64_t *__restrict__ olo, uint64_t *__restrict__ ohi, V *__restrict__ oval, size_t n, int word,
     int shift, const uint32_t *__restrict__ hist, uint32_t nblocks)
 {
+    constexpr int kTile = kThreads * IT, kItems = IT;
     __shared__ uint64_t s_lo[kTile];
     __shared__ uint64_t s_hi[W == 2 ? kTile : 1];
     __shared__ V s_val[kTile];
@@ -257,12 +262,16 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const double *__restrict_
     h[threadIdx.x] = 0u;
     __syncthreads();
     const uint64_t prefix = st->prefix, mask = st->mask;
-    const size_t base = (size_t)blockIdx.x * kTile;
-    for (int i = threadIdx.x; i < kTile; i += kThreads) {
-        size_t j = base + i;
-        if (j < n) {
-            uint64_t o = abs_order(score[j]);
-            if ((o & mask) == prefix) atomicAdd(&h[(o >> shift) & 0xFFu], 1u);
+    // the workgroups stride over the tiles, so that few of them add their
+    // counts to the global bins (the leading digits of |A| fall into very few
+    // bins, and atomics on one address serialise)
+    for (size_t base = (size_t)blockIdx.x * kTile; base < n; base += (size_t)gridDim.x * kTile) {
+        for (int i = threadIdx.x; i < kTile; i += kThreads) {
+            size_t j = base + i;
+            if (j < n) {
+                uint64_t o = abs_order(score[j]);
+                if ((o & mask) == prefix) atomicAdd(&h[(o >> shift) & 0xFFu], 1u);
+            }
         }
     }
     __syncthreads();
@@ -371,33 +380,53 @@ int radix_sort(uint64_t *keys_lo[2], uint64_t *keys_hi[2], V *vals[2], size_t n,
     int cur = 0;
     if (n <= 1 || digits.empty()) return cur;
     require(n < (1ull << 32), ASCI_EINVAL, "radix sort: too many records");
-    size_t nb = (n + kTile - 1) / kTile;
+    // the smallest tile that keeps the histogram short (its scan is one small launch)
+    int it = 16;
+    for (int c : {2, 4, 8})
+        if ((n + (size_t)kThreads * c - 1) / ((size_t)kThreads * c) <= 64) {
+            it = c;
+            break;
+        }
+    const size_t tile = (size_t)kThreads * it;
+    size_t nb = (n + tile - 1) / tile;
     uint32_t *hist = ar.take<uint32_t>(nb * 256);
     for (const Digit &d : digits) {
         const int nxt = cur ^ 1;
         const double kb = 8.0 * words, rb = kb + sizeof(V);
         {
         ProfScope ps(prof, "rs_hist", kb * n, s);
-        if (words == 2) {
-            k_rs_hist<2><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], keys_hi[cur], n, d.word, d.shift,
-                                                           hist, (uint32_t)nb);
-        } else {
-            k_rs_hist<1><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], nullptr, n, 0, d.shift, hist,
-                                                           (uint32_t)nb);
-        }
+        auto hist_k = [&](auto itc) {
+            constexpr int I = decltype(itc)::value;
+            if (words == 2)
+                k_rs_hist<2, I><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], keys_hi[cur], n, d.word, d.shift,
+                                                                  hist, (uint32_t)nb);
+            else
+                k_rs_hist<1, I><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], nullptr, n, 0, d.shift, hist,
+                                                                  (uint32_t)nb);
+        };
+        if (it == 2) hist_k(std::integral_constant<int, 2>{});
+        else if (it == 4) hist_k(std::integral_constant<int, 4>{});
+        else if (it == 8) hist_k(std::integral_constant<int, 8>{});
+        else hist_k(std::integral_constant<int, 16>{});
         ASCI_LAUNCH_CHECK();
         }
         scan_u32(hist, hist, nb * 256, nullptr, ar, s, prof);
         ProfScope ps(prof, "rs_scatter", 2.0 * rb * n, s);
-        if (words == 2) {
-            k_rs_scatter<2, V><<<(unsigned)nb, kThreads, 0, s>>>(
-                keys_lo[cur], keys_hi[cur], vals[cur], keys_lo[nxt], keys_hi[nxt], vals[nxt], n, d.word,
-                d.shift, hist, (uint32_t)nb);
-        } else {
-            k_rs_scatter<1, V><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], nullptr, vals[cur],
-                                                                 keys_lo[nxt], nullptr, vals[nxt], n, 0,
-                                                                 d.shift, hist, (uint32_t)nb);
-        }
+        auto scat_k = [&](auto itc) {
+            constexpr int I = decltype(itc)::value;
+            if (words == 2)
+                k_rs_scatter<2, V, I><<<(unsigned)nb, kThreads, 0, s>>>(
+                    keys_lo[cur], keys_hi[cur], vals[cur], keys_lo[nxt], keys_hi[nxt], vals[nxt], n, d.word,
+                    d.shift, hist, (uint32_t)nb);
+            else
+                k_rs_scatter<1, V, I><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], nullptr, vals[cur],
+                                                                        keys_lo[nxt], nullptr, vals[nxt], n, 0,
+                                                                        d.shift, hist, (uint32_t)nb);
+        };
+        if (it == 2) scat_k(std::integral_constant<int, 2>{});
+        else if (it == 4) scat_k(std::integral_constant<int, 4>{});
+        else if (it == 8) scat_k(std::integral_constant<int, 8>{});
+        else scat_k(std::integral_constant<int, 16>{});
         ASCI_LAUNCH_CHECK();
         cur = nxt;
     }
@@ -495,7 +524,7 @@ void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_
         }
         if (nb) {
             ProfScope ps(prof, "select_hist", 8.0 * n, s);
-            k_sel_hist<<<(unsigned)nb, kThreads, 0, s>>>(x, n, shift, d_state);
+            k_sel_hist<<<(unsigned)std::min<size_t>(nb, 2048), kThreads, 0, s>>>(x, n, shift, d_state);
             ASCI_LAUNCH_CHECK();
         }
         k_sel_pick<<<1, 64, 0, s>>>(d_state, shift);
