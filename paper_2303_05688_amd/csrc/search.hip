@@ -172,26 +172,14 @@ struct GenArgs {
     uint64_t *klo, *khi;
     double *vals;
     size_t cap;
-    unsigned long long *key_or_and;
 };
 
 template <int W>
-__device__ __forceinline__ void emit(const GenArgs &g, size_t dst, uint64_t a2, uint64_t b2, double v,
-                                     uint64_t &or0, uint64_t &and0, uint64_t &or1, uint64_t &and1)
+__device__ __forceinline__ void emit(const GenArgs &g, size_t dst, uint64_t a2, uint64_t b2, double v)
 {
     if (dst < g.cap) {
         put_key<W>(g.klo, g.khi, dst, a2, b2, g.n);
         g.vals[dst] = v;
-    }
-    if (W == 1) {
-        const uint64_t k = (a2 << g.n) | b2;
-        or0 |= k;
-        and0 &= k;
-    } else {
-        or0 |= b2;
-        and0 &= b2;
-        or1 |= a2;
-        and1 &= a2;
     }
 }
 
@@ -288,7 +276,6 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     if (lane == 0 && self_in) cur[cs - g.c0] += g.f0;
     __syncthreads();
 
-    uint64_t or0 = 0ull, and0 = ~0ull, or1 = 0ull, and1 = ~0ull;
     // f0 block: the alpha string is unchanged
     if (self_in && g.f0) {
         const size_t base = g.offsets[(size_t)(cs - g.c0) * g.nq + i];
@@ -296,7 +283,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         for (uint32_t t = lane; t < ns1; t += 64) {
             const uint32_t x = bsX[t];
             const double hv = single_value(g.h, g.eri, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
-            emit<W>(g, base + t, a, bsB[t], hv * ci, or0, and0, or1, and1);
+            emit<W>(g, base + t, a, bsB[t], hv * ci);
         }
         // beta-beta doubles y = hole pair * pvb2 + particle pair, the pair
         // indices advanced by the 64 records a lane strides over
@@ -309,8 +296,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
                 const uint64_t hb = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
                 const uint64_t pb = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
                 const uint64_t b2 = (b & ~hb) | pb;
-                emit<W>(g, base + ns1 + y, a, b2, double_same_value(g.eri, n, b, hb, pb) * ci, or0, and0, or1,
-                        and1);
+                emit<W>(g, base + ns1 + y, a, b2, double_same_value(g.eri, n, b, hb, pb) * ci);
                 pp += r64;
                 hp += q64;
                 if (pp >= g.pvb2) {
@@ -354,13 +340,13 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             const uint64_t a2 = asA[u];
             const size_t dst = (size_t)asP[u] + j;
             if (j == 0) {
-                emit<W>(g, dst, a2, b, asV[u] * ci, or0, and0, or1, and1);
+                emit<W>(g, dst, a2, b, asV[u] * ci);
             } else {
                 const uint32_t x = bsX[j - 1], xa = asX[u];
                 const int p = (int)(xa & 0xFFu), q = (int)((xa >> 8) & 0xFFu);
                 const int r = (int)(x & 0xFFu), s = (int)((x >> 8) & 0xFFu);
                 const int sg = (((xa ^ x) >> 16) & 1u) ? -1 : 1;
-                emit<W>(g, dst, a2, bsB[j - 1], (sg * eri4(g.eri, n, q, p, s, r)) * ci, or0, and0, or1, and1);
+                emit<W>(g, dst, a2, bsB[j - 1], (sg * eri4(g.eri, n, q, p, s, r)) * ci);
             }
         }
     }
@@ -393,29 +379,10 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             if (act) {
                 const size_t dst = (size_t)before + (uint32_t)__popcll(peers & lt);
                 if ((peers & lt) == 0ull) cur[key] = before + (uint32_t)__popcll(peers);
-                emit<W>(g, dst, a2, b, double_same_value(g.eri, n, a, holes, parts) * ci, or0, and0, or1, and1);
+                emit<W>(g, dst, a2, b, double_same_value(g.eri, n, a, holes, parts) * ci);
             }
         }
     }
-    for (int d = 32; d >= 1; d >>= 1) {
-        or0 |= __shfl_xor(or0, d, 64);
-        and0 &= __shfl_xor(and0, d, 64);
-        or1 |= __shfl_xor(or1, d, 64);
-        and1 &= __shfl_xor(and1, d, 64);
-    }
-    if (lane == 0) {
-        atomicOr(&g.key_or_and[0], (unsigned long long)or0);
-        atomicAnd(&g.key_or_and[1], (unsigned long long)and0);
-        if (W == 2) {
-            atomicOr(&g.key_or_and[2], (unsigned long long)or1);
-            atomicAnd(&g.key_or_and[3], (unsigned long long)and1);
-        }
-    }
-}
-
-__global__ void k_init_or_and(unsigned long long *p)
-{
-    if (threadIdx.x < 4) p[threadIdx.x] = (threadIdx.x & 1) ? ~0ull : 0ull;
 }
 
 // ---- stable compaction of the pool to its keepk largest |score| entries:
@@ -1156,7 +1123,6 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     double *p_score[2] = {ar.take<double>(pool_cap), ar.take<double>(pool_cap)};
     SelectState *d_sel = ar.take<SelectState>(1);
     uint32_t *d_cnt = ar.take<uint32_t>(16);
-    unsigned long long *d_misc = ar.take<unsigned long long>(16);
     const size_t loop_mark = ar.used();
 
     HostStage &hs = ctx->stage;
@@ -1214,7 +1180,6 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         }
         scan_u32(counts, offs, ent, d_cnt + 2, ar, s, prof);
         // step 5: generate
-        k_init_or_and<<<1, 64, 0, s>>>(d_misc);
         ASCI_LAUNCH_CHECK();
         {
             ProfScope ps(prof, "generate", (8.0 * W + 8.0) * P, s);
@@ -1248,7 +1213,6 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.khi = k_hi[0];
             ga.vals = v[0];
             ga.cap = Pb;
-            ga.key_or_and = d_misc;
             const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 +
                                2 * ((size_t)ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
             k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
