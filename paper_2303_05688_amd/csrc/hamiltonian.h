@@ -15,9 +15,12 @@ namespace asci {
 // logic error from turning into an out-of-bounds load.
 __device__ __forceinline__ int orb(int p, int n) { return (int)min((unsigned)p, (unsigned)(n - 1)); }
 
+// n <= 64, so the flat index (below 64^4) fits 32-bit arithmetic
 __device__ __forceinline__ double eri4(const double *__restrict__ eri, int n, int p, int q, int r, int s)
 {
-    return eri[(((size_t)orb(p, n) * n + orb(q, n)) * n + orb(r, n)) * n + orb(s, n)];
+    const uint32_t un = (uint32_t)n;
+    return eri[(((uint32_t)orb(p, n) * un + (uint32_t)orb(q, n)) * un + (uint32_t)orb(r, n)) * un +
+               (uint32_t)orb(s, n)];
 }
 
 // <a|H|i> for a single p -> q in the spin string `same` of i; `other` is the
