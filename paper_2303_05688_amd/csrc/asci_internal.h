@@ -85,6 +85,7 @@ class Profiler {
     std::vector<ProfEntry> entries;
     int begin(const char *name, double bytes, hipStream_t s);  // -1 when off
     void end(int token, hipStream_t s);
+    void set_bytes(int token, double bytes);  // bytes of a launch only known later
     void collect();  // after the stream has been synchronised
     void reset();
 
@@ -366,7 +367,11 @@ struct BucketArgs {
     int finish_cap = 4096;          // LDS capacity of a final segment (tunable)
     uint64_t *clo, *chi;            // candidate slots (P)
     double *cnum, *cscore;
-    // results of bucket_accumulate
+    // results of bucket_accumulate.  With defer_v the candidate count V is
+    // left in flight to *h_v (pinned): bucket_read_v waits for it, so that
+    // work the count does not gate (the collect) can be queued first.
+    bool defer_v = false;
+    const uint32_t *h_v = nullptr;
     uint32_t nfinal = 0, V = 0, levels = 0;
     const uint32_t *order = nullptr, *cnt_sorted = nullptr, *off = nullptr;
     const void *finals = nullptr;
@@ -379,7 +384,8 @@ size_t bucket_workspace_bytes(size_t P, size_t nc, int W, int finish_cap);
 template <int W>
 void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, HostStage &hs);
 template <int W>
-void bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof);
+int bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof);  // profiler token (-1: untimed)
+void bucket_read_v(BucketArgs &b, hipStream_t s);
 // sum over the batch's candidates of N_a * A_a (deterministic order)
 double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs);
 

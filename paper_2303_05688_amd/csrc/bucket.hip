@@ -1455,8 +1455,13 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     }
     scan_u32(cs, co, nf, d_v, ar, s, nullptr);
     ASCI_HIP(hipMemcpyAsync(hcnt + 6, d_v, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    ASCI_HIP(hipStreamSynchronize(s));
-    b.V = hcnt[6];
+    b.h_v = hcnt + 6;
+    if (b.defer_v) {
+        b.V = ~0u;  // unknown until bucket_read_v
+    } else {
+        ASCI_HIP(hipStreamSynchronize(s));
+        b.V = hcnt[6];
+    }
     b.order = si[r];
     b.cnt_sorted = cs;
     b.off = co;
@@ -1464,14 +1469,24 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
 }
 
 template <int W>
-void bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof)
+int bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof)
 {
-    if (b.nfinal == 0 || b.V == 0) return;
-    ProfScope ps(prof, "collect", (8.0 * W + 8.0) * 2.0 * b.V, s);
+    if (b.nfinal == 0 || b.V == 0) return -1;
+    // with the count still in flight the bytes are set once it is known
+    ProfScope ps(prof, "collect", b.defer_v ? 0.0 : (8.0 * W + 8.0) * 2.0 * b.V, s);
     k_collect<W><<<std::min<uint32_t>(b.nfinal, 65536u), 256, 0, s>>>((const Seg *)b.finals, b.nfinal, b.order, b.cnt_sorted, b.off, b.clo, b.chi, b.cnum,
                                          b.cscore, b.pool_lo, b.pool_hi, b.pool_num, b.pool_score, b.pool_base,
                                          b.pool_cap);
     ASCI_LAUNCH_CHECK();
+    return ps.tok;
+}
+
+void bucket_read_v(BucketArgs &b, hipStream_t s)
+{
+    if (!b.defer_v) return;
+    ASCI_HIP(hipStreamSynchronize(s));
+    b.V = *b.h_v;
+    b.defer_v = false;
 }
 
 // sum of N_a * A_a over the batch's candidates: per final segment in key
@@ -1522,7 +1537,7 @@ double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs)
 
 template void bucket_accumulate<1>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);
 template void bucket_accumulate<2>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);
-template void bucket_collect<1>(BucketArgs &, hipStream_t, Profiler *);
-template void bucket_collect<2>(BucketArgs &, hipStream_t, Profiler *);
+template int bucket_collect<1>(BucketArgs &, hipStream_t, Profiler *);
+template int bucket_collect<2>(BucketArgs &, hipStream_t, Profiler *);
 
 }  // namespace asci

@@ -476,6 +476,11 @@ int Profiler::begin(const char *name, double bytes, hipStream_t s)
 
 void Profiler::end(int token, hipStream_t s) { ASCI_HIP(hipEventRecord(pending_[token].b, s)); }
 
+void Profiler::set_bytes(int token, double bytes)
+{
+    if (token >= 0 && (size_t)token < pending_.size()) pending_[(size_t)token].bytes = bytes;
+}
+
 void Profiler::collect()
 {
     for (auto &p : pending_) {

@@ -1247,29 +1247,47 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.chi = c_hi;
         ba.cnum = c_num;
         ba.cscore = c_score;
-        bucket_accumulate<W>(ba, ar, s, prof, hs);
-        if (out.pt2) {
-            out.pt2_energy = out.pt2_energy + bucket_pt2(ba, ar, s, hs);
-            out.count += ba.V;
-            continue;
-        }
-        const uint32_t V = ba.V;
-        ctx->last_finals += ba.nfinal;
-        ctx->last_levels = std::max<int64_t>(ctx->last_levels, ba.levels);
-        ctx->last_candidates += V;
-        if (topk && pool_n + V > pool_cap) prune((size_t)std::min<uint64_t>(pool_n, (uint64_t)out.k));
-        if (pool_n + V > pool_cap)
-            throw Error{ASCI_ENOMEM, "candidate pool overflow: pool " + std::to_string(pool_n) + " + batch " +
-                                         std::to_string(V) + " > capacity " + std::to_string(pool_cap) +
-                                         " (batch pairs " + std::to_string(P) + ", finals " +
-                                         std::to_string(ba.nfinal) + ", max batch " + std::to_string(Pb) + ")"};
+        // when the batch cannot overflow the pool, its collect is queued
+        // before the host waits for the candidate count
+        const bool early = !out.pt2 && pool_n + P <= pool_cap;
+        ba.defer_v = early;
         ba.pool_lo = p_lo[pcur];
         ba.pool_hi = p_hi[pcur];
         ba.pool_num = p_num;
         ba.pool_score = p_score[pcur];
         ba.pool_base = pool_n;
         ba.pool_cap = pool_cap;
-        bucket_collect<W>(ba, s, prof);
+        bucket_accumulate<W>(ba, ar, s, prof, hs);
+        if (out.pt2) {
+            out.pt2_energy = out.pt2_energy + bucket_pt2(ba, ar, s, hs);
+            out.count += ba.V;
+            continue;
+        }
+        int collect_tok = -1;
+        if (early) {
+            collect_tok = bucket_collect<W>(ba, s, prof);
+            bucket_read_v(ba, s);
+            if (prof) prof->set_bytes(collect_tok, (8.0 * W + 8.0) * 2.0 * ba.V);
+        }
+        const uint32_t V = ba.V;
+        ctx->last_finals += ba.nfinal;
+        ctx->last_levels = std::max<int64_t>(ctx->last_levels, ba.levels);
+        ctx->last_candidates += V;
+        if (!early) {
+            if (topk && pool_n + V > pool_cap) prune((size_t)std::min<uint64_t>(pool_n, (uint64_t)out.k));
+            if (pool_n + V > pool_cap)
+                throw Error{ASCI_ENOMEM, "candidate pool overflow: pool " + std::to_string(pool_n) + " + batch " +
+                                             std::to_string(V) + " > capacity " + std::to_string(pool_cap) +
+                                             " (batch pairs " + std::to_string(P) + ", finals " +
+                                             std::to_string(ba.nfinal) + ", max batch " + std::to_string(Pb) + ")"};
+            ba.pool_lo = p_lo[pcur];
+            ba.pool_hi = p_hi[pcur];
+            ba.pool_num = p_num;
+            ba.pool_score = p_score[pcur];
+            ba.pool_base = pool_n;
+            ba.pool_cap = pool_cap;
+            bucket_collect<W>(ba, s, prof);
+        }
         pool_n += V;
         if (topk && bi + 1 < batches.size() && pool_n > (uint64_t)out.k) {
             prune((size_t)out.k);
