@@ -120,6 +120,30 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *s_tmp, uint
     return base + x - v;
 }
 
+// The same scan with one barrier: consecutive calls alternate between the two
+// halves of s_tmp (2 * NW entries), so a call's totals are never overwritten
+// before every thread has passed the next call's barrier.  `parity` flips per
+// call and must be uniform across the workgroup.
+template <int NW>
+__device__ __forceinline__ uint32_t block_scan1(uint32_t v, uint32_t *s_tmp, uint32_t &parity, uint32_t &total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t *buf = s_tmp + parity * NW;
+    parity ^= 1u;
+    const uint32_t x = wave_incl_scan(v);
+    if (lane == 63) buf[w] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const uint32_t t = buf[i];
+        base += (i < w) ? t : 0u;
+        tot += t;
+    }
+    total = tot;
+    return base + x - v;
+}
+
 // ---------------------------------------------------------------- split level
 struct SplitArgs {
     const Seg *segs;          // large segments of this level
@@ -672,7 +696,7 @@ struct FinishLds {
         uint8_t aidx[CAP];
     };
     uint32_t dbase[256];
-    uint32_t tmp[NW];
+    uint32_t tmp[2 * NW];
     uint32_t nruns, nalpha;
     uint64_t red[4][NW];  // per-wave OR / AND of the key words
 };
@@ -693,6 +717,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
     const Seg sg = f.finals[sidx];
     const uint32_t buf = seg_buf(sg);
     const uint64_t nmask = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+    uint32_t parity = 0;  // half of S.tmp for the next block scan
     const uint64_t *gk = f.klo[buf] + sg.start;
     const uint64_t *gh = f.khi[buf] + sg.start;
     const double *gv = f.val[buf] + sg.start;
@@ -948,7 +973,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
         }
         const uint32_t cnt = (uint32_t)__popc(flags & 0xFFFFu) | ((uint32_t)__popc(flags >> 16) << 16);
         uint32_t tot;
-        const uint32_t at = block_scan<NW>(cnt, S.tmp, tot);
+        const uint32_t at = block_scan1<NW>(cnt, S.tmp, parity, tot);
         nruns = tot & 0xFFFFu;
         nalpha = tot >> 16;
         // counts are below 2^16 (size <= CAP <= 4096), so the packed scan is exact
@@ -1080,7 +1105,7 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
             }
         }
         uint32_t tot;
-        const uint32_t at = block_scan<NW>(keep ? 1u : 0u, S.tmp, tot);
+        const uint32_t at = block_scan1<NW>(keep ? 1u : 0u, S.tmp, parity, tot);
         if (keep) {
             const size_t d = (size_t)sg.start + written + at;
             f.clo[d] = lo;
