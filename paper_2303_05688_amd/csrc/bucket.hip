@@ -764,18 +764,19 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
     {
         uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
         double rv[IT];
+        // record r = wv * 64 * IT + k * 64 + lane: the layout of the radix
+        // passes' items, so the first pass ranks straight from these registers
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
+            const uint32_t r = (uint32_t)wv * 64 * IT + (uint32_t)k * 64 + (uint32_t)lane;
             rk[k] = r < size ? gk[r] : 0ull;
             rv[k] = r < size ? gv[r] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
+            const uint32_t r = (uint32_t)wv * 64 * IT + (uint32_t)k * 64 + (uint32_t)lane;
             if (r < size) {
                 const uint64_t lo = rk[k], hi = W == 2 ? gh[r] : 0ull;
-                S.ix[0][r] = (uint16_t)r;
                 S.val[r] = rv[k];
                 o0 |= lo;
                 a0 &= lo;
@@ -816,21 +817,32 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
     const int span = low < 0 ? 0 : key_top<W>(var_lo, var_hi, n) - low;
     const int nwin = (span + 31) / 32;  // 32-bit windows holding the varying bits
 
-    // stable LSD radix sort of the record indices, one window at a time
+    // stable LSD radix sort of the record indices, one window at a time.  The
+    // first pass of one-word keys takes its items (the identity order) and
+    // windows from registers and stores the windows for the later passes.
     int cur = 0;
+    if (nwin == 0) {
+        // one key: no pass runs, the order stays the identity
+        for (uint32_t r = tid; r < size; r += NT) S.ix[0][r] = (uint16_t)r;
+        __syncthreads();
+    }
     for (int win = 0; win < nwin; ++win) {
         const int o = low + 32 * win;
         const uint32_t vwin = key_window<W>(var_lo, var_hi, n, o);
-        if (W == 1) {
+        const bool regs = W == 1 && win == 0;
+        if (W == 1 && !regs) {
 #pragma unroll
             for (int k = 0; k < IT; ++k) {
-                const uint32_t r = (uint32_t)tid + (uint32_t)k * NT;
+                const uint32_t r = (uint32_t)wv * 64 * IT + (uint32_t)k * 64 + (uint32_t)lane;
                 if (r < size) S.ck[r] = key_window<W>(rk[k], 0ull, n, o);
             }
-        } else {
-            for (uint32_t r = tid; r < size; r += NT) S.ck[r] = key_window<W>(gk[r], W == 2 ? gh[r] : 0ull, n, o);
+        } else if (W == 2) {
+            for (uint32_t r = tid; r < size; r += NT) S.ck[r] = key_window<W>(gk[r], gh[r], n, o);
+            // the first pass of two-word keys reads the identity order from LDS
+            if (win == 0)
+                for (uint32_t r = tid; r < size; r += NT) S.ix[0][r] = (uint16_t)r;
         }
-        __syncthreads();
+        if (!regs) __syncthreads();
         for (int sh = 0; sh < 32; sh += 8) {
             const uint32_t dv = (vwin >> sh) & 0xFFu;
             if (dv == 0u) continue;  // no record differs in these bits
@@ -843,14 +855,25 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
             // loads are unconditional and in bounds; past the segment's end the
             // values are ignored)
             static_assert((CAP & (CAP - 1)) == 0, "CAP must be a power of two");
-#pragma unroll
-            for (int q = 0; q < IT; ++q) {
-                const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
-                item[q] = (uint32_t)S.ix[cur][li] & (uint32_t)(CAP - 1);
-            }
             uint32_t cw[IT];
+            if (regs && sh == 0) {
+                // window 0 always varies in its lowest bit, so this is the first pass
 #pragma unroll
-            for (int q = 0; q < IT; ++q) cw[q] = S.ck[item[q]];
+                for (int q = 0; q < IT; ++q) {
+                    const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+                    item[q] = li;
+                    cw[q] = key_window<W>(rk[q], 0ull, n, o);
+                    if (li < size) S.ck[li] = cw[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < IT; ++q) {
+                    const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
+                    item[q] = (uint32_t)S.ix[cur][li] & (uint32_t)(CAP - 1);
+                }
+#pragma unroll
+                for (int q = 0; q < IT; ++q) cw[q] = S.ck[item[q]];
+            }
 #pragma unroll
             for (int q = 0; q < IT; ++q) {
                 const uint32_t li = (uint32_t)wv * 64 * IT + (uint32_t)q * 64 + lane;
