@@ -5,10 +5,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 imports, links or calls it.
 
 The arithmetic lives in ``asci_oracle.c`` (plain C, compiled with gcc
-``-O2 -ffp-contract=off``); this module compiles it and wraps it with ctypes.
-Which passage of the paper each function follows is stated in the C file.
-Every function here is pinned by tests against brute force, closed forms or
-invariants; none is "parity unpinned".
+``-O2 -ffp-contract=off -fopenmp``); this module compiles it and wraps it with
+ctypes.  Which passage of the paper each function follows is stated in the C
+file.  Every function here is pinned by tests against brute force, closed
+forms, invariants or another oracle function that is itself pinned; none is
+"parity unpinned".
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc; returns the shared-library path."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -37,7 +38,14 @@ def build(force: bool = True) -> str:
 class _Result(C.Structure):
     _fields_ = [("count", C.c_int64), ("keys", C.POINTER(C.c_uint64)),
                 ("num", C.POINTER(C.c_double)), ("hdiag", C.POINTER(C.c_double)),
-                ("score", C.POINTER(C.c_double)), ("npairs", C.c_int64)]
+                ("score", C.POINTER(C.c_double)), ("num_abs", C.POINTER(C.c_double)),
+                ("hdiag_abs", C.POINTER(C.c_double)), ("tol", C.POINTER(C.c_double)),
+                ("npairs", C.c_int64)]
+
+
+class _BucketStats(C.Structure):
+    _fields_ = [("candidates", C.c_int64), ("npairs", C.c_int64), ("pt2", C.c_double),
+                ("pt2_abs", C.c_double), ("pt2_tol", C.c_double), ("max_drop_upper", C.c_double)]
 
 
 def lib():
@@ -77,9 +85,16 @@ def lib():
         L.oracle_target_numerators.restype = C.c_int
         L.oracle_target_numerators.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_double, up, dp,
                                                C.c_int64, C.c_int64, up, C.c_int64, dp, dp,
-                                               C.POINTER(C.c_int), ip]
+                                               C.POINTER(C.c_int), ip, dp, dp]
+        L.oracle_score_tol.restype = C.c_double
+        L.oracle_score_tol.argtypes = [C.c_double] * 5
+        L.oracle_search_buckets.restype = C.c_int
+        L.oracle_search_buckets.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_double, up, dp,
+                                            C.c_int64, C.c_double, C.c_int64, C.c_double, C.c_int, C.c_int,
+                                            C.c_int, C.c_int, C.c_int64, C.POINTER(_Result),
+                                            C.POINTER(_BucketStats)]
         L.oracle_hmat_dense.restype = C.c_int
-        L.oracle_hmat_dense.argtypes = [dp, dp, C.c_int, C.c_double, up, C.c_int64, dp]
+        L.oracle_hmat_dense.argtypes = [dp, dp, C.c_int, C.c_double, up, C.c_int64, dp, dp]
         L.oracle_balance.restype = C.c_int
         L.oracle_balance.argtypes = [ip, C.c_int64, C.c_int, C.POINTER(C.c_int), ip]
         _lib = L
@@ -143,10 +158,29 @@ def energy(h, eri, dets, coeffs, ecore=0.0):
     return lib().oracle_energy(hp, ep, n, ecore, dp, cp, len(c))
 
 
+_FIELDS = ("num", "hdiag", "score", "num_abs", "hdiag_abs", "tol")
+
+
+def _take(r):
+    """Copy an oracle_result into numpy arrays (the C side is freed by the caller)."""
+    u = r.count
+    out = {"keys": np.ctypeslib.as_array(r.keys, shape=(2 * u,)).reshape(u, 2).copy() if u
+           else np.zeros((0, 2), np.uint64), "npairs": r.npairs}
+    for f in _FIELDS:
+        out[f] = np.ctypeslib.as_array(getattr(r, f), shape=(u,)).copy() if u else np.zeros(0)
+    return out
+
+
+def score_tol(num, num_abs, hdiag, hdiag_abs, E0):
+    """Absolute tolerance of a score evaluated in another order (C: oracle_score_tol)."""
+    return lib().oracle_score_tol(float(num), float(num_abs), float(hdiag), float(hdiag_abs), float(E0))
+
+
 def search_all(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, ecore=0.0,
                keep_psi=False):
     """Every candidate of the search: dict of keys (U x 2 uint64, ascending),
-    num (N_a), hdiag (H_aa), score (A_a), npairs."""
+    num (N_a), hdiag (H_aa), score (A_a), the magnitude sums num_abs and
+    hdiag_abs, tol (absolute score tolerance of another evaluation order), npairs."""
     keep, hp, ep, n = _ham(h, eri)
     if n != norb:
         raise ValueError("norb does not match the integrals")
@@ -158,17 +192,40 @@ def search_all(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, 
     if rc != 0:
         raise ValueError("oracle_search failed with code %d" % rc)
     try:
-        u = r.count
-        out = {
-            "keys": np.ctypeslib.as_array(r.keys, shape=(2 * u,)).reshape(u, 2).copy() if u else np.zeros((0, 2), np.uint64),
-            "num": np.ctypeslib.as_array(r.num, shape=(u,)).copy() if u else np.zeros(0),
-            "hdiag": np.ctypeslib.as_array(r.hdiag, shape=(u,)).copy() if u else np.zeros(0),
-            "score": np.ctypeslib.as_array(r.score, shape=(u,)).copy() if u else np.zeros(0),
-            "npairs": r.npairs,
-        }
+        out = _take(r)
     finally:
         lib().oracle_free(C.byref(r))
     return out
+
+
+def search_buckets(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, ecore=0.0, nbuckets=64,
+                   buckets=None, threads=None, keep_top=0):
+    """The search computed by target buckets (C: oracle_search_buckets): the
+    candidates of buckets [b0, b1) (default all), bucket by bucket, ascending key
+    inside a bucket, or each bucket's keep_top best by (|A| desc, key asc).
+    Returns (dict as search_all, stats dict)."""
+    keep, hp, ep, n = _ham(h, eri)
+    if n != norb:
+        raise ValueError("norb does not match the integrals")
+    d, dp = _u(dets)
+    c, cp = _d(coeffs)
+    b0, b1 = (0, nbuckets) if buckets is None else buckets
+    if threads is None:
+        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    r = _Result()
+    st = _BucketStats()
+    rc = lib().oracle_search_buckets(hp, ep, n, nalpha, nbeta, ecore, dp, cp, len(c), float(E0), int(ncore),
+                                     float(eps), int(nbuckets), int(b0), int(b1), int(threads), int(keep_top),
+                                     C.byref(r), C.byref(st))
+    try:
+        if rc != 0:
+            raise ValueError("oracle_search_buckets failed with code %d" % rc)
+        out = _take(r)
+    finally:
+        lib().oracle_free(C.byref(r))
+    stats = {f: getattr(st, f) for f, _ in _BucketStats._fields_}
+    stats["threads"] = threads
+    return out, stats
 
 
 def topk_index(keys, score, k):
@@ -209,9 +266,10 @@ def class_counts(norb, nalpha, nbeta, dets, coeffs, ncore=0, level=3):
     raise RuntimeError("class count changed between calls")
 
 
-def target_numerators(h, eri, norb, nalpha, nbeta, dets, coeffs, targets, ncore=0, ecore=0.0):
+def target_numerators(h, eri, norb, nalpha, nbeta, dets, coeffs, targets, ncore=0, ecore=0.0, with_abs=False):
     """For each target determinant: (N_a, H_aa, is an input determinant, number of
-    connected core determinants), evaluated one target at a time."""
+    connected core determinants), evaluated one target at a time; with_abs adds
+    the magnitude sums (num_abs, hdiag_abs) of the tolerance."""
     keep, hp, ep, n = _ham(h, eri)
     d, dp = _u(dets)
     c, cp = _d(coeffs)
@@ -221,13 +279,18 @@ def target_numerators(h, eri, norb, nalpha, nbeta, dets, coeffs, targets, ncore=
     hd = np.zeros(m)
     inp = np.zeros(m, dtype=np.int32)
     nconn = np.zeros(m, dtype=np.int64)
+    na_, ha_ = np.zeros(m), np.zeros(m)
     rc = lib().oracle_target_numerators(hp, ep, n, nalpha, nbeta, ecore, dp, cp, len(c), int(ncore), tp, m,
                                         num.ctypes.data_as(C.POINTER(C.c_double)),
                                         hd.ctypes.data_as(C.POINTER(C.c_double)),
                                         inp.ctypes.data_as(C.POINTER(C.c_int)),
-                                        nconn.ctypes.data_as(C.POINTER(C.c_int64)))
+                                        nconn.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        na_.ctypes.data_as(C.POINTER(C.c_double)),
+                                        ha_.ctypes.data_as(C.POINTER(C.c_double)))
     if rc != 0:
         raise ValueError("invalid determinants")
+    if with_abs:
+        return num, hd, inp.astype(bool), nconn, na_, ha_
     return num, hd, inp.astype(bool), nconn
 
 
@@ -264,15 +327,18 @@ def balance(counts, npe):
 
 # ---------------------------------------------------------------- the ASCI loop (Alg. 1)
 
-def hamiltonian(h, eri, dets, ecore=0.0):
+def hamiltonian(h, eri, dets, ecore=0.0, with_abs=False):
     """Dense H over a determinant set by the plain double loop (Sec. II.C):
-    <D_i|H|D_j> where the two differ by at most a double excitation, else 0."""
+    <D_i|H|D_j> where the two differ by at most a double excitation, else 0;
+    with_abs also returns the sum of |terms| of every element."""
     keep, hp, ep, n = _ham(h, eri)
     d, dp = _u(dets)
     nd = len(d)
     out = np.zeros((nd, nd))
-    lib().oracle_hmat_dense(hp, ep, n, float(ecore), dp, nd, out.ctypes.data_as(C.POINTER(C.c_double)))
-    return out
+    ab = np.zeros((nd, nd)) if with_abs else None
+    lib().oracle_hmat_dense(hp, ep, n, float(ecore), dp, nd, out.ctypes.data_as(C.POINTER(C.c_double)),
+                            ab.ctypes.data_as(C.POINTER(C.c_double)) if with_abs else None)
+    return (out, ab) if with_abs else out
 
 
 def lowest(H):
@@ -316,3 +382,36 @@ def asci_loop(h, eri, norb, nalpha, nbeta, dets0, coeffs0, ntdets, ncore=0, max_
         if done:
             break
     return hist
+
+
+# ---------------------------------------------------------------- selection under the score tolerance
+
+def topk_bands(keys, score, tol, k, outside_upper=0.0):
+    """Which candidates any evaluation order within the tolerance must select.
+
+    Every score A_a is known to lie in [|A_a| - tol_a, |A_a| + tol_a] (L_a, U_a)
+    for a result computed in another order.  A candidate is surely among the k
+    selected when fewer than k others can reach its lower bound
+    (#{b != a: U_b >= L_a} < k) and it beats every candidate not listed
+    (L_a > outside_upper, the largest U of those); it is surely out when k
+    others are above it for certain (#{b: L_b > U_a} >= k).  The rest are
+    ambiguous: the selection may take either.  Returns (sure_in, ambiguous)
+    masks and whether every candidate not listed is surely out."""
+    a = np.abs(np.asarray(score, dtype=np.float64))
+    tol = np.asarray(tol, dtype=np.float64)
+    L, U = a - tol, a + tol
+    Us, Ls = np.sort(U), np.sort(L)
+    reach = len(U) - np.searchsorted(Us, L, side="left") - 1  # others with U_b >= L_a
+    sure_in = (reach < k) & (L > outside_upper)
+    above = len(L) - np.searchsorted(Ls, U, side="right")      # others with L_b > U_a
+    sure_out = above >= k
+    if (sure_in & sure_out).any():
+        raise AssertionError("inconsistent tolerance bands")
+    outside_ok = outside_upper <= 0.0 or (len(L) - np.searchsorted(Ls, outside_upper, side="right")) >= k
+    return sure_in, ~sure_in & ~sure_out, bool(outside_ok)
+
+
+def key_codes(keys):
+    """(alpha, beta) keys as one sortable structured array (order = key order)."""
+    keys = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64).reshape(-1, 2))
+    return keys.view([("a", np.uint64), ("b", np.uint64)]).ravel()

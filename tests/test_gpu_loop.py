@@ -1,13 +1,17 @@
 """The variational step and the ASCI loop on the GPU (Alg. 1, Alg. 5, Sec. II.C)
-against the oracle: the double-loop Hamiltonian (bit-exact elements, same
-sparsity), its product with a vector, Davidson against a dense eigensolver, and
-loop iterations against the oracle's selection rule, up to the full-CI limit."""
+against the oracle: the double-loop Hamiltonian (same sparsity, every element
+within 64 u of the sum of |terms| that form it: the diagonal is grouped
+differently on the two sides), its product with a vector, Davidson against a
+dense eigensolver, and loop iterations against the oracle's selection rule
+under the score tolerance, up to the full-CI limit."""
 import numpy as np
 import pytest
 
 import asci_synth as syn
 import sq_bruteforce as bf
 from gpu_util import host, to_dev
+
+U = 2.0 ** -53
 
 pytestmark = pytest.mark.gpu
 
@@ -62,9 +66,12 @@ def test_hamiltonian_equals_oracle_double_loop(asci, oracle_lib, n, na, nb, nd, 
     pattern = np.zeros((nd, nd), bool)
     pattern[np.repeat(np.arange(nd), np.diff(rp)), cols] = True
     assert (pattern == mask).all()
-    want = oracle_lib.hamiltonian(c["h"], c["eri"], c["dets"], ecore=0.3)
-    # same Slater-Condon routines and operation order: bit for bit
-    assert (got == want).all(), np.abs(got - want).max()
+    want, wabs = oracle_lib.hamiltonian(c["h"], c["eri"], c["dets"], ecore=0.3, with_abs=True)
+    # every element within 64 u of its magnitude sum (the off-diagonal ones
+    # share the oracle's term order and come out bit-identical in practice)
+    assert (np.abs(got - want) <= np.maximum(1e-12 * np.abs(want), 64 * U * wabs)).all(), np.abs(got - want).max()
+    off = ~np.eye(nd, dtype=bool)
+    print("off-diagonal elements bit-identical: %d of %d" % ((got[off] == want[off]).sum(), off.sum()))
     # H v against the dense product
     x = np.random.default_rng(seed).standard_normal(nd)
     import torch
@@ -123,8 +130,12 @@ def test_davidson_at_full_size_16e20o(asci):
 
 def _step_parity(asci, oracle_lib, c, d, opts, steps):
     """Iterate loop_step on the GPU; at every step the oracle, given the same
-    psi_k, C_k and E_k, selects the same psi_{k+1} (bit for bit) and its dense
-    eigensolver gives the same energy."""
+    psi_k, C_k and E_k, ranks psi_k by |C_i| and the candidates by |A_a| (within
+    their tolerances): the GPU's psi_{k+1} holds every entry that rule surely
+    selects and nothing it surely rejects, in non-increasing score order, and
+    its energy is the lowest eigenvalue of the oracle's H over psi_{k+1}."""
+    import oracle
+
     n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
     dets_d = d["dets"]
     C_d = d["coeffs"]
@@ -133,16 +144,28 @@ def _step_parity(asci, oracle_lib, c, d, opts, steps):
     for k in range(steps):
         nd_d, nc_d, info = asci.loop_step(d["h"], d["eri"], n, na, nb, dets_d, C_d, E, opts)
         dets_h, C_h = host(dets_d), host(C_d)
-        cand, sc = oracle_lib.search(c["h"], c["eri"], n, na, nb, dets_h, C_h, E, opts.ntdets, ncore=opts.ncore)
-        want_dets, want_guess = oracle_lib.select_next(dets_h, C_h, cand, sc, opts.ntdets)
+        cand = oracle_lib.search_all(c["h"], c["eri"], n, na, nb, dets_h, C_h, E, ncore=opts.ncore)
+        keys = np.concatenate([dets_h, cand["keys"]])
+        score = np.concatenate([np.abs(C_h), np.abs(cand["score"])])
+        tol = np.concatenate([np.zeros(len(C_h)), cand["tol"]])
+        o = np.argsort(oracle.key_codes(keys), kind="stable")
+        keys, score, tol = keys[o], score[o], tol[o]
+        sure, amb, _ = oracle_lib.topk_bands(keys, score, tol, opts.ntdets)
         got = host(nd_d)
-        print("step", k, "size", len(got), "E", info["energy"], flush=True)
-        assert got.shape == want_dets.shape and (got == want_dets).all()
-        Hw = oracle_lib.hamiltonian(c["h"], c["eri"], want_dets)
+        print("step", k, "size", len(got), "E", info["energy"], "ambiguous", int(amb.sum()), flush=True)
+        assert len(got) == min(opts.ntdets, len(keys))
+        pos = np.searchsorted(oracle.key_codes(keys), oracle.key_codes(got))
+        assert (keys[pos] == got).all()
+        chosen = np.zeros(len(keys), bool)
+        chosen[pos] = True
+        assert not (sure & ~chosen).any() and not (chosen & ~sure & ~amb).any()
+        s_got, t_got = score[pos], tol[pos]
+        assert (s_got[:-1] + t_got[:-1] >= s_got[1:] - t_got[1:]).all()
+        Hw = oracle_lib.hamiltonian(c["h"], c["eri"], got)
         w = np.linalg.eigvalsh(Hw)
         gap = w[1] - w[0] if len(w) > 1 else 1.0
         assert abs(info["energy"] - w[0]) <= info["davidson_resid"] ** 2 / gap + 1e-11 * abs(w[0])
-        assert info["ndets"] == len(got) and info["nnz"] == int(_coupled(want_dets).sum())
+        assert info["ndets"] == len(got) and info["nnz"] == int(_coupled(got).sum())
         dets_d, C_d, E = nd_d.contiguous(), nc_d.contiguous(), info["energy"]
         energies.append(E)
     return energies
@@ -203,5 +226,5 @@ def test_run_with_pt2(asci, oracle_lib):
     fd, fc = host(r["dets"]), host(r["coeffs"])
     w = np.linalg.eigvalsh(oracle_lib.hamiltonian(h, eri, fd))
     assert abs(r["energy"] - w[0]) <= 1e-8 * abs(w[0])
-    e2, cnt, sabs = oracle_lib.pt2(h, eri, n, na, nb, fd, fc, r["energy"], with_abs=True)
-    assert abs(r["pt2"] - e2) <= 6144 * 2.0 ** -53 * sabs + 2 * 2.0 ** -53 * abs(e2)
+    _, st = oracle_lib.search_buckets(h, eri, n, na, nb, fd, fc, r["energy"], nbuckets=8)
+    assert abs(r["pt2"] - st["pt2"]) <= (6144 + 4) * U * st["pt2_abs"] + st["pt2_tol"]

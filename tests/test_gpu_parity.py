@@ -1,8 +1,12 @@
 """GPU parity: the HIP search (through the C ABI) against the CPU oracle.
 
-Bar: candidate sets and top-k keys bit-exact; N_a and A_a within 1e-12
-relative (both sides use the same canonical evaluation order without FMA, so
-they are expected to agree bit for bit; the tolerance is the stated bar).
+Bar: candidate sets and selected keys bit-exact (a selection may differ only
+among candidates the oracle's tolerance bands mark ambiguous); N_a within
+max(1e-12 |N_a|, 64 u num_abs) and A_a within the oracle's per-candidate
+tolerance max(1e-12 |A_a|, 64 u |A_a| (kappa_num + kappa_den)).  The oracle
+adds the diagonal element in the textbook order, the kernels group it by spin
+string, so the two differ in the last bits on most candidates; the tests do
+not rely on a shared rounding order.
 """
 import hashlib
 import json
@@ -12,11 +16,11 @@ import numpy as np
 import pytest
 
 import asci_synth as syn
-from gpu_util import assert_topk_parity, host, rel_err, to_dev
+from gpu_util import (assert_candidates, assert_head, assert_selection_order, assert_topk, assert_topk_golden,
+                      host, locate, num_tol, to_dev)
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-TOL = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -53,11 +57,8 @@ def _all_parity(asci, oracle_lib, c, E0, ncore=0, pair_buffer_bytes=0, eps=0.0, 
                                        pair_buffer_bytes=pair_buffer_bytes, eps=eps,
                                        constraint_level=constraint_level, split_pairs=split_pairs)
     want = oracle_lib.search_all(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, ncore=ncore, eps=eps)
-    gk = host(keys)
-    assert gk.shape == want["keys"].shape
-    assert (gk == want["keys"]).all()
-    assert rel_err(host(num), want["num"]).max(initial=0) <= TOL
-    assert rel_err(host(score), want["score"]).max(initial=0) <= TOL
+    exact, relaxed = assert_candidates(host(keys), host(num), host(score), want)
+    print("  %d candidates, %d scores bit-identical, %d in the relaxed band" % (len(want["keys"]), exact, relaxed))
     return want
 
 
@@ -102,8 +103,7 @@ def test_pair_threshold_eps(asci, oracle_lib, eps):
         assert len(want["keys"]) < _golden("8e12o")["ncandidates"]
     d = to_dev(c)
     gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 700, eps=eps)
-    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 700, eps=eps)
-    assert_topk_parity(host(gk), host(gs), wk, ws, TOL)
+    assert_topk(host(gk), host(gs), want, 700)
 
 
 def test_pair_threshold_eps_tiny(asci, oracle_lib):
@@ -131,17 +131,16 @@ def test_topk_8e12o(asci, oracle_lib, k):
     E0 = float.fromhex(_golden("8e12o")["E0"])
     d = to_dev(c)
     gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, k)
-    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, k)
-    assert_topk_parity(host(gk), host(gs), wk, ws, TOL)
+    want = oracle_lib.search_all(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0)
+    assert_topk(host(gk), host(gs), want, k)
 
 
-def test_topk_8e12o_matches_golden_hash(asci):
+def test_topk_8e12o_matches_golden_bands(asci):
     c = syn.workload("8e12o")
     g = _golden("8e12o")
     d = to_dev(c)
     gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], float.fromhex(g["E0"]), c["k"])
-    assert len(gk) == g["topk_count"]
-    assert _sha(host(gk)) == g["topk_keys_sha256"]
+    assert_topk_golden(host(gk), host(gs), g)
 
 
 @pytest.mark.parametrize("ncore", [1, 50, 200])
@@ -150,16 +149,16 @@ def test_topk_core_subset(asci, oracle_lib, ncore):
     E0 = float.fromhex(_golden("8e12o")["E0"])
     d = to_dev(c)
     gk, gs = asci.search(d["h"], d["eri"], 12, 4, 4, d["dets"], d["coeffs"], E0, 500, ncore=ncore)
-    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 500, ncore=ncore)
-    assert_topk_parity(host(gk), host(gs), wk, ws, TOL)
+    want = oracle_lib.search_all(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, ncore=ncore)
+    assert_topk(host(gk), host(gs), want, 500)
 
 
 def test_host_entry_point_matches_device(asci, oracle_lib):
     c = syn.workload("8e12o")
     E0 = float.fromhex(_golden("8e12o")["E0"])
     hk, hs = asci.search_host(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 1000)
-    wk, ws = oracle_lib.search(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0, 1000)
-    assert_topk_parity(hk, hs, wk, ws, TOL)
+    want = oracle_lib.search_all(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0)
+    assert_topk(hk, hs, want, 1000)
 
 
 def test_class_counts(asci, oracle_lib):
@@ -187,7 +186,8 @@ def test_energy(asci, oracle_lib, name):
     c = syn.workload(name)
     d = to_dev(c)
     e = asci.energy(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"])
-    assert e == pytest.approx(float.fromhex(_golden(name)["E0"]), rel=TOL)
+    # the GPU groups the diagonal differently: E0 agrees to a few ulps of sum |C_i C_j H_ij| (~|E0| here)
+    assert e == pytest.approx(float.fromhex(_golden(name)["E0"]), rel=1e-12)
 
 
 def test_deterministic_and_permutation_invariant(asci, oracle_lib):
@@ -201,9 +201,12 @@ def test_deterministic_and_permutation_invariant(asci, oracle_lib):
     cp = dict(c, dets=c["dets"][perm], coeffs=c["coeffs"][perm])
     dp = to_dev(cp)
     k3, s3 = asci.search(dp["h"], dp["eri"], 12, 4, 4, dp["dets"], dp["coeffs"], E0, 2000)
-    wk, ws = oracle_lib.search(cp["h"], cp["eri"], 12, 4, 4, cp["dets"], cp["coeffs"], E0, 2000)
-    assert_topk_parity(host(k3), host(s3), wk, ws, TOL)
-    assert_topk_parity(host(k3), host(s3), host(k1), host(s1), 1e-10)
+    want = oracle_lib.search_all(cp["h"], cp["eri"], 12, 4, 4, cp["dets"], cp["coeffs"], E0)
+    assert_topk(host(k3), host(s3), want, 2000)
+    # a permutation of the inputs changes the core order (hence the summation
+    # order of N_a) but not the selection outside near ties
+    assert_topk(host(k1), host(s1), oracle_lib.search_all(c["h"], c["eri"], 12, 4, 4, c["dets"], c["coeffs"], E0),
+                2000)
 
 
 def test_invalid_inputs(asci):
@@ -234,45 +237,54 @@ def test_invalid_inputs(asci):
 
 def _sampled_checks(oracle_lib, c, E0, gk, gs, ncheck=1500, seed=0):
     """Check returned candidates one at a time against the oracle: connected to
-    the core set, not an input determinant, A_a = N_a / (E0 - H_aa) within TOL."""
+    the core set, not an input determinant, A_a = N_a / (E0 - H_aa) within the
+    candidate's tolerance.  Returns how many of the checked scores are bit-identical."""
     n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
     rng = np.random.default_rng(seed)
     m = len(gk)
     idx = np.unique(np.concatenate([np.arange(min(m, ncheck // 3)),
                                     rng.integers(0, m, ncheck - ncheck // 3), [m - 1]]))
-    num, hd, inp, nconn = oracle_lib.target_numerators(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"],
-                                                       gk[idx])
+    num, hd, inp, nconn, nabs, habs = oracle_lib.target_numerators(c["h"], c["eri"], n, na, nb, c["dets"],
+                                                                   c["coeffs"], gk[idx], with_abs=True)
     assert not inp.any()
     assert (nconn >= 1).all()
     want = num / (E0 - hd)
-    assert rel_err(gs[idx], want).max() <= TOL
+    tol = np.array([oracle_lib.score_tol(x, xa, y, ya, E0) for x, xa, y, ya in zip(num, nabs, hd, habs)])
+    assert (np.abs(gs[idx] - want) <= tol).all()
+    return int((gs[idx] == want).sum())
+
+
+def _oracle_full(oracle_lib, c, E0, **kw):
+    """Every candidate from the oracle's bucketed mode, ascending key order."""
+    r, st = oracle_lib.search_buckets(c["h"], c["eri"], c["norb"], c["nalpha"], c["nbeta"], c["dets"], c["coeffs"],
+                                      E0, nbuckets=64, **kw)
+    o = np.lexsort((r["keys"][:, 1], r["keys"][:, 0]))
+    return {f: (v[o] if isinstance(v, np.ndarray) else v) for f, v in r.items()}, st
 
 
 def test_full_size_16e20o(asci, oracle_lib):
-    """The bench workload at full size: exact candidate set and top-k against
-    the oracle's stored hashes, plus per-candidate oracle checks."""
+    """The (16e,20o) workload at full size, element by element: every one of
+    the 3.7e7 candidates against the oracle (run here, threaded over target
+    buckets), the candidate keys against the stored hash, and the top 10^5
+    against the stored bands."""
     c = syn.workload("16e20o")
     g = _golden("16e20o")
     E0 = float.fromhex(g["E0"])
     d = to_dev(c)
     keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], E0)
-    hk = host(keys)
+    hk, hn, hs = host(keys), host(num), host(score)
+    del keys, num, score
     assert len(hk) == g["ncandidates"]
     assert _sha(hk) == g["cand_keys_sha256"]
-    hs = host(score)
-    if _sha(hs) != g["cand_score_sha256"]:  # not bit-exact: fall back to the tolerance bar, sampled
-        _sampled_checks(oracle_lib, c, E0, hk, hs, ncheck=3000, seed=1)
-    del keys, num, score
+    want, st = _oracle_full(oracle_lib, c, E0)
+    assert st["npairs"] == g["npairs"]
+    exact, relaxed = assert_candidates(hk, hn, hs, want)
+    print("16e20o: %d candidates, %d scores bit-identical, %d in the relaxed band" % (len(hk), exact, relaxed))
+    del hk, hn, hs
     gk, gs = asci.search(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], E0, c["k"])
     gk, gs = host(gk), host(gs)
-    assert len(gk) == g["topk_count"]
-    head = np.array([[a, b] for a, b, _ in g["topk_head"]], dtype=np.uint64)
-    assert (gk[:len(head)] == head).all()
-    assert rel_err(gs[:len(head)], [float.fromhex(x) for _, _, x in g["topk_head"]]).max() <= TOL
-    assert _sha(gk) == g["topk_keys_sha256"]
-    _sampled_checks(oracle_lib, c, E0, gk, gs)
-    order = np.lexsort((gk[:, 1], gk[:, 0], -np.abs(gs)))
-    assert (order == np.arange(len(gk))).all()
+    assert_topk_golden(gk, gs, g)
+    assert_topk(gk, gs, want, c["k"])
 
 
 SPIN_TABLE_CASES = [(12, 6, 6, 150, 41), (9, 5, 2, 60, 42), (34, 3, 2, 12, 43), (14, 7, 1, 80, 44), (6, 0, 3, 6, 45)]
@@ -295,15 +307,19 @@ def test_spin_tables_change_no_bit(asci, oracle_lib):
                                                              E0)])
             for a, b in zip(*got):
                 assert a.shape == b.shape and a.tobytes() == b.tobytes()
-        # the full-size workload, direct evaluation: the stored hashes still hold
-        ctx.set_param("spin_tables", 0)
+        # the full-size workload: direct evaluation gives the tables' bits
         c = syn.workload("16e20o")
         g = _golden("16e20o")
         d = to_dev(c)
-        keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"],
-                                           float.fromhex(g["E0"]))
-        assert _sha(host(keys)) == g["cand_keys_sha256"]
-        assert _sha(host(score)) == g["cand_score_sha256"]
+        got = []
+        for flag in (1, 0):
+            ctx.set_param("spin_tables", flag)
+            keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"],
+                                               float.fromhex(g["E0"]))
+            assert _sha(host(keys)) == g["cand_keys_sha256"]
+            got.append((_sha(host(num)), _sha(host(score))))
+            del keys, num, score
+        assert got[0] == got[1]
     finally:
         ctx.set_param("spin_tables", 1)
 
@@ -375,16 +391,20 @@ def test_class_larger_than_pair_buffer_is_split(asci, oracle_lib):
 
 @pytest.mark.parametrize("level,split", [(6, 0), (6, 1 << 18)])
 def test_full_size_16e20o_levels(asci, level, split):
-    """The bench workload with hextuplet classes (18,564 of them, about ten
-    class batches) and with only the heavy triplets split: same candidates."""
+    """The (16e,20o) workload with hextuplet classes (18,564 of them, about ten
+    class batches) and with only the heavy triplets split: the oracle's
+    candidate keys, and numerators and scores bit-identical to the triplet
+    search (the classes only partition the work)."""
     c = syn.workload("16e20o")
     g = _golden("16e20o")
     d = to_dev(c)
-    keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], float.fromhex(g["E0"]),
+    E0 = float.fromhex(g["E0"])
+    ref = [_sha(host(t)) for t in asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], E0)]
+    keys, num, score = asci.candidates(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], E0,
                                        constraint_level=level, split_pairs=split)
-    assert _sha(host(keys)) == g["cand_keys_sha256"]
-    assert _sha(host(num)) == g["cand_num_sha256"]
-    assert _sha(host(score)) == g["cand_score_sha256"]
+    assert _sha(host(keys)) == g["cand_keys_sha256"] == ref[0]
+    assert _sha(host(num)) == ref[1]
+    assert _sha(host(score)) == ref[2]
 
 
 def test_full_size_16e20o_multi_batch(asci, oracle_lib):
@@ -395,13 +415,18 @@ def test_full_size_16e20o_multi_batch(asci, oracle_lib):
     d = to_dev(c)
     gk, gs = asci.search(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], float.fromhex(g["E0"]), c["k"],
                          pair_buffer_bytes=1 << 30)
-    assert _sha(host(gk)) == g["topk_keys_sha256"]
-    assert _sha(host(gs)) == g["topk_scores_sha256"]
+    gk, gs = host(gk), host(gs)
+    assert_topk_golden(gk, gs, g)
+    k1, s1 = asci.search(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], float.fromhex(g["E0"]), c["k"])
+    assert (host(k1) == gk).all() and (host(s1) == gs).all()
 
 
-def test_full_size_24e30o_sampled(asci, oracle_lib):
-    """The Cr2-shaped (24e,30o) workload: 6.7e9 pairs in class batches; checked
-    per candidate against the oracle, plus ordering and count invariants."""
+def test_full_size_24e30o(asci, oracle_lib):
+    """The Cr2-shaped (24e,30o) workload: 6.7e9 pairs in class batches.  The top
+    10^6 against the oracle's stored bands (every surely selected key, nothing
+    surely out, the k-th |A| inside its bounds, the head), returned entries
+    checked one at a time against the oracle, and the number of candidates and
+    the PT2 sum over all of them against the stored totals."""
     c = syn.workload("24e30o")
     g = _golden("24e30o")
     E0 = float.fromhex(g["E0"])
@@ -409,10 +434,28 @@ def test_full_size_24e30o_sampled(asci, oracle_lib):
     gk, gs = asci.search(d["h"], d["eri"], 30, 12, 12, d["dets"], d["coeffs"], E0, c["k"])
     gk, gs = host(gk), host(gs)
     assert len(gk) == c["k"]
-    assert len(np.unique(gk, axis=0)) == len(gk)
-    order = np.lexsort((gk[:, 1], gk[:, 0], -np.abs(gs)))
-    assert (order == np.arange(len(gk))).all()
-    _sampled_checks(oracle_lib, c, E0, gk, gs, ncheck=600, seed=3)
+    assert_topk_golden(gk, gs, g)
+    same = _sampled_checks(oracle_lib, c, E0, gk, gs, ncheck=900, seed=3)
+    print("24e30o: %d of ~900 sampled scores bit-identical" % same)
+    e, cnt = asci.pt2(d["h"], d["eri"], 30, 12, 12, d["dets"], d["coeffs"], E0)
+    assert cnt == g["ncandidates"]
+    want = float.fromhex(g["pt2"])
+    assert abs(e - want) <= pt2_tol(want, float.fromhex(g["pt2_abs_terms"]), float.fromhex(g["pt2_term_tol"]))
+
+
+def test_two_word_keys_batch_sized(asci, oracle_lib):
+    """Keys of two words at a batch-like size: (16e,36o), 150 determinants,
+    1.1e7 pairs, every candidate compared with the oracle, then the top 10^4."""
+    c = _case(36, 8, 8, 150, seed=3608, sampler="level")
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    assert len(c["coeffs"]) * oracle_lib.sd_count(36, 8, 8) >= 10 ** 7
+    d = to_dev(c)
+    keys, num, score = asci.candidates(d["h"], d["eri"], 36, 8, 8, d["dets"], d["coeffs"], E0)
+    want, st = _oracle_full(oracle_lib, c, E0)
+    exact, relaxed = assert_candidates(host(keys), host(num), host(score), want)
+    print("36 orbitals: %d candidates, %d bit-identical, %d relaxed" % (len(want["keys"]), exact, relaxed))
+    gk, gs = asci.search(d["h"], d["eri"], 36, 8, 8, d["dets"], d["coeffs"], E0, 10_000)
+    assert_topk(host(gk), host(gs), want, 10_000)
 
 
 def test_one_target_from_more_cores_than_fit_in_lds(asci, oracle_lib):
@@ -435,45 +478,48 @@ def test_one_target_from_more_cores_than_fit_in_lds(asci, oracle_lib):
     hk, hn, hs = host(keys), host(num), host(score)
     at = np.nonzero((hk[:, 0] == t[0]) & (hk[:, 1] == t[1]))[0]
     assert len(at) == 1
-    wn, wh, inp, nconn = oracle_lib.target_numerators(h, eri, n, na, nb, dets, C, np.array([t], dtype=np.uint64))
+    wn, wh, inp, nconn, wna, wha = oracle_lib.target_numerators(h, eri, n, na, nb, dets, C,
+                                                                np.array([t], dtype=np.uint64), with_abs=True)
     assert nconn[0] == 7875 and not inp[0]
-    assert rel_err(hn[at], wn)[0] <= TOL
-    assert rel_err(hs[at], wn / (E0 - wh))[0] <= TOL
+    assert abs(hn[at][0] - wn[0]) <= num_tol(wn, wna)[0]
+    assert abs(hs[at][0] - wn[0] / (E0 - wh[0])) <= oracle_lib.score_tol(wn[0], wna[0], wh[0], wha[0], E0)
     # sampled candidates, and no input determinant among them
     rng2 = np.random.default_rng(1)
     idx = rng2.integers(0, len(hk), 400)
-    wn2, wh2, inp2, nconn2 = oracle_lib.target_numerators(h, eri, n, na, nb, dets, C, hk[idx])
+    wn2, wh2, inp2, nconn2, wna2, _ = oracle_lib.target_numerators(h, eri, n, na, nb, dets, C, hk[idx],
+                                                                   with_abs=True)
     assert not inp2.any() and (nconn2 >= 1).all()
-    assert rel_err(hn[idx], wn2).max() <= TOL
+    assert (np.abs(hn[idx] - wn2) <= num_tol(wn2, wna2)).all()
     gk, gs = asci.search(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, 1000)
-    order = np.lexsort((host(gk)[:, 1], host(gk)[:, 0], -np.abs(host(gs))))
-    assert (order == np.arange(len(order))).all()
+    assert_selection_order(host(gk), host(gs))
 
 
 def _pt2_case(asci, oracle_lib, c, E0, **kw):
     d = to_dev(c)
     n, na, nb = c["norb"], c["nalpha"], c["nbeta"]
     e, cnt = asci.pt2(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, **kw)
-    we, wc, sabs = oracle_lib.pt2(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, with_abs=True,
-                                  **{k: v for k, v in kw.items() if k != "pair_buffer_bytes"})
-    assert cnt == wc
-    assert abs(e - we) <= pt2_tol(we, sabs)
-    return e, pt2_tol(we, sabs)
+    okw = {k: v for k, v in kw.items() if k != "pair_buffer_bytes"}
+    _, st = oracle_lib.search_buckets(c["h"], c["eri"], n, na, nb, c["dets"], c["coeffs"], E0, nbuckets=8, **okw)
+    assert cnt == st["candidates"]
+    tol = pt2_tol(st["pt2"], st["pt2_abs"], st["pt2_tol"])
+    assert abs(e - st["pt2"]) <= tol
+    return e, tol
 
 
-def pt2_tol(exact, sabs):
-    """The terms N_a * A_a are bit-identical on both sides; the GPU adds them in
-    segments of at most 4096 candidates, then adds the segment sums (a few per
-    thread, then a 1024-wide tree, then the batches), so its error is at most
-    about (4096 + 2048) u S with S the sum of |terms| (Higham, ch. 4); the
-    oracle's compensated sum is exact to 2u|E|."""
+def pt2_tol(exact, sabs, term_tol):
+    """The GPU adds the terms N_a * A_a in segments of at most 4096 candidates,
+    then adds the segment sums (a few per thread, then a 1024-wide tree, then the
+    batches), so its summation error is at most about (4096 + 2048) u S with S
+    the sum of |terms| (Higham, ch. 4); the oracle's compensated sums are exact
+    to 4u S; and each term may differ from the oracle's by its own tolerance
+    (term_tol: sum of |N_a| tol_a + |A_a| tol(N_a))."""
     u = 2.0 ** -53
-    return 6144 * u * sabs + 2 * u * abs(exact)
+    return 6144 * u * sabs + 4 * u * sabs + term_tol
 
 
 def test_pt2_energy(asci, oracle_lib):
-    """E_PT2 = sum_a N_a^2 / (E0 - H_aa): the candidates and every term are
-    exact, only the order of the additions differs (bound in pt2_tol)."""
+    """E_PT2 = sum_a N_a^2 / (E0 - H_aa): the candidates are exact, every term
+    within its tolerance, only the order of the additions differs."""
     c = syn.workload("8e12o")
     E0 = float.fromhex(_golden("8e12o")["E0"])
     e1, tol = _pt2_case(asci, oracle_lib, c, E0)
@@ -494,7 +540,7 @@ def test_pt2_energy_16e20o(asci):
     e, cnt = asci.pt2(d["h"], d["eri"], 20, 8, 8, d["dets"], d["coeffs"], float.fromhex(g["E0"]))
     assert cnt == g["ncandidates"]
     want = float.fromhex(g["pt2"])
-    assert abs(e - want) <= pt2_tol(want, float.fromhex(g["pt2_abs_terms"]))
+    assert abs(e - want) <= pt2_tol(want, float.fromhex(g["pt2_abs_terms"]), float.fromhex(g["pt2_term_tol"]))
 
 
 def test_profiler_entries_and_kernel_filter(asci, oracle_lib):
