@@ -251,10 +251,8 @@ def mode_serve(args, asci, syn, torch):
             if due > now:
                 time.sleep(due - now)
             sent.append((srv.submit(r), time.perf_counter()))
-        for t, ts in sent:
-            srv.wait(t)
+        res = [srv.wait(t) for t, _ in sent]
         st = srv.stats()
-        res = [srv.poll(t) for t, _ in sent]
         lat = sorted(x.latency_ms for x in res if x is not None)
         points.append({"load": f, "qps": round(qps, 3), "requests": len(batch),
                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),

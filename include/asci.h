@@ -105,6 +105,11 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *                 Both give the same bits (same summation order).
  *   "release_workspace" (value 1): free the context's device workspaces and
  *                 the batch workers (they are allocated again on demand).
+ *   "fault_test": 1 makes every later search on ctx raise a forced fault in
+ *                 its generator, so that the call fails with ASCI_EDEVICE
+ *                 (a test of the error path: the kernels' internal-consistency
+ *                 faults, such as a record slot past its buffer, are reported
+ *                 the same way); 0 (default) turns it off.
  * Read-only diagnostics of the last search on ctx (asci_ctx_get_param):
  *   "last_batches" (class batches), "last_finals" (LDS buckets),
  *   "last_levels" (deepest bucket split), "last_candidates" (candidates).
@@ -371,14 +376,19 @@ int asci_autotune(asci_ctx *ctx, const asci_request *sample, int nsample, int64_
                   int64_t *best_finish_cap);
 
 /*
- * A request loop with continuous batching on one device.  Requests wait in a
- * FIFO queue and are admitted while a worker slot is free and the bytes
- * budgeted for the running requests plus the workspace the workers keep
- * stay within hbm_budget; requests that arrive while others run are admitted
- * as slots and memory free up, and their kernels overlap on the device.
- * A request whose footprint alone exceeds hbm_budget is rejected at
- * submission with ASCI_ENOMEM.  Request buffers must stay valid until the
- * request completes.
+ * A request loop with continuous batching on one device.  Requests wait in
+ * arrival order; a free worker slot takes the oldest request whose bytes,
+ * added to those budgeted for the running requests and the workspace the
+ * workers keep, stay within hbm_budget, so a small request passes a large one
+ * that does not fit yet; once the oldest request has waited longer than the
+ * age bound ("age_ms", default 250 ms) nothing passes it.  Requests that
+ * arrive while others run are admitted as slots and memory free up, and
+ * their kernels overlap on the device.  A request is checked at submission
+ * like asci_search_device's arguments (ASCI_EINVAL, nothing queued); one whose
+ * footprint alone exceeds hbm_budget is rejected with ASCI_ENOMEM.  Request
+ * buffers must stay valid until the request completes.  Each result is handed
+ * over once, by poll or wait, and then forgotten (a later poll or wait of the
+ * ticket returns ASCI_EINVAL).
  */
 typedef struct asci_server asci_server;
 
@@ -389,6 +399,8 @@ typedef struct asci_server_stats {
     double p50_ms, p99_ms, mean_ms;  /* latency: submission to completion */
     double wall_s;              /* first submission to last completion */
     int64_t contributions;      /* pairs generated by completed requests */
+    int64_t bypassed;           /* requests started before an older one that did not fit */
+    int64_t held_results;       /* finished results not yet handed over by poll / wait */
 } asci_server_stats;
 
 int asci_server_create(int device, int64_t hbm_budget, int slots, asci_server **out);
@@ -396,12 +408,16 @@ int asci_server_create(int device, int64_t hbm_budget, int slots, asci_server **
  * footprint * ns_per_byte nanoseconds and keeps its footprint resident. */
 int asci_server_create_fake(int64_t hbm_budget, int slots, double ns_per_byte, asci_server **out);
 int asci_server_submit(asci_server *srv, const asci_request *req, uint64_t *ticket);
+/* Scheduler parameters: "age_ms" (>= 0), the wait after which the oldest
+ * request can no longer be passed.  Unknown names or values: ASCI_EINVAL. */
+int asci_server_set_param(asci_server *srv, const char *name, double value);
 /* Bytes this server budgets for a request: the server caps each request's
  * pair buffer at hbm_budget / (slots * 160) records, so large requests run in
  * more class batches instead of being refused. */
 int64_t asci_server_footprint(asci_server *srv, const asci_request *req);
-/* ASCI_OK and *res when the request has completed, ASCI_EAGAIN (1) while it
- * has not; ASCI_EINVAL for an unknown ticket. */
+/* ASCI_OK and *res when the request has completed (the result is then
+ * forgotten), ASCI_EAGAIN (1) while it has not; ASCI_EINVAL for an unknown
+ * ticket or one whose result was already handed over. */
 int asci_server_poll(asci_server *srv, uint64_t ticket, asci_result *res);
 int asci_server_wait(asci_server *srv, uint64_t ticket, asci_result *res);
 int asci_server_get_stats(asci_server *srv, asci_server_stats *st);

@@ -23,6 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libasci.so")
 
 ASCI_OK, ASCI_EINVAL, ASCI_ENOMEM, ASCI_EDEVICE = 0, -1, -2, -3
+ASCI_EAGAIN = 1
 
 
 class AsciError(RuntimeError):
@@ -67,7 +68,7 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("rejected", C.c_int64), ("max_running", C.c_int64), ("peak_bytes", C.c_int64),
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("wall_s", C.c_double),
-                ("contributions", C.c_int64)]
+                ("contributions", C.c_int64), ("bypassed", C.c_int64), ("held_results", C.c_int64)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -132,6 +133,7 @@ _lib.asci_server_footprint.argtypes = [_vp, C.POINTER(Request)]
 _lib.asci_server_wait.argtypes = [_vp, C.c_uint64, C.POINTER(Result)]
 _lib.asci_server_get_stats.argtypes = [_vp, C.POINTER(ServerStats)]
 _lib.asci_server_destroy.argtypes = [_vp]
+_lib.asci_server_set_param.argtypes = [_vp, C.c_char_p, C.c_double]
 
 EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_default", "asci_ctx_create",
            "asci_ctx_destroy", "asci_ctx_set_param", "asci_ctx_get_param", "asci_ctx_set_profiling",
@@ -142,7 +144,7 @@ EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_def
            "asci_loop_options_default", "asci_loop_step_device", "asci_run_device",
            "asci_request_footprint", "asci_search_batch", "asci_autotune", "asci_server_create",
            "asci_server_create_fake", "asci_server_submit", "asci_server_footprint", "asci_server_poll",
-           "asci_server_wait",
+           "asci_server_wait", "asci_server_set_param",
            "asci_server_get_stats", "asci_server_destroy"]
 
 
@@ -466,14 +468,24 @@ class Server:
         return _lib.asci_server_footprint(self.ptr, C.byref(c))
 
     def poll(self, ticket):
+        """The result once the request has completed (handed over once), else None."""
         r = Result()
         rc = _lib.asci_server_poll(self.ptr, ticket, C.byref(r))
-        return r if rc == ASCI_OK else None
+        if rc == ASCI_OK:
+            self.requests.pop(ticket, None)
+            return r
+        if rc != ASCI_EAGAIN:
+            _check(rc)
+        return None
 
     def wait(self, ticket):
         r = Result()
         _check(_lib.asci_server_wait(self.ptr, ticket, C.byref(r)))
+        self.requests.pop(ticket, None)
         return r
+
+    def set_param(self, name, value):
+        _check(_lib.asci_server_set_param(self.ptr, name.encode(), float(value)))
 
     def stats(self):
         st = ServerStats()

@@ -7,6 +7,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 
 namespace asci {
 
@@ -65,6 +67,8 @@ int fail(const Error &e)
     return e.code;
 }
 
+}  // namespace
+
 void check_common(int norb, int nalpha, int nbeta, int64_t ndets)
 {
     require(norb >= 1 && norb <= 64, ASCI_EINVAL, "norb must be in [1, 64]");
@@ -85,6 +89,8 @@ asci_options resolve(const asci_options *opt)
     require(!(o.eps < 0.0) && o.eps == o.eps, ASCI_EINVAL, "eps must be >= 0");
     return o;
 }
+
+namespace {
 
 struct Staging {
     Arena io;
@@ -142,6 +148,10 @@ int asci_ctx_create(int device, asci_ctx **out)
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -180,6 +190,11 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
             ctx->spin_tables = (int)value;
             return ASCI_OK;
         }
+        if (key == "fault_test") {
+            require(value == 0 || value == 1, ASCI_EINVAL, "fault_test must be 0 or 1");
+            ctx->fault_test = (int)value;
+            return ASCI_OK;
+        }
         if (key == "release_workspace") {
             require(value == 1, ASCI_EINVAL, "release_workspace takes the value 1");
             ASCI_HIP(hipSetDevice(ctx->device));
@@ -195,6 +210,10 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
         throw Error{ASCI_EINVAL, "unknown parameter: " + key};
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -206,6 +225,7 @@ int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value)
         if (key == "finish_cap") *value = ctx->finish_cap;
         else if (key == "batch_slots") *value = ctx->batch_slots;
         else if (key == "spin_tables") *value = ctx->spin_tables;
+        else if (key == "fault_test") *value = ctx->fault_test;
         else if (key == "last_batches") *value = ctx->last_batches;
         else if (key == "last_finals") *value = ctx->last_finals;
         else if (key == "last_levels") *value = ctx->last_levels;
@@ -214,6 +234,10 @@ int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value)
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -227,6 +251,10 @@ int asci_ctx_set_profiling(asci_ctx *ctx, int enable)
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -238,6 +266,10 @@ int asci_ctx_profile_only(asci_ctx *ctx, const char *kernel)
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -259,6 +291,10 @@ int asci_ctx_profile_entry(asci_ctx *ctx, int index, char *name, int name_cap, d
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -283,6 +319,10 @@ int asci_search_device(asci_ctx *ctx, const double *d_h, const double *d_eri, in
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -310,6 +350,10 @@ int asci_candidates_device(asci_ctx *ctx, const double *d_h, const double *d_eri
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -332,6 +376,10 @@ int asci_pt2_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -354,6 +402,10 @@ int asci_hmat_build_device(asci_ctx *ctx, const double *d_h, const double *d_eri
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -366,6 +418,10 @@ int asci_hmat_info(const asci_hmat *H, int64_t *nrows, int64_t *nnz)
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -385,6 +441,10 @@ int asci_hmat_export(const asci_hmat *H, int64_t *d_rowptr, int32_t *d_cols, dou
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -397,6 +457,10 @@ int asci_hmat_matvec_device(const asci_hmat *H, const double *d_x, double *d_y, 
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -423,6 +487,10 @@ int asci_davidson_device(asci_ctx *ctx, const asci_hmat *H, const double *d_gues
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -483,6 +551,10 @@ int asci_loop_step_device(asci_ctx *ctx, const double *d_h, const double *d_eri,
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -511,6 +583,10 @@ int asci_run_device(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -536,6 +612,10 @@ int asci_class_counts_device(asci_ctx *ctx, int norb, int nalpha, int nbeta, con
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -567,6 +647,10 @@ int asci_balance_classes(const int64_t *counts, int64_t nclasses, int32_t npe, i
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -583,6 +667,10 @@ int asci_energy_device(asci_ctx *ctx, const double *d_h, const double *d_eri, in
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 
@@ -637,6 +725,10 @@ int asci_search(const double *h, const double *eri, int norb, int nalpha, int nb
         return ASCI_OK;
     } catch (const Error &e) {
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
     }
 }
 

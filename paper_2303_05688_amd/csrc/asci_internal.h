@@ -122,6 +122,7 @@ struct asci_ctx {
     int finish_cap = 4096;  // tunable: records per LDS bucket (see asci_ctx_set_param)
     int batch_slots = 2;    // tunable: concurrent searches of a batch
     int spin_tables = 1;    // tunable: 1 = spin-string energy tables when they pay, 0 = never
+    int fault_test = 0;     // 1: the next search raises a forced fault (tests of the error path)
     // diagnostics of the last search
     int64_t last_batches = 0, last_finals = 0, last_levels = 0, last_candidates = 0;
     asci::Profiler prof;
@@ -388,6 +389,9 @@ int bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof);  // profiler t
 void bucket_read_v(BucketArgs &b, hipStream_t s);
 // sum over the batch's candidates of N_a * A_a (deterministic order)
 double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs);
+// the fault word of the bucket kernels (see hamiltonian.h): clear / queue a copy to pinned *dst
+void bucket_fault_clear(hipStream_t s);
+void bucket_fault_fetch(unsigned int *dst, hipStream_t s);
 
 // ---------------------------------------------------------------- search (search.hip)
 struct SearchArgs {
@@ -418,6 +422,11 @@ void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *d
 // closed-form pair count and workspace estimate of a request (server.hip)
 int64_t request_pairs(const asci_request &r);
 int64_t request_footprint(const asci_request &r, uint64_t cap_records, int finish_cap = 4096);
+
+// argument checks shared by every entry point (ASCI_EINVAL on failure): sizes,
+// and options resolved against the defaults (NULL = defaults)
+void check_common(int norb, int nalpha, int nbeta, int64_t ndets);
+asci_options resolve(const asci_options *opt);
 
 // throws ASCI_EINVAL unless every determinant has na/nb electrons inside norb orbitals
 void validate_dets(asci_ctx *ctx, const uint64_t *dets, int64_t ndets, int n, int na, int nb, hipStream_t s);

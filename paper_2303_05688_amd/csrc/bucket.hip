@@ -1210,7 +1210,10 @@ __global__ __launch_bounds__(256) void k_collect(const Seg *__restrict__ finals,
         const size_t dst0 = base + off[j];
         for (uint32_t t = threadIdx.x; t < c; t += 256) {
             const size_t s = (size_t)sg.start + t, d = dst0 + t;
-            if (d >= cap) break;
+            if (d >= cap) {
+                raise_fault(kFaultSlot);
+                break;
+            }
             plo[d] = clo[s];
             if (W == 2) phi[d] = chi[s];
             if (pnum) pnum[d] = cnum[s];
@@ -1582,6 +1585,9 @@ double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs)
     ASCI_HIP(hipStreamSynchronize(s));
     return *h;
 }
+
+void bucket_fault_clear(hipStream_t s) { fault_clear(s); }
+void bucket_fault_fetch(unsigned int *dst, hipStream_t s) { fault_fetch(dst, s); }
 
 template void bucket_accumulate<1>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);
 template void bucket_accumulate<2>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);

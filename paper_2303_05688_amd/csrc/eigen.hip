@@ -360,6 +360,7 @@ void hmat_build(asci_ctx *ctx, const double *h, const double *eri, int n, int na
     unsigned long long *csum = ar.take<unsigned long long>(nchunks);
     ASCI_HIP(hipMalloc((void **)&H.rowptr, ((size_t)nd + 1) * sizeof(int64_t)));
     ASCI_HIP(hipMalloc((void **)&H.diag, (size_t)nd * sizeof(double)));
+    fault_clear(s);
     k_hm_table<<<(unsigned)((n * n + kHBlock - 1) / kHBlock), kHBlock, 0, s>>>(eri, h, n, jk);
     ASCI_LAUNCH_CHECK();
 
@@ -409,7 +410,11 @@ void hmat_build(asci_ctx *ctx, const double *h, const double *eri, int n, int na
         k_hbuild<true><<<grid, kHBlock, 0, s>>>(g);
         ASCI_LAUNCH_CHECK();
     }
+    HostStage &hst = ctx->stage;
+    hst.reserve(256);
+    fault_fetch((unsigned int *)((char *)hst.ptr + 64), s);
     ASCI_HIP(hipStreamSynchronize(s));
+    fault_check(*(unsigned int *)((char *)hst.ptr + 64), "the Hamiltonian build");
     H.nrows = ndets;
     H.nnz = nnz;
 }

@@ -103,6 +103,7 @@ double energy_device(asci_ctx *ctx, const double *h, const double *eri, int n, c
     double *row = ar.take<double>(nd);
     double *jk = ar.take<double>((size_t)2 * n * n + n);
     double *out = ar.take<double>(1);
+    fault_clear(s);
     k_jk_table<<<(unsigned)((n * n + kBlock - 1) / kBlock), kBlock, 0, s>>>(eri, h, n, jk);
     ASCI_LAUNCH_CHECK();
     k_energy_rows<<<(nd + kBlock - 1) / kBlock, kBlock, 0, s>>>(dets, coeffs, nd, h, eri, jk, n, ecore, row);
@@ -112,7 +113,9 @@ double energy_device(asci_ctx *ctx, const double *h, const double *eri, int n, c
     HostStage &hs = ctx->stage;
     hs.reserve(256);
     ASCI_HIP(hipMemcpyAsync(hs.ptr, out, sizeof(double), hipMemcpyDeviceToHost, s));
+    fault_fetch((unsigned int *)((char *)hs.ptr + 64), s);
     ASCI_HIP(hipStreamSynchronize(s));
+    fault_check(*(unsigned int *)((char *)hs.ptr + 64), "the energy double loop");
     return *(double *)hs.ptr;
 }
 

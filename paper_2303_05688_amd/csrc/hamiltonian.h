@@ -11,9 +11,57 @@
 
 namespace asci {
 
-// Orbital indices come from validated bit strings; the clamp only keeps a
-// logic error from turning into an out-of-bounds load.
-__device__ __forceinline__ int orb(int p, int n) { return (int)min((unsigned)p, (unsigned)(n - 1)); }
+// Internal-consistency faults of this translation unit's kernels, one bit per
+// kind.  Only a logic error sets them: a record whose slot lies past its
+// buffer (the counts and offsets disagree with what a kernel writes), or an
+// orbital index outside the string width.  The write is dropped (or the index
+// clamped) so that no access leaves its buffer, the bit records it, and the
+// host fails the call with ASCI_EDEVICE after reading the word (fault_fetch).
+// The word is per device and per translation unit; calls running at once on
+// one device may see each other's faults.
+constexpr unsigned kFaultSlot = 1u;     // a write past the end of its buffer was dropped
+constexpr unsigned kFaultOrbital = 2u;  // an orbital index >= norb was clamped
+constexpr unsigned kFaultForced = 4u;   // raised on request (tests of the error path)
+static __device__ unsigned int g_fault;
+
+__device__ __forceinline__ void raise_fault(unsigned f) { atomicOr(&g_fault, f); }
+
+// Orbital indices come from validated bit strings; an index out of range is a
+// logic error, clamped so that it cannot turn into an out-of-bounds load.
+__device__ __forceinline__ int orb(int p, int n)
+{
+    if ((unsigned)p >= (unsigned)n) {
+        raise_fault(kFaultOrbital);
+        return n - 1;
+    }
+    return p;
+}
+
+// Host side: clear the word (queued on s), and queue its copy to pinned host
+// memory *dst (valid once s has been synchronised).
+static inline void fault_clear(hipStream_t s)
+{
+    void *p = nullptr;
+    ASCI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(g_fault)));
+    ASCI_HIP(hipMemsetAsync(p, 0, sizeof(unsigned int), s));
+}
+
+static inline void fault_fetch(unsigned int *dst, hipStream_t s)
+{
+    void *p = nullptr;
+    ASCI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(g_fault)));
+    ASCI_HIP(hipMemcpyAsync(dst, p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+}
+
+// after the stream has been synchronised: fail on any recorded fault
+static inline void fault_check(unsigned int word, const char *where)
+{
+    if (word)
+        throw Error{ASCI_EDEVICE, std::string("internal consistency fault in ") + where + ": " +
+                                      ((word & kFaultSlot) ? "a record slot past its buffer; " : "") +
+                                      ((word & kFaultOrbital) ? "an orbital index out of range; " : "") +
+                                      ((word & kFaultForced) ? "forced by the fault_test parameter" : "")};
+}
 
 // n <= 64, so the flat index (below 64^4) fits 32-bit arithmetic
 __device__ __forceinline__ double eri4(const double *__restrict__ eri, int n, int p, int q, int r, int s)

@@ -172,6 +172,7 @@ struct GenArgs {
     uint64_t *klo, *khi;
     double *vals;
     size_t cap;
+    int force_fault;  // raise kFaultForced once (tests of the error path)
 };
 
 template <int W>
@@ -180,6 +181,8 @@ __device__ __forceinline__ void emit(const GenArgs &g, size_t dst, uint64_t a2, 
     if (dst < g.cap) {
         put_key<W>(g.klo, g.khi, dst, a2, b2, g.n);
         g.vals[dst] = v;
+    } else {
+        raise_fault(kFaultSlot);
     }
 }
 
@@ -205,6 +208,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // matrix) meet in the same L2
     const uint32_t per = (g.nq + 7u) / 8u;
     const uint32_t i = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    if (g.force_fault && blockIdx.x == 0 && threadIdx.x == 0) raise_fault(kFaultForced);
     if (i >= g.nq) return;
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -520,6 +524,8 @@ __global__ __launch_bounds__(kBlock) void k_keep_scatter(const uint64_t *__restr
                 olo[d] = ilo[j];
                 if (W == 2) ohi[d] = ihi[j];
                 oscore[d] = iscore[j];
+            } else {
+                raise_fault(kFaultSlot);
             }
         }
         at += (uint32_t)__popcll(keptm[i]);
@@ -679,6 +685,7 @@ inline uint64_t choose_u64(uint64_t x, int k)
 // (all na orbitals when na < L)
 std::vector<uint64_t> make_classes(int n, int na, int L)
 {
+    require(L >= 0 && L <= 64 && na >= 0 && na <= n, ASCI_EINVAL, "constraint level out of range");
     std::vector<uint64_t> out;
     L = std::min(L, na);
     if (L == 0) {
@@ -1127,6 +1134,16 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
 
     HostStage &hs = ctx->stage;
     hs.reserve(256);
+    fault_clear(s);
+    bucket_fault_clear(s);
+    // the end of every path: both fault words read with the last sync
+    unsigned int *h_fault = (unsigned int *)((char *)hs.ptr + 224);
+    auto finish = [&]() {
+        fault_fetch(h_fault, s);
+        bucket_fault_fetch(h_fault + 1, s);
+        ASCI_HIP(hipStreamSynchronize(s));
+        fault_check(h_fault[0] | h_fault[1], "the search");
+    };
     int pcur = 0;
     size_t pool_n = 0;
     ctx->last_batches = (int64_t)batches.size();
@@ -1213,6 +1230,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.khi = k_hi[0];
             ga.vals = v[0];
             ga.cap = Pb;
+            ga.force_fault = ctx->fault_test;
             const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 +
                                2 * ((size_t)ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
             k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
@@ -1298,26 +1316,29 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     ar.reset();
     (void)ar.take<char>(loop_mark);
     if (out.pt2) {
-        ASCI_HIP(hipStreamSynchronize(s));
+        finish();
         return;
     }
     if (!topk) {
         out.count = (int64_t)pool_n;
-        if (pool_n > (size_t)out.capacity) return;  // the caller reports ENOMEM
+        if (pool_n > (size_t)out.capacity) {  // the caller reports ENOMEM
+            finish();
+            return;
+        }
         if (pool_n) {
             k_unpack<W><<<grid_for(pool_n), kBlock, 0, s>>>(p_lo[pcur], p_hi[pcur], pool_n, n, out.out_dets);
             ASCI_LAUNCH_CHECK();
             ASCI_HIP(hipMemcpyAsync(out.out_num, p_num, pool_n * sizeof(double), hipMemcpyDeviceToDevice, s));
             ASCI_HIP(hipMemcpyAsync(out.out_scores, p_score[pcur], pool_n * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
-        ASCI_HIP(hipStreamSynchronize(s));
+        finish();
         return;
     }
     // step 10: the k largest |A| (ties: smaller key), then |A| descending
     const size_t kk = (size_t)std::min<uint64_t>((uint64_t)out.k, pool_n);
     out.count = (int64_t)kk;
     if (kk == 0) {
-        ASCI_HIP(hipStreamSynchronize(s));
+        finish();
         return;
     }
     if (kk < pool_n) prune(kk);
@@ -1334,7 +1355,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
                                                           out.out_dets, out.out_scores);
         ASCI_LAUNCH_CHECK();
     }
-    ASCI_HIP(hipStreamSynchronize(s));
+    finish();
 }
 
 void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s)

@@ -2,11 +2,14 @@
 //
 // A worker pool: each worker owns a context (workspace arenas) and a HIP
 // stream, so searches on different workers overlap on the device.  Requests
-// are admitted from a FIFO queue while a worker is free and the bytes budgeted
-// for running requests, plus the workspace idle workers keep, fit the HBM
-// budget; idle workers give their workspace back when a request needs room.
-// The batch entry point runs a transient pool over a fixed request list,
-// largest estimated cost first.
+// wait in arrival order; a free worker takes the oldest one whose bytes,
+// added to those budgeted for running requests and the workspace idle
+// workers keep, fit the HBM budget, so small requests pass a large one that
+// does not fit yet.  Once the oldest request has waited longer than the age
+// bound, nothing passes it: workers then start it as soon as it fits.  Idle
+// workers give their workspace back when a request needs room.  A result is
+// handed over once (poll or wait) and then forgotten.  The batch entry point
+// runs a pool over a fixed request list, largest estimated cost first.
 #include "asci_internal.h"
 
 #include <algorithm>
@@ -16,8 +19,11 @@
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 
 namespace asci {
 
@@ -62,6 +68,18 @@ int64_t request_footprint(const asci_request &r, uint64_t cap_records, int finis
                           pool * ((8 * W + 8) * 2 + 12) + std::min(k, pool) * 24 + (1 << 20);
     const uint64_t tables = spin_table_plan(r.norb, r.nalpha, r.nbeta, P, true).bytes;
     return (int64_t)(setup + main + tables);
+}
+
+// Argument checks of a request before it is queued (the checks of the search
+// entry points): sizes, options, and for a device request its buffers.
+static void check_request(const asci_request &r, bool device)
+{
+    check_common(r.norb, r.nalpha, r.nbeta, r.ndets);
+    require(r.k >= 1, ASCI_EINVAL, "k must be >= 1");
+    (void)resolve(&r.opt);
+    if (device)
+        require(r.h && r.eri && r.dets && r.coeffs && r.out_dets && r.out_scores, ASCI_EINVAL,
+                "null buffer in a request");
 }
 
 // ---------------------------------------------------------------- the pool
@@ -116,11 +134,14 @@ class Pool {
         ASCI_HIP(hipEventDestroy(ready));
     }
 
-    // forget the results of finished tickets (a batch's bookkeeping)
+    // forget finished tickets whose results were not collected
     void forget(const std::vector<uint64_t> &tickets)
     {
         std::unique_lock<std::mutex> lk(mu_);
-        for (uint64_t t : tickets) done_.erase(t);
+        for (uint64_t t : tickets) {
+            done_.erase(t);
+            live_.erase(t);
+        }
     }
 
     ~Pool()
@@ -149,6 +170,7 @@ class Pool {
 
     int submit(const asci_request &r, uint64_t *ticket)
     {
+        check_request(r, !fake_);
         Job j;
         j.req = shaped(r);
         j.pairs = request_pairs(r);
@@ -156,6 +178,7 @@ class Pool {
         std::unique_lock<std::mutex> lk(mu_);
         j.ticket = next_ticket_++;
         *ticket = j.ticket;
+        live_.insert(j.ticket);
         ++submitted_;
         if (first_submit_ < 0) first_submit_ = now_ms();
         if (j.footprint > budget_) {
@@ -172,19 +195,35 @@ class Pool {
         return ASCI_OK;
     }
 
+    // a finished request's result is handed over once, then forgotten
     int poll(uint64_t t, asci_result *res, bool block)
     {
         std::unique_lock<std::mutex> lk(mu_);
-        if (t == 0 || t >= next_ticket_) return ASCI_EINVAL;
+        if (live_.find(t) == live_.end()) return ASCI_EINVAL;  // unknown, or already handed over
         for (;;) {
             auto it = done_.find(t);
             if (it != done_.end()) {
                 if (res) *res = it->second;
+                done_.erase(it);
+                live_.erase(t);
                 return ASCI_OK;
             }
             if (!block) return ASCI_EAGAIN;
             cv_done_.wait(lk);
         }
+    }
+
+    void set_age_bound(double ms)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        age_ms_ = ms;
+        cv_work_.notify_all();
+    }
+
+    size_t pending() const
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        return done_.size() + live_.size();
     }
 
     void drain()
@@ -235,6 +274,8 @@ class Pool {
         st->mean_ms = l.empty() ? 0.0 : sum / (double)l.size();
         st->wall_s = (first_submit_ >= 0 && last_done_ >= 0) ? (last_done_ - first_submit_) * 1e-3 : 0.0;
         st->contributions = contributions_;
+        st->bypassed = bypassed_;
+        st->held_results = (int64_t)done_.size();
     }
 
   private:
@@ -259,11 +300,10 @@ class Pool {
         w.resident = 0;
     }
 
-    bool admit_locked(int wi)
+    // whether a job of footprint fp fits next to the running ones if worker
+    // wi takes it (idle workspaces are given back when that makes room)
+    bool fits_locked(WorkerState &me, int64_t fp)
     {
-        WorkerState &me = *ws_[(size_t)wi];
-        if (queue_.empty()) return false;
-        const int64_t fp = queue_.front().footprint;
         auto fits = [&] { return committed_locked() - me.resident + need_for(me, fp) <= budget_; };
         if (!fits() && me.resident > fp) release_locked(me);
         if (!fits()) {
@@ -271,6 +311,24 @@ class Pool {
                 if (!w->busy && w.get() != &me && w->resident > 0) release_locked(*w);
         }
         return fits();
+    }
+
+    // the queue position worker wi starts next, or npos: the oldest job that
+    // fits; only the oldest once it has waited longer than the age bound
+    static constexpr size_t npos = ~size_t(0);
+    static constexpr size_t kScan = 64;  // jobs looked at past the head
+    size_t choose_locked(int wi)
+    {
+        if (queue_.empty()) return npos;
+        WorkerState &me = *ws_[(size_t)wi];
+        const bool head_old = now_ms() - queue_.front().t_submit > age_ms_;
+        const size_t lim = head_old ? 1 : std::min(queue_.size(), kScan);
+        for (size_t q = 0; q < lim; ++q)
+            if (fits_locked(me, queue_[q].footprint)) {
+                if (q > 0) ++bypassed_;
+                return q;
+            }
+        return npos;
     }
 
     void loop(int wi)
@@ -281,11 +339,14 @@ class Pool {
             Job j;
             {
                 std::unique_lock<std::mutex> lk(mu_);
-                cv_work_.wait(lk, [&] { return stop_ || admit_locked(wi); });
+                size_t pick = npos;
+                // re-checked at least every few ms: the head's age changes the choice
+                while (!stop_ && (pick = choose_locked(wi)) == npos)
+                    cv_work_.wait_for(lk, std::chrono::milliseconds(5));
                 if (stop_ && queue_.empty()) return;
-                if (stop_ && !admit_locked(wi)) return;
-                j = queue_.front();
-                queue_.pop_front();
+                if (stop_ && (pick = choose_locked(wi)) == npos) return;
+                j = queue_[pick];
+                queue_.erase(queue_.begin() + (std::ptrdiff_t)pick);
                 me.busy = true;
                 me.reserved = need_for(me, j.footprint);
                 ++running_;
@@ -314,6 +375,10 @@ class Pool {
                     res.count = out.count;
                 } catch (const Error &e) {
                     res.status = e.code;
+                } catch (const std::bad_alloc &) {
+                    res.status = ASCI_ENOMEM;
+                } catch (const std::exception &) {
+                    res.status = ASCI_EDEVICE;
                 }
             }
             const double t_end = now_ms();
@@ -350,10 +415,13 @@ class Pool {
     uint64_t cap_records_ = 1 << 26;
     int finish_cap_ = 4096;
     std::vector<std::unique_ptr<WorkerState>> ws_;
-    std::mutex mu_;
+    mutable std::mutex mu_;
     std::condition_variable cv_work_, cv_done_;
     std::deque<Job> queue_;
-    std::unordered_map<uint64_t, asci_result> done_;
+    std::unordered_map<uint64_t, asci_result> done_;  // finished, not yet handed over
+    std::unordered_set<uint64_t> live_;               // submitted, not yet handed over
+    double age_ms_ = 250.0;
+    int64_t bypassed_ = 0;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;
     int64_t running_ = 0, max_running_ = 0, peak_bytes_ = 0;
@@ -371,8 +439,6 @@ struct asci_server {
 using namespace asci;
 
 namespace {
-
-thread_local std::string g_srv_error;
 
 int srv_fail(const Error &e) { return e.code; }
 
@@ -407,6 +473,10 @@ int asci_server_create(int device, int64_t hbm_budget, int slots, asci_server **
         return ASCI_OK;
     } catch (const Error &e) {
         return srv_fail(e);
+    } catch (const std::bad_alloc &) {
+        return ASCI_ENOMEM;
+    } catch (const std::exception &) {
+        return ASCI_EDEVICE;
     }
 }
 
@@ -421,14 +491,36 @@ int asci_server_create_fake(int64_t hbm_budget, int slots, double ns_per_byte, a
         return ASCI_OK;
     } catch (const Error &e) {
         return srv_fail(e);
+    } catch (const std::bad_alloc &) {
+        return ASCI_ENOMEM;
+    } catch (const std::exception &) {
+        return ASCI_EDEVICE;
     }
 }
 
 int asci_server_submit(asci_server *srv, const asci_request *req, uint64_t *ticket)
 {
     if (!srv || !req || !ticket) return ASCI_EINVAL;
-    if (req->k < 1 || req->ndets < 1 || req->norb < 1 || req->norb > 64) return ASCI_EINVAL;
-    return srv->pool->submit(*req, ticket);
+    try {
+        return srv->pool->submit(*req, ticket);
+    } catch (const Error &e) {
+        return srv_fail(e);
+    } catch (const std::bad_alloc &) {
+        return ASCI_ENOMEM;
+    } catch (const std::exception &) {
+        return ASCI_EDEVICE;
+    }
+}
+
+int asci_server_set_param(asci_server *srv, const char *name, double value)
+{
+    if (!srv || !name) return ASCI_EINVAL;
+    if (std::string(name) == "age_ms") {
+        if (!(value >= 0.0)) return ASCI_EINVAL;
+        srv->pool->set_age_bound(value);
+        return ASCI_OK;
+    }
+    return ASCI_EINVAL;
 }
 
 int64_t asci_server_footprint(asci_server *srv, const asci_request *req)
@@ -498,10 +590,19 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
         std::vector<uint64_t> tickets((size_t)nreq, 0);
         int rc = ASCI_OK;
         for (int i : order) {
-            const int r = pool.submit(reqs[i], &tickets[(size_t)i]);
+            int r;
+            try {
+                r = pool.submit(reqs[i], &tickets[(size_t)i]);
+            } catch (const Error &e) {  // rejected by the argument checks: never queued
+                r = e.code;
+                tickets[(size_t)i] = 0;
+                res[i] = asci_result{};
+                res[i].status = r;
+            }
             if (r != ASCI_OK && rc == ASCI_OK) rc = r;
         }
         for (int i = 0; i < nreq; ++i) {
+            if (tickets[(size_t)i] == 0) continue;
             pool.poll(tickets[(size_t)i], &res[i], true);
             if (res[i].status != ASCI_OK && rc == ASCI_OK) rc = res[i].status;
         }
@@ -509,6 +610,10 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
         return rc;
     } catch (const Error &e) {
         return srv_fail(e);
+    } catch (const std::bad_alloc &) {
+        return ASCI_ENOMEM;
+    } catch (const std::exception &) {
+        return ASCI_EDEVICE;
     }
 }
 
@@ -545,6 +650,10 @@ int asci_autotune(asci_ctx *ctx, const asci_request *sample, int nsample, int64_
         return best < 1e300 ? ASCI_OK : ASCI_EDEVICE;
     } catch (const Error &e) {
         return srv_fail(e);
+    } catch (const std::bad_alloc &) {
+        return ASCI_ENOMEM;
+    } catch (const std::exception &) {
+        return ASCI_EDEVICE;
     }
 }
 

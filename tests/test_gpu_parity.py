@@ -570,3 +570,45 @@ def test_profiler_entries_and_kernel_filter(asci, oracle_lib):
         ctx.set_profiling(False)
     for a, b, e in zip(base, got, got2):
         assert a.tobytes() == b.tobytes() == e.tobytes()
+
+
+def test_forced_fault_fails_the_call_and_clears(asci, oracle_lib):
+    """The kernels' internal-consistency fault word (a dropped write past a
+    buffer, a clamped orbital index) fails the call with ASCI_EDEVICE; forced
+    from the host, the search raises it, writes no result, and the next
+    search on the context is correct again."""
+    c = _case(8, 4, 3, 40, seed=5)
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    d = to_dev(c)
+    ctx = asci.Context.get(0)
+    try:
+        ctx.set_param("fault_test", 1)
+        with pytest.raises(asci.AsciError) as e:
+            asci.search(d["h"], d["eri"], 8, 4, 3, d["dets"], d["coeffs"], E0, 100, ctx=ctx)
+        assert e.value.code == asci.ASCI_EDEVICE
+    finally:
+        ctx.set_param("fault_test", 0)
+    gk, gs = asci.search(d["h"], d["eri"], 8, 4, 3, d["dets"], d["coeffs"], E0, 100, ctx=ctx)
+    want = oracle_lib.search_all(c["h"], c["eri"], 8, 4, 3, c["dets"], c["coeffs"], E0)
+    assert_topk(host(gk), host(gs), want, 100)
+
+
+def test_invalid_requests_rejected_by_batch_and_server(asci, oracle_lib):
+    """A request with an invalid option (a negative constraint level) is
+    refused before any GPU work: by the server at submission, by the batch
+    per request while the valid requests of the batch still complete."""
+    c = _case(10, 4, 4, 50, seed=6)
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    d = to_dev(c)
+    good = asci.SearchRequest(d["h"], d["eri"], 10, 4, 4, d["dets"], d["coeffs"], E0, 50)
+    bad = asci.SearchRequest(d["h"], d["eri"], 10, 4, 4, d["dets"], d["coeffs"], E0, 50, constraint_level=-1)
+    srv = asci.Server(device=0, slots=1)
+    try:
+        with pytest.raises(asci.AsciError) as e:
+            srv.submit(bad)
+        assert e.value.code == asci.ASCI_EINVAL
+        assert srv.wait(srv.submit(good)).status == 0
+    finally:
+        srv.close()
+    with pytest.raises(asci.AsciError):
+        asci.search_batch([good, bad])

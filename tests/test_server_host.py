@@ -66,7 +66,8 @@ def test_poll_reports_pending_then_done():
     t = srv.submit(r)
     assert srv.poll(t) is None  # still running (about 50 ms)
     assert srv.wait(t).status == 0
-    assert srv.poll(t) is not None
+    with pytest.raises(asci.AsciError):  # handed over once, then forgotten
+        srv.poll(t)
     srv.close()
 
 
@@ -102,3 +103,72 @@ def test_class_skew_statistics():
     assert st["largest_share"] == 0.7
     assert st["imbalance"][1] == 1.0
     assert st["imbalance"][4] == 70 / 25
+
+
+def test_invalid_request_rejected_at_submission():
+    """A request whose options fail the search's argument checks (here a
+    negative constraint level) is refused before anything is queued."""
+    ok = asci.fake_request(20, 8, 8, 1000, 10_000)
+    bad = asci.fake_request(20, 8, 8, 1000, 10_000)
+    bad.opt.constraint_level = -1
+    bad_n = asci.fake_request(70, 8, 8, 1000, 10_000)
+    bad_k = asci.fake_request(20, 8, 8, 1000, 0)
+    srv = asci.Server(hbm_budget=int(8e9), slots=2, fake_ns_per_byte=1e-3)
+    for r in (bad, bad_n, bad_k):
+        with pytest.raises(asci.AsciError) as e:
+            srv.submit(r)
+        assert e.value.code == asci.ASCI_EINVAL
+    t = srv.submit(ok)
+    assert srv.wait(t).status == 0
+    st = srv.stats()
+    srv.close()
+    assert st["submitted"] == 1 and st["completed"] == 1
+
+
+def test_results_are_handed_over_once():
+    reqs = _reqs([(20, 8, 8, 1000, 10_000)] * 6)
+    srv = asci.Server(hbm_budget=int(8e9), slots=2, fake_ns_per_byte=1e-3)
+    tickets = [srv.submit(r) for r in reqs]
+    for t in tickets:
+        assert srv.wait(t).status == 0
+    assert srv.stats()["held_results"] == 0
+    with pytest.raises(asci.AsciError):
+        srv.wait(tickets[0])
+    with pytest.raises(asci.AsciError):
+        srv.poll(tickets[1])
+    srv.close()
+
+
+def test_small_requests_pass_a_large_one_that_does_not_fit():
+    """Budget for one large request: while it waits for room, small requests
+    behind it start; with an age bound of 0 nothing passes the oldest."""
+    big = (30, 12, 12, 100_000, 1_000_000)
+    small = (20, 8, 8, 1000, 10_000)
+    specs = [big, big] + [small] * 8
+
+    def run(age_ms):
+        reqs = _reqs(specs)
+        srv = asci.Server(hbm_budget=int(3.2e9), slots=4, fake_ns_per_byte=5e-3)
+        srv.set_param("age_ms", age_ms)
+        fp_big, fp_small = srv.footprint(reqs[0]), srv.footprint(reqs[2])
+        assert fp_big + fp_small <= 3.2e9 < 2 * fp_big
+        tickets = [srv.submit(r) for r in reqs]
+        res = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        srv.close()
+        assert all(r.status == 0 for r in res)
+        assert st["peak_bytes"] <= 3.2e9
+        return res, st
+
+    res, st = run(1e6)
+    assert st["bypassed"] >= 1
+    # small requests run while the second large one waits for room
+    assert min(r.latency_ms for r in res[2:]) < res[0].latency_ms
+    res0, st0 = run(0.0)
+    assert st0["bypassed"] == 0
+    # without passing, every small request waits until the first large one is done
+    assert min(r.latency_ms for r in res0[2:]) > res0[0].latency_ms
+    mean = lambda rs: sum(r.latency_ms for r in rs) / len(rs)  # noqa: E731
+    assert mean(res[2:]) < mean(res0[2:])
+    with pytest.raises(asci.AsciError):
+        asci.Server(hbm_budget=int(1e9), slots=1, fake_ns_per_byte=1e-3).set_param("age_ms", -1.0)
