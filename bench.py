@@ -2,12 +2,14 @@
 
 One step = one whole search (every step of the path: inputs resident in HBM,
 psi keys, class counts, generation, sort, accumulation, exclusion, diagonal +
-score, top-k) on the (16e,20o) workload: 20 orbitals, 8 alpha + 8 beta
-electrons, 10^4 core determinants, k = 10^5.  The metric is H_ai C_i
-contributions per second: the closed-form number of (core, target) pairs
-divided by the search wall time.
+score, top-k) on the Cr2-shaped (24e,30o) workload: 30 orbitals, 12 alpha +
+12 beta electrons, 10^5 core determinants, k = 10^6 (6.7e9 pairs, the
+largest single-GPU configuration).  The metric is H_ai C_i contributions per
+second: the closed-form number of (core, target) pairs divided by the search
+wall time.  The (16e,20o) workload (10^4 cores, k = 10^5) is timed as well
+and reported under "extra_workloads".
 
-    python bench.py [--steps K] [--warmup W] [--workload 16e20o] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload 24e30o] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -23,13 +25,14 @@ METRIC = "H_ai·C_i contributions/sec + search wall-time; batched/served vs sing
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
-    the kernel's sources changed since the counters were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain
+    copy), or None when the kernel's sources changed since the counters were
+    taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "%s_16e20o_pmc.md" % kernel)
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -52,25 +55,56 @@ def sd_per_det(n, na, nb):
     return na * va + nb * vb + comb(na, 2) * comb(va, 2) + comb(nb, 2) * comb(vb, 2) + na * va * nb * vb
 
 
-def cpu_baseline(case, E0, budget_s=12.0):
+def cpu_info():
+    """(CPU model, logical CPUs, CPUs this process may use)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(case, E0, budget_s=8.0):
     """The oracle, as it stands, on a bounded sample: the first m input
-    determinants of the same workload as the whole wave function (a smaller
-    search of the same shape).  Returns contributions/s on one host thread."""
+    determinants of the same workload as the wave function (a smaller search
+    of the same shape), through the oracle's bucketed search (generate, sort,
+    accumulate, exclude, score, each bucket's top k, then the top k of their
+    union), once on one thread and once on every host thread this process may
+    use (at most 16).  Returns contributions/s with the thread counts and the
+    CPU model."""
     import oracle
 
     oracle.build(force=False)
-    n, na, nb = case["norb"], case["nalpha"], case["nbeta"]
+    n, na, nb, k = case["norb"], case["nalpha"], case["nbeta"], case["k"]
     per = sd_per_det(n, na, nb)
-    m = max(1, min(len(case["coeffs"]), int(1.0e6 * budget_s / 1.3 / per)))
-    dets, C = case["dets"][:m], case["coeffs"][:m]
-    t0 = time.perf_counter()
-    allc = oracle.search_all(case["h"], case["eri"], n, na, nb, dets, C, E0)
-    oracle.topk_index(allc["keys"], allc["score"], case["k"])
-    dt = time.perf_counter() - t0
-    return {"value": m * per / dt, "unit": "contributions/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d input determinants of %s as the wave function; full oracle search "
-                      "(generate, sort, accumulate, exclude, score, top-%d); %.1f s" % (
-                          m, len(case["coeffs"]), case["name"], case["k"], dt)}
+    model, ncpu, avail = cpu_info()
+    threads = max(1, min(avail, 16))
+
+    def run(m, th):
+        dets, C = case["dets"][:m], case["coeffs"][:m]
+        t0 = time.perf_counter()
+        r, st = oracle.search_buckets(case["h"], case["eri"], n, na, nb, dets, C, E0, nbuckets=4 * th,
+                                      threads=th, keep_top=k)
+        oracle.topk_index(r["keys"], r["score"], k)
+        return m * per / (time.perf_counter() - t0), time.perf_counter() - t0
+
+    # size the one-thread sample from a short probe, then the all-thread one from it
+    m0 = max(1, min(len(case["coeffs"]), int(2.0e5 / per) + 1))
+    r0, _ = run(m0, 1)
+    m1 = max(1, min(len(case["coeffs"]), int(r0 * budget_s / per)))
+    r1, t1 = run(m1, 1)
+    mt = max(1, min(len(case["coeffs"]), int(r1 * threads * budget_s / per)))
+    rt, tt = run(mt, threads)
+    return {"value": rt, "unit": "contributions/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d (all threads) and %d (one thread) of %d input determinants of %s as the wave "
+                      "function; oracle bucketed search (generate, sort, accumulate, exclude, score, top-%d); "
+                      "%.1f s and %.1f s" % (mt, m1, len(case["coeffs"]), case["name"], k, tt, t1),
+            "single_thread_value": r1, "cpu_model": model, "nproc": ncpu, "threads_available": avail}
 
 
 def _dev_case(case, torch, dev):
@@ -304,7 +338,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="16e20o")
+    ap.add_argument("--workload", default="24e30o")
+    ap.add_argument("--extra", default="16e20o", help="search mode: further workloads timed (comma list, '' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--finish-cap", type=int, default=0, help="records per LDS bucket (tuning parameter)")
     ap.add_argument("--mode", default="search", choices=["search", "levels", "loop", "batch", "serve", "copy", "host"],
@@ -333,7 +368,31 @@ def main():
         print(json.dumps(fn(args, asci, syn, torch)), flush=True)
         return
 
-    case = syn.workload(args.workload)
+    ctx = asci.Context.get(0)
+    if args.finish_cap:
+        ctx.set_param("finish_cap", args.finish_cap)
+    line = measure_search(args, asci, syn, torch, np, ctx, args.workload, args.steps, args.warmup, full=True)
+    extras = [w for w in args.extra.split(",") if w and w != args.workload]
+    if extras:
+        line["extra_workloads"] = {}
+        for w in extras:
+            print("extra workload %s ..." % w, file=sys.stderr, flush=True)
+            line["extra_workloads"][w] = measure_search(args, asci, syn, torch, np, ctx, w, max(args.steps, 5),
+                                                        max(args.warmup, 2), full=False)
+    if not args.no_cpu_baseline:
+        print("cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(line.pop("_case"), line.pop("_E0"))
+    else:
+        line.pop("_case")
+        line.pop("_E0")
+    print(json.dumps(line), flush=True)
+
+
+def measure_search(args, asci, syn, torch, np, ctx, workload, steps, warmup, full):
+    """Time `steps` whole searches of `workload` after `warmup` untimed ones.
+    full: the default line (roofline of the dominant kernel, per-phase
+    breakdown); otherwise the rate and wall time only."""
+    case = syn.workload(workload)
     n, na, nb = case["norb"], case["nalpha"], case["nbeta"]
     nd, k = len(case["coeffs"]), case["k"]
     dev = torch.device("cuda", 0)
@@ -341,22 +400,29 @@ def main():
     eri = torch.from_numpy(case["eri"]).to(dev)
     dets = torch.from_numpy(np.ascontiguousarray(case["dets"]).view(np.int64)).to(dev).view(torch.uint64)
     coeffs = torch.from_numpy(case["coeffs"]).to(dev)
-    ctx = asci.Context.get(0)
-    if args.finish_cap:
-        ctx.set_param("finish_cap", args.finish_cap)
     E0 = asci.energy(h, eri, n, na, nb, dets, coeffs, ctx=ctx)
     P = nd * sd_per_det(n, na, nb)
 
     def step():
         return asci.search(h, eri, n, na, nb, dets, coeffs, E0, k, ctx=ctx)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    print("warmup done", file=sys.stderr, flush=True)
+    print("%s: warmup done" % workload, file=sys.stderr, flush=True)
+    desc = "%s: (%de,%do) synthetic integrals, %d core determinants, keep %d" % (workload, na + nb, n, nd, k)
+    if not full:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out_k, out_s = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        return {"workload": desc, "value": P / (ms * 1e-3), "unit": "contributions/s", "ms_per_step": round(ms, 4),
+                "steps": steps, "contributions": P, "selected": int(out_k.shape[0])}
     # every kernel timed (outside the timed region): the per-phase breakdown and
     # the dominant kernel, the one with the largest total time
-    nph = max(1, min(args.steps, 3))
+    nph = max(1, min(steps, 3))
     ctx.set_profiling(True)
     for _ in range(nph):
         step()
@@ -368,41 +434,39 @@ def main():
     ctx.set_profiling(True, only=name)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         out_k, out_s = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile()
     ctx.set_profiling(False)
-    ms = (t1 - t0) * 1000.0 / args.steps
-    print("timed steps done", file=sys.stderr, flush=True)
+    ms = (t1 - t0) * 1000.0 / steps
+    print("%s: timed steps done" % workload, file=sys.stderr, flush=True)
 
     kms, launches, kbytes = prof[name]
     avg_ms = kms / max(launches, 1)
     achieved = (kbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(name) if args.workload == "16e20o" else None
     roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches / args.steps}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
+                "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches / steps,
+                "algorithmic_bytes_per_launch": kbytes / max(launches, 1)}
     phases = {kname: {"ms_per_step": round(v[0] / nph, 4), "launches_per_step": v[1] / nph,
                       "GB/s": round((v[2] / max(v[0], 1e-9)) / 1e6, 1)} for kname, v in sorted(allprof.items())}
-
-    line = {
+    return {
         "metric": METRIC,
         "value": P / (ms * 1e-3),
         "unit": "contributions/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: (%de,%do) synthetic integrals, %d core determinants, keep %d" % (
-            args.workload, na + nb, n, nd, k), "norb": n, "nalpha": na, "nbeta": nb, "ndets": nd, "k": k,
-            "contributions": P, "seed": case["seed"], "finish_cap": ctx.get_param("finish_cap")},
+        "config": {"workload": desc, "norb": n, "nalpha": na, "nbeta": nb, "ndets": nd, "k": k,
+                   "contributions": P, "seed": case["seed"], "finish_cap": ctx.get_param("finish_cap")},
         "search_wall_ms": round(ms, 4),
         "diagnostics": {kk: ctx.get_param(kk) for kk in ("last_batches", "last_finals", "last_levels",
                                                           "last_candidates")},
@@ -410,11 +474,9 @@ def main():
         "roofline": roofline,
         "phases": phases,
         "phases_steps": nph,
+        "_case": case,
+        "_E0": E0,
     }
-    if not args.no_cpu_baseline:
-        print("cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(case, E0)
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -15,6 +15,7 @@ namespace asci {
 void Arena::reserve(size_t bytes)
 {
     if (bytes <= cap_) return;
+    if (fixed_) throw Error{ASCI_ENOMEM, "request larger than the fixed scratch region"};
     const size_t grown = cap_ + cap_ / 4;  // grow by a quarter at least: fewer reallocations
     release();
     auto round = [](size_t b) { return (b + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1); };
@@ -37,14 +38,16 @@ void Arena::reserve(size_t bytes)
 
 void Arena::release()
 {
-    if (base_) (void)hipFree(base_);
+    if (base_ && !fixed_) (void)hipFree(base_);
     base_ = nullptr;
     cap_ = used_ = 0;
+    fixed_ = false;
 }
 
 void HostStage::reserve(size_t b)
 {
     if (b <= bytes) return;
+    if (fixed) throw Error{ASCI_ENOMEM, "host staging larger than its fixed region"};
     if (ptr) (void)hipHostFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -54,7 +57,7 @@ void HostStage::reserve(size_t b)
 
 HostStage::~HostStage()
 {
-    if (ptr) (void)hipHostFree(ptr);
+    if (ptr && !fixed) (void)hipHostFree(ptr);
 }
 
 namespace {
@@ -68,6 +71,8 @@ int fail(const Error &e)
 }
 
 }  // namespace
+
+int report_error(const Error &e) { return fail(e); }
 
 void check_common(int norb, int nalpha, int nbeta, int64_t ndets)
 {

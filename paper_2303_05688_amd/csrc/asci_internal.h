@@ -37,10 +37,20 @@ inline void require(bool ok, int code, const char *what)
 // ---------------------------------------------------------------- workspace
 // A bump allocator over one device allocation that grows on demand.  Every
 // search carves its buffers from it; nothing is freed until the context dies.
+// An attached arena carves from memory it does not own (a fixed region) and
+// never allocates: a reserve beyond the region fails with ASCI_ENOMEM.
 class Arena {
   public:
     ~Arena() { release(); }
     void reserve(size_t bytes);  // ensure capacity; invalidates earlier carves
+    void attach(void *base, size_t bytes)
+    {
+        release();
+        base_ = (char *)base;
+        cap_ = bytes;
+        used_ = 0;
+        fixed_ = true;
+    }
     void reset() { used_ = 0; }
     template <typename T> T *take(size_t count)
     {
@@ -57,13 +67,22 @@ class Arena {
   private:
     char *base_ = nullptr;
     size_t cap_ = 0, used_ = 0;
+    bool fixed_ = false;
 };
 
-// Pinned host staging for small device->host reads.
+// Pinned host staging for small device->host reads.  An attached stage uses
+// host memory it does not own and never allocates.
 struct HostStage {
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool fixed = false;
     void reserve(size_t b);
+    void attach(void *p, size_t b)
+    {
+        ptr = p;
+        bytes = b;
+        fixed = true;
+    }
     ~HostStage();
 };
 
@@ -374,6 +393,8 @@ struct BucketArgs {
     bool defer_v = false;
     const uint32_t *h_v = nullptr;
     uint32_t nfinal = 0, V = 0, levels = 0;
+    Profiler *prof = nullptr;       // the finish launch's profiler token, for its byte count
+    int finish_tok = -1;
     const uint32_t *order = nullptr, *cnt_sorted = nullptr, *off = nullptr;
     const void *finals = nullptr;
     // destination of bucket_collect
@@ -416,6 +437,12 @@ struct SearchOut {
 };
 
 void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s);
+// closed-form number of (core, target) pairs of a search
+uint64_t search_pairs(const SearchArgs &in);
+// Upper bound of the device bytes a search of one class batch takes from its
+// setup and main arenas (top-k mode when k > 0), with the pair buffer set to
+// hold every pair; setup_part receives the setup arena's share (first).
+size_t search_scratch_bound(const SearchArgs &in, int64_t k, int finish_cap, size_t &setup_part);
 void class_counts_device(asci_ctx *ctx, int n, int na, int nb, const uint64_t *dets, const double *coeffs,
                          int64_t ndets, const asci_options &opt, std::vector<uint64_t> &masks,
                          std::vector<uint64_t> &counts, hipStream_t s);
@@ -426,6 +453,8 @@ int64_t request_footprint(const asci_request &r, uint64_t cap_records, int finis
 // argument checks shared by every entry point (ASCI_EINVAL on failure): sizes,
 // and options resolved against the defaults (NULL = defaults)
 void check_common(int norb, int nalpha, int nbeta, int64_t ndets);
+// records e as the calling thread's last error (asci_last_error); returns its code
+int report_error(const Error &e);
 asci_options resolve(const asci_options *opt);
 
 // throws ASCI_EINVAL unless every determinant has na/nb electrons inside norb orbitals

@@ -1320,7 +1320,7 @@ size_t bucket_workspace_bytes(size_t P, size_t nc, int W, int finish_cap)
 constexpr size_t kFinishLdsBudget = 80 * 1024;
 
 template <int W, int CAP, int NT>
-static void launch_finish(FinishArgs &fa, const BucketArgs &b, uint32_t nf, hipStream_t s, Profiler *prof)
+static int launch_finish(FinishArgs &fa, const BucketArgs &b, uint32_t nf, hipStream_t s, Profiler *prof)
 {
     const size_t base_lds = (sizeof(FinishLds<W, CAP, NT>) + 15) & ~size_t(15);
     const size_t n = (size_t)b.n;
@@ -1349,9 +1349,21 @@ static void launch_finish(FinishArgs &fa, const BucketArgs &b, uint32_t nf, hipS
     ASCI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds));
     // one resident grid: every workgroup strides over the segments
     const uint32_t grid = std::min<uint32_t>(nf, (uint32_t)std::max(1, ncu * std::max(per_cu, 1)));
+    // bytes: every record read once; the candidates it writes are added once
+    // their number is known (finish_bytes)
     ProfScope ps(prof, "finish", (8.0 * W + 8.0) * (double)b.P, s);
     k_finish<W, CAP, NT><<<grid, NT, lds, s>>>(fa);
     ASCI_LAUNCH_CHECK();
+    return ps.tok;
+}
+
+// algorithmic bytes of a finish launch: records read, candidates written
+// (key and score, plus N_a when every candidate is kept)
+static void finish_bytes(const BucketArgs &b, int W)
+{
+    if (b.prof && b.finish_tok >= 0)
+        b.prof->set_bytes(b.finish_tok, (8.0 * W + 8.0) * (double)b.P +
+                                            (8.0 * W + 8.0 + (b.cnum ? 8.0 : 0.0)) * (double)b.V);
 }
 
 template <int W>
@@ -1483,9 +1495,10 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.nfinal = nf;
         fa.psi = b.psi;
         // eight records per thread
-        if (CAP == 4096) launch_finish<W, 4096, 512>(fa, b, nf, s, prof);
-        else if (CAP == 2048) launch_finish<W, 2048, 256>(fa, b, nf, s, prof);
-        else launch_finish<W, 1024, 128>(fa, b, nf, s, prof);
+        b.prof = prof;
+        if (CAP == 4096) b.finish_tok = launch_finish<W, 4096, 512>(fa, b, nf, s, prof);
+        else if (CAP == 2048) b.finish_tok = launch_finish<W, 2048, 256>(fa, b, nf, s, prof);
+        else b.finish_tok = launch_finish<W, 1024, 128>(fa, b, nf, s, prof);
     }
     // candidates in key order: final segments by start, counts scanned
     uint64_t *sk[2] = {ar.take<uint64_t>(nf + 1), ar.take<uint64_t>(nf + 1)};
@@ -1512,6 +1525,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     } else {
         ASCI_HIP(hipStreamSynchronize(s));
         b.V = hcnt[6];
+        finish_bytes(b, W);
     }
     b.order = si[r];
     b.cnt_sorted = cs;
@@ -1538,6 +1552,7 @@ void bucket_read_v(BucketArgs &b, hipStream_t s)
     ASCI_HIP(hipStreamSynchronize(s));
     b.V = *b.h_v;
     b.defer_v = false;
+    finish_bytes(b, b.n <= 32 ? 1 : 2);
 }
 
 // sum of N_a * A_a over the batch's candidates: per final segment in key

@@ -26,6 +26,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kMaxBatchClasses = 2048;
+constexpr size_t kMaxClasses = (size_t)1 << 20;  // classes of one search, all levels
 
 // ---------------------------------------------------------------- class items
 // Counts of one (class T, core alpha string a) item.  A target is in class T
@@ -819,6 +820,27 @@ static SpinTables build_spin_tables(asci_ctx *ctx, const SpinTablePlan &pl, cons
     return st;
 }
 
+// bytes of the setup arena of a search: inputs keyed, the psi hash set and
+// filter, core set, class masks / totals / split tree, integral tables
+static size_t setup_bytes(size_t nd, size_t nq, int n, int W)
+{
+    const size_t hist_bytes = ((nd + kScanTile - 1) / kScanTile) * 256 * 4 * 2 + (1 << 16);
+    return nd * (8 * 2 * W + 4 * 2) + nd * (8 * 2 + 4 * 2) + nq * 8 * 4 + kMaxClasses * 20 + (size_t)2 * n * n * 8 +
+           2 * hist_bytes + 64 * 256 + (nd * 8 + 1024) * 20 + nd * 8 + (1 << 14);
+}
+
+// bytes of the main arena: count matrix and offsets (E entries), the pair
+// buffers of one class batch (Pb records), the candidate pool, the selection
+static size_t main_bytes(size_t E, size_t Pb, size_t pool_cap, uint32_t max_nc, size_t kk_max, bool topk, int W,
+                         int finish_cap)
+{
+    const size_t rec_bytes = 2 * (8 * W + 8);
+    const size_t scan_tmp = ((std::max<size_t>(Pb, E) + kScanTile - 1) / kScanTile) * 4 + 4096;
+    return E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + (topk ? 8 : 16)) +
+           bucket_workspace_bytes(Pb, max_nc, W, finish_cap) + pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 1) +
+           kk_max * 24 + 64 * 256 + (1 << 16);
+}
+
 // inputs shared by the search entry points: validated, keyed and core-selected
 template <int W>
 struct Prepared {
@@ -863,8 +885,6 @@ static void count_classes(const uint64_t *q_a, uint32_t nq, const std::vector<ui
 // Either way a class with more than `fit` pairs (the pair buffer) is split
 // further, up to level 6, so that it fits.  The split classes partition the
 // targets exactly like the classes they replace.
-constexpr size_t kMaxClasses = (size_t)1 << 20;
-
 static void plan_classes(int n, int na, int L, int64_t split_pairs, uint64_t fit, const uint64_t *q_a,
                          uint32_t nq, uint64_t *d_cls, unsigned long long *d_tot, uint64_t full,
                          const BetaFactors &bf, HostStage &hs, std::vector<uint64_t> &cls,
@@ -959,10 +979,8 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     const size_t nq = pp.nq;
 
     Arena &ar = ctx->setup;
-    const size_t hist_bytes = ((nd + kScanTile - 1) / kScanTile) * 256 * 4 * 2 + (1 << 16);
     ar.reset();
-    ar.reserve(nd * (8 * 2 * W + 4 * 2) + nd * (8 * 2 + 4 * 2) + nq * 8 * 4 + kMaxClasses * 20 +
-               (size_t)2 * n * n * 8 + 2 * hist_bytes + 64 * 256 + (nd * 8 + 1024) * 20 + nd * 8 + (1 << 14));
+    ar.reserve(setup_bytes(nd, nq, n, W));
     ar.reset();
     unsigned int *d_err = ar.take<unsigned int>(16);
     pp.d_cls = ar.take<uint64_t>(kMaxClasses);
@@ -1073,7 +1091,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
 
     Prepared<W> pp;
     prepare<W>(ctx, in.h, in.eri, n, in.na, in.nb, in.dets, in.coeffs, in.ndets, in.opt, cap, true, pp, s);
-    const size_t nd = pp.nd, nq = pp.nq;
+    const size_t nq = pp.nq;
     const uint32_t ncls = (uint32_t)pp.cls.size();
     uint64_t all_pairs = 0;
     for (uint64_t t : pp.totals) all_pairs += t;
@@ -1106,14 +1124,12 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     else if (topk) pool_cap = (size_t)std::min<uint64_t>(total + 1, std::max<uint64_t>(4 * (uint64_t)out.k, Pb) + (uint64_t)out.k);
     else pool_cap = total + 1;
     require(pool_cap < (1ull << 32), ASCI_ENOMEM, "candidate pool too large");
-    const size_t scan_tmp = ((std::max<size_t>(Pb, E) + kScanTile - 1) / kScanTile) * 4 + 4096;
     const size_t kk_max = topk ? (size_t)std::min<uint64_t>((uint64_t)out.k, pool_cap) : 0;
     uint32_t max_nc = 1;
     for (const auto &bt : batches) max_nc = std::max<uint32_t>(max_nc, bt.second - bt.first);
     Arena &ar = ctx->main;
     ar.reset();
-    ar.reserve(E * 8 + Pb * rec_bytes + scan_tmp + Pb * (8 * W + (topk ? 8 : 16)) + bucket_workspace_bytes(Pb, max_nc, W, ctx->finish_cap) +
-               pool_cap * ((8 * W + 8) * 2 + (topk ? 0 : 8) + 1) + kk_max * 24 + 64 * 256 + (1 << 16));
+    ar.reserve(main_bytes(E, Pb, pool_cap, max_nc, kk_max, topk, W, ctx->finish_cap));
     ar.reset();
     uint32_t *counts = ar.take<uint32_t>(E);
     uint32_t *offs = ar.take<uint32_t>(E);
@@ -1356,6 +1372,37 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ASCI_LAUNCH_CHECK();
     }
     finish();
+}
+
+size_t search_scratch_bound(const SearchArgs &in, int64_t k, int finish_cap, size_t &setup_part)
+{
+    const int W = in.n <= 32 ? 1 : 2;
+    const size_t nd = (size_t)in.ndets;
+    const size_t nq = (in.opt.ncore > 0 && (size_t)in.opt.ncore < nd) ? (size_t)in.opt.ncore : nd;
+    const BetaFactors bf = beta_factors(in.n, in.nb);
+    const uint64_t va = (uint64_t)(in.n - in.na);
+    const uint64_t per = (uint64_t)in.na * va + choose_u64((uint64_t)in.na, 2) * choose_u64(va, 2) +
+                         (uint64_t)bf.f[0] + (uint64_t)in.na * va * (uint64_t)(bf.f[1] - 1u);
+    const uint64_t P = std::max<uint64_t>(per * nq, 1);
+    const int L = std::min(in.opt.constraint_level, in.na);
+    const uint64_t ncls = std::max<uint64_t>(choose_u64((uint64_t)(in.n - in.na + L), L), 1);
+    const size_t E = (size_t)std::min<uint64_t>(ncls, kMaxBatchClasses) * nq;
+    const size_t pool_cap = k > 0 ? (size_t)std::min<uint64_t>(P + 1, std::max<uint64_t>(4 * (uint64_t)k, P) + (uint64_t)k)
+                                  : (size_t)P + 1;
+    const size_t kk = k > 0 ? (size_t)std::min<uint64_t>((uint64_t)k, pool_cap) : 0;
+    setup_part = (setup_bytes(nd, nq, in.n, W) + 255) & ~size_t(255);
+    return setup_part + main_bytes(E, (size_t)P, pool_cap, (uint32_t)std::min<uint64_t>(ncls, kMaxBatchClasses), kk,
+                                   k > 0, W, finish_cap);
+}
+
+uint64_t search_pairs(const SearchArgs &in)
+{
+    const BetaFactors bf = beta_factors(in.n, in.nb);
+    const uint64_t va = (uint64_t)(in.n - in.na);
+    const size_t nd = (size_t)in.ndets;
+    const size_t nq = (in.opt.ncore > 0 && (size_t)in.opt.ncore < nd) ? (size_t)in.opt.ncore : nd;
+    return ((uint64_t)in.na * va + choose_u64((uint64_t)in.na, 2) * choose_u64(va, 2) + (uint64_t)bf.f[0] +
+            (uint64_t)in.na * va * (uint64_t)(bf.f[1] - 1u)) * nq;
 }
 
 void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s)

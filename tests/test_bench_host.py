@@ -28,7 +28,7 @@ def _write_record(tmp, src_text, sha=None):
 def test_traffic_record_used_while_sources_match(tmp_path, monkeypatch):
     _write_record(str(tmp_path), "kernel v1\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("finish") == pytest.approx(1024.0 * (1000.0 * 2.0 + 500.0 * 1.0))
+    assert bench.measured_traffic("finish", "16e20o") == pytest.approx(1024.0 * (1000.0 * 2.0 + 500.0 * 1.0))
 
 
 def test_traffic_record_dropped_once_sources_change(tmp_path, monkeypatch):
@@ -36,12 +36,12 @@ def test_traffic_record_dropped_once_sources_change(tmp_path, monkeypatch):
     with open(os.path.join(str(tmp_path), "k.hip"), "w") as f:
         f.write("kernel v2\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("finish") is None
+    assert bench.measured_traffic("finish", "16e20o") is None
 
 
 def test_traffic_record_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("finish") is None
+    assert bench.measured_traffic("finish", "16e20o") is None
 
 
 def test_committed_record_names_existing_sources():
