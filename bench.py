@@ -184,42 +184,78 @@ def _requests(asci, syn, torch, specs, dev):
 
 
 def mode_batch(args, asci, syn, torch):
-    """64 uneven searches: one batched call against the same searches one by
-    one on one context, each timed after a warm-up pass that sizes its
-    workspaces."""
+    """64 uneven searches: one by one on one context, then as batches: the
+    requests inside the asynchronous search's scope as one captured graph
+    (replayed; the rest on worker streams at the same time), and with the
+    graph turned off (worker streams only).  Every batch result is compared
+    bit for bit with the one-by-one result.  Each timing follows an untimed
+    pass that sizes the workspaces (and captures the graph)."""
+    import numpy as np
+
     dev = torch.device("cuda", 0)
     specs = syn.batch_specs(args.batch_count, seed=64)
     reqs, P = _requests(asci, syn, torch, specs, dev)
     print("batch inputs ready: %d searches, %.3g pairs" % (len(reqs), P), file=sys.stderr, flush=True)
     ctx = asci.Context.get(0)
+    gctx = asci.Context(0)
+
+    def snapshot():
+        return [(r.out_dets.view(torch.int64).cpu().numpy().copy(), r.out_scores.cpu().numpy().copy()) for r in reqs]
+
     for r, sp in zip(reqs, specs):  # warm-up: size the context's workspace
         h, eri, dets, coeffs = r.keep
         asci.search(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, r.c.E0, sp["k"], ctx=ctx)
     torch.cuda.synchronize()
-    per = []
+    per, single_out = [], []
     t0 = time.perf_counter()
     for r, sp in zip(reqs, specs):
         t1 = time.perf_counter()
         h, eri, dets, coeffs = r.keep
-        asci.search(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, r.c.E0, sp["k"], ctx=ctx)
+        k_, s_ = asci.search(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, r.c.E0, sp["k"], ctx=ctx)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
+        single_out.append((k_.view(torch.int64).cpu().numpy().copy(), s_.cpu().numpy().copy()))
         pairs = sp["ndets"] * sd_per_det(sp["n"], sp["na"], sp["nb"])
-        per.append({"norb": sp["n"], "nalpha": sp["na"], "ndets": sp["ndets"], "pairs": pairs,
-                    "ms": round(dt * 1e3, 3), "contributions_per_s": pairs / dt})
+        per.append({"norb": sp["n"], "nalpha": sp["na"], "ndets": sp["ndets"], "k": sp["k"], "pairs": pairs,
+                    "single_ms": round(dt * 1e3, 3), "graph": bool(asci.graph_capable(r, ctx=gctx))})
     single = time.perf_counter() - t0
-    # warm-up of the batch workers (the context's workspace gives way to theirs)
-    asci.search_batch(reqs, ctx=ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = asci.search_batch(reqs, ctx=ctx)
-    torch.cuda.synchronize()
-    batch = time.perf_counter() - t0
+
+    def identical(res):
+        got = snapshot()
+        return all(rr.status == 0 and int(rr.count) == len(w[0]) and (g[0][:rr.count] == w[0]).all() and
+                   (g[1][:rr.count] == w[1]).all() for rr, g, w in zip(res, got, single_out))
+
+    def timed_batch(graph, subset=None):
+        gctx.set_param("batch_graph", 1 if graph else 0)
+        rs = reqs if subset is None else [reqs[i] for i in subset]
+        asci.search_batch(rs, ctx=gctx)  # untimed: workspaces sized, graph captured
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = asci.search_batch(rs, ctx=gctx)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, res
+
+    batch_graph, res_g = timed_batch(True)
+    same_g = identical(res_g)
+    print("graph batch %.3f s (identical %s)" % (batch_graph, same_g), file=sys.stderr, flush=True)
+    batch_workers, res_w = timed_batch(False)
+    same_w = identical(res_w)
+    print("worker batch %.3f s (identical %s)" % (batch_workers, same_w), file=sys.stderr, flush=True)
+    sub = [i for i, p in enumerate(per) if p["graph"]]
+    sub_single = sum(per[i]["single_ms"] for i in sub) * 1e-3
+    sub_graph, _ = timed_batch(True, sub)
+    sub_workers, _ = timed_batch(False, sub)
+    sub_pairs = sum(per[i]["pairs"] for i in sub)
+    gctx.close()
     return {"metric": "batched vs single searches", "searches": len(reqs), "contributions": P,
-            "single_s": round(single, 3), "batch_s": round(batch, 3),
-            "single_contributions_per_s": P / single, "batch_contributions_per_s": P / batch,
-            "speedup": single / batch, "batch_slots": ctx.get_param("batch_slots"),
-            "all_ok": all(r.status == 0 for r in res), "per_search": per}
+            "single_s": round(single, 3), "batch_s": round(batch_graph, 3), "batch_workers_only_s": round(batch_workers, 3),
+            "single_contributions_per_s": P / single, "batch_contributions_per_s": P / batch_graph,
+            "speedup": single / batch_graph, "speedup_workers_only": single / batch_workers,
+            "identical_to_single": bool(same_g and same_w),
+            "graph_subset": {"searches": len(sub), "contributions": sub_pairs, "single_s": round(sub_single, 4),
+                             "graph_s": round(sub_graph, 4), "workers_s": round(sub_workers, 4),
+                             "speedup_graph": sub_single / sub_graph, "speedup_workers": sub_single / sub_workers},
+            "batch_slots": ctx.get_param("batch_slots"), "per_search": per}
 
 
 SERVE_MIX = [(0.70, dict(n=20, na=8, nb=8, ndets=1_000)), (0.25, dict(n=26, na=10, nb=10, ndets=10_000)),
@@ -339,7 +375,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="24e30o")
-    ap.add_argument("--extra", default="16e20o", help="search mode: further workloads timed (comma list, '' = none)")
+    ap.add_argument("--extra", default="16e20o", help="search mode: further workloads timed (comma list, 'none' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--finish-cap", type=int, default=0, help="records per LDS bucket (tuning parameter)")
     ap.add_argument("--mode", default="search", choices=["search", "levels", "loop", "batch", "serve", "copy", "host"],
@@ -372,7 +408,7 @@ def main():
     if args.finish_cap:
         ctx.set_param("finish_cap", args.finish_cap)
     line = measure_search(args, asci, syn, torch, np, ctx, args.workload, args.steps, args.warmup, full=True)
-    extras = [w for w in args.extra.split(",") if w and w != args.workload]
+    extras = [w for w in args.extra.split(",") if w and w not in ("none", args.workload)]
     if extras:
         line["extra_workloads"] = {}
         for w in extras:

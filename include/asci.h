@@ -105,6 +105,9 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *                 Both give the same bits (same summation order).
  *   "release_workspace" (value 1): free the context's device workspaces and
  *                 the batch workers (they are allocated again on demand).
+ *   "batch_graph": 1 (default) runs the requests of asci_search_batch that fit
+ *                 asci_search_async's scope as one captured graph; 0 sends
+ *                 them to the worker streams.
  *   "fault_test": 1 makes every later search on ctx raise a forced fault in
  *                 its generator, so that the call fails with ASCI_EDEVICE
  *                 (a test of the error path: the kernels' internal-consistency
@@ -348,22 +351,65 @@ typedef struct asci_result {
     int64_t contributions;     /* pairs the search generated */
 } asci_result;
 
+/*
+ * The search of asci_search_device, queued with nothing read back (Alg. 2;
+ * the per-class counts are formed on the fly on the device, Sec. II.B): the
+ * class plan, the pair counts, the bucket split levels, the candidate count
+ * and the selection run from counts kept in device memory, so the call
+ * returns once the work is queued on `stream` and never waits on the device.
+ * req names device buffers (req->out_dets, req->out_scores: capacity k);
+ * d_result is device memory that receives, when the queued work completes,
+ * the number of candidates written (min(k, candidates)) and the status
+ * (ASCI_OK, ASCI_EINVAL for invalid or repeated input determinants found on
+ * the device, ASCI_EDEVICE for an internal failure); on a failure no output is
+ * written and count is 0.  Synchronise the stream (or wait on an event
+ * recorded after the call) before reading it.  Results equal
+ * asci_search_device's bit for bit.
+ * Scope: the search must fit one class batch: every pair in the pair buffer
+ * (fewer than 2^31 pairs), split_pairs = 0; when the requested constraint
+ * level has more than 2048 classes the highest lower level with at most 2048
+ * is used (the classes only partition the work).  Otherwise the call returns
+ * ASCI_EINVAL at once and queues nothing.
+ * ctx's workspace is in use until the queued work completes: calls that may
+ * overlap need contexts of their own (one per stream).  A call that needs more
+ * workspace than ctx holds allocates it first (hipMalloc, which may wait for
+ * the device); later calls of the same or smaller size allocate nothing.
+ * The call itself returns ASCI_OK once queued, or ASCI_EINVAL / ASCI_ENOMEM
+ * for argument and workspace failures (nothing queued).
+ */
+typedef struct asci_async_result {
+    int64_t count;   /* candidates written */
+    int32_t status;  /* ASCI_OK or an error code */
+    int32_t flags;   /* device-side failure bits (0 when status is ASCI_OK) */
+} asci_async_result;
+
+int asci_search_async(asci_ctx *ctx, const asci_request *req, asci_async_result *d_result, void *stream);
+
+/* Device bytes asci_search_async's workspace takes for req on ctx (*out_bytes;
+ * 0 when req is outside its scope).  Host only; ASCI_EINVAL for bad sizes. */
+int asci_request_async_bytes(asci_ctx *ctx, const asci_request *req, int64_t *out_bytes);
+
 /* Device bytes the library budgets for one request (workspace estimate). */
 int64_t asci_request_footprint(const asci_request *req);
 
 /*
- * Run nreq searches as one batch on ctx's device: the requests are ordered by
- * estimated cost (largest first) and run concurrently on `slots` worker
- * streams (ctx parameter "batch_slots", default 2; see asci_autotune), each
- * with its own workspace.  The workers stay with ctx between calls (until
- * "release_workspace", a change of "batch_slots" or "finish_cap", or
- * asci_ctx_destroy) and keep their workspaces while only batches run; the
- * context's own workspaces are freed when a batch starts, and a single search
- * on ctx frees the idle workers' workspaces, so the two never hold HBM at the
- * same time.  Work already queued on `stream` completes first; the call
- * returns when every result is written.  res[i] is request i's result; the
- * return value is ASCI_OK when every request succeeded, else the first error
- * code.
+ * Run nreq searches as one batch on ctx's device.  Requests inside the scope
+ * of asci_search_async whose workspace fits a share of the free HBM run as
+ * one captured HIP graph: placed on "batch_slots" streams (largest first, to
+ * the least loaded; each stream with a context of its own) that fork from
+ * and join back to one launch stream; the graph is replayed by later calls
+ * with the same requests (same buffers, sizes and options) and captured
+ * again otherwise.  The other requests are ordered by estimated cost
+ * (largest first) and run at the same time on worker streams, each with its
+ * own workspace.  Context parameter "batch_graph" = 0 sends every request to
+ * the workers.  The workers and the graph's contexts stay with ctx between
+ * calls (until "release_workspace", a change of "batch_slots" or
+ * "finish_cap", or asci_ctx_destroy); the context's own workspaces are
+ * freed when a batch starts, and a single search on ctx frees the idle
+ * workers' workspaces.  Work already queued on `stream` completes first; the
+ * call returns when every result is written.  res[i] is request i's result;
+ * the return value is ASCI_OK when every request succeeded, else the first
+ * error code.
  */
 int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_result *res, void *stream);
 

@@ -64,6 +64,10 @@ class Result(C.Structure):
                 ("contributions", C.c_int64)]
 
 
+class AsyncResult(C.Structure):
+    _fields_ = [("count", C.c_int64), ("status", C.c_int32), ("flags", C.c_int32)]
+
+
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("rejected", C.c_int64), ("max_running", C.c_int64), ("peak_bytes", C.c_int64),
@@ -134,6 +138,8 @@ _lib.asci_server_wait.argtypes = [_vp, C.c_uint64, C.POINTER(Result)]
 _lib.asci_server_get_stats.argtypes = [_vp, C.POINTER(ServerStats)]
 _lib.asci_server_destroy.argtypes = [_vp]
 _lib.asci_server_set_param.argtypes = [_vp, C.c_char_p, C.c_double]
+_lib.asci_search_async.argtypes = [_vp, C.POINTER(Request), _vp, _vp]
+_lib.asci_request_async_bytes.argtypes = [_vp, C.POINTER(Request), _ip]
 
 EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_default", "asci_ctx_create",
            "asci_ctx_destroy", "asci_ctx_set_param", "asci_ctx_get_param", "asci_ctx_set_profiling",
@@ -144,7 +150,8 @@ EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_def
            "asci_loop_options_default", "asci_loop_step_device", "asci_run_device",
            "asci_request_footprint", "asci_search_batch", "asci_autotune", "asci_server_create",
            "asci_server_create_fake", "asci_server_submit", "asci_server_footprint", "asci_server_poll",
-           "asci_server_wait", "asci_server_set_param",
+           "asci_server_wait", "asci_server_set_param", "asci_search_async",
+           "asci_request_async_bytes",
            "asci_server_get_stats", "asci_server_destroy"]
 
 
@@ -206,10 +213,15 @@ class Context:
             i += 1
         return out
 
+    def close(self):
+        """Free the context (its device workspace) now."""
+        if self.ptr:
+            _lib.asci_ctx_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
     def __del__(self):
         try:
-            if self.ptr:
-                _lib.asci_ctx_destroy(self.ptr)
+            self.close()
         except Exception:
             pass
 
@@ -405,6 +417,42 @@ class SearchRequest:
 
     def result(self, count):
         return self.out_dets[:count], self.out_scores[:count]
+
+
+def search_async(req, result=None, ctx=None, stream=None):
+    """Queue a SearchRequest with nothing read back (asci_search_async) on
+    `stream` (a torch.cuda.Stream, default the current one).  result: a device
+    int64 tensor of 2 elements that receives (count, status | flags << 32);
+    returned.  Read it after synchronising the stream (async_status)."""
+    torch = _torch()
+    dev = req.out_dets.device
+    ctx = ctx or Context.get(dev.index if dev.index is not None else torch.cuda.current_device())
+    if result is None:
+        result = torch.zeros(2, dtype=torch.int64, device=dev)
+    st = stream.cuda_stream if stream is not None else _stream(dev.index if dev.index is not None else 0)
+    _check(_lib.asci_search_async(ctx.ptr, C.byref(req.c), result.data_ptr(), st))
+    return result
+
+
+def graph_capable(req, ctx=None):
+    """Whether a SearchRequest is inside the asynchronous search's scope (and so
+    runs in the captured graph of a batch)."""
+    torch = _torch()
+    dev = req.out_dets.device
+    ctx = ctx or Context.get(dev.index if dev.index is not None else torch.cuda.current_device())
+    v = C.c_int64()
+    _check(_lib.asci_request_async_bytes(ctx.ptr, C.byref(req.c), C.byref(v)))
+    return v.value
+
+
+def async_status(result):
+    """(count, status, flags) of an asci_async_result held in a 2-element int64 tensor."""
+    r = result.cpu().tolist()
+    count, word = int(r[0]), int(r[1]) & 0xFFFFFFFFFFFFFFFF
+    status = word & 0xFFFFFFFF
+    if status >= 1 << 31:
+        status -= 1 << 32
+    return count, status, word >> 32
 
 
 def fake_request(norb, nalpha, nbeta, ndets, k):

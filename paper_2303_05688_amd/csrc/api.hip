@@ -195,6 +195,11 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
             ctx->spin_tables = (int)value;
             return ASCI_OK;
         }
+        if (key == "batch_graph") {
+            require(value == 0 || value == 1, ASCI_EINVAL, "batch_graph must be 0 or 1");
+            ctx->batch_graph = (int)value;
+            return ASCI_OK;
+        }
         if (key == "fault_test") {
             require(value == 0 || value == 1, ASCI_EINVAL, "fault_test must be 0 or 1");
             ctx->fault_test = (int)value;
@@ -207,6 +212,8 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
             if (ctx->batch_pool) ctx->batch_pool_free(ctx->batch_pool);
             ctx->batch_pool = nullptr;
             ctx->batch_pool_slots = ctx->batch_pool_cap = 0;
+            if (ctx->graph_batch) ctx->graph_batch_free(ctx->graph_batch);
+            ctx->graph_batch = nullptr;
             ctx->setup.release();
             ctx->main.release();
             ctx->tables.release();
@@ -231,6 +238,7 @@ int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value)
         else if (key == "batch_slots") *value = ctx->batch_slots;
         else if (key == "spin_tables") *value = ctx->spin_tables;
         else if (key == "fault_test") *value = ctx->fault_test;
+        else if (key == "batch_graph") *value = ctx->batch_graph;
         else if (key == "last_batches") *value = ctx->last_batches;
         else if (key == "last_finals") *value = ctx->last_finals;
         else if (key == "last_levels") *value = ctx->last_levels;
@@ -326,6 +334,43 @@ int asci_search_device(asci_ctx *ctx, const double *d_h, const double *d_eri, in
         return fail(e);
     } catch (const std::bad_alloc &) {
         return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
+    }
+}
+
+int asci_search_async(asci_ctx *ctx, const asci_request *req, asci_async_result *d_result, void *stream)
+{
+    try {
+        require(ctx != nullptr && req != nullptr && d_result != nullptr, ASCI_EINVAL, "null argument");
+        check_common(req->norb, req->nalpha, req->nbeta, req->ndets);
+        require(req->h && req->eri && req->dets && req->coeffs && req->out_dets && req->out_scores, ASCI_EINVAL,
+                "null buffer in the request");
+        ASCI_HIP(hipSetDevice(ctx->device));
+        SearchArgs in{req->h, req->eri, req->norb, req->nalpha, req->nbeta, req->dets, req->coeffs, req->ndets,
+                      req->E0, resolve(&req->opt)};
+        search_async(ctx, in, req->k, req->out_dets, req->out_scores, d_result, (hipStream_t)stream);
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        return fail(Error{ASCI_ENOMEM, "host memory allocation failed"});
+    } catch (const std::exception &e) {
+        return fail(Error{ASCI_EDEVICE, e.what()});
+    }
+}
+
+int asci_request_async_bytes(asci_ctx *ctx, const asci_request *req, int64_t *out_bytes)
+{
+    try {
+        require(ctx != nullptr && req != nullptr && out_bytes != nullptr, ASCI_EINVAL, "null argument");
+        check_common(req->norb, req->nalpha, req->nbeta, req->ndets);
+        SearchArgs in{req->h, req->eri, req->norb, req->nalpha, req->nbeta, req->dets, req->coeffs, req->ndets,
+                      req->E0, resolve(&req->opt)};
+        *out_bytes = (int64_t)search_async_bytes(in, req->k, ctx->finish_cap, ctx->spin_tables != 0);
+        return ASCI_OK;
+    } catch (const Error &e) {
+        return fail(e);
     } catch (const std::exception &e) {
         return fail(Error{ASCI_EDEVICE, e.what()});
     }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -142,6 +143,7 @@ struct asci_ctx {
     int batch_slots = 2;    // tunable: concurrent searches of a batch
     int spin_tables = 1;    // tunable: 1 = spin-string energy tables when they pay, 0 = never
     int fault_test = 0;     // 1: the next search raises a forced fault (tests of the error path)
+    int batch_graph = 1;    // 1: batch requests within the asynchronous search's scope run as one graph
     // diagnostics of the last search
     int64_t last_batches = 0, last_finals = 0, last_levels = 0, last_candidates = 0;
     asci::Profiler prof;
@@ -155,12 +157,15 @@ struct asci_ctx {
     void (*batch_pool_free)(void *) = nullptr;
     void (*batch_pool_trim)(void *) = nullptr;  // free the idle workers' workspaces
     int batch_pool_slots = 0, batch_pool_cap = 0;
+    void *graph_batch = nullptr;  // asci::GraphBatch of asci_search_batch (graph part)
+    void (*graph_batch_free)(void *) = nullptr;
     asci_ctx() = default;
     asci_ctx(const asci_ctx &) = delete;
     asci_ctx &operator=(const asci_ctx &) = delete;
     ~asci_ctx()
     {
         if (batch_pool && batch_pool_free) batch_pool_free(batch_pool);
+        if (graph_batch && graph_batch_free) graph_batch_free(graph_batch);
     }
 };
 
@@ -255,9 +260,17 @@ struct KeySpec {
 // ---------------------------------------------------------------- primitives (prims.hip)
 constexpr int kScanTile = 4096;
 
+// Device-side counts: a primitive given `dn` (device) treats min(n, *dn) as
+// its length, with n the host bound its launch is sized for; nothing past the
+// count is read or written.
+
 // exclusive scan of n uint32 values (n < 2^28); *d_total (device) gets the sum
 void scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, Arena &ar,
-              hipStream_t s, Profiler *prof = nullptr);
+              hipStream_t s, Profiler *prof = nullptr, const uint32_t *dn = nullptr);
+
+// p[0 .. n) = v by a kernel (a fill that a captured graph replays correctly)
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v);
+void fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 
 // stable LSD radix sort by selected 8-bit digits of a 1- or 2-word key, with a
 // payload.  keys_lo/keys_hi/vals are ping-pong pairs; `digits` lists (word,
@@ -269,7 +282,8 @@ struct Digit {
 };
 template <typename V>
 int radix_sort(uint64_t *keys_lo[2], uint64_t *keys_hi[2], V *vals[2], size_t n, int words,
-               const std::vector<Digit> &digits, Arena &ar, hipStream_t s, Profiler *prof = nullptr);
+               const std::vector<Digit> &digits, Arena &ar, hipStream_t s, Profiler *prof = nullptr,
+               const uint32_t *dn = nullptr);
 
 // radix selection on the IEEE bit pattern of |score[j]|, j < n: finds t, the
 // k-th largest value (1 <= k <= n), and how many entries equal to t must be
@@ -289,8 +303,10 @@ struct SelectWork {
     unsigned int *d_count;
     unsigned int *h_count;
 };
+// With dn (and dk: k = min(k, *dk), device) the compaction is skipped.
 void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_state,
-                      hipStream_t s, Profiler *prof = nullptr, const SelectWork *work = nullptr);
+                      hipStream_t s, Profiler *prof = nullptr, const SelectWork *work = nullptr,
+                      const uint32_t *dn = nullptr, const uint32_t *dk = nullptr);
 
 // ---------------------------------------------------------------- input-determinant set
 // Open-addressing hash set of the input keys (linear probing; a slot is taken
@@ -395,6 +411,8 @@ struct BucketArgs {
     uint32_t nfinal = 0, V = 0, levels = 0;
     Profiler *prof = nullptr;       // the finish launch's profiler token, for its byte count
     int finish_tok = -1;
+    // the device-driven variant: nfinal and V are then bounds, the counts are on the device
+    const uint32_t *dn_final = nullptr, *dn_V = nullptr;
     const uint32_t *order = nullptr, *cnt_sorted = nullptr, *off = nullptr;
     const void *finals = nullptr;
     // destination of bucket_collect
@@ -410,8 +428,24 @@ int bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof);  // profiler t
 void bucket_read_v(BucketArgs &b, hipStream_t s);
 // sum over the batch's candidates of N_a * A_a (deterministic order)
 double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs);
+// The same sort-and-accumulate with no count read back (asynchronous search):
+// launches sized for host bounds, a fixed number of split levels, counts in
+// b.dn_final and b.dn_V.  A failure sets bits of *d_stat (kStat*).
+template <int W>
+void bucket_accumulate_dev(BucketArgs &b, Arena &ar, hipStream_t s, uint32_t *d_stat);
+template <int W>
+void bucket_collect_dev(BucketArgs &b, hipStream_t s);
+// status bits of a search that reads nothing back
+constexpr uint32_t kStatInvalid = 1u;    // wrong electron count or orbital >= norb
+constexpr uint32_t kStatDuplicate = 2u;  // an input determinant given twice
+constexpr uint32_t kStatSplit = 4u;      // the bucket split did not finish in its levels / lists overflowed
+constexpr uint32_t kStatPool = 8u;       // candidate pool overflow
+constexpr uint32_t kStatFault = 16u;     // a kernel consistency fault (see hamiltonian.h)
+
 // the fault word of the bucket kernels (see hamiltonian.h): clear / queue a copy to pinned *dst
 void bucket_fault_clear(hipStream_t s);
+void bucket_fault_reset_dev(hipStream_t s);                          // by a kernel
+void bucket_fault_take_dev(uint32_t *stat, uint32_t bit, hipStream_t s);  // stat |= bit if set
 void bucket_fault_fetch(unsigned int *dst, hipStream_t s);
 
 // ---------------------------------------------------------------- search (search.hip)
@@ -439,6 +473,14 @@ struct SearchOut {
 void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s);
 // closed-form number of (core, target) pairs of a search
 uint64_t search_pairs(const SearchArgs &in);
+// The top-k search with nothing read back (asci_search_async): one class batch,
+// every count on the device; d_result (device) receives count and status.
+// plan_only: check the request and size ctx's workspaces, queue nothing.
+void search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uint64_t *out_dets, double *out_scores,
+                  asci_async_result *d_result, hipStream_t s, bool plan_only = false);
+// device bytes of search_async's workspaces for this request; 0 when the
+// request is outside its scope (one class batch)
+size_t search_async_bytes(const SearchArgs &in, int64_t k, int finish_cap, bool spin_tables);
 // Upper bound of the device bytes a search of one class batch takes from its
 // setup and main arenas (top-k mode when k > 0), with the pair buffer set to
 // hold every pair; setup_part receives the setup arena's share (first).
@@ -459,6 +501,36 @@ asci_options resolve(const asci_options *opt);
 
 // throws ASCI_EINVAL unless every determinant has na/nb electrons inside norb orbitals
 void validate_dets(asci_ctx *ctx, const uint64_t *dets, int64_t ndets, int n, int na, int nb, hipStream_t s);
+
+// ---------------------------------------------------------------- batches as one graph (graph.hip)
+// Contexts and streams of the graph slots, the captured graph and the device
+// result records of its requests; replayed while the requests stay the same.
+struct GraphBatch {
+    int device = 0;
+    std::vector<std::unique_ptr<asci_ctx>> ctxs;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    hipStream_t main = nullptr;   // capture and launch stream
+    hipEvent_t order = nullptr;   // orders it with the caller's stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+    asci_async_result *d_res = nullptr;
+    size_t nres = 0;
+    GraphBatch() = default;
+    GraphBatch(const GraphBatch &) = delete;
+    GraphBatch &operator=(const GraphBatch &) = delete;
+    ~GraphBatch();
+    void release_graph();
+};
+// workspace bytes of a request in a graph slot, 0 when outside the asynchronous search's scope
+size_t graph_request_bytes(const asci_request &r, int finish_cap, bool spin_tables);
+// queue requests reqs[idx[j]] as one graph on `stream` (captured, or replayed
+// when the same requests were captured last); result j goes to record j
+void graph_batch_launch(GraphBatch &gb, int device, const asci_request *reqs, const std::vector<int> &idx, int slots,
+                        int finish_cap, int spin_tables, hipStream_t stream);
+// after the stream has finished: the result records of the last launch
+void graph_batch_results(GraphBatch &gb, size_t count, std::vector<asci_async_result> &out);
 
 // ---------------------------------------------------------------- variational step (eigen.hip)
 // H over a determinant set in CSR: rows in set order, columns ascending, both

@@ -54,16 +54,6 @@ __host__ __device__ __forceinline__ uint32_t make_meta(uint32_t top, uint32_t bu
     return top | (buf << 8) | (single ? 512u : 0u) | (bits ? 1024u : 0u);
 }
 
-// Workgroups are handed to the 8 XCDs in turn; tile kernels map them so that
-// each XCD takes a contiguous range of tiles (neighbouring tiles write
-// neighbouring parts of the same ranges, whose shared lines then meet in one
-// L2).  The grid is 8 * ceil(ntiles / 8); indices past ntiles exit.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t ntiles)
-{
-    const uint32_t per = (ntiles + 7u) / 8u;
-    return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-}
-
 constexpr int kMaxSplit = 256;       // ranges per split
 constexpr int kSplitSample = 16;     // samples per range
 
@@ -159,7 +149,11 @@ struct SplitArgs {
     const uint64_t *spl_lo, *spl_hi;  // splitters: kMaxSplit - 1 per segment
     unsigned long long *kor, *kand;   // per segment: OR and AND of its keys (2 words each)
     uint8_t *dig;                     // per record: its digit, from the histogram pass
+    const uint32_t *dn_seg = nullptr;    // device: segments of the level (nseg is then a bound)
+    const uint32_t *dn_tiles = nullptr;  // device: tiles of the level (ntiles is then a bound)
 };
+
+__device__ __forceinline__ uint32_t dev_count(uint32_t n, const uint32_t *dn) { return dn ? min(n, *dn) : n; }
 
 // ranges of a splitter split: about half the LDS capacity each, 2 to 256
 __host__ __device__ __forceinline__ uint32_t split_ranges(uint32_t size, uint32_t cap)
@@ -238,19 +232,22 @@ struct KeyBufs {
 
 template <int W, int T>
 __global__ __launch_bounds__(T) void k_seg_splitters(const Seg *__restrict__ segs, uint32_t cap, KeyBufs kb,
-                                                       uint64_t *__restrict__ g_lo, uint64_t *__restrict__ g_hi)
+                                                       uint64_t *__restrict__ g_lo, uint64_t *__restrict__ g_hi,
+                                                       uint32_t nseg, const uint32_t *dn_seg)
 {
     constexpr int kMaxSample = kMaxSplit * kSplitSample;  // 4096
     __shared__ uint64_t x_lo[kMaxSample];
     __shared__ uint64_t x_hi[W == 2 ? kMaxSample : 1];
-    const uint32_t s = blockIdx.x;
+    const uint32_t ns = dev_count(nseg, dn_seg);
+    for (uint32_t s = blockIdx.x; s < ns; s += gridDim.x) {
     const Seg sg = segs[s];
-    if (seg_bits(sg)) return;
+    if (seg_bits(sg)) continue;  // uniform per block
     const uint32_t nb = split_ranges(sg.size, cap);
     const uint32_t m = min(sg.size, nb * (uint32_t)kSplitSample);
     uint32_t p = 1;
     while (p < m) p <<= 1;
     const uint64_t *klo = kb.lo[seg_buf(sg)], *khi = kb.hi[seg_buf(sg)];
+    __syncthreads();  // the previous segment's samples are read
     for (uint32_t i = threadIdx.x; i < p; i += T) {
         if (i < m) {
             const size_t j = (size_t)sg.start + (size_t)(((uint64_t)2 * i + 1) * sg.size / (2 * (uint64_t)m));
@@ -289,36 +286,48 @@ __global__ __launch_bounds__(T) void k_seg_splitters(const Seg *__restrict__ seg
         g_lo[(size_t)s * (kMaxSplit - 1) + j] = x_lo[q];
         if (W == 2) g_hi[(size_t)s * (kMaxSplit - 1) + j] = x_hi[q];
     }
+    }
 }
 
-// per segment: number of tiles
 // tiles per large segment; also clears the level's skip flags and the count of
 // next-level segments (instead of separate fill launches)
 __global__ __launch_bounds__(256) void k_seg_tiles(const Seg *__restrict__ segs, uint32_t nseg,
                                                    uint32_t *__restrict__ ntile, uint32_t *__restrict__ skip,
-                                                   uint32_t *__restrict__ nnext)
+                                                   uint32_t *__restrict__ nnext, const uint32_t *dn_seg)
 {
-    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
-    if (s < nseg) ntile[s] = (segs[s].size + kTileN - 1) / kTileN;
-    if (s <= nseg) skip[s] = 0u;
-    if (s == 0) *nnext = 0u;
+    const uint32_t ns = dev_count(nseg, dn_seg);
+    for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s <= ns; s += gridDim.x * 256) {
+        if (s < ns) ntile[s] = (segs[s].size + kTileN - 1) / kTileN;
+        skip[s] = 0u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nnext = 0u;
 }
 
 // the segment of every tile; also starts the OR / AND of every segment's keys
 __global__ __launch_bounds__(256) void k_seg_expand(const Seg *__restrict__ segs, uint32_t nseg,
                                                     const uint32_t *__restrict__ tile_base,
                                                     uint32_t *__restrict__ tile_seg, unsigned long long *__restrict__ kor,
-                                                    unsigned long long *__restrict__ kand)
+                                                    unsigned long long *__restrict__ kand, const uint32_t *dn_seg)
 {
-    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= nseg) return;
-    kor[2 * s] = 0ull;
-    kor[2 * s + 1] = 0ull;
-    kand[2 * s] = ~0ull;
-    kand[2 * s + 1] = ~0ull;
-    const uint32_t nt = (segs[s].size + kTileN - 1) / kTileN, tb = tile_base[s];
-    for (uint32_t t = 0; t < nt; ++t) tile_seg[tb + t] = s;
+    const uint32_t ns = dev_count(nseg, dn_seg);
+    for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < ns; s += gridDim.x * 256) {
+        kor[2 * s] = 0ull;
+        kor[2 * s + 1] = 0ull;
+        kand[2 * s] = ~0ull;
+        kand[2 * s + 1] = ~0ull;
+        const uint32_t nt = (segs[s].size + kTileN - 1) / kTileN, tb = tile_base[s];
+        for (uint32_t t = 0; t < nt; ++t) tile_seg[tb + t] = s;
+    }
 }
+
+// Tiles of a level, XCD-contiguous: the tiles [x * per, (x + 1) * per) go to
+// XCD x (workgroups are handed to the 8 XCDs in turn), taken by that XCD's
+// workgroups in turn.  With a grid of 8 * per workgroups each takes one tile.
+#define FOR_LEVEL_TILES(a, t)                                                          \
+    const uint32_t nt_all_ = dev_count((a).ntiles, (a).dn_tiles);                     \
+    const uint32_t per_ = (nt_all_ + 7u) / 8u, slots_ = max(gridDim.x >> 3, 1u);      \
+    for (uint32_t i_ = blockIdx.x >> 3, t = (blockIdx.x & 7u) * per_ + i_;            \
+         i_ < per_ && t < nt_all_; i_ += slots_, t = (blockIdx.x & 7u) * per_ + i_)
 
 template <int W>
 __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
@@ -326,13 +335,13 @@ __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
     __shared__ uint32_t h[kHistT / 64][256];
     __shared__ uint64_t spl_lo[kMaxSplit - 1];
     __shared__ uint64_t spl_hi[W == 2 ? kMaxSplit - 1 : 1];
-    const uint32_t t = xcd_tile(a.ntiles);
-    if (t >= a.ntiles) return;
+    FOR_LEVEL_TILES(a, t) {
     const uint32_t s = a.tile_seg[t];
     const Seg sg = a.segs[s];
     const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
     const SplitRule rule = split_rule(sg, a.cap);
     const uint32_t buf = seg_buf(sg);
+    __syncthreads();  // the previous tile's counts are written out
     for (int i = threadIdx.x; i < (kHistT / 64) * 256; i += kHistT) (&h[0][0])[i] = 0u;
     load_splitters<W>(rule, a.spl_lo, a.spl_hi, s, spl_lo, spl_hi);
     const uint32_t r0 = tl * kTileN, r1 = min(sg.size, r0 + kTileN);
@@ -387,6 +396,7 @@ __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
         for (int i = 0; i < kHistT / 64; ++i) c += h[i][d];
         a.hist[(size_t)tb * 256 + (size_t)d * nt + tl] = c;
     }
+    }
 }
 
 // children of every large segment (one block of 256 threads per segment).
@@ -404,12 +414,15 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
                                                         Seg *__restrict__ next, uint32_t *__restrict__ nnext,
                                                         uint32_t next_cap, uint32_t *__restrict__ overflow,
                                                         const unsigned long long *__restrict__ kor,
-                                                        const unsigned long long *__restrict__ kand, int n)
+                                                        const unsigned long long *__restrict__ kand, int n,
+                                                        const uint32_t *dn_seg)
 {
     __shared__ uint32_t s_cnt[256], s_off[256];
     __shared__ Seg s_fin[256], s_nxt[256];
     __shared__ uint32_t s_nf, s_nn, s_bf, s_bn;
-    const uint32_t s = blockIdx.x;
+    const uint32_t ns = dev_count(nseg, dn_seg);
+    for (uint32_t s = blockIdx.x; s < ns; s += gridDim.x) {
+    __syncthreads();  // the previous segment's children are copied out
     const Seg sg = segs[s];
     const uint32_t tb = tile_base[s], nt = (sg.size + kTileN - 1) / kTileN;
     const SplitRule rule = split_rule(sg, cap);
@@ -505,6 +518,7 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
         if (bn + i < next_cap) next[bn + i] = s_nxt[i];
         else atomicOr(overflow, 1u);
     }
+    }
 }
 
 template <int W>
@@ -521,14 +535,14 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
     __shared__ uint32_t s_tmp[NW];
     __shared__ uint8_t s_dg[kTileN];
 
-    const uint32_t t = xcd_tile(a.ntiles);
-    if (t >= a.ntiles) return;
+    FOR_LEVEL_TILES(a, t) {
     const uint32_t s = a.tile_seg[t];
-    if (skip[s]) return;  // uniform per block
+    if (skip[s]) continue;  // uniform per block
     const Seg sg = a.segs[s];
     const uint32_t tb = a.tile_base[s], nt = (sg.size + kTileN - 1) / kTileN, tl = t - tb;
     const uint32_t ib = seg_buf(sg), ob = ib ^ 1u;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __syncthreads();  // the previous tile's records are written out
     for (int i = tid; i < NW * 256; i += kTileT) (&s_wcnt[0][0])[i] = 0u;
     __syncthreads();
     const uint32_t r0 = tl * kTileN, rn = min(sg.size - r0, (uint32_t)kTileN);
@@ -597,6 +611,7 @@ __global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uin
             a.val[ob][g] = s_val[i];
         }
     }
+    }
     (void)scan;
 }
 
@@ -614,6 +629,7 @@ struct FinishArgs {
     double *cnum, *cscore;
     uint32_t *cnt;              // per final segment: candidates written
     uint32_t nfinal;
+    const uint32_t *dn_final;   // device: final segments (nfinal is then a bound; optional)
     PsiSet psi;                 // input determinants (exclusion)
     int tab_in_lds;             // staged in LDS: 1 J, J-K, h_pp; 2 J and the binomials; 3 the binomials; 0 none
 };
@@ -1169,7 +1185,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (nj) J = tab;
         st.binom = bt;
     }
-    for (uint32_t sidx = blockIdx.x; sidx < f.nfinal; sidx += gridDim.x) {
+    const uint32_t nf = dev_count(f.nfinal, f.dn_final);
+    for (uint32_t sidx = blockIdx.x; sidx < nf; sidx += gridDim.x) {
         __syncthreads();
         finish_segment<W, CAP, NT>(f, st, S, J, X, hd, sidx);
     }
@@ -1177,20 +1194,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ---------------------------------------------------------------- collect
 __global__ __launch_bounds__(256) void k_final_keys_start(const Seg *__restrict__ finals, uint32_t nf,
-                                                          uint64_t *__restrict__ key, uint32_t *__restrict__ idx)
+                                                          uint64_t *__restrict__ key, uint32_t *__restrict__ idx,
+                                                          const uint32_t *dn)
 {
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= nf) return;
+    if (j >= dev_count(nf, dn)) return;
     key[j] = finals[j].start;
     idx[j] = j;
 }
 
 __global__ __launch_bounds__(256) void k_gather_counts(const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ cnt, uint32_t nf,
-                                                       uint32_t *__restrict__ out)
+                                                       uint32_t *__restrict__ out, const uint32_t *dn)
 {
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j < nf) out[j] = cnt[order[j]];
+    if (j < dev_count(nf, dn)) out[j] = cnt[order[j]];
 }
 
 // one block per final segment (in key order): copy its candidates to the pool
@@ -1202,8 +1220,10 @@ __global__ __launch_bounds__(256) void k_collect(const Seg *__restrict__ finals,
                                                  const uint64_t *__restrict__ chi, const double *__restrict__ cnum,
                                                  const double *__restrict__ cscore, uint64_t *__restrict__ plo,
                                                  uint64_t *__restrict__ phi, double *__restrict__ pnum,
-                                                 double *__restrict__ pscore, size_t base, size_t cap)
+                                                 double *__restrict__ pscore, size_t base, size_t cap,
+                                                 const uint32_t *dn)
 {
+    nf = dev_count(nf, dn);
     for (uint32_t j = blockIdx.x; j < nf; j += gridDim.x) {
         const Seg sg = finals[order[j]];
         const uint32_t c = cnt_sorted[j];
@@ -1228,17 +1248,20 @@ __global__ __launch_bounds__(256) void k_class_segs(const uint64_t *__restrict__
                                                     uint32_t nq, const uint32_t *__restrict__ offsets,
                                                     const uint32_t *__restrict__ total, int n, uint32_t cap,
                                                     Seg *__restrict__ large, uint32_t *__restrict__ nlarge,
-                                                    Seg *__restrict__ finals, uint32_t *__restrict__ nfinal)
+                                                    Seg *__restrict__ finals, uint32_t *__restrict__ nfinal,
+                                                    uint32_t nrec)
 {
     // class bounds and masks staged in LDS in parallel; one thread then walks
-    // the classes (the counters start at zero and this kernel is their only writer)
+    // the classes (the counters start at zero and this kernel is their only
+    // writer).  Bounds are clamped to the record buffer (nrec records): counts
+    // that overrun it (inputs that fail validation) cannot send a segment past it.
     __shared__ uint32_t s_start[kMaxClassSegs + 1];
     __shared__ uint64_t s_cls[kMaxClassSegs];
     for (uint32_t c = threadIdx.x; c < nc; c += 256) {
-        s_start[c] = offsets[(size_t)c * nq];
+        s_start[c] = min(offsets[(size_t)c * nq], nrec);
         s_cls[c] = cls[c0 + c];
     }
-    if (threadIdx.x == 0) s_start[nc] = *total;
+    if (threadIdx.x == 0) s_start[nc] = min(*total, nrec);
     __syncthreads();
     if (threadIdx.x != 0) return;
     uint32_t nf = 0, nl = 0;
@@ -1381,7 +1404,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     ASCI_HIP(hipMemsetAsync(ctr, 0, 8 * sizeof(uint32_t), s));
     require(b.nc <= kMaxClassSegs, ASCI_EINVAL, "too many classes in one batch");
     k_class_segs<<<1, 256, 0, s>>>(b.cls, b.c0, b.nc, b.nq, b.offsets, b.total, b.n, (uint32_t)CAP, lv[0], ctr + 1,
-                                   finals, ctr);
+                                   finals, ctr, (uint32_t)std::min<size_t>(P, 0xFFFFFFFFu));
     ASCI_LAUNCH_CHECK();
     ASCI_HIP(hipMemcpyAsync(hcnt, ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     ASCI_HIP(hipStreamSynchronize(s));
@@ -1399,7 +1422,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         uint32_t *tbase = ar.take<uint32_t>(nlarge + 1);
         uint32_t *skip = ar.take<uint32_t>(nlarge + 1);
         uint32_t *d_ntiles = ar.take<uint32_t>(4);
-        k_seg_tiles<<<(nlarge + 256) / 256, 256, 0, s>>>(segs, nlarge, ntile, skip, nnext);
+        k_seg_tiles<<<(nlarge + 256) / 256, 256, 0, s>>>(segs, nlarge, ntile, skip, nnext, nullptr);
         ASCI_LAUNCH_CHECK();
         scan_u32(ntile, tbase, nlarge, d_ntiles, ar, s, prof);
         ASCI_HIP(hipMemcpyAsync(hcnt + 4, d_ntiles, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -1412,15 +1435,15 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         uint64_t *spl_hi = W == 2 ? ar.take<uint64_t>((size_t)nlarge * (kMaxSplit - 1)) : nullptr;
         unsigned long long *kor = ar.take<unsigned long long>(2 * (size_t)nlarge);
         unsigned long long *kand = ar.take<unsigned long long>(2 * (size_t)nlarge);
-        k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg, kor, kand);
+        k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg, kor, kand, nullptr);
         ASCI_LAUNCH_CHECK();
         {
             ProfScope ps(prof, "split_sample", 0.0, s);
             const KeyBufs kb{{b.klo[0], b.klo[1]}, {b.khi[0], b.khi[1]}};
             // class-sized segments of the first level sort up to 4096 samples:
             // more threads per sort; later levels sort a few hundred
-            if (lev == 0) k_seg_splitters<W, 1024><<<nlarge, 1024, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi);
-            else k_seg_splitters<W, 256><<<nlarge, 256, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi);
+            if (lev == 0) k_seg_splitters<W, 1024><<<nlarge, 1024, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi, nlarge, nullptr);
+            else k_seg_splitters<W, 256><<<nlarge, 256, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi, nlarge, nullptr);
             ASCI_LAUNCH_CHECK();
         }
         SplitArgs sa;
@@ -1450,7 +1473,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         }
         scan_u32(hist, hscan, (size_t)ntiles * 256, nullptr, ar, s, prof);
         k_split_children<W><<<nlarge, 256, 0, s>>>(segs, nlarge, tbase, hscan, (uint32_t)CAP, skip, finals, ctr,
-                                                   finals_cap, next, nnext, level_cap, ctr + 3, kor, kand, b.n);
+                                                   finals_cap, next, nnext, level_cap, ctr + 3, kor, kand, b.n, nullptr);
         ASCI_LAUNCH_CHECK();
         sa.hist = hscan;
         {
@@ -1493,6 +1516,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         fa.cscore = b.cscore;
         fa.cnt = cnt;
         fa.nfinal = nf;
+        fa.dn_final = nullptr;
         fa.psi = b.psi;
         // eight records per thread
         b.prof = prof;
@@ -1509,12 +1533,12 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
     uint64_t *nohi[2] = {nullptr, nullptr};
     int r = 0;
     if (nf) {
-        k_final_keys_start<<<(nf + 255) / 256, 256, 0, s>>>(finals, nf, sk[0], si[0]);
+        k_final_keys_start<<<(nf + 255) / 256, 256, 0, s>>>(finals, nf, sk[0], si[0], nullptr);
         ASCI_LAUNCH_CHECK();
         std::vector<Digit> dg;
         for (int sh = 0; sh < 32; sh += 8) dg.push_back({0, sh});
         r = radix_sort<uint32_t>(sk, nohi, si, nf, 1, dg, ar, s, nullptr);
-        k_gather_counts<<<(nf + 255) / 256, 256, 0, s>>>(si[r], cnt, nf, cs);
+        k_gather_counts<<<(nf + 255) / 256, 256, 0, s>>>(si[r], cnt, nf, cs, nullptr);
         ASCI_LAUNCH_CHECK();
     }
     scan_u32(cs, co, nf, d_v, ar, s, nullptr);
@@ -1541,7 +1565,7 @@ int bucket_collect(BucketArgs &b, hipStream_t s, Profiler *prof)
     ProfScope ps(prof, "collect", b.defer_v ? 0.0 : (8.0 * W + 8.0) * 2.0 * b.V, s);
     k_collect<W><<<std::min<uint32_t>(b.nfinal, 65536u), 256, 0, s>>>((const Seg *)b.finals, b.nfinal, b.order, b.cnt_sorted, b.off, b.clo, b.chi, b.cnum,
                                          b.cscore, b.pool_lo, b.pool_hi, b.pool_num, b.pool_score, b.pool_base,
-                                         b.pool_cap);
+                                         b.pool_cap, nullptr);
     ASCI_LAUNCH_CHECK();
     return ps.tok;
 }
@@ -1601,7 +1625,191 @@ double bucket_pt2(BucketArgs &b, Arena &ar, hipStream_t s, HostStage &hs)
     return *h;
 }
 
+// ---------------------------------------------------------------- device-driven variant
+constexpr int kDevLevels = 8;  // split levels run when no count is read back
+
+__global__ __launch_bounds__(64) void k_times256(const uint32_t *__restrict__ n, uint32_t *__restrict__ out)
+{
+    if (threadIdx.x == 0) *out = *n * 256u;
+}
+
+// after the last level: segments still too large for the finish, or a list
+// that overflowed its capacity, fail the call
+__global__ __launch_bounds__(64) void k_levels_done(const uint32_t *__restrict__ ctr, int last_parity,
+                                                    uint32_t *__restrict__ stat)
+{
+    if (threadIdx.x != 0) return;
+    if (ctr[1 + last_parity] != 0u || ctr[3] != 0u) atomicOr(stat, kStatSplit);
+}
+
+template <int W>
+void bucket_accumulate_dev(BucketArgs &b, Arena &ar, hipStream_t s, uint32_t *d_stat)
+{
+    const int CAP = b.finish_cap >= 4096 ? 4096 : (b.finish_cap >= 2048 ? 2048 : 1024);
+    const size_t P = b.P;
+    const uint32_t finals_cap = (uint32_t)std::min<size_t>(b.nc + P / 8 + 65536, 0xFFFFFFF0u);
+    const uint32_t level_cap = (uint32_t)(P / CAP + b.nc + 16);
+    const uint32_t max_tiles = (uint32_t)((P + kTileN - 1) / kTileN + level_cap);
+    Seg *finals = ar.take<Seg>(finals_cap);
+    Seg *lv[2] = {ar.take<Seg>(level_cap), ar.take<Seg>(level_cap)};
+    uint32_t *ctr = ar.take<uint32_t>(8);  // 0: finals, 1/2: large segments per level parity, 3: overflow
+    require(b.nc <= kMaxClassSegs, ASCI_EINVAL, "too many classes in one batch");
+    fill_u32(ctr, 8, 0u, s);
+    k_class_segs<<<1, 256, 0, s>>>(b.cls, b.c0, b.nc, b.nq, b.offsets, b.total, b.n, (uint32_t)CAP, lv[0], ctr + 1,
+                                   finals, ctr, (uint32_t)std::min<size_t>(P, 0xFFFFFFFFu));
+    ASCI_LAUNCH_CHECK();
+    uint8_t *dig = ar.take<uint8_t>(P + 1);
+    uint32_t *ntile = ar.take<uint32_t>((size_t)level_cap + 1);
+    uint32_t *tbase = ar.take<uint32_t>((size_t)level_cap + 1);
+    uint32_t *skip = ar.take<uint32_t>((size_t)level_cap + 1);
+    uint32_t *d_ntiles = ar.take<uint32_t>(4);
+    uint32_t *tseg = ar.take<uint32_t>((size_t)max_tiles + 1);
+    uint32_t *hist = ar.take<uint32_t>((size_t)max_tiles * 256 + 1);
+    uint32_t *hscan = ar.take<uint32_t>((size_t)max_tiles * 256 + 1);
+    uint64_t *spl_lo = ar.take<uint64_t>((size_t)level_cap * (kMaxSplit - 1));
+    uint64_t *spl_hi = W == 2 ? ar.take<uint64_t>((size_t)level_cap * (kMaxSplit - 1)) : nullptr;
+    unsigned long long *kor = ar.take<unsigned long long>(2 * (size_t)level_cap);
+    unsigned long long *kand = ar.take<unsigned long long>(2 * (size_t)level_cap);
+    // launch shapes: per-segment kernels stride over the level's segments, tile
+    // kernels over its tiles (eight XCD groups of workgroups)
+    const unsigned g_seg = std::min<uint32_t>(level_cap, 2048u);
+    const unsigned g_seg256 = std::min<uint32_t>((level_cap + 256) / 256, 1024u);
+    const unsigned g_tiles = 8u * std::min<uint32_t>((max_tiles + 7) / 8, 256u);
+    const size_t mark = ar.used();
+    const KeyBufs kb{{b.klo[0], b.klo[1]}, {b.khi[0], b.khi[1]}};
+    for (int lev = 0; lev < kDevLevels; ++lev) {
+        ar.reset();
+        (void)ar.take<char>(mark);
+        Seg *segs = lv[lev & 1], *next = lv[(lev & 1) ^ 1];
+        const uint32_t *dn_seg = ctr + 1 + (lev & 1);
+        uint32_t *nnext = ctr + 1 + ((lev & 1) ^ 1);
+        k_seg_tiles<<<g_seg256, 256, 0, s>>>(segs, level_cap, ntile, skip, nnext, dn_seg);
+        ASCI_LAUNCH_CHECK();
+        scan_u32(ntile, tbase, level_cap, d_ntiles, ar, s, nullptr, dn_seg);
+        k_seg_expand<<<g_seg256, 256, 0, s>>>(segs, level_cap, tbase, tseg, kor, kand, dn_seg);
+        ASCI_LAUNCH_CHECK();
+        if (lev == 0) k_seg_splitters<W, 1024><<<g_seg, 1024, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi, level_cap, dn_seg);
+        else k_seg_splitters<W, 256><<<g_seg, 256, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi, level_cap, dn_seg);
+        ASCI_LAUNCH_CHECK();
+        SplitArgs sa;
+        sa.segs = segs;
+        sa.nseg = level_cap;
+        sa.tile_base = tbase;
+        sa.tile_seg = tseg;
+        sa.ntiles = max_tiles;
+        sa.hist = hist;
+        sa.klo[0] = b.klo[0];
+        sa.klo[1] = b.klo[1];
+        sa.khi[0] = b.khi[0];
+        sa.khi[1] = b.khi[1];
+        sa.val[0] = b.val[0];
+        sa.val[1] = b.val[1];
+        sa.n = b.n;
+        sa.cap = (uint32_t)CAP;
+        sa.spl_lo = spl_lo;
+        sa.spl_hi = spl_hi;
+        sa.kor = kor;
+        sa.kand = kand;
+        sa.dig = dig;
+        sa.dn_seg = dn_seg;
+        sa.dn_tiles = d_ntiles;
+        k_split_hist<W><<<g_tiles, kHistT, 0, s>>>(sa);
+        ASCI_LAUNCH_CHECK();
+        k_times256<<<1, 64, 0, s>>>(d_ntiles, d_ntiles + 1);
+        ASCI_LAUNCH_CHECK();
+        scan_u32(hist, hscan, (size_t)max_tiles * 256, nullptr, ar, s, nullptr, d_ntiles + 1);
+        k_split_children<W><<<g_seg, 256, 0, s>>>(segs, level_cap, tbase, hscan, (uint32_t)CAP, skip, finals, ctr,
+                                                  finals_cap, next, nnext, level_cap, ctr + 3, kor, kand, b.n, dn_seg);
+        ASCI_LAUNCH_CHECK();
+        sa.hist = hscan;
+        k_split_scatter<W><<<g_tiles, kTileT, 0, s>>>(sa, hscan, skip);
+        ASCI_LAUNCH_CHECK();
+    }
+    k_levels_done<<<1, 64, 0, s>>>(ctr, kDevLevels & 1, d_stat);
+    ASCI_LAUNCH_CHECK();
+    ar.reset();
+    (void)ar.take<char>(mark);
+    uint32_t *cnt = ar.take<uint32_t>((size_t)finals_cap + 1);
+    FinishArgs fa;
+    fa.finals = finals;
+    fa.klo[0] = b.klo[0];
+    fa.klo[1] = b.klo[1];
+    fa.khi[0] = b.khi[0];
+    fa.khi[1] = b.khi[1];
+    fa.val[0] = b.val[0];
+    fa.val[1] = b.val[1];
+    fa.n = b.n;
+    fa.jk = b.jk;
+    fa.h = b.h;
+    fa.st = b.st;
+    fa.thr = nullptr;
+    fa.ecore = b.ecore;
+    fa.E0 = b.E0;
+    fa.eps = b.eps;
+    fa.clo = b.clo;
+    fa.chi = b.chi;
+    fa.cnum = b.cnum;
+    fa.cscore = b.cscore;
+    fa.cnt = cnt;
+    fa.nfinal = finals_cap;
+    fa.dn_final = ctr;
+    fa.psi = b.psi;
+    if (CAP == 4096) (void)launch_finish<W, 4096, 512>(fa, b, finals_cap, s, nullptr);
+    else if (CAP == 2048) (void)launch_finish<W, 2048, 256>(fa, b, finals_cap, s, nullptr);
+    else (void)launch_finish<W, 1024, 128>(fa, b, finals_cap, s, nullptr);
+    // candidates in key order: final segments by start, counts scanned
+    uint64_t *sk[2] = {ar.take<uint64_t>((size_t)finals_cap + 1), ar.take<uint64_t>((size_t)finals_cap + 1)};
+    uint32_t *si[2] = {ar.take<uint32_t>((size_t)finals_cap + 1), ar.take<uint32_t>((size_t)finals_cap + 1)};
+    uint32_t *cs = ar.take<uint32_t>((size_t)finals_cap + 1);
+    uint32_t *co = ar.take<uint32_t>((size_t)finals_cap + 1);
+    uint32_t *d_v = ar.take<uint32_t>(4);
+    uint64_t *nohi[2] = {nullptr, nullptr};
+    const unsigned gf = std::min<uint32_t>((finals_cap + 255) / 256, 65535u);
+    k_final_keys_start<<<(finals_cap + 255) / 256, 256, 0, s>>>(finals, finals_cap, sk[0], si[0], ctr);
+    ASCI_LAUNCH_CHECK();
+    std::vector<Digit> dg;
+    for (int sh = 0; sh < 32; sh += 8) dg.push_back({0, sh});
+    const int r = radix_sort<uint32_t>(sk, nohi, si, finals_cap, 1, dg, ar, s, nullptr, ctr);
+    k_gather_counts<<<(finals_cap + 255) / 256, 256, 0, s>>>(si[r], cnt, finals_cap, cs, ctr);
+    ASCI_LAUNCH_CHECK();
+    scan_u32(cs, co, finals_cap, d_v, ar, s, nullptr, ctr);
+    (void)gf;
+    b.nfinal = finals_cap;  // a bound: the count is *dn_final
+    b.dn_final = ctr;
+    b.dn_V = d_v;
+    b.V = (uint32_t)std::min<size_t>(P, 0xFFFFFFFFu);  // a bound: the count is *dn_V
+    b.order = si[r];
+    b.cnt_sorted = cs;
+    b.off = co;
+    b.finals = finals;
+}
+
+// the collect of the device-driven variant: counts read on the device
+template <int W>
+void bucket_collect_dev(BucketArgs &b, hipStream_t s)
+{
+    k_collect<W><<<std::min<uint32_t>(b.nfinal, 65536u), 256, 0, s>>>(
+        (const Seg *)b.finals, b.nfinal, b.order, b.cnt_sorted, b.off, b.clo, b.chi, b.cnum, b.cscore, b.pool_lo,
+        b.pool_hi, b.pool_num, b.pool_score, b.pool_base, b.pool_cap, b.dn_final);
+    ASCI_LAUNCH_CHECK();
+}
+
+template void bucket_accumulate_dev<1>(BucketArgs &, Arena &, hipStream_t, uint32_t *);
+template void bucket_accumulate_dev<2>(BucketArgs &, Arena &, hipStream_t, uint32_t *);
+template void bucket_collect_dev<1>(BucketArgs &, hipStream_t);
+template void bucket_collect_dev<2>(BucketArgs &, hipStream_t);
+
 void bucket_fault_clear(hipStream_t s) { fault_clear(s); }
+void bucket_fault_reset_dev(hipStream_t s)
+{
+    k_fault_reset<<<1, 64, 0, s>>>();
+    ASCI_LAUNCH_CHECK();
+}
+void bucket_fault_take_dev(uint32_t *stat, uint32_t bit, hipStream_t s)
+{
+    k_fault_take<<<1, 64, 0, s>>>(stat, bit);
+    ASCI_LAUNCH_CHECK();
+}
 void bucket_fault_fetch(unsigned int *dst, hipStream_t s) { fault_fetch(dst, s); }
 
 template void bucket_accumulate<1>(BucketArgs &, Arena &, hipStream_t, Profiler *, HostStage &);

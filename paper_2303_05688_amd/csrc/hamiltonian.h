@@ -53,6 +53,20 @@ static inline void fault_fetch(unsigned int *dst, hipStream_t s)
     ASCI_HIP(hipMemcpyAsync(dst, p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
 }
 
+// The same word handled on the device (no host readback): cleared by a kernel
+// (a fill that a captured graph replays correctly), and folded into a status
+// word at the end of a call.
+namespace {
+__global__ __launch_bounds__(64) void k_fault_reset()
+{
+    if (threadIdx.x == 0) atomicAnd(&g_fault, 0u);
+}
+__global__ __launch_bounds__(64) void k_fault_take(uint32_t *stat, uint32_t bit)
+{
+    if (threadIdx.x == 0 && atomicOr(&g_fault, 0u) != 0u) atomicOr(stat, bit);
+}
+}  // namespace
+
 // after the stream has been synchronised: fail on any recorded fault
 static inline void fault_check(unsigned int word, const char *where)
 {

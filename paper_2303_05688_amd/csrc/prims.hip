@@ -14,6 +14,9 @@ constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // 4096
 static_assert(kTile == kScanTile, "scan tile");
 
+// a host bound on a count, tightened by the count on the device when given
+__device__ __forceinline__ size_t dev_n(size_t n, const uint32_t *dn) { return dn ? min(n, (size_t)*dn) : n; }
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
     const int lane = threadIdx.x & 63;
@@ -47,9 +50,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp,
 
 // ---------------------------------------------------------------- scan
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__restrict__ in, size_t n,
-                                                          uint32_t *__restrict__ partial)
+                                                          uint32_t *__restrict__ partial, const uint32_t *dn)
 {
     __shared__ uint32_t s_tmp[kWaves];
+    n = dev_n(n, dn);
     const size_t base = (size_t)blockIdx.x * kTile;
     uint32_t s = 0;
     for (int i = threadIdx.x; i < kTile; i += kThreads) {
@@ -81,9 +85,10 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t *__restrict__ p
 // chunks of 4096 scanned in turn with a running carry
 constexpr size_t kScanSmall = 65536;
 __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_t *out, uint32_t n,
-                                                     uint32_t *__restrict__ d_total)
+                                                     uint32_t *__restrict__ d_total, const uint32_t *dn)
 {
     __shared__ uint32_t s_tmp[16];
+    n = (uint32_t)dev_n(n, dn);
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < n; c0 += 4096) {
         const uint32_t j0 = c0 + threadIdx.x * 4u;
@@ -106,9 +111,10 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *in, uint32_t *out, size_t n,
-                                                        const uint32_t *__restrict__ partial)
+                                                        const uint32_t *__restrict__ partial, const uint32_t *dn)
 {
     __shared__ uint32_t s_tmp[kWaves];
+    n = dev_n(n, dn);
     const size_t base = (size_t)blockIdx.x * kTile + (size_t)threadIdx.x * kItems;
     uint32_t v[kItems];
     uint32_t s = 0;
@@ -142,9 +148,11 @@ template <int W, int IT>
 __global__ __launch_bounds__(kThreads) void k_rs_hist(const uint64_t *__restrict__ klo,
                                                       const uint64_t *__restrict__ khi, size_t n,
                                                       int word, int shift,
-                                                      uint32_t *__restrict__ hist, uint32_t nblocks)
+                                                      uint32_t *__restrict__ hist, uint32_t nblocks,
+                                                      const uint32_t *dn)
 {
     constexpr int TILE = kThreads * IT;
+    n = dev_n(n, dn);
     __shared__ uint32_t h[kWaves][256];
     const int tid = threadIdx.x, w = tid >> 6;
     for (int i = tid; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0u;
@@ -171,9 +179,10 @@ template <int W, typename V, int IT>
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(
     const uint64_t *__restrict__ ilo, const uint64_t *__restrict__ ihi, const V *__restrict__ ival,
     uint64_t *__restrict__ olo, uint64_t *__restrict__ ohi, V *__restrict__ oval, size_t n, int word,
-    int shift, const uint32_t *__restrict__ hist, uint32_t nblocks)
+    int shift, const uint32_t *__restrict__ hist, uint32_t nblocks, const uint32_t *dn)
 {
     constexpr int kTile = kThreads * IT, kItems = IT;
+    n = dev_n(n, dn);
     __shared__ uint64_t s_lo[kTile];
     __shared__ uint64_t s_hi[W == 2 ? kTile : 1];
     __shared__ V s_val[kTile];
@@ -184,6 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const size_t tile0 = (size_t)blockIdx.x * kTile;
+    if (tile0 >= n) return;  // uniform: a tile past a device-side count
     for (int i = tid; i < kWaves * 256; i += kThreads) (&s_wcnt[0][0])[i] = 0u;
     __syncthreads();
 
@@ -245,20 +255,21 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(
 }
 
 // ---------------------------------------------------------------- radix select
-__global__ __launch_bounds__(kThreads) void k_sel_init(SelectState *st, uint64_t k)
+__global__ __launch_bounds__(kThreads) void k_sel_init(SelectState *st, uint64_t k, const uint32_t *dk)
 {
     if (threadIdx.x == 0) {
         st->prefix = 0ull;
         st->mask = 0ull;
-        st->krem = k;
+        st->krem = dk ? min(k, (uint64_t)*dk) : k;
     }
     st->hist[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(kThreads) void k_sel_hist(const double *__restrict__ score, size_t n,
-                                                       int shift, SelectState *st)
+                                                       int shift, SelectState *st, const uint32_t *dn)
 {
     __shared__ uint32_t h[256];
+    n = dev_n(n, dn);
     h[threadIdx.x] = 0u;
     __syncthreads();
     const uint64_t prefix = st->prefix, mask = st->mask;
@@ -347,16 +358,31 @@ __global__ __launch_bounds__(64) void k_sel_pick(SelectState *st, int shift)
 
 }  // namespace
 
+__global__ __launch_bounds__(64) void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v)
+{
+    for (uint32_t i = blockIdx.x * 64 + threadIdx.x; i < n; i += gridDim.x * 64) p[i] = v;
+}
+
+void fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s)
+{
+    if (n == 0) return;
+    k_fill_u32<<<(unsigned)std::min<size_t>((n + 63) / 64, 4096), 64, 0, s>>>(p, (uint32_t)n, v);
+    ASCI_LAUNCH_CHECK();
+}
+
 void scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, Arena &ar, hipStream_t s,
-              Profiler *prof)
+              Profiler *prof, const uint32_t *dn)
 {
     if (n == 0) {
-        if (d_total) ASCI_HIP(hipMemsetAsync(d_total, 0, sizeof(uint32_t), s));
+        if (d_total) {
+            k_fill_u32<<<1, 64, 0, s>>>(d_total, 1, 0u);
+            ASCI_LAUNCH_CHECK();
+        }
         return;
     }
     ProfScope ps(prof, "scan", 8.0 * n, s);
     if (n <= kScanSmall) {
-        k_scan_small<<<1, 1024, 0, s>>>(in, out, (uint32_t)n, d_total);
+        k_scan_small<<<1, 1024, 0, s>>>(in, out, (uint32_t)n, d_total, dn);
         ASCI_LAUNCH_CHECK();
         return;
     }
@@ -364,18 +390,18 @@ void scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *d_total, Ar
     require(nb <= (1u << 26), ASCI_EINVAL, "scan too long");
     size_t mark = ar.used();
     uint32_t *partial = ar.take<uint32_t>(nb);
-    k_scan_reduce<<<(unsigned)nb, kThreads, 0, s>>>(in, n, partial);
+    k_scan_reduce<<<(unsigned)nb, kThreads, 0, s>>>(in, n, partial, dn);
     ASCI_LAUNCH_CHECK();
     k_scan_partials<<<1, 1024, 0, s>>>(partial, (uint32_t)nb, d_total);
     ASCI_LAUNCH_CHECK();
-    k_scan_down<<<(unsigned)nb, kThreads, 0, s>>>(in, out, n, partial);
+    k_scan_down<<<(unsigned)nb, kThreads, 0, s>>>(in, out, n, partial, dn);
     ASCI_LAUNCH_CHECK();
     (void)mark;
 }
 
 template <typename V>
 int radix_sort(uint64_t *keys_lo[2], uint64_t *keys_hi[2], V *vals[2], size_t n, int words,
-               const std::vector<Digit> &digits, Arena &ar, hipStream_t s, Profiler *prof)
+               const std::vector<Digit> &digits, Arena &ar, hipStream_t s, Profiler *prof, const uint32_t *dn)
 {
     int cur = 0;
     if (n <= 1 || digits.empty()) return cur;
@@ -399,10 +425,10 @@ int radix_sort(uint64_t *keys_lo[2], uint64_t *keys_hi[2], V *vals[2], size_t n,
             constexpr int I = decltype(itc)::value;
             if (words == 2)
                 k_rs_hist<2, I><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], keys_hi[cur], n, d.word, d.shift,
-                                                                  hist, (uint32_t)nb);
+                                                                  hist, (uint32_t)nb, dn);
             else
                 k_rs_hist<1, I><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], nullptr, n, 0, d.shift, hist,
-                                                                  (uint32_t)nb);
+                                                                  (uint32_t)nb, dn);
         };
         if (it == 2) hist_k(std::integral_constant<int, 2>{});
         else if (it == 4) hist_k(std::integral_constant<int, 4>{});
@@ -410,18 +436,18 @@ int radix_sort(uint64_t *keys_lo[2], uint64_t *keys_hi[2], V *vals[2], size_t n,
         else hist_k(std::integral_constant<int, 16>{});
         ASCI_LAUNCH_CHECK();
         }
-        scan_u32(hist, hist, nb * 256, nullptr, ar, s, prof);
+        scan_u32(hist, hist, nb * 256, nullptr, ar, s, prof);  // every block writes its column
         ProfScope ps(prof, "rs_scatter", 2.0 * rb * n, s);
         auto scat_k = [&](auto itc) {
             constexpr int I = decltype(itc)::value;
             if (words == 2)
                 k_rs_scatter<2, V, I><<<(unsigned)nb, kThreads, 0, s>>>(
                     keys_lo[cur], keys_hi[cur], vals[cur], keys_lo[nxt], keys_hi[nxt], vals[nxt], n, d.word,
-                    d.shift, hist, (uint32_t)nb);
+                    d.shift, hist, (uint32_t)nb, dn);
             else
                 k_rs_scatter<1, V, I><<<(unsigned)nb, kThreads, 0, s>>>(keys_lo[cur], nullptr, vals[cur],
                                                                         keys_lo[nxt], nullptr, vals[nxt], n, 0,
-                                                                        d.shift, hist, (uint32_t)nb);
+                                                                        d.shift, hist, (uint32_t)nb, dn);
         };
         if (it == 2) scat_k(std::integral_constant<int, 2>{});
         else if (it == 4) scat_k(std::integral_constant<int, 4>{});
@@ -434,9 +460,9 @@ int radix_sort(uint64_t *keys_lo[2], uint64_t *keys_hi[2], V *vals[2], size_t n,
 }
 
 template int radix_sort<double>(uint64_t *[2], uint64_t *[2], double *[2], size_t, int,
-                                const std::vector<Digit> &, Arena &, hipStream_t, Profiler *);
+                                const std::vector<Digit> &, Arena &, hipStream_t, Profiler *, const uint32_t *);
 template int radix_sort<uint32_t>(uint64_t *[2], uint64_t *[2], uint32_t *[2], size_t, int,
-                                  const std::vector<Digit> &, Arena &, hipStream_t, Profiler *);
+                                  const std::vector<Digit> &, Arena &, hipStream_t, Profiler *, const uint32_t *);
 
 Profiler::~Profiler()
 {
@@ -504,11 +530,12 @@ void Profiler::reset()
 }
 
 void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_state, hipStream_t s,
-                      Profiler *prof, const SelectWork *work)
+                      Profiler *prof, const SelectWork *work, const uint32_t *dn, const uint32_t *dk)
 {
     require(k >= 1 && k <= n, ASCI_EINVAL, "radix select: k out of range");
+    if (dn) work = nullptr;  // the compaction reads its count back on the host
     size_t nb = (n + kTile - 1) / kTile;
-    k_sel_init<<<1, kThreads, 0, s>>>(d_state, k);
+    k_sel_init<<<1, kThreads, 0, s>>>(d_state, k, dk);
     ASCI_LAUNCH_CHECK();
     const double *x = score;
     for (int shift = 56; shift >= 0; shift -= 8) {
@@ -529,7 +556,7 @@ void radix_select_abs(const double *score, size_t n, uint64_t k, SelectState *d_
         }
         if (nb) {
             ProfScope ps(prof, "select_hist", 8.0 * n, s);
-            k_sel_hist<<<(unsigned)std::min<size_t>(nb, 2048), kThreads, 0, s>>>(x, n, shift, d_state);
+            k_sel_hist<<<(unsigned)std::min<size_t>(nb, 2048), kThreads, 0, s>>>(x, n, shift, d_state, dn);
             ASCI_LAUNCH_CHECK();
         }
         k_sel_pick<<<1, 64, 0, s>>>(d_state, shift);

@@ -418,10 +418,13 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, u
     return base + x - v;
 }
 
+__device__ __forceinline__ size_t dcount(size_t n, const uint32_t *dn) { return dn ? min(n, (size_t)*dn) : n; }
+
 __global__ __launch_bounds__(kBlock) void k_keep_count(const double *__restrict__ score, size_t n,
                                                        const SelectState *__restrict__ st, uint32_t *__restrict__ tgt,
-                                                       uint32_t *__restrict__ teq)
+                                                       uint32_t *__restrict__ teq, const uint32_t *dn)
 {
+    n = dcount(n, dn);
     __shared__ uint32_t s_w[kBlock / 64];
     const uint64_t t = st->prefix;
     const size_t base = (size_t)blockIdx.x * kKeepTile;
@@ -477,9 +480,10 @@ __global__ __launch_bounds__(kBlock) void k_keep_scatter(const uint64_t *__restr
                                                          const uint32_t *__restrict__ eqbase,
                                                          const uint32_t *__restrict__ keptbase,
                                                          uint64_t *__restrict__ olo, uint64_t *__restrict__ ohi,
-                                                         double *__restrict__ oscore, size_t cap)
+                                                         double *__restrict__ oscore, size_t cap, const uint32_t *dn)
 {
     constexpr int NW = kBlock / 64;
+    n = dcount(n, dn);
     __shared__ uint32_t s_w[NW];
     const uint64_t t = st->prefix, krem = st->krem;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -535,10 +539,11 @@ __global__ __launch_bounds__(kBlock) void k_keep_scatter(const uint64_t *__restr
 
 // sort key for the final order: ~|score| bits so that ascending = descending |score|
 __global__ __launch_bounds__(kBlock) void k_final_keys(const double *__restrict__ score, size_t n,
-                                                       uint64_t *__restrict__ key, uint32_t *__restrict__ idx)
+                                                       uint64_t *__restrict__ key, uint32_t *__restrict__ idx,
+                                                       const uint32_t *dn)
 {
     const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
+    if (j >= dcount(n, dn)) return;
     key[j] = ~abs_order(score[j]);
     idx[j] = (uint32_t)j;
 }
@@ -549,10 +554,11 @@ __global__ __launch_bounds__(kBlock) void k_final_gather(const uint32_t *__restr
                                                          const uint64_t *__restrict__ shi,
                                                          const double *__restrict__ sscore, int norb,
                                                          uint64_t *__restrict__ out_dets,
-                                                         double *__restrict__ out_scores)
+                                                         double *__restrict__ out_scores, const uint32_t *dn,
+                                                         const uint32_t *stat)
 {
     const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
+    if (j >= dcount(n, dn) || (stat && *stat)) return;  // a failed call writes no output
     const uint32_t i = idx[j];
     const uint64_t lo = slo[i];
     const uint64_t nmask = (norb == 64) ? ~0ull : ((1ull << norb) - 1ull);
@@ -1176,12 +1182,12 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         const int o = pcur ^ 1;
         {
             ProfScope ps(prof, "keep", 2.0 * 8.0 * pool_n + (8.0 * W + 8.0) * 2.0 * keepk, s);
-            k_keep_count<<<ntile, kBlock, 0, s>>>(p_score[pcur], pool_n, d_sel, tgt, teq);
+            k_keep_count<<<ntile, kBlock, 0, s>>>(p_score[pcur], pool_n, d_sel, tgt, teq, nullptr);
             ASCI_LAUNCH_CHECK();
             k_keep_bases<<<1, 1024, 0, s>>>(tgt, teq, ntile, d_sel, eqb, kb);
             ASCI_LAUNCH_CHECK();
             k_keep_scatter<W><<<ntile, kBlock, 0, s>>>(p_lo[pcur], p_hi[pcur], p_score[pcur], pool_n, d_sel, eqb, kb,
-                                                       p_lo[o], p_hi[o], p_score[o], keepk);
+                                                       p_lo[o], p_hi[o], p_score[o], keepk, nullptr);
             ASCI_LAUNCH_CHECK();
         }
         pcur = o;
@@ -1362,16 +1368,371 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         uint64_t *fk[2] = {ar.take<uint64_t>(kk), ar.take<uint64_t>(kk)};
         uint32_t *fi[2] = {ar.take<uint32_t>(kk), ar.take<uint32_t>(kk)};
         uint64_t *nohi[2] = {nullptr, nullptr};
-        k_final_keys<<<grid_for(kk), kBlock, 0, s>>>(p_score[pcur], kk, fk[0], fi[0]);
+        k_final_keys<<<grid_for(kk), kBlock, 0, s>>>(p_score[pcur], kk, fk[0], fi[0], nullptr);
         ASCI_LAUNCH_CHECK();
         std::vector<Digit> fd;
         for (int sh = 0; sh < 64; sh += 8) fd.push_back({0, sh});
         const int rr = radix_sort<uint32_t>(fk, nohi, fi, kk, 1, fd, ar, s, prof);
         k_final_gather<W><<<grid_for(kk), kBlock, 0, s>>>(fi[rr], kk, p_lo[pcur], p_hi[pcur], p_score[pcur], n,
-                                                          out.out_dets, out.out_scores);
+                                                          out.out_dets, out.out_scores, nullptr, nullptr);
         ASCI_LAUNCH_CHECK();
     }
     finish();
+}
+
+// ---------------------------------------------------------------- the search with nothing read back
+namespace {
+
+// class c of level L in ascending mask order: the c-th L-subset (colex rank)
+// of the orbitals na - L .. n - 1, unranked in the combinatorial number system
+__global__ __launch_bounds__(kBlock) void k_class_masks(uint64_t *__restrict__ cls, uint32_t ncls, int n, int na,
+                                                        int L)
+{
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncls) return;
+    uint64_t m = 0;
+    uint32_t r = c;
+    int x = n - na + L - 1;
+    for (int j = L; j >= 1; --j) {
+        while (x > 0 && choose_le6((uint32_t)x, j) > r) --x;
+        m |= 1ull << (x + na - L);
+        r -= choose_le6((uint32_t)x, j);
+        --x;
+    }
+    cls[c] = m;
+}
+
+// C(p, k) for k < rows, p <= n, saturated at 2^32 - 1; rows past kmax are zero
+__global__ __launch_bounds__(64) void k_binom_table(uint32_t *__restrict__ out, int n, int kmax, int rows)
+{
+    if (threadIdx.x != 0) return;
+    // Pascal's rule row by row over p (64-bit, saturating)
+    uint64_t prev[65], cur[65];
+    for (int k = 0; k <= 64; ++k) prev[k] = k == 0 ? 1ull : 0ull;  // p = 0
+    for (int p = 0; p <= n; ++p) {
+        if (p > 0) {
+            cur[0] = 1ull;
+            for (int k = 1; k <= 64; ++k) {
+                const uint64_t v = prev[k - 1] + prev[k];
+                cur[k] = v > 0xFFFFFFFFull ? 0xFFFFFFFFull : v;
+            }
+            for (int k = 0; k <= 64; ++k) prev[k] = cur[k];
+        }
+        for (int k = 0; k < rows; ++k) out[(size_t)k * (n + 1) + p] = k <= kmax ? (uint32_t)prev[k] : 0u;
+    }
+}
+
+// *dst = min(k, *n)
+__global__ __launch_bounds__(64) void k_min_count(const uint32_t *__restrict__ n, uint64_t k, uint32_t *__restrict__ dst)
+{
+    if (threadIdx.x == 0) *dst = (uint32_t)min((uint64_t)*n, k);
+}
+
+// the validation flags of the setup arena folded into the status word
+__global__ __launch_bounds__(64) void k_stat_or(const unsigned int *__restrict__ err, uint32_t *__restrict__ stat)
+{
+    if (threadIdx.x == 0 && *err) atomicOr(stat, *err & (kStatInvalid | kStatDuplicate));
+}
+
+__global__ __launch_bounds__(64) void k_async_done(const uint32_t *__restrict__ stat, const uint32_t *__restrict__ kk,
+                                                   asci_async_result *__restrict__ res)
+{
+    if (threadIdx.x != 0) return;
+    const uint32_t f = *stat;
+    res->flags = (int32_t)f;
+    res->status = f == 0u ? ASCI_OK : ((f & (kStatInvalid | kStatDuplicate)) ? ASCI_EINVAL : ASCI_EDEVICE);
+    res->count = f == 0u ? (int64_t)*kk : 0;
+}
+
+}  // namespace
+
+template <int W>
+static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uint64_t *out_dets, double *out_scores,
+                             asci_async_result *d_result, hipStream_t s, bool plan_only)
+{
+    const int n = in.n, na = in.na, nb = in.nb;
+    const uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+    const BetaFactors bf = beta_factors(n, nb);
+    const size_t nd = (size_t)in.ndets;
+    const size_t nq = (in.opt.ncore > 0 && (size_t)in.opt.ncore < nd) ? (size_t)in.opt.ncore : nd;
+    const uint64_t P = search_pairs(in);
+    // the requested level, or the highest lower one whose classes fit one batch
+    // (the classes only partition the targets: the result is the same)
+    int L = std::min(in.opt.constraint_level, na);
+    while (L > 0 && choose_u64((uint64_t)(n - na + L), L) > kMaxBatchClasses) --L;
+    const uint64_t ncls = std::max<uint64_t>(choose_u64((uint64_t)(n - na + L), L), 1);
+    require(in.opt.split_pairs == 0, ASCI_EINVAL, "asynchronous search: split_pairs needs class totals on the host");
+    require(P >= 1 && P < (1ull << 31), ASCI_EINVAL, "asynchronous search: pair count outside one class batch");
+    const size_t rec_bytes = 2 * (8 * W + 8);
+    if (in.opt.pair_buffer_bytes > 0)
+        require(P <= (uint64_t)in.opt.pair_buffer_bytes / rec_bytes, ASCI_EINVAL,
+                "asynchronous search: the pair buffer does not hold every pair");
+    const size_t E = (size_t)ncls * nq;
+    require(E < (1ull << 31), ASCI_ENOMEM, "batch (class x core) matrix too large");
+    const size_t Pb = (size_t)P;
+    const size_t pool_cap = Pb + 1;
+    const uint64_t kh = std::min<uint64_t>((uint64_t)k, P);  // a bound on the selection's size
+
+    // ---- workspaces (allocated only when larger than what ctx holds)
+    Arena &su = ctx->setup;
+    su.reset();
+    su.reserve(setup_bytes(nd, nq, n, W));
+    su.reset();
+    Arena &ar = ctx->main;
+    ar.reset();
+    const SpinTablePlan pl = spin_table_plan(n, na, nb, P, ctx->spin_tables != 0);
+    // the bound of the one-batch search, the tables, and the collect's sort of
+    // final segments sized for their bound instead of their count
+    ar.reserve(main_bytes(E, Pb, pool_cap, (uint32_t)ncls, (size_t)kh, true, W, ctx->finish_cap) + pl.bytes + Pb / 4 +
+               ((size_t)16 << 20));
+    ar.reset();
+    if (plan_only) return;  // workspaces sized, nothing queued
+
+    // ---- inputs: validation (flags on the device), integral tables, psi set, core set, class masks
+    unsigned int *d_err = su.take<unsigned int>(16);
+    uint64_t *d_cls = su.take<uint64_t>(kMaxClasses);
+    (void)su.take<unsigned long long>(kMaxClasses);
+    (void)su.take<uint32_t>(kMaxClasses);
+    double *d_jk = su.take<double>((size_t)2 * n * n + n);
+    uint64_t *q_a = su.take<uint64_t>(nq), *q_b = su.take<uint64_t>(nq);
+    double *q_c = su.take<double>(nq);
+    uint32_t tsize = 1024;
+    while (tsize < 4 * nd) tsize <<= 1;
+    uint64_t *t_lo = su.take<uint64_t>(tsize), *t_hi = su.take<uint64_t>(tsize);
+    uint32_t *t_state = su.take<uint32_t>(tsize);
+    size_t fbits = (size_t)1 << 16;
+    while (fbits < 32 * nd && fbits < ((size_t)1 << 34)) fbits <<= 1;
+    unsigned long long *t_filter = su.take<unsigned long long>(fbits / 64);
+    PsiSet psi;
+    psi.lo = t_lo;
+    psi.hi = t_hi;
+    psi.state = t_state;
+    psi.mask = tsize - 1;
+    psi.filter = t_filter;
+    psi.fmask = (uint32_t)(fbits / 64 - 1);
+    uint32_t *d_stat = ar.take<uint32_t>(16);  // [0] status bits, [1] selection size
+    fill_u32(d_stat, 16, 0u, s);
+    fill_u32((uint32_t *)d_err, 16, 0u, s);
+    k_fault_reset<<<1, 64, 0, s>>>();
+    bucket_fault_reset_dev(s);
+    k_validate<<<grid_for(nd), kBlock, 0, s>>>(in.dets, nd, full, na, nb, d_err);
+    ASCI_LAUNCH_CHECK();
+    k_jk<<<grid_for((size_t)n * n), kBlock, 0, s>>>(in.eri, in.h, n, d_jk);
+    ASCI_LAUNCH_CHECK();
+    fill_u32(t_state, tsize, 0u, s);
+    fill_u32((uint32_t *)t_filter, fbits / 32, 0u, s);
+    k_psi_insert<W><<<grid_for(nd), kBlock, 0, s>>>(in.dets, nd, n, t_lo, t_hi, t_state, tsize - 1, t_filter, psi.fmask);
+    ASCI_LAUNCH_CHECK();
+    k_psi_dups<W><<<grid_for(nd), kBlock, 0, s>>>(in.dets, nd, n, psi, d_err);
+    ASCI_LAUNCH_CHECK();
+    k_stat_or<<<1, 64, 0, s>>>(d_err, d_stat);
+    ASCI_LAUNCH_CHECK();
+    if (nq < nd) {
+        uint64_t *ck[2] = {su.take<uint64_t>(nd), su.take<uint64_t>(nd)};
+        uint32_t *ci[2] = {su.take<uint32_t>(nd), su.take<uint32_t>(nd)};
+        uint64_t *nohi[2] = {nullptr, nullptr};
+        k_core_keys<<<grid_for(nd), kBlock, 0, s>>>(in.coeffs, nd, ck[0], ci[0]);
+        ASCI_LAUNCH_CHECK();
+        std::vector<Digit> cd;
+        for (int sh = 0; sh < 64; sh += 8) cd.push_back({0, sh});
+        const int r1 = radix_sort<uint32_t>(ck, nohi, ci, nd, 1, cd, su, s);
+        uint64_t *ik[2] = {ck[r1 ^ 1], su.take<uint64_t>(nq)};
+        uint32_t *ii[2] = {ci[r1 ^ 1], su.take<uint32_t>(nq)};
+        k_index_keys<<<grid_for(nq), kBlock, 0, s>>>(ci[r1], nq, ik[0]);
+        ASCI_LAUNCH_CHECK();
+        std::vector<Digit> id;
+        for (int sh = 0; sh < 32; sh += 8) id.push_back({0, sh});
+        const int r2 = radix_sort<uint32_t>(ik, nohi, ii, nq, 1, id, su, s);
+        k_gather_core<<<grid_for(nq), kBlock, 0, s>>>(in.dets, in.coeffs, ik[r2], nq, q_a, q_b, q_c);
+    } else {
+        k_gather_core<<<grid_for(nq), kBlock, 0, s>>>(in.dets, in.coeffs, nullptr, nq, q_a, q_b, q_c);
+    }
+    ASCI_LAUNCH_CHECK();
+    k_class_masks<<<grid_for(ncls), kBlock, 0, s>>>(d_cls, (uint32_t)ncls, n, na, L);
+    ASCI_LAUNCH_CHECK();
+
+    // ---- spin-string tables (binomials built on the device)
+    SpinTables st;
+    if (pl.bytes) {
+        uint32_t *d_binom = ar.take<uint32_t>((size_t)(pl.kmax + 4) * (n + 1));
+        k_binom_table<<<1, 64, 0, s>>>(d_binom, n, pl.kmax, pl.kmax + 4);
+        ASCI_LAUNCH_CHECK();
+        st.binom = d_binom;
+        st.kmax = pl.kmax;
+        const int ne[2] = {na, nb};
+        for (int i = 0; i < 2; ++i) {
+            if (pl.count[i] == 0) continue;
+            if (i == 1 && pl.share) {
+                st.e[1] = st.e[0];
+                continue;
+            }
+            double *t = ar.take<double>(pl.count[i]);
+            k_spin_table<<<(unsigned)((pl.count[i] + kBlock - 1) / kBlock), kBlock, 0, s>>>(d_jk, n, ne[i], d_binom,
+                                                                                        (uint32_t)pl.count[i], t);
+            ASCI_LAUNCH_CHECK();
+            st.e[i] = t;
+        }
+    }
+
+    // ---- count matrix, record offsets, generation (one batch: every class)
+    uint32_t *counts = ar.take<uint32_t>(E);
+    uint32_t *offs = ar.take<uint32_t>(E);
+    uint64_t *k_lo[2] = {ar.take<uint64_t>(Pb), ar.take<uint64_t>(Pb)};
+    uint64_t *k_hi[2] = {W == 2 ? ar.take<uint64_t>(Pb) : nullptr, W == 2 ? ar.take<uint64_t>(Pb) : nullptr};
+    double *v[2] = {ar.take<double>(Pb), ar.take<double>(Pb)};
+    uint64_t *c_lo = ar.take<uint64_t>(Pb);
+    uint64_t *c_hi = W == 2 ? ar.take<uint64_t>(Pb) : nullptr;
+    double *c_score = ar.take<double>(Pb);
+    uint64_t *p_lo[2] = {ar.take<uint64_t>(pool_cap), ar.take<uint64_t>(pool_cap)};
+    uint64_t *p_hi[2] = {W == 2 ? ar.take<uint64_t>(pool_cap) : nullptr, W == 2 ? ar.take<uint64_t>(pool_cap) : nullptr};
+    double *p_score[2] = {ar.take<double>(pool_cap), ar.take<double>(pool_cap)};
+    SelectState *d_sel = ar.take<SelectState>(1);
+    uint32_t *d_cnt = ar.take<uint32_t>(16);
+    const ClassMap cmap{L, na, nullptr};
+    {
+        dim3 g((unsigned)((nq + kBlock - 1) / kBlock), (unsigned)ncls);
+        k_count<<<g, kBlock, 0, s>>>(q_a, (uint32_t)nq, d_cls, 0u, full, bf, counts, nullptr);
+        ASCI_LAUNCH_CHECK();
+    }
+    scan_u32(counts, offs, E, d_cnt + 2, ar, s, nullptr);
+    {
+        GenArgs ga;
+        ga.core_a = q_a;
+        ga.core_b = q_b;
+        ga.core_c = q_c;
+        ga.nq = (uint32_t)nq;
+        ga.c0 = 0;
+        ga.nc = (uint32_t)ncls;
+        ga.nbits = 1;
+        while ((1u << ga.nbits) < ga.nc) ++ga.nbits;
+        ga.offsets = offs;
+        ga.h = in.h;
+        ga.eri = in.eri;
+        ga.n = n;
+        ga.na = na;
+        ga.nb = nb;
+        ga.cmap = cmap;
+        ga.full = full;
+        const uint32_t va = (uint32_t)(n - na), vb = (uint32_t)(n - nb);
+        ga.nas = (uint32_t)na * va;
+        ga.nbs = (uint32_t)nb * vb;
+        ga.f0 = bf.f[0];
+        ga.f1 = bf.f[1];
+        ga.pva2 = va * (va - (va ? 1u : 0u)) / 2u;
+        ga.npa2 = (uint32_t)na * (uint32_t)(na - (na ? 1 : 0)) / 2u;
+        ga.pvb2 = bf.pairs_vb;
+        ga.npb2 = (uint32_t)nb * (uint32_t)(nb - (nb ? 1 : 0)) / 2u;
+        ga.klo = k_lo[0];
+        ga.khi = k_hi[0];
+        ga.vals = v[0];
+        ga.cap = Pb;
+        ga.force_fault = ctx->fault_test;
+        const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)ga.nc * 4 + 256 +
+                           2 * ((size_t)ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
+        k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
+        ASCI_LAUNCH_CHECK();
+    }
+
+    // ---- sort and accumulate, exclusion, diagonal and score (device-driven)
+    BucketArgs ba;
+    ba.P = Pb;
+    ba.c0 = 0;
+    ba.nc = (uint32_t)ncls;
+    ba.nq = (uint32_t)nq;
+    ba.n = n;
+    ba.cls = d_cls;
+    ba.offsets = offs;
+    ba.total = d_cnt + 2;
+    ba.klo[0] = k_lo[0];
+    ba.klo[1] = k_lo[1];
+    ba.khi[0] = k_hi[0];
+    ba.khi[1] = k_hi[1];
+    ba.val[0] = v[0];
+    ba.val[1] = v[1];
+    ba.psi = psi;
+    ba.jk = d_jk;
+    ba.h = in.h;
+    ba.st = st;
+    ba.thr = nullptr;
+    ba.ecore = in.opt.ecore;
+    ba.E0 = in.E0;
+    ba.eps = in.opt.eps;
+    ba.finish_cap = ctx->finish_cap;
+    ba.clo = c_lo;
+    ba.chi = c_hi;
+    ba.cnum = nullptr;
+    ba.cscore = c_score;
+    ba.pool_lo = p_lo[0];
+    ba.pool_hi = p_hi[0];
+    ba.pool_num = nullptr;
+    ba.pool_score = p_score[0];
+    ba.pool_base = 0;
+    ba.pool_cap = pool_cap;
+    bucket_accumulate_dev<W>(ba, ar, s, d_stat);
+    bucket_collect_dev<W>(ba, s);
+    const uint32_t *d_V = ba.dn_V;
+
+    // ---- the k largest |A| (ties: smaller key), then |A| descending
+    uint32_t *d_kk = d_stat + 1;
+    k_min_count<<<1, 64, 0, s>>>(d_V, (uint64_t)k, d_kk);
+    ASCI_LAUNCH_CHECK();
+    radix_select_abs(p_score[0], Pb, kh, d_sel, s, nullptr, nullptr, d_V, d_kk);
+    const uint32_t ntile = (uint32_t)((Pb + kKeepTile - 1) / kKeepTile);
+    uint32_t *tgt = ar.take<uint32_t>(ntile), *teq = ar.take<uint32_t>(ntile);
+    uint32_t *eqb = ar.take<uint32_t>(ntile), *kbs = ar.take<uint32_t>(ntile);
+    k_keep_count<<<ntile, kBlock, 0, s>>>(p_score[0], Pb, d_sel, tgt, teq, d_V);
+    ASCI_LAUNCH_CHECK();
+    k_keep_bases<<<1, 1024, 0, s>>>(tgt, teq, ntile, d_sel, eqb, kbs);
+    ASCI_LAUNCH_CHECK();
+    k_keep_scatter<W><<<ntile, kBlock, 0, s>>>(p_lo[0], p_hi[0], p_score[0], Pb, d_sel, eqb, kbs, p_lo[1], p_hi[1],
+                                               p_score[1], (size_t)kh, d_V);
+    ASCI_LAUNCH_CHECK();
+    {
+        uint64_t *fk[2] = {ar.take<uint64_t>(kh), ar.take<uint64_t>(kh)};
+        uint32_t *fi[2] = {ar.take<uint32_t>(kh), ar.take<uint32_t>(kh)};
+        uint64_t *nohi[2] = {nullptr, nullptr};
+        k_final_keys<<<grid_for(kh), kBlock, 0, s>>>(p_score[1], kh, fk[0], fi[0], d_kk);
+        ASCI_LAUNCH_CHECK();
+        std::vector<Digit> fd;
+        for (int sh = 0; sh < 64; sh += 8) fd.push_back({0, sh});
+        const int rr = radix_sort<uint32_t>(fk, nohi, fi, kh, 1, fd, ar, s, nullptr, d_kk);
+        // every fault raised so far fails the call before any output is written
+        k_fault_take<<<1, 64, 0, s>>>(d_stat, kStatFault);
+        ASCI_LAUNCH_CHECK();
+        bucket_fault_take_dev(d_stat, kStatFault, s);
+        k_final_gather<W><<<grid_for(kh), kBlock, 0, s>>>(fi[rr], kh, p_lo[1], p_hi[1], p_score[1], n, out_dets,
+                                                          out_scores, d_kk, d_stat);
+        ASCI_LAUNCH_CHECK();
+    }
+    k_async_done<<<1, 64, 0, s>>>(d_stat, d_kk, d_result);
+    ASCI_LAUNCH_CHECK();
+}
+
+void search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uint64_t *out_dets, double *out_scores,
+                  asci_async_result *d_result, hipStream_t s, bool plan_only)
+{
+    require(k >= 1, ASCI_EINVAL, "k must be >= 1");
+    if (in.n <= 32) run_search_async<1>(ctx, in, k, out_dets, out_scores, d_result, s, plan_only);
+    else run_search_async<2>(ctx, in, k, out_dets, out_scores, d_result, s, plan_only);
+}
+
+size_t search_async_bytes(const SearchArgs &in, int64_t k, int finish_cap, bool spin_tables)
+{
+    const int n = in.n, na = in.na, W = n <= 32 ? 1 : 2;
+    const size_t nd = (size_t)in.ndets;
+    const size_t nq = (in.opt.ncore > 0 && (size_t)in.opt.ncore < nd) ? (size_t)in.opt.ncore : nd;
+    const uint64_t P = search_pairs(in);
+    if (in.opt.split_pairs != 0 || P < 1 || P >= (1ull << 31) || k < 1) return 0;
+    if (in.opt.pair_buffer_bytes > 0 && P > (uint64_t)in.opt.pair_buffer_bytes / (2 * (8 * W + 8))) return 0;
+    int L = std::min(in.opt.constraint_level, na);
+    while (L > 0 && choose_u64((uint64_t)(n - na + L), L) > kMaxBatchClasses) --L;
+    const uint64_t ncls = std::max<uint64_t>(choose_u64((uint64_t)(n - na + L), L), 1);
+    if ((size_t)ncls * nq >= (1ull << 31)) return 0;
+    const uint64_t kh = std::min<uint64_t>((uint64_t)k, P);
+    const SpinTablePlan pl = spin_table_plan(n, na, in.nb, P, spin_tables);
+    return setup_bytes(nd, nq, n, W) + main_bytes((size_t)ncls * nq, (size_t)P, (size_t)P + 1, (uint32_t)ncls,
+                                                  (size_t)kh, true, W, finish_cap) +
+           pl.bytes + (size_t)P / 4 + ((size_t)16 << 20);
 }
 
 size_t search_scratch_bound(const SearchArgs &in, int64_t k, int finish_cap, size_t &setup_part)

@@ -562,6 +562,7 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
         require(ctx != nullptr && (nreq == 0 || (reqs && res)), ASCI_EINVAL, "null argument");
         require(nreq >= 0, ASCI_EINVAL, "nreq must be >= 0");
         if (nreq == 0) return ASCI_OK;
+        const hipStream_t st = (hipStream_t)stream;
         if (!ctx->batch_pool || ctx->batch_pool_slots != ctx->batch_slots ||
             ctx->batch_pool_cap != ctx->finish_cap) {
             if (ctx->batch_pool) ctx->batch_pool_free(ctx->batch_pool);
@@ -577,19 +578,48 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
         // the context's own workspaces are idle during the batch: give their
         // HBM to the workers (work queued on `stream` finishes first)
         ASCI_HIP(hipSetDevice(ctx->device));
-        ASCI_HIP(hipStreamSynchronize((hipStream_t)stream));
+        ASCI_HIP(hipStreamSynchronize(st));
         ctx->setup.release();
         ctx->main.release();
         ctx->tables.release();
+        // requests inside the asynchronous search's scope, whose workspace fits
+        // a share of the free HBM, run as one captured graph on `stream`; the
+        // rest on the worker streams, at the same time
+        std::vector<int> gidx, pidx;
+        if (ctx->batch_graph) {
+            size_t fr = 0, tt = 0;
+            ASCI_HIP(hipMemGetInfo(&fr, &tt));
+            const size_t limit = (size_t)((double)fr * 0.4) / (size_t)std::max(ctx->batch_slots, 1);
+            for (int i = 0; i < nreq; ++i) {
+                size_t b = 0;
+                try {
+                    check_request(reqs[i], true);
+                    b = graph_request_bytes(reqs[i], ctx->finish_cap, ctx->spin_tables != 0);
+                } catch (const Error &) {
+                    b = 0;  // the worker path reports it
+                }
+                if (b > 0 && b <= limit) gidx.push_back(i);
+                else pidx.push_back(i);
+            }
+        } else {
+            for (int i = 0; i < nreq; ++i) pidx.push_back(i);
+        }
+        pool.order_after(st);  // before the graph: the workers do not wait for it
+        const double t0 = now_ms();
+        if (!gidx.empty()) {
+            if (!ctx->graph_batch) {
+                ctx->graph_batch = new GraphBatch();
+                ctx->graph_batch_free = [](void *p) { delete static_cast<GraphBatch *>(p); };
+            }
+            graph_batch_launch(*static_cast<GraphBatch *>(ctx->graph_batch), ctx->device, reqs, gidx,
+                               ctx->batch_slots, ctx->finish_cap, ctx->spin_tables, st);
+        }
         pool.set_budget(device_budget(ctx->device));
-        pool.order_after((hipStream_t)stream);
-        std::vector<int> order((size_t)nreq);
-        for (int i = 0; i < nreq; ++i) order[(size_t)i] = i;
-        std::stable_sort(order.begin(), order.end(),
+        std::stable_sort(pidx.begin(), pidx.end(),
                          [&](int a, int b) { return request_pairs(reqs[a]) > request_pairs(reqs[b]); });
         std::vector<uint64_t> tickets((size_t)nreq, 0);
         int rc = ASCI_OK;
-        for (int i : order) {
+        for (int i : pidx) {
             int r;
             try {
                 r = pool.submit(reqs[i], &tickets[(size_t)i]);
@@ -601,10 +631,25 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
             }
             if (r != ASCI_OK && rc == ASCI_OK) rc = r;
         }
-        for (int i = 0; i < nreq; ++i) {
+        for (int i : pidx) {
             if (tickets[(size_t)i] == 0) continue;
             pool.poll(tickets[(size_t)i], &res[i], true);
             if (res[i].status != ASCI_OK && rc == ASCI_OK) rc = res[i].status;
+        }
+        if (!gidx.empty()) {
+            ASCI_HIP(hipStreamSynchronize(st));
+            const double t1 = now_ms();
+            std::vector<asci_async_result> ar;
+            graph_batch_results(*static_cast<GraphBatch *>(ctx->graph_batch), gidx.size(), ar);
+            for (size_t j = 0; j < gidx.size(); ++j) {
+                asci_result &r = res[gidx[j]];
+                r = asci_result{};
+                r.status = ar[j].status;
+                r.count = ar[j].count;
+                r.latency_ms = r.run_ms = t1 - t0;
+                r.contributions = request_pairs(reqs[gidx[j]]);
+                if (r.status != ASCI_OK && rc == ASCI_OK) rc = r.status;
+            }
         }
         pool.forget(tickets);
         return rc;

@@ -148,3 +148,24 @@ def test_batch_and_single_alternate_on_one_context(setup):
         k, s = asci.search(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], c["E0"],
                            c["kk"], ctx=ctx)
         assert (host(k) == alone[0][0]).all() and (host(s) == alone[0][1]).all()
+
+
+def test_batch_graph_replay_and_worker_path_agree(setup):
+    """Requests inside the asynchronous search's scope run as one captured
+    graph (replayed on the second call with the same requests); with the graph
+    turned off they run on the worker streams: every result is bit for bit the
+    search run alone, on every path."""
+    asci, cases, alone = setup
+    reqs = _requests(asci, cases)
+    ctx = asci.Context(0)
+    try:
+        for flag in (1, 1, 0, 1):
+            ctx.set_param("batch_graph", flag)
+            for q in reqs:
+                q.out_scores.fill_(7.0)
+            res = asci.search_batch(reqs, ctx=ctx)
+            for r, q, want in zip(res, reqs, alone):
+                assert r.status == 0
+                assert _same(q, r, want)
+    finally:
+        ctx.close()
