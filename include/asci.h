@@ -170,6 +170,27 @@ int asci_search_device(asci_ctx *ctx, const double *d_h, const double *d_eri, in
                        void *stream);
 
 /*
+ * The search of asci_search_device for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, meaning and result (the same kernels);
+ * no device or pinned host memory is allocated: every device buffer of the
+ * call comes from a fixed scratch region of 256 MiB that the library holds
+ * on each device it runs on from load time until the process ends, and host
+ * readbacks go through a fixed host buffer (the host-side planning still uses
+ * the C++ heap).  The pair buffer holds every pair of the search (one class
+ * batch) and the spin-string tables are not built (the diagonal element is
+ * evaluated directly, the same bits).  A search whose workspace bound
+ * exceeds the region (roughly beyond 2.5e6 pairs) is rejected with
+ * ASCI_ENOMEM before any device work.  Calls on one device share the region:
+ * the library runs them one at a time (each returns after its outputs are
+ * written), and a call starts from no state of the previous one.
+ */
+int asci_search_device_noalloc(const double *d_h, const double *d_eri, int norb, int nalpha, int nbeta,
+                               const uint64_t *d_dets, const double *d_coeffs, int64_t ndets, double E0,
+                               int64_t k, const asci_options *opt, uint64_t *d_out_dets, double *d_out_scores,
+                               int64_t *out_count, void *stream);
+
+/*
  * Every candidate of the search (no selection), device buffers: keys in
  * ascending (alpha, beta) order, their numerators N_a and scores A_a.
  * capacity: length of the output arrays.  *out_count receives the number of

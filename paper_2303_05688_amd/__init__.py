@@ -92,6 +92,8 @@ _lib.asci_search.argtypes = [_dp, _dp, C.c_int, C.c_int, C.c_int, _up, _dp, C.c_
                              C.POINTER(Options), _up, _dp, _ip]
 _lib.asci_search_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
                                     C.c_int64, C.POINTER(Options), _vp, _vp, _ip, _vp]
+_lib.asci_search_device_noalloc.argtypes = [_vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double,
+                                            C.c_int64, C.POINTER(Options), _vp, _vp, _ip, _vp]
 _lib.asci_candidates_device.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64,
                                         C.c_double, C.POINTER(Options), C.c_int64, _vp, _vp, _vp, _ip, _vp]
 _lib.asci_class_counts_device.argtypes = [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int64,
@@ -150,7 +152,7 @@ EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_def
            "asci_loop_options_default", "asci_loop_step_device", "asci_run_device",
            "asci_request_footprint", "asci_search_batch", "asci_autotune", "asci_server_create",
            "asci_server_create_fake", "asci_server_submit", "asci_server_footprint", "asci_server_poll",
-           "asci_server_wait", "asci_server_set_param", "asci_search_async",
+           "asci_server_wait", "asci_server_set_param", "asci_search_device_noalloc", "asci_search_async",
            "asci_request_async_bytes",
            "asci_server_get_stats", "asci_server_destroy"]
 
@@ -272,6 +274,25 @@ def search(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, ncore=0, eps=0.0, e
                                    C.byref(cnt), _stream(dev)))
     m = cnt.value
     return out_d[:m], out_s[:m]
+
+
+def search_noalloc(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, k, out_dets, out_scores, ncore=0, eps=0.0,
+                   ecore=0.0, constraint_level=3, split_pairs=0):
+    """asci_search_device_noalloc into caller-owned outputs (out_dets[k, 2]
+    uint64, out_scores[k] float64 device tensors); returns the count.  The
+    call allocates no device memory."""
+    torch = _torch()
+    dev = h.device.index if h.device.index is not None else torch.cuda.current_device()
+    dets = _dets_tensor(dets)
+    if out_dets.shape[0] < int(k) or out_scores.shape[0] < int(k):
+        raise ValueError("outputs shorter than k")
+    cnt = C.c_int64(0)
+    o = options(ncore, eps, ecore, 0, constraint_level, split_pairs)
+    _check(_lib.asci_search_device_noalloc(_dev(h, torch.float64), _dev(eri, torch.float64), norb, nalpha, nbeta,
+                                           _dev(dets, torch.uint64), _dev(coeffs, torch.float64), dets.shape[0],
+                                           float(E0), int(k), C.byref(o), _dev(out_dets, torch.uint64),
+                                           _dev(out_scores, torch.float64), C.byref(cnt), _stream(dev)))
+    return cnt.value
 
 
 def candidates(h, eri, norb, nalpha, nbeta, dets, coeffs, E0, ncore=0, eps=0.0, ecore=0.0,
