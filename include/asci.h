@@ -22,6 +22,9 @@
  *     vacuum.  This fixes the sign of every H_ai, hence of every score.
  *   - h is norb x norb, eri is (pq|rs) in chemists' notation, norb^4,
  *     row-major, real, with the 8-fold permutational symmetry (h symmetric).
+ *     The search entry points check the symmetry bit for bit (their
+ *     generator reads a packed copy of the distinct entries) and fail with
+ *     ASCI_EINVAL otherwise (asynchronous search: status ASCI_EINVAL).
  *   - The candidate key order is (alpha, beta) compared as unsigned integers.
  *   - Output order is |A| descending (compared as the IEEE-754 bit pattern of
  *     |A|, i.e. numerically for non-NaN values), ties by key ascending.
@@ -105,9 +108,12 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *                 Both give the same bits (same summation order).
  *   "release_workspace" (value 1): free the context's device workspaces and
  *                 the batch workers (they are allocated again on demand).
- *   "batch_graph": 1 (default) runs the requests of asci_search_batch that fit
- *                 asci_search_async's scope as one captured graph; 0 sends
- *                 them to the worker streams.
+ *   "use_tuned": 1 (default) lets a search use the per-shape finish_cap that
+ *                 asci_tune_shapes recorded for its shape; 0 always uses
+ *                 the context's "finish_cap".
+ *   "batch_graph": 1 runs the requests of asci_search_batch that fit
+ *                 asci_search_async's scope as one captured graph; 0
+ *                 (default) sends them to the worker streams.
  *   "fault_test": 1 makes every later search on ctx raise a forced fault in
  *                 its generator, so that the call fails with ASCI_EDEVICE
  *                 (a test of the error path: the kernels' internal-consistency
@@ -414,16 +420,16 @@ int asci_request_async_bytes(asci_ctx *ctx, const asci_request *req, int64_t *ou
 int64_t asci_request_footprint(const asci_request *req);
 
 /*
- * Run nreq searches as one batch on ctx's device.  Requests inside the scope
- * of asci_search_async whose workspace fits a share of the free HBM run as
- * one captured HIP graph: placed on "batch_slots" streams (largest first, to
+ * Run nreq searches as one batch on ctx's device.  With context parameter
+ * "batch_graph" = 1, requests inside the scope of asci_search_async whose
+ * workspace fits a share of the free HBM run as one captured HIP graph: placed on "batch_slots" streams (largest first, to
  * the least loaded; each stream with a context of its own) that fork from
  * and join back to one launch stream; the graph is replayed by later calls
  * with the same requests (same buffers, sizes and options) and captured
  * again otherwise.  The other requests are ordered by estimated cost
  * (largest first) and run at the same time on worker streams, each with its
- * own workspace.  Context parameter "batch_graph" = 0 sends every request to
- * the workers.  The workers and the graph's contexts stay with ctx between
+ * own workspace ("batch_graph" = 0, the default, sends every request to the
+ * workers).  The workers and the graph's contexts stay with ctx between
  * calls (until "release_workspace", a change of "batch_slots" or
  * "finish_cap", or asci_ctx_destroy); the context's own workspaces are
  * freed when a batch starts, and a single search on ctx frees the idle
@@ -435,12 +441,37 @@ int64_t asci_request_footprint(const asci_request *req);
 int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_result *res, void *stream);
 
 /*
- * Pick ctx's "batch_slots" (1..4) and "finish_cap" (2048 or 4096) by timing
- * asci_search_batch on the given sample requests; the chosen values are
- * stored in ctx and returned.  Results never depend on them.
+ * Tune for requests like the given sample: every distinct shape of the
+ * sample gets its finish capacity by asci_tune_shapes (synchronous searches
+ * on ctx).  *best_finish_cap receives the capacity recorded for the sample's
+ * largest request, *best_slots ctx's "batch_slots" (left unchanged).
+ * Results never depend on either.
  */
 int asci_autotune(asci_ctx *ctx, const asci_request *sample, int nsample, int64_t *best_slots,
                   int64_t *best_finish_cap);
+
+/*
+ * Per-shape tuning (speed only, never results): asci_tune_shapes times each
+ * distinct shape of the given requests (device architecture, norb, nalpha,
+ * floor(log2 pairs)) with the finish capacity ("finish_cap") 4096, 2048 and
+ * 1024 (one untimed and two timed searches each, on ctx, synchronous) and
+ * records the fastest in a process-wide table; searches on contexts with
+ * "use_tuned" = 1 (the default) then use the recorded capacity of their shape.
+ * *out_tuned receives the number of shapes timed.  The table can be saved to
+ * a text file and loaded in a later process (one "arch norb nalpha bucket
+ * finish_cap" line per shape; ASCI_EINVAL for a malformed line), looked up
+ * (*finish_cap = 0 when the shape has no entry), recorded directly, and
+ * cleared.  asci_tune_arch writes the architecture name the table keys
+ * device's entries by ("gfx950", or "unknown" without a device) into
+ * buf[cap] (ASCI_EINVAL when it does not fit).
+ */
+int asci_tune_shapes(asci_ctx *ctx, const asci_request *reqs, int nreq, int *out_tuned);
+int asci_tune_record(const char *arch, int norb, int nalpha, int bucket, int finish_cap);
+int asci_tune_lookup(int device, int norb, int nalpha, int64_t pairs, int *finish_cap);
+int asci_tune_arch(int device, char *buf, int cap);
+int asci_tune_clear(void);
+int asci_tune_save(const char *path);
+int asci_tune_load(const char *path, int *out_entries);
 
 /*
  * A request loop with continuous batching on one device.  Requests wait in

@@ -142,6 +142,12 @@ _lib.asci_server_destroy.argtypes = [_vp]
 _lib.asci_server_set_param.argtypes = [_vp, C.c_char_p, C.c_double]
 _lib.asci_search_async.argtypes = [_vp, C.POINTER(Request), _vp, _vp]
 _lib.asci_request_async_bytes.argtypes = [_vp, C.POINTER(Request), _ip]
+_lib.asci_tune_shapes.argtypes = [_vp, C.POINTER(Request), C.c_int, C.POINTER(C.c_int)]
+_lib.asci_tune_record.argtypes = [C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_int]
+_lib.asci_tune_lookup.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, C.POINTER(C.c_int)]
+_lib.asci_tune_save.argtypes = [C.c_char_p]
+_lib.asci_tune_load.argtypes = [C.c_char_p, C.POINTER(C.c_int)]
+_lib.asci_tune_arch.argtypes = [C.c_int, C.c_char_p, C.c_int]
 
 EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_default", "asci_ctx_create",
            "asci_ctx_destroy", "asci_ctx_set_param", "asci_ctx_get_param", "asci_ctx_set_profiling",
@@ -153,7 +159,8 @@ EXPORTS = ["asci_version", "asci_strerror", "asci_last_error", "asci_options_def
            "asci_request_footprint", "asci_search_batch", "asci_autotune", "asci_server_create",
            "asci_server_create_fake", "asci_server_submit", "asci_server_footprint", "asci_server_poll",
            "asci_server_wait", "asci_server_set_param", "asci_search_device_noalloc", "asci_search_async",
-           "asci_request_async_bytes",
+           "asci_request_async_bytes", "asci_tune_shapes", "asci_tune_record", "asci_tune_lookup",
+           "asci_tune_clear", "asci_tune_save", "asci_tune_load", "asci_tune_arch",
            "asci_server_get_stats", "asci_server_destroy"]
 
 
@@ -368,6 +375,13 @@ def balance_classes(counts, npe):
     return owner, load
 
 
+def pairs_per_det(norb, nalpha, nbeta):
+    """Singles and doubles of one determinant (the closed-form pair count per core)."""
+    va, vb = norb - nalpha, norb - nbeta
+    c2 = lambda x: x * (x - 1) // 2  # noqa: E731
+    return nalpha * va + nbeta * vb + c2(nalpha) * c2(va) + c2(nbeta) * c2(vb) + nalpha * va * nbeta * vb
+
+
 def class_skew(counts, npes=(8, 64, 256, 1024)):
     """Skew statistics of a class partition (the single-GPU analogue of the
     per-element pair counts by constraint level): number of non-empty classes,
@@ -476,6 +490,48 @@ def async_status(result):
     return count, status, word >> 32
 
 
+def tune_shapes(requests, ctx=None):
+    """Time each distinct request shape with finish_cap 4096 / 2048 / 1024 and
+    record the fastest (process-wide); returns the number of shapes timed."""
+    torch = _torch()
+    ctx = ctx or Context.get(torch.cuda.current_device())
+    arr = (Request * len(requests))(*[r.c for r in requests])
+    n = C.c_int()
+    _check(_lib.asci_tune_shapes(ctx.ptr, arr, len(requests), C.byref(n)))
+    return n.value
+
+
+def tune_record(arch, norb, nalpha, bucket, finish_cap):
+    _check(_lib.asci_tune_record(arch.encode(), norb, nalpha, bucket, finish_cap))
+
+
+def tune_lookup(device, norb, nalpha, pairs):
+    v = C.c_int()
+    _check(_lib.asci_tune_lookup(device, norb, nalpha, int(pairs), C.byref(v)))
+    return v.value
+
+
+def tune_arch(device=0):
+    """The architecture name the per-shape tuning table keys device's entries by."""
+    buf = C.create_string_buffer(128)
+    _check(_lib.asci_tune_arch(device, buf, 128))
+    return buf.value.decode()
+
+
+def tune_clear():
+    _check(_lib.asci_tune_clear())
+
+
+def tune_save(path):
+    _check(_lib.asci_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    n = C.c_int()
+    _check(_lib.asci_tune_load(str(path).encode(), C.byref(n)))
+    return n.value
+
+
 def fake_request(norb, nalpha, nbeta, ndets, k):
     """A request with no buffers, for the fake (host-only) server."""
     return Request(None, None, norb, nalpha, nbeta, None, None, ndets, 0.0, k, options(), None, None)
@@ -499,6 +555,8 @@ def search_batch(requests, ctx=None):
 
 
 def autotune(sample_requests, ctx=None):
+    """Per-shape tuning of the sample's shapes (asci_autotune): returns the batch
+    slots (unchanged) and the finish capacity recorded for the largest request."""
     torch = _torch()
     ctx = ctx or Context.get(torch.cuda.current_device())
     arr = (Request * len(sample_requests))(*[r.c for r in sample_requests])

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["prims.hip", "search.hip", "bucket.hip", "energy.hip", "eigen.hip", "loop.hip", "server.hip", "graph.hip", "noalloc.hip", "api.hip"]
+SOURCES = ["prims.hip", "search.hip", "bucket.hip", "energy.hip", "eigen.hip", "loop.hip", "server.hip", "graph.hip", "tune.hip", "noalloc.hip", "api.hip"]
 LIB = os.path.join(HERE, "libasci.so")
 
 HIPCC_FLAGS = [

@@ -143,7 +143,8 @@ struct asci_ctx {
     int batch_slots = 2;    // tunable: concurrent searches of a batch
     int spin_tables = 1;    // tunable: 1 = spin-string energy tables when they pay, 0 = never
     int fault_test = 0;     // 1: the next search raises a forced fault (tests of the error path)
-    int batch_graph = 1;    // 1: batch requests within the asynchronous search's scope run as one graph
+    int batch_graph = 0;    // 1: batch requests within the asynchronous search's scope run as one graph
+    int use_tuned = 1;      // 1: a search takes the tuned finish_cap of its shape when one is recorded
     // diagnostics of the last search
     int64_t last_batches = 0, last_finals = 0, last_levels = 0, last_candidates = 0;
     asci::Profiler prof;
@@ -441,6 +442,7 @@ constexpr uint32_t kStatDuplicate = 2u;  // an input determinant given twice
 constexpr uint32_t kStatSplit = 4u;      // the bucket split did not finish in its levels / lists overflowed
 constexpr uint32_t kStatPool = 8u;       // candidate pool overflow
 constexpr uint32_t kStatFault = 16u;     // a kernel consistency fault (see hamiltonian.h)
+constexpr uint32_t kStatIntegrals = 32u; // two-electron integrals not 8-fold symmetric
 
 // the fault word of the bucket kernels (see hamiltonian.h): clear / queue a copy to pinned *dst
 void bucket_fault_clear(hipStream_t s);
@@ -473,6 +475,8 @@ struct SearchOut {
 void search_device(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipStream_t s);
 // closed-form number of (core, target) pairs of a search
 uint64_t search_pairs(const SearchArgs &in);
+// the finish capacity a search of this shape uses on ctx (tune.hip)
+int effective_finish_cap(const asci_ctx *ctx, int norb, int na, uint64_t pairs);
 // The top-k search with nothing read back (asci_search_async): one class batch,
 // every count on the device; d_result (device) receives count and status.
 // plan_only: check the request and size ctx's workspaces, queue nothing.

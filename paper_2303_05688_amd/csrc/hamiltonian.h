@@ -85,36 +85,83 @@ __device__ __forceinline__ double eri4(const double *__restrict__ eri, int n, in
                (uint32_t)orb(s, n)];
 }
 
+// The integrals behind an accessor E(p, q, r, s) = (pq|rs): the full n^4
+// tensor, or its 8-fold packed form.  Packed: pair indices pq = tri(p, q) and
+// rs = tri(r, s), then tri(pq, rs), with tri(a, b) = max(a,b)(max(a,b)+1)/2 +
+// min(a,b); 8-fold symmetric integrals give the same value either way (the
+// search checks that they are, bit for bit, before it reads the packed form).
+__device__ __forceinline__ uint32_t tri(uint32_t a, uint32_t b)
+{
+    return a >= b ? a * (a + 1u) / 2u + b : b * (b + 1u) / 2u + a;
+}
+
+struct EriFull {
+    const double *__restrict__ e;
+    int n;
+    __device__ __forceinline__ double operator()(int p, int q, int r, int s) const { return eri4(e, n, p, q, r, s); }
+};
+
+struct EriPacked {
+    const double *__restrict__ e;
+    int n;
+    __device__ __forceinline__ double operator()(int p, int q, int r, int s) const
+    {
+        const uint32_t pq = tri((uint32_t)orb(p, n), (uint32_t)orb(q, n));
+        const uint32_t rs = tri((uint32_t)orb(r, n), (uint32_t)orb(s, n));
+        return e[tri(pq, rs)];
+    }
+};
+
+// entries of the packed form of n orbitals
+inline size_t eri_packed_count(int n)
+{
+    const size_t npp = (size_t)n * (n + 1) / 2;
+    return npp * (npp + 1) / 2;
+}
+
 // <a|H|i> for a single p -> q in the spin string `same` of i; `other` is the
 // other spin string of i:
 //   sign * ( h_qp + sum_{r in same, r != p} [(qp|rr) - (qr|rp)] + sum_{r in other} (qp|rr) )
-__device__ __forceinline__ double single_value(const double *__restrict__ h,
-                                               const double *__restrict__ eri, int n, uint64_t same,
-                                               uint64_t other, int p, int q)
+template <class E>
+__device__ __forceinline__ double single_value_e(const double *__restrict__ h, const E &eri, int n, uint64_t same,
+                                                 uint64_t other, int p, int q)
 {
     double v = h[(size_t)orb(q, n) * n + orb(p, n)];
     for (uint64_t m = same & ~(1ull << p); m; m &= m - 1ull) {
         const int r = lowbit(m);
-        v = v + (eri4(eri, n, q, p, r, r) - eri4(eri, n, q, r, r, p));
+        v = v + (eri(q, p, r, r) - eri(q, r, r, p));
     }
     for (uint64_t m = other; m; m &= m - 1ull) {
         const int r = lowbit(m);
-        v = v + eri4(eri, n, q, p, r, r);
+        v = v + eri(q, p, r, r);
     }
     return between_sign(same, p, q) * v;
 }
 
+__device__ __forceinline__ double single_value(const double *__restrict__ h, const double *__restrict__ eri, int n,
+                                               uint64_t same, uint64_t other, int p, int q)
+{
+    return single_value_e(h, EriFull{eri, n}, n, same, other, p, q);
+}
+
 // same-spin double: holes p < r (in string si), particles q < s
 //   sign(p->q on si) * sign(r->s on si') * [(qp|sr) - (qr|sp)]
-__device__ __forceinline__ double double_same_value(const double *__restrict__ eri, int n, uint64_t si,
-                                                    uint64_t holes, uint64_t parts)
+template <class E>
+__device__ __forceinline__ double double_same_value_e(const E &eri, int n, uint64_t si, uint64_t holes,
+                                                      uint64_t parts)
 {
     const int p = lowbit(holes), r = lowbit(holes & (holes - 1ull));
     const int q = lowbit(parts), s = lowbit(parts & (parts - 1ull));
     const int s1 = between_sign(si, p, q);
     const uint64_t mid = (si & ~(1ull << p)) | (1ull << q);
     const int s2 = between_sign(mid, r, s);
-    return s1 * s2 * (eri4(eri, n, q, p, s, r) - eri4(eri, n, q, r, s, p));
+    return s1 * s2 * (eri(q, p, s, r) - eri(q, r, s, p));
+}
+
+__device__ __forceinline__ double double_same_value(const double *__restrict__ eri, int n, uint64_t si,
+                                                    uint64_t holes, uint64_t parts)
+{
+    return double_same_value_e(EriFull{eri, n}, n, si, holes, parts);
 }
 
 // opposite-spin double: alpha p -> q, beta r -> s: sign_a * sign_b * (qp|sr)

@@ -165,7 +165,8 @@ struct GenArgs {
     uint32_t c0, nc;          // batch classes [c0, c0 + nc)
     int nbits;                // bits of nc - 1
     const uint32_t *offsets;  // [nc][nq] start of every (class, core) item
-    const double *h, *eri;
+    const double *h;
+    const double *eri8;  // the integrals in 8-fold packed form (checked symmetric)
     int n, na, nb;
     ClassMap cmap;
     uint64_t full;
@@ -215,6 +216,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     const uint64_t lt = (1ull << lane) - 1ull;
     const int n = g.n;
     const uint32_t va = (uint32_t)(n - g.na), vb = (uint32_t)(n - g.nb);
+    const EriPacked E{g.eri8, n};
 
     double *asV = (double *)smem;                     // nas
     uint64_t *asA = (uint64_t *)(asV + g.nas);        // nas
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const uint64_t a2 = (a & ~(1ull << p)) | (1ull << q);
         const uint32_t c = class_of(a2, g.cmap);
         asA[u] = a2;
-        asV[u] = single_value(g.h, g.eri, n, a, b, p, q);
+        asV[u] = single_value_e(g.h, E, n, a, b, p, q);
         asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u);
         asP[u] = (c >= g.c0 && c < g.c0 + g.nc) ? c - g.c0 : ~0u;
     }
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const uint32_t ns1 = min(g.nbs, g.f0);
         for (uint32_t t = lane; t < ns1; t += 64) {
             const uint32_t x = bsX[t];
-            const double hv = single_value(g.h, g.eri, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
+            const double hv = single_value_e(g.h, E, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
             emit<W>(g, base + t, a, bsB[t], hv * ci);
         }
         // beta-beta doubles y = hole pair * pvb2 + particle pair, the pair
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
                 const uint64_t hb = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
                 const uint64_t pb = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
                 const uint64_t b2 = (b & ~hb) | pb;
-                emit<W>(g, base + ns1 + y, a, b2, double_same_value(g.eri, n, b, hb, pb) * ci);
+                emit<W>(g, base + ns1 + y, a, b2, double_same_value_e(E, n, b, hb, pb) * ci);
                 pp += r64;
                 hp += q64;
                 if (pp >= g.pvb2) {
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
                 const int p = (int)(xa & 0xFFu), q = (int)((xa >> 8) & 0xFFu);
                 const int r = (int)(x & 0xFFu), s = (int)((x >> 8) & 0xFFu);
                 const int sg = (((xa ^ x) >> 16) & 1u) ? -1 : 1;
-                emit<W>(g, dst, a2, bsB[j - 1], (sg * eri4(g.eri, n, q, p, s, r)) * ci);
+                emit<W>(g, dst, a2, bsB[j - 1], (sg * E(q, p, s, r)) * ci);
             }
         }
     }
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             if (act) {
                 const size_t dst = (size_t)before + (uint32_t)__popcll(peers & lt);
                 if ((peers & lt) == 0ull) cur[key] = before + (uint32_t)__popcll(peers);
-                emit<W>(g, dst, a2, b, double_same_value(g.eri, n, a, holes, parts) * ci);
+                emit<W>(g, dst, a2, b, double_same_value_e(E, n, a, holes, parts) * ci);
             }
         }
     }
@@ -677,6 +679,34 @@ __global__ __launch_bounds__(kBlock) void k_jk(const double *__restrict__ eri, c
     if (q == 0) jk[2 * n * n + p] = h[(size_t)p * n + p];
 }
 
+// The 8-fold packed copy of the integrals (the form the generator reads: a
+// few hundred KB that stay in L2, where the full tensor does not), written by
+// the canonical entry of each set of equal ones (p >= q, r >= s, pq >= rs).
+__global__ __launch_bounds__(kBlock) void k_eri_pack(const double *__restrict__ eri, int n,
+                                                     double *__restrict__ packed)
+{
+    const uint32_t un = (uint32_t)n;
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= un * un * un * un) return;
+    const uint32_t s_ = t % un, r = (t / un) % un, q = (t / (un * un)) % un, p = t / (un * un * un);
+    if (p < q || r < s_) return;
+    const uint32_t pq = tri(p, q), rs = tri(r, s_);
+    if (pq >= rs) packed[tri(pq, rs)] = eri[t];
+}
+
+// every entry equals its packed representative bit for bit, else the
+// integrals are not 8-fold symmetric: err |= 4
+__global__ __launch_bounds__(kBlock) void k_eri_check(const double *__restrict__ eri, int n,
+                                                      const double *__restrict__ packed, unsigned int *err)
+{
+    const uint32_t un = (uint32_t)n;
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= un * un * un * un) return;
+    const uint32_t s_ = t % un, r = (t / un) % un, q = (t / (un * un)) % un, p = t / (un * un * un);
+    const double v = packed[tri(tri(p, q), tri(r, s_))];
+    if (__double_as_longlong(v) != __double_as_longlong(eri[t])) atomicOr(err, 4u);
+}
+
 inline unsigned grid_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 inline uint64_t choose_u64(uint64_t x, int k)
@@ -832,7 +862,7 @@ static size_t setup_bytes(size_t nd, size_t nq, int n, int W)
 {
     const size_t hist_bytes = ((nd + kScanTile - 1) / kScanTile) * 256 * 4 * 2 + (1 << 16);
     return nd * (8 * 2 * W + 4 * 2) + nd * (8 * 2 + 4 * 2) + nq * 8 * 4 + kMaxClasses * 20 + (size_t)2 * n * n * 8 +
-           2 * hist_bytes + 64 * 256 + (nd * 8 + 1024) * 20 + nd * 8 + (1 << 14);
+           2 * hist_bytes + 64 * 256 + (nd * 8 + 1024) * 20 + nd * 8 + eri_packed_count(n) * 8 + 256 + (1 << 14);
 }
 
 // bytes of the main arena: count matrix and offsets (E entries), the pair
@@ -855,6 +885,7 @@ struct Prepared {
     double *q_c = nullptr;
     uint64_t *d_cls = nullptr;
     double *d_jk = nullptr;
+    double *d_eri8 = nullptr;  // the integrals, 8-fold packed (when given)
     std::vector<uint64_t> cls, totals;  // final classes (ascending mask) and their pair counts
     int Lr = 0;                         // level of the root classes
     uint32_t *d_tree = nullptr;         // split tree (null when no class is split)
@@ -993,6 +1024,7 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     unsigned long long *d_tot = ar.take<unsigned long long>(kMaxClasses);
     uint32_t *d_tree = ar.take<uint32_t>(kMaxClasses);
     pp.d_jk = ar.take<double>((size_t)2 * n * n + n);
+    pp.d_eri8 = ar.take<double>(eri_packed_count(n));
     pp.q_a = ar.take<uint64_t>(nq);
     pp.q_b = ar.take<uint64_t>(nq);
     pp.q_c = ar.take<double>(nq);
@@ -1016,6 +1048,11 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     ASCI_LAUNCH_CHECK();
     if (d_eri && d_h) {
         k_jk<<<grid_for((size_t)n * n), kBlock, 0, s>>>(d_eri, d_h, n, pp.d_jk);
+        ASCI_LAUNCH_CHECK();
+        const size_t n4 = (size_t)n * n * n * n;
+        k_eri_pack<<<grid_for(n4), kBlock, 0, s>>>(d_eri, n, pp.d_eri8);
+        ASCI_LAUNCH_CHECK();
+        k_eri_check<<<grid_for(n4), kBlock, 0, s>>>(d_eri, n, pp.d_eri8, d_err);
         ASCI_LAUNCH_CHECK();
     }
     if (need_psi) {
@@ -1057,6 +1094,7 @@ static void prepare(asci_ctx *ctx, const double *d_h, const double *d_eri, int n
     ASCI_HIP(hipStreamSynchronize(s));
     if (h_err[0] & 1u) throw Error{ASCI_EINVAL, "input determinant with wrong electron count or orbital >= norb"};
     if (h_err[0] & 2u) throw Error{ASCI_EINVAL, "duplicate input determinants"};
+    if (h_err[0] & 4u) throw Error{ASCI_EINVAL, "two-electron integrals are not 8-fold symmetric"};
     // step 4, totals per class (and the split of heavy classes)
     std::vector<uint32_t> tree;
     plan_classes(n, na, opt.constraint_level, opt.split_pairs, fit, pp.q_a, (uint32_t)nq, pp.d_cls, d_tot, full, bf,
@@ -1135,7 +1173,8 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
     for (const auto &bt : batches) max_nc = std::max<uint32_t>(max_nc, bt.second - bt.first);
     Arena &ar = ctx->main;
     ar.reset();
-    ar.reserve(main_bytes(E, Pb, pool_cap, max_nc, kk_max, topk, W, ctx->finish_cap));
+    const int fcap = effective_finish_cap(ctx, n, in.na, search_pairs(in));
+    ar.reserve(main_bytes(E, Pb, pool_cap, max_nc, kk_max, topk, W, fcap));
     ar.reset();
     uint32_t *counts = ar.take<uint32_t>(E);
     uint32_t *offs = ar.take<uint32_t>(E);
@@ -1233,7 +1272,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             while ((1u << ga.nbits) < nc) ++ga.nbits;
             ga.offsets = offs;
             ga.h = in.h;
-            ga.eri = in.eri;
+            ga.eri8 = pp.d_eri8;
             ga.n = n;
             ga.na = in.na;
             ga.nb = in.nb;
@@ -1282,7 +1321,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
         ba.ecore = in.opt.ecore;
         ba.E0 = in.E0;
         ba.eps = in.opt.eps;
-        ba.finish_cap = ctx->finish_cap;
+        ba.finish_cap = fcap;
         ba.clo = c_lo;
         ba.chi = c_hi;
         ba.cnum = c_num;
@@ -1431,7 +1470,8 @@ __global__ __launch_bounds__(64) void k_min_count(const uint32_t *__restrict__ n
 // the validation flags of the setup arena folded into the status word
 __global__ __launch_bounds__(64) void k_stat_or(const unsigned int *__restrict__ err, uint32_t *__restrict__ stat)
 {
-    if (threadIdx.x == 0 && *err) atomicOr(stat, *err & (kStatInvalid | kStatDuplicate));
+    if (threadIdx.x == 0 && *err)
+        atomicOr(stat, (*err & (kStatInvalid | kStatDuplicate)) | ((*err & 4u) ? kStatIntegrals : 0u));
 }
 
 __global__ __launch_bounds__(64) void k_async_done(const uint32_t *__restrict__ stat, const uint32_t *__restrict__ kk,
@@ -1440,7 +1480,8 @@ __global__ __launch_bounds__(64) void k_async_done(const uint32_t *__restrict__ 
     if (threadIdx.x != 0) return;
     const uint32_t f = *stat;
     res->flags = (int32_t)f;
-    res->status = f == 0u ? ASCI_OK : ((f & (kStatInvalid | kStatDuplicate)) ? ASCI_EINVAL : ASCI_EDEVICE);
+    res->status = f == 0u ? ASCI_OK
+                          : ((f & (kStatInvalid | kStatDuplicate | kStatIntegrals)) ? ASCI_EINVAL : ASCI_EDEVICE);
     res->count = f == 0u ? (int64_t)*kk : 0;
 }
 
@@ -1483,7 +1524,8 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
     const SpinTablePlan pl = spin_table_plan(n, na, nb, P, ctx->spin_tables != 0);
     // the bound of the one-batch search, the tables, and the collect's sort of
     // final segments sized for their bound instead of their count
-    ar.reserve(main_bytes(E, Pb, pool_cap, (uint32_t)ncls, (size_t)kh, true, W, ctx->finish_cap) + pl.bytes + Pb / 4 +
+    const int fcap = effective_finish_cap(ctx, n, na, P);
+    ar.reserve(main_bytes(E, Pb, pool_cap, (uint32_t)ncls, (size_t)kh, true, W, fcap) + pl.bytes + Pb / 4 +
                ((size_t)16 << 20));
     ar.reset();
     if (plan_only) return;  // workspaces sized, nothing queued
@@ -1494,6 +1536,7 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
     (void)su.take<unsigned long long>(kMaxClasses);
     (void)su.take<uint32_t>(kMaxClasses);
     double *d_jk = su.take<double>((size_t)2 * n * n + n);
+    double *d_eri8 = su.take<double>(eri_packed_count(n));
     uint64_t *q_a = su.take<uint64_t>(nq), *q_b = su.take<uint64_t>(nq);
     double *q_c = su.take<double>(nq);
     uint32_t tsize = 1024;
@@ -1519,6 +1562,13 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
     ASCI_LAUNCH_CHECK();
     k_jk<<<grid_for((size_t)n * n), kBlock, 0, s>>>(in.eri, in.h, n, d_jk);
     ASCI_LAUNCH_CHECK();
+    {
+        const size_t n4 = (size_t)n * n * n * n;
+        k_eri_pack<<<grid_for(n4), kBlock, 0, s>>>(in.eri, n, d_eri8);
+        ASCI_LAUNCH_CHECK();
+        k_eri_check<<<grid_for(n4), kBlock, 0, s>>>(in.eri, n, d_eri8, d_err);
+        ASCI_LAUNCH_CHECK();
+    }
     fill_u32(t_state, tsize, 0u, s);
     fill_u32((uint32_t *)t_filter, fbits / 32, 0u, s);
     k_psi_insert<W><<<grid_for(nd), kBlock, 0, s>>>(in.dets, nd, n, t_lo, t_hi, t_state, tsize - 1, t_filter, psi.fmask);
@@ -1607,7 +1657,7 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
         while ((1u << ga.nbits) < ga.nc) ++ga.nbits;
         ga.offsets = offs;
         ga.h = in.h;
-        ga.eri = in.eri;
+        ga.eri8 = d_eri8;
         ga.n = n;
         ga.na = na;
         ga.nb = nb;
@@ -1657,7 +1707,7 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
     ba.ecore = in.opt.ecore;
     ba.E0 = in.E0;
     ba.eps = in.opt.eps;
-    ba.finish_cap = ctx->finish_cap;
+    ba.finish_cap = fcap;
     ba.clo = c_lo;
     ba.chi = c_hi;
     ba.cnum = nullptr;

@@ -667,32 +667,20 @@ int asci_autotune(asci_ctx *ctx, const asci_request *sample, int nsample, int64_
 {
     try {
         require(ctx != nullptr && sample != nullptr && nsample >= 1, ASCI_EINVAL, "bad arguments");
-        std::vector<asci_result> res((size_t)nsample);
-        double best = 1e300;
-        int bs = ctx->batch_slots, bc = ctx->finish_cap;
-        const int caps[2] = {4096, 2048};
-        for (int cap : caps) {
-            for (int slots = 1; slots <= 4; ++slots) {
-                ctx->finish_cap = cap;
-                ctx->batch_slots = slots;
-                // one untimed pass warms the workspaces of this configuration
-                int rc = asci_search_batch(ctx, sample, nsample, res.data(), nullptr);
-                if (rc != ASCI_OK) continue;
-                const double t0 = now_ms();
-                rc = asci_search_batch(ctx, sample, nsample, res.data(), nullptr);
-                const double dt = now_ms() - t0;
-                if (rc == ASCI_OK && dt < best) {
-                    best = dt;
-                    bs = slots;
-                    bc = cap;
-                }
-            }
-        }
-        ctx->batch_slots = bs;
-        ctx->finish_cap = bc;
-        if (best_slots) *best_slots = bs;
-        if (best_finish_cap) *best_finish_cap = bc;
-        return best < 1e300 ? ASCI_OK : ASCI_EDEVICE;
+        // every shape of the sample gets its own finish capacity (synchronous
+        // searches on ctx); the batch configuration is left as it is
+        int tuned = 0;
+        int rc = asci_tune_shapes(ctx, sample, nsample, &tuned);
+        if (rc != ASCI_OK) return rc;
+        int big = 0;
+        for (int i = 1; i < nsample; ++i)
+            if (request_pairs(sample[i]) > request_pairs(sample[big])) big = i;
+        int cap = 0;
+        rc = asci_tune_lookup(ctx->device, sample[big].norb, sample[big].nalpha, request_pairs(sample[big]), &cap);
+        if (rc != ASCI_OK) return rc;
+        if (best_slots) *best_slots = ctx->batch_slots;
+        if (best_finish_cap) *best_finish_cap = cap ? cap : ctx->finish_cap;
+        return ASCI_OK;
     } catch (const Error &e) {
         return srv_fail(e);
     } catch (const std::bad_alloc &) {

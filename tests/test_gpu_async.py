@@ -157,6 +157,12 @@ def test_async_failures_reported_on_the_device(asci, oracle_lib):
     req = asci.SearchRequest(d["h"], d["eri"], 8, 4, 3, bad.view(torch.uint64), d["coeffs"], E0, 50)
     count, status, flags = _async(asci, req)
     assert status == asci.ASCI_EINVAL and flags & 1
+    # integrals without the 8-fold symmetry (one entry changed alone)
+    asym = d["eri"].clone()
+    asym.view(-1)[((1 * 8 + 2) * 8 + 3) * 8 + 5] += 1e-3
+    req = asci.SearchRequest(d["h"], asym, 8, 4, 3, d["dets"], d["coeffs"], E0, 50)
+    count, status, flags = _async(asci, req)
+    assert status == asci.ASCI_EINVAL and count == 0 and flags & 32
     # the forced fault of the error-path test
     ctx = asci.Context.get(0)
     req = asci.SearchRequest(d["h"], d["eri"], 8, 4, 3, d["dets"], d["coeffs"], E0, 50)

@@ -233,6 +233,19 @@ def test_invalid_inputs(asci):
         asci.search(d["h"], d["eri"], 65, 3, 3, d["dets"], d["coeffs"], 0.0, 10)
     with pytest.raises(asci.AsciError):
         asci.search(d["h"], d["eri"], 6, 3, 3, d["dets"], d["coeffs"], 0.0, 10, eps=-1.0)
+    # integrals without the 8-fold symmetry: one entry changed alone, then the
+    # same change made to all eight equal entries (accepted again)
+    asym = d["eri"].clone()
+    asym.view(-1)[((0 * 6 + 2) * 6 + 1) * 6 + 4] += 1e-3
+    with pytest.raises(asci.AsciError) as e:
+        asci.search(d["h"], asym, 6, 3, 3, d["dets"], d["coeffs"], 0.0, 10)
+    assert e.value.code == asci.ASCI_EINVAL and "symmetric" in str(e.value)
+    sym = d["eri"].clone().view(6, 6, 6, 6)
+    for p, q, r, t in {(0, 2, 1, 4), (2, 0, 1, 4), (0, 2, 4, 1), (2, 0, 4, 1),
+                       (1, 4, 0, 2), (4, 1, 0, 2), (1, 4, 2, 0), (4, 1, 2, 0)}:
+        sym[p, q, r, t] += 1e-3
+    k_, s_ = asci.search(d["h"], sym.reshape(-1), 6, 3, 3, d["dets"], d["coeffs"], 0.0, 10)
+    assert len(k_) == 10
 
 
 def _sampled_checks(oracle_lib, c, E0, gk, gs, ncheck=1500, seed=0):

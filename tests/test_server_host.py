@@ -172,3 +172,36 @@ def test_small_requests_pass_a_large_one_that_does_not_fit():
     assert mean(res[2:]) < mean(res0[2:])
     with pytest.raises(asci.AsciError):
         asci.Server(hbm_budget=int(1e9), slots=1, fake_ns_per_byte=1e-3).set_param("age_ms", -1.0)
+
+
+def test_tuning_table_record_save_load(tmp_path):
+    """The per-shape tuning table (host only): record, look up by the bucket of
+    the pair count, save, clear, load; malformed files are refused."""
+    asci.tune_clear()
+    # device 0's entries are keyed by its architecture ("unknown" without a
+    # device); a recorded entry is found for every pair count in the same
+    # power-of-two bucket, and not for another architecture
+    arch = asci.tune_arch(0)
+    assert arch in ("unknown", "gfx950")
+    other = "gfx942" if arch != "gfx942" else "gfx950"
+    asci.tune_record(arch, 20, 8, 26, 2048)
+    assert asci.tune_lookup(0, 20, 8, 1 << 26) == 2048
+    assert asci.tune_lookup(0, 20, 8, (1 << 27) - 1) == 2048
+    assert asci.tune_lookup(0, 20, 8, 1 << 27) == 0
+    asci.tune_record(other, 30, 12, 32, 4096)
+    assert asci.tune_lookup(0, 30, 12, 1 << 32) == 0
+    path = tmp_path / "tune.txt"
+    asci.tune_save(path)
+    lines = sorted(open(path).read().split("\n")[:-1])
+    assert lines == sorted(["%s 30 12 32 4096" % other, "%s 20 8 26 2048" % arch])
+    asci.tune_clear()
+    assert asci.tune_lookup(0, 20, 8, 1 << 26) == 0
+    assert asci.tune_load(path) == 2
+    assert asci.tune_lookup(0, 20, 8, 1 << 26) == 2048
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 30 12 32 3000\n")
+    with pytest.raises(asci.AsciError):
+        asci.tune_load(bad)
+    with pytest.raises(asci.AsciError):
+        asci.tune_record("gfx950", 30, 12, 70, 4096)
+    asci.tune_clear()
