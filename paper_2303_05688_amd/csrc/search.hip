@@ -252,10 +252,12 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const int p = occA[u / va], q = virA[u % va];
         const uint64_t a2 = (a & ~(1ull << p)) | (1ull << q);
         const uint32_t c = class_of(a2, g.cmap);
+        const bool in = c >= g.c0 && c < g.c0 + g.nc;
         asA[u] = a2;
-        asV[u] = single_value_e(g.h, E, n, a, b, p, q);
+        // the element (an O(n) sum) only for singles whose class is in the batch
+        asV[u] = in ? single_value_e(g.h, E, n, a, b, p, q) : 0.0;
         asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u);
-        asP[u] = (c >= g.c0 && c < g.c0 + g.nc) ? c - g.c0 : ~0u;
+        asP[u] = in ? c - g.c0 : ~0u;
     }
     // occupied and virtual orbital pairs of both spins (hole and particle pairs
     // of the doubles)
@@ -380,6 +382,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
                 ++hp;
             }
             const bool act = c >= g.c0 && c < g.c0 + g.nc;
+            if (__ballot(act) == 0ull) continue;  // no double of this round is in the batch
             const uint32_t key = act ? c - g.c0 : 0u;
             const uint64_t peers = wave_match(key, act, g.nbits);
             const uint32_t before = cur[key];
