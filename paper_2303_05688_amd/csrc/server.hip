@@ -158,11 +158,20 @@ class Pool {
     }
 
     // the request as this pool runs it: pair buffer capped at cap_records_
+    // records, then halved while the whole workspace exceeds the budget (its
+    // other parts, such as the class x core matrix and the spin tables, do
+    // not shrink with the pair buffer), down to 2^20 records
     asci_request shaped(const asci_request &r) const
     {
         asci_request q = r;
-        const int64_t capb = (int64_t)(cap_records_ * (r.norb <= 32 ? 32 : 48));
-        if (q.opt.pair_buffer_bytes == 0 || q.opt.pair_buffer_bytes > capb) q.opt.pair_buffer_bytes = capb;
+        const int64_t rec = r.norb <= 32 ? 32 : 48;  // ping-pong keys + values per record
+        int64_t cap = (int64_t)cap_records_;
+        if (q.opt.pair_buffer_bytes > 0) cap = std::max<int64_t>(1, std::min<int64_t>(cap, q.opt.pair_buffer_bytes / rec));
+        q.opt.pair_buffer_bytes = cap * rec;
+        while (cap > (1 << 20) && request_footprint(q, cap_records_, finish_cap_) > budget_) {
+            cap = std::max<int64_t>(cap / 2, 1 << 20);
+            q.opt.pair_buffer_bytes = cap * rec;
+        }
         return q;
     }
 

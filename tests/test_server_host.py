@@ -205,3 +205,18 @@ def test_tuning_table_record_save_load(tmp_path):
     with pytest.raises(asci.AsciError):
         asci.tune_record("gfx950", 30, 12, 70, 4096)
     asci.tune_clear()
+
+
+def test_one_slot_pool_fits_large_requests_into_its_budget():
+    """With one slot the pair buffer alone may take most of the budget; the
+    rest of the workspace (class x core matrix, spin tables, candidate pool)
+    does not shrink with it, so the pool shrinks the pair buffer until the
+    whole request fits instead of refusing it."""
+    reqs = _reqs([(30, 12, 12, 100_000, 1_000_000), (40, 11, 11, 61_089, 610_890)])
+    for budget in (20e9, 40e9, 160e9):
+        srv = asci.Server(hbm_budget=int(budget), slots=1, fake_ns_per_byte=1e-9)
+        try:
+            assert all(srv.footprint(r) <= budget for r in reqs)
+            assert all(srv.wait(srv.submit(r)).status == 0 for r in reqs)
+        finally:
+            srv.close()
