@@ -111,6 +111,11 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *   "use_tuned": 1 (default) lets a search use the per-shape finish_cap that
  *                 asci_tune_shapes recorded for its shape; 0 always uses
  *                 the context's "finish_cap".
+ *   "batch_solo_pairs": requests of asci_search_batch with at least this
+ *                 many (core, target) pairs run one at a time on ctx itself
+ *                 (default 2^30: those needing more than one class batch,
+ *                 which fill the GPU alone); 0 sends every request to the
+ *                 workers.
  *   "batch_graph": 1 runs the requests of asci_search_batch that fit
  *                 asci_search_async's scope as one captured graph; 0
  *                 (default) sends them to the worker streams.
@@ -420,7 +425,10 @@ int asci_request_async_bytes(asci_ctx *ctx, const asci_request *req, int64_t *ou
 int64_t asci_request_footprint(const asci_request *req);
 
 /*
- * Run nreq searches as one batch on ctx's device.  With context parameter
+ * Run nreq searches as one batch on ctx's device.  Requests of at least
+ * "batch_solo_pairs" pairs fill the GPU on their own: they run one at a
+ * time on ctx (largest first, with its whole workspace) after the others,
+ * which run at the same time as follows.  With context parameter
  * "batch_graph" = 1, requests inside the scope of asci_search_async whose
  * workspace fits a share of the free HBM run as one captured HIP graph: placed on "batch_slots" streams (largest first, to
  * the least loaded; each stream with a context of its own) that fork from
@@ -432,8 +440,8 @@ int64_t asci_request_footprint(const asci_request *req);
  * workers).  The workers and the graph's contexts stay with ctx between
  * calls (until "release_workspace", a change of "batch_slots" or
  * "finish_cap", or asci_ctx_destroy); the context's own workspaces are
- * freed when a batch starts, and a single search on ctx frees the idle
- * workers' workspaces.  Work already queued on `stream` completes first; the
+ * freed when a batch without requests for ctx itself starts, and a search
+ * on ctx frees the idle workers' workspaces.  Work already queued on `stream` completes first; the
  * call returns when every result is written.  res[i] is request i's result;
  * the return value is ASCI_OK when every request succeeded, else the first
  * error code.

@@ -200,6 +200,11 @@ int asci_ctx_set_param(asci_ctx *ctx, const char *name, int64_t value)
             ctx->use_tuned = (int)value;
             return ASCI_OK;
         }
+        if (key == "batch_solo_pairs") {
+            require(value >= 0, ASCI_EINVAL, "batch_solo_pairs must be >= 0");
+            ctx->batch_solo_pairs = value;
+            return ASCI_OK;
+        }
         if (key == "batch_graph") {
             require(value == 0 || value == 1, ASCI_EINVAL, "batch_graph must be 0 or 1");
             ctx->batch_graph = (int)value;
@@ -244,6 +249,7 @@ int asci_ctx_get_param(asci_ctx *ctx, const char *name, int64_t *value)
         else if (key == "spin_tables") *value = ctx->spin_tables;
         else if (key == "fault_test") *value = ctx->fault_test;
         else if (key == "batch_graph") *value = ctx->batch_graph;
+        else if (key == "batch_solo_pairs") *value = ctx->batch_solo_pairs;
         else if (key == "use_tuned") *value = ctx->use_tuned;
         else if (key == "last_batches") *value = ctx->last_batches;
         else if (key == "last_finals") *value = ctx->last_finals;

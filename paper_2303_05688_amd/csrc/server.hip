@@ -584,34 +584,44 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
             ctx->batch_pool_cap = ctx->finish_cap;
         }
         Pool &pool = *static_cast<Pool *>(ctx->batch_pool);
-        // the context's own workspaces are idle during the batch: give their
-        // HBM to the workers (work queued on `stream` finishes first)
         ASCI_HIP(hipSetDevice(ctx->device));
-        ASCI_HIP(hipStreamSynchronize(st));
-        ctx->setup.release();
-        ctx->main.release();
-        ctx->tables.release();
-        // requests inside the asynchronous search's scope, whose workspace fits
-        // a share of the free HBM, run as one captured graph on `stream`; the
-        // rest on the worker streams, at the same time
-        std::vector<int> gidx, pidx;
+        ASCI_HIP(hipStreamSynchronize(st));  // work queued on `stream` finishes first
+        // requests of at least batch_solo_pairs pairs fill the GPU on their own:
+        // they run one at a time on ctx, with its whole workspace, after the
+        // rest.  Of the rest, requests inside the asynchronous search's scope
+        // whose workspace fits a share of the free HBM run as one captured
+        // graph on `stream` (batch_graph = 1); the others on the worker
+        // streams, at the same time.
+        std::vector<int> gidx, pidx, solo;
+        size_t limit = 0;
         if (ctx->batch_graph) {
             size_t fr = 0, tt = 0;
             ASCI_HIP(hipMemGetInfo(&fr, &tt));
-            const size_t limit = (size_t)((double)fr * 0.4) / (size_t)std::max(ctx->batch_slots, 1);
-            for (int i = 0; i < nreq; ++i) {
-                size_t b = 0;
+            limit = (size_t)((double)fr * 0.4) / (size_t)std::max(ctx->batch_slots, 1);
+        }
+        for (int i = 0; i < nreq; ++i) {
+            if (ctx->batch_solo_pairs > 0 && request_pairs(reqs[i]) >= ctx->batch_solo_pairs) {
+                solo.push_back(i);
+                continue;
+            }
+            size_t b = 0;
+            if (ctx->batch_graph) {
                 try {
                     check_request(reqs[i], true);
                     b = graph_request_bytes(reqs[i], ctx->finish_cap, ctx->spin_tables != 0);
                 } catch (const Error &) {
                     b = 0;  // the worker path reports it
                 }
-                if (b > 0 && b <= limit) gidx.push_back(i);
-                else pidx.push_back(i);
             }
-        } else {
-            for (int i = 0; i < nreq; ++i) pidx.push_back(i);
+            if (b > 0 && b <= limit) gidx.push_back(i);
+            else pidx.push_back(i);
+        }
+        // without requests for ctx itself its workspaces are idle during the
+        // batch: their HBM goes to the workers
+        if (solo.empty()) {
+            ctx->setup.release();
+            ctx->main.release();
+            ctx->tables.release();
         }
         pool.order_after(st);  // before the graph: the workers do not wait for it
         const double t0 = now_ms();
@@ -661,6 +671,36 @@ int asci_search_batch(asci_ctx *ctx, const asci_request *reqs, int nreq, asci_re
             }
         }
         pool.forget(tickets);
+        // the requests that fill the GPU alone, largest first, on ctx (a search
+        // on ctx first frees the idle workers' workspaces)
+        std::stable_sort(solo.begin(), solo.end(),
+                         [&](int a, int b) { return request_pairs(reqs[a]) > request_pairs(reqs[b]); });
+        for (int i : solo) {
+            const asci_request &r = reqs[i];
+            asci_result &out = res[i];
+            out = asci_result{};
+            const double t_run = now_ms();
+            try {
+                check_request(r, true);
+                SearchArgs in{r.h, r.eri, r.norb, r.nalpha, r.nbeta, r.dets, r.coeffs, r.ndets, r.E0, resolve(&r.opt)};
+                SearchOut so;
+                so.k = r.k;
+                so.out_dets = r.out_dets;
+                so.out_scores = r.out_scores;
+                search_device(ctx, in, so, st);
+                out.count = so.count;
+                out.status = ASCI_OK;
+                out.contributions = request_pairs(r);
+            } catch (const Error &e) {
+                out.status = e.code;
+            } catch (const std::bad_alloc &) {
+                out.status = ASCI_ENOMEM;
+            }
+            const double t_end = now_ms();
+            out.run_ms = t_end - t_run;
+            out.latency_ms = t_end - t0;
+            if (out.status != ASCI_OK && rc == ASCI_OK) rc = out.status;
+        }
         return rc;
     } catch (const Error &e) {
         return srv_fail(e);

@@ -174,6 +174,29 @@ def test_batch_and_single_alternate_on_one_context(setup):
         assert (host(k) == alone[0][0]).all() and (host(s) == alone[0][1]).all()
 
 
+def test_large_requests_run_alone_on_the_context(setup):
+    """Requests at or above the batch_solo_pairs threshold run one at a time
+    on the context itself, the rest on the workers at the same time: every
+    result is still the search run alone, bit for bit, on every split."""
+    asci, cases, alone = setup
+    reqs = _requests(asci, cases)
+    pairs = sorted(len(c["coeffs"]) * asci.pairs_per_det(c["norb"], c["nalpha"], c["nbeta"]) for c in cases)
+    ctx = asci.Context(0)
+    try:
+        for thr in (pairs[0], pairs[len(pairs) // 2], pairs[-1] + 1, 0):
+            ctx.set_param("batch_solo_pairs", int(thr))
+            for q in reqs:
+                q.out_scores.fill_(7.0)
+            res = asci.search_batch(reqs, ctx=ctx)
+            for r, q, want in zip(res, reqs, alone):
+                assert r.status == 0 and r.run_ms > 0
+                assert _same(q, r, want)
+        with pytest.raises(asci.AsciError):
+            ctx.set_param("batch_solo_pairs", -1)
+    finally:
+        ctx.close()
+
+
 def test_batch_graph_replay_and_worker_path_agree(setup):
     """Requests inside the asynchronous search's scope run as one captured
     graph (replayed on the second call with the same requests); with the graph
