@@ -15,4 +15,5 @@ from .gen import (  # noqa: F401
     uniform_dets,
     workload,
     batch_specs,
+    small_batch_specs,
 )

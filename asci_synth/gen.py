@@ -45,6 +45,7 @@ __all__ = [
     "workload",
     "WORKLOADS",
     "batch_specs",
+    "small_batch_specs",
 ]
 
 
@@ -236,5 +237,23 @@ def batch_specs(count=64, seed=64):
         ncore = int(round(10 ** rng.uniform(3, 5)))
         ncore = max(1, min(ncore, hilbert_dim(n, na, na) // 4))
         specs.append(dict(n=n, na=na, nb=na, ndets=ncore, seed=1000 + i, sampler="level",
+                          tau=max(ncore / 10.0, 1.0), k=10 * ncore))
+    return specs
+
+
+def small_batch_specs(count=256, seed=65):
+    """Sizes for a batch of small searches (the regime where one search does
+    not fill the GPU): norb ~ U{10..20}, even electron count ~ U{4..12} with
+    n_alpha = n_beta <= norb - 2, core count round(10^U(2,3)) clamped to a
+    quarter of the Hilbert space, k = 10 x core count."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(rng.integers(10, 21))
+        ne = int(rng.integers(2, 7)) * 2
+        na = min(ne // 2, n - 2)
+        ncore = int(round(10 ** rng.uniform(2, 3)))
+        ncore = max(1, min(ncore, hilbert_dim(n, na, na) // 4))
+        specs.append(dict(n=n, na=na, nb=na, ndets=ncore, seed=5000 + i, sampler="level",
                           tau=max(ncore / 10.0, 1.0), k=10 * ncore))
     return specs

@@ -183,19 +183,17 @@ def _requests(asci, syn, torch, specs, dev):
     return reqs, pairs
 
 
-def mode_batch(args, asci, syn, torch):
-    """64 uneven searches: one by one on one context, then as batches: the
-    requests inside the asynchronous search's scope as one captured graph
-    (replayed; the rest on worker streams at the same time), and with the
-    graph turned off (worker streams only).  Every batch result is compared
-    bit for bit with the one-by-one result.  Each timing follows an untimed
-    pass that sizes the workspaces (and captures the graph)."""
-    import numpy as np
-
+def _batch_compare(asci, syn, torch, specs, label):
+    """The searches of `specs` one by one on one context (each bracketed by
+    device synchronisations; the total is the sum of those times), then as
+    batches: every request on the worker streams, and the requests inside the
+    asynchronous search's scope as one captured graph (replayed; the rest on
+    the workers at the same time).  Every batch result is compared bit for bit
+    with the one-by-one result.  Each batch timing follows an untimed pass
+    that sizes the workspaces (and captures the graph)."""
     dev = torch.device("cuda", 0)
-    specs = syn.batch_specs(args.batch_count, seed=64)
     reqs, P = _requests(asci, syn, torch, specs, dev)
-    print("batch inputs ready: %d searches, %.3g pairs" % (len(reqs), P), file=sys.stderr, flush=True)
+    print("%s batch inputs ready: %d searches, %.3g pairs" % (label, len(reqs), P), file=sys.stderr, flush=True)
     ctx = asci.Context.get(0)
     gctx = asci.Context(0)
 
@@ -207,10 +205,9 @@ def mode_batch(args, asci, syn, torch):
         asci.search(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, r.c.E0, sp["k"], ctx=ctx)
     torch.cuda.synchronize()
     per, single_out = [], []
-    t0 = time.perf_counter()
     for r, sp in zip(reqs, specs):
-        t1 = time.perf_counter()
         h, eri, dets, coeffs = r.keep
+        t1 = time.perf_counter()
         k_, s_ = asci.search(h, eri, sp["n"], sp["na"], sp["nb"], dets, coeffs, r.c.E0, sp["k"], ctx=ctx)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
@@ -218,7 +215,7 @@ def mode_batch(args, asci, syn, torch):
         pairs = sp["ndets"] * sd_per_det(sp["n"], sp["na"], sp["nb"])
         per.append({"norb": sp["n"], "nalpha": sp["na"], "ndets": sp["ndets"], "k": sp["k"], "pairs": pairs,
                     "single_ms": round(dt * 1e3, 3), "graph": bool(asci.graph_capable(r, ctx=gctx))})
-    single = time.perf_counter() - t0
+    single = sum(p["single_ms"] for p in per) * 1e-3
 
     def identical(res):
         got = snapshot()
@@ -235,27 +232,39 @@ def mode_batch(args, asci, syn, torch):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, res
 
-    batch_graph, res_g = timed_batch(True)
-    same_g = identical(res_g)
-    print("graph batch %.3f s (identical %s)" % (batch_graph, same_g), file=sys.stderr, flush=True)
     batch_workers, res_w = timed_batch(False)
     same_w = identical(res_w)
-    print("worker batch %.3f s (identical %s)" % (batch_workers, same_w), file=sys.stderr, flush=True)
+    print("%s: one by one %.3f s, worker batch %.3f s (identical %s)" % (label, single, batch_workers, same_w),
+          file=sys.stderr, flush=True)
+    batch_graph, res_g = timed_batch(True)
+    same_g = identical(res_g)
+    print("%s: graph batch %.3f s (identical %s)" % (label, batch_graph, same_g), file=sys.stderr, flush=True)
     sub = [i for i, p in enumerate(per) if p["graph"]]
-    sub_single = sum(per[i]["single_ms"] for i in sub) * 1e-3
-    sub_graph, _ = timed_batch(True, sub)
-    sub_workers, _ = timed_batch(False, sub)
-    sub_pairs = sum(per[i]["pairs"] for i in sub)
+    out = {"searches": len(reqs), "contributions": P, "single_s": round(single, 4),
+           "batch_s": round(batch_workers, 4), "batch_graph_s": round(batch_graph, 4),
+           "single_contributions_per_s": P / single, "batch_contributions_per_s": P / batch_workers,
+           "speedup": single / batch_workers, "speedup_graph": single / batch_graph,
+           "identical_to_single": bool(same_g and same_w), "batch_slots": gctx.get_param("batch_slots")}
+    if sub and len(sub) < len(reqs):
+        sub_single = sum(per[i]["single_ms"] for i in sub) * 1e-3
+        sub_graph, _ = timed_batch(True, sub)
+        sub_workers, _ = timed_batch(False, sub)
+        out["graph_subset"] = {"searches": len(sub), "contributions": sum(per[i]["pairs"] for i in sub),
+                               "single_s": round(sub_single, 4), "graph_s": round(sub_graph, 4),
+                               "workers_s": round(sub_workers, 4), "speedup_graph": sub_single / sub_graph,
+                               "speedup_workers": sub_single / sub_workers}
+    out["per_search"] = per
     gctx.close()
-    return {"metric": "batched vs single searches", "searches": len(reqs), "contributions": P,
-            "single_s": round(single, 3), "batch_s": round(batch_graph, 3), "batch_workers_only_s": round(batch_workers, 3),
-            "single_contributions_per_s": P / single, "batch_contributions_per_s": P / batch_graph,
-            "speedup": single / batch_graph, "speedup_workers_only": single / batch_workers,
-            "identical_to_single": bool(same_g and same_w),
-            "graph_subset": {"searches": len(sub), "contributions": sub_pairs, "single_s": round(sub_single, 4),
-                             "graph_s": round(sub_graph, 4), "workers_s": round(sub_workers, 4),
-                             "speedup_graph": sub_single / sub_graph, "speedup_workers": sub_single / sub_workers},
-            "batch_slots": ctx.get_param("batch_slots"), "per_search": per}
+    return out
+
+
+def mode_batch(args, asci, syn, torch):
+    """Batched vs one-by-one searches on two batches: 64 searches of uneven
+    active spaces and core counts (most fill the GPU alone), and 256 small
+    searches (each far from filling it)."""
+    return {"metric": "batched vs single searches",
+            "uneven": _batch_compare(asci, syn, torch, syn.batch_specs(args.batch_count, seed=64), "uneven"),
+            "small": _batch_compare(asci, syn, torch, syn.small_batch_specs(4 * args.batch_count, seed=65), "small")}
 
 
 SERVE_MIX = [(0.70, dict(n=20, na=8, nb=8, ndets=1_000)), (0.25, dict(n=26, na=10, nb=10, ndets=10_000)),
@@ -265,8 +274,9 @@ SERVE_MIX = [(0.70, dict(n=20, na=8, nb=8, ndets=1_000)), (0.25, dict(n=26, na=1
 def mode_serve(args, asci, syn, torch):
     """Poisson arrivals of a 70/25/5 mix of (16e,20o)/10^3, (20e,26o)/10^4 and
     (24e,30o)/10^5 searches (k = 10 x cores) against the request server:
-    saturated throughput (after a warm-up pass), then latency p50/p99 at
-    fractions of it."""
+    each class's time alone, saturated throughput (after a warm-up pass),
+    then latency p50/p99 at fractions of it, overall and per class, against
+    1.5 x the largest class's time alone."""
     import numpy as np
 
     dev = torch.device("cuda", 0)
@@ -276,7 +286,7 @@ def mode_serve(args, asci, syn, torch):
         specs = [dict(base, seed=500 + 10 * len(pools) + j, sampler="level", tau=base["ndets"] / 10.0,
                       k=10 * base["ndets"]) for j in range(npool)]
         reqs, P = _requests(asci, syn, torch, specs, dev)
-        pools.append((frac, reqs, P / len(reqs)))
+        pools.append((frac, reqs, P / len(reqs), "%de%do/%d" % (base["na"] + base["nb"], base["n"], base["ndets"])))
     print("serve pools ready", file=sys.stderr, flush=True)
     rng = np.random.default_rng(55)
 
@@ -284,56 +294,78 @@ def mode_serve(args, asci, syn, torch):
         out = []
         for _ in range(count):
             u, acc = rng.random(), 0.0
-            for frac, reqs, per in pools:
+            for ci, (frac, reqs, per, _) in enumerate(pools):
                 acc += frac
                 if u <= acc:
-                    out.append((reqs[int(rng.integers(len(reqs)))], per))
+                    out.append((reqs[int(rng.integers(len(reqs)))], per, ci))
                     break
             else:
-                out.append((pools[-1][1][0], pools[-1][2]))
+                out.append((pools[-1][1][0], pools[-1][2], len(pools) - 1))
         return out
 
     srv = asci.Server(device=0, slots=args.slots)
+    # each class alone on the server (after one untimed run)
+    solo = []
+    for _, reqs, _, name in pools:
+        srv.wait(srv.submit(reqs[0]))
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            srv.wait(srv.submit(reqs[0]))
+            ts.append((time.perf_counter() - t0) * 1e3)
+        solo.append(min(ts))
+        print("alone %s: %.1f ms" % (name, solo[-1]), file=sys.stderr, flush=True)
+    bar_ms = 1.5 * max(solo)
     # saturated: everything queued at once, timed after an untimed pass of the
     # same requests that sizes the workers' workspaces
     batch = draw(args.requests)
-    for t in [srv.submit(r) for r, _ in batch]:
+    for t in [srv.submit(r) for r, _, _ in batch]:
         srv.wait(t)
     t0 = time.perf_counter()
-    tickets = [srv.submit(r) for r, _ in batch]
+    tickets = [srv.submit(r) for r, _, _ in batch]
     for t in tickets:
         srv.wait(t)
     sat_s = time.perf_counter() - t0
     sat_qps = len(batch) / sat_s
-    sat_cps = sum(per for _, per in batch) / sat_s
+    sat_cps = sum(per for _, per, _ in batch) / sat_s
+    print("saturated: %.2f requests/s" % sat_qps, file=sys.stderr, flush=True)
     points = []
-    for f in (0.25, 0.5, 0.75, 0.9):
+    for f in (0.5, 0.75, 0.9):
         qps = f * sat_qps
         batch = draw(args.requests)
         gaps = rng.exponential(1.0 / qps, len(batch))
-        lat = []
-        t_start = time.perf_counter()
-        due = t_start
+        due = time.perf_counter()
         sent = []
-        for (r, _), g in zip(batch, gaps):
+        for i, ((r, _, ci), g) in enumerate(zip(batch, gaps)):
             due += g
             now = time.perf_counter()
             if due > now:
                 time.sleep(due - now)
-            sent.append((srv.submit(r), time.perf_counter()))
-        res = [srv.wait(t) for t, _ in sent]
+            sent.append((srv.submit(r), ci))
+            if (i + 1) % 500 == 0:
+                print("load %.2f: %d sent" % (f, i + 1), file=sys.stderr, flush=True)
+        res = [(srv.wait(t), ci) for t, ci in sent]
         st = srv.stats()
-        lat = sorted(x.latency_ms for x in res if x is not None)
+        lat = np.array([x.latency_ms for x, _ in res])
+        cls = np.array([ci for _, ci in res])
+        per_class = {}
+        for ci, (_, _, _, name) in enumerate(pools):
+            m = lat[cls == ci]
+            if len(m):
+                per_class[name] = {"requests": int(len(m)), "p50_ms": float(np.percentile(m, 50)),
+                                   "p99_ms": float(np.percentile(m, 99)), "alone_ms": round(solo[ci], 2)}
         points.append({"load": f, "qps": round(qps, 3), "requests": len(batch),
                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                       "max_running": st["max_running"]})
-        print("load %.2f: p50 %.1f ms p99 %.1f ms" % (f, points[-1]["p50_ms"], points[-1]["p99_ms"]),
-              file=sys.stderr, flush=True)
+                       "p99_over_bar": float(np.percentile(lat, 99)) / bar_ms, "per_class": per_class,
+                       "max_running": st["max_running"], "bypassed": st["bypassed"]})
+        print("load %.2f: p50 %.1f ms p99 %.1f ms (bar %.1f ms)" % (f, points[-1]["p50_ms"], points[-1]["p99_ms"],
+                                                                  bar_ms), file=sys.stderr, flush=True)
     srv.close()
     return {"metric": "served searches: saturated throughput and latency under Poisson load",
             "mix": "70% (16e,20o)/1e3, 25% (20e,26o)/1e4, 5% (24e,30o)/1e5; k = 10 x cores",
-            "requests_per_point": args.requests, "slots": args.slots, "saturated_qps": sat_qps,
-            "saturated_contributions_per_s": sat_cps, "points": points}
+            "requests_per_point": args.requests, "slots": args.slots, "alone_ms": [round(x, 2) for x in solo],
+            "p99_bar_ms": bar_ms, "saturated_qps": sat_qps, "saturated_contributions_per_s": sat_cps,
+            "points": points}
 
 
 def mode_host(args, asci, syn, torch):
@@ -384,7 +416,7 @@ def main():
     ap.add_argument("--ncore", type=int, default=0, help="loop mode: N_cdets (0 = all)")
     ap.add_argument("--iters", type=int, default=4, help="loop mode: outer iterations")
     ap.add_argument("--batch-count", type=int, default=64, help="batch mode: searches")
-    ap.add_argument("--requests", type=int, default=200, help="serve mode: requests per load point")
+    ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
     ap.add_argument("--slots", type=int, default=4, help="serve mode: server worker slots")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
