@@ -106,9 +106,17 @@ struct EriPacked {
     int n;
     __device__ __forceinline__ double operator()(int p, int q, int r, int s) const
     {
-        const uint32_t pq = tri((uint32_t)orb(p, n), (uint32_t)orb(q, n));
-        const uint32_t rs = tri((uint32_t)orb(r, n), (uint32_t)orb(s, n));
-        return e[tri(pq, rs)];
+        uint32_t up = (uint32_t)p, uq = (uint32_t)q, ur = (uint32_t)r, us = (uint32_t)s;
+        // one range test for the four indices (orb's clamp and fault, taken together)
+        if (max(max(up, uq), max(ur, us)) >= (uint32_t)n) {
+            raise_fault(kFaultOrbital);
+            const uint32_t m = (uint32_t)n - 1u;
+            up = min(up, m);
+            uq = min(uq, m);
+            ur = min(ur, m);
+            us = min(us, m);
+        }
+        return e[tri(tri(up, uq), tri(ur, us))];
     }
 };
 

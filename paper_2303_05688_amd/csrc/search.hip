@@ -229,6 +229,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     uint8_t *occA = (uint8_t *)(cur + g.nc), *virA = occA + 64, *occB = occA + 128, *virB = occA + 192;
     // orbital pairs in the order unrank_pair enumerates them: lo | hi << 8
     uint16_t *pOA = (uint16_t *)(occA + 256), *pVA = pOA + g.npa2, *pOB = pVA + g.pva2, *pVB = pOB + g.npb2;
+    uint16_t *hpL = pVB + g.pvb2;  // npa2: alpha hole pairs whose doubles can reach the batch
     __shared__ uint32_t s_nsel;
 
     const uint64_t a = g.core_a[i], b = g.core_b[i];
@@ -359,27 +360,49 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             }
         }
     }
-    // alpha-alpha doubles, one record each
-    {
-        const uint32_t total = g.npa2 * g.pva2;
-        const uint32_t q64 = total ? 64u / g.pva2 : 0u, r64 = total ? 64u % g.pva2 : 0u;
-        uint32_t hp = total ? (uint32_t)lane / g.pva2 : 0u, pp = total ? (uint32_t)lane % g.pva2 : 0u;
+    // alpha-alpha doubles, one record each.  The class index grows with the
+    // alpha string, so the doubles of one hole pair lie between the classes of
+    // its smallest and largest targets (the two lowest and the two highest
+    // virtual orbitals added): hole pairs whose range misses the batch are
+    // left out, and the doubles of the others are enumerated flattened over
+    // (listed hole pair, particle pair), in the order of the full enumeration.
+    if (g.npa2 && g.pva2) {
+        const uint64_t vlo = (1ull << virA[0]) | (1ull << virA[1]);
+        const uint64_t vhi = (1ull << virA[va - 1]) | (1ull << virA[va - 2]);
+        uint32_t nact = 0;
+        for (uint32_t h0 = 0; h0 < g.npa2; h0 += 64) {
+            const uint32_t hp = h0 + (uint32_t)lane;
+            bool act = false;
+            if (hp < g.npa2) {
+                const uint32_t po = pOA[hp];
+                const uint64_t rest = a & ~((1ull << (po & 0xFFu)) | (1ull << (po >> 8)));
+                const uint32_t clo = class_of(rest | vlo, g.cmap), chi = class_of(rest | vhi, g.cmap);
+                act = chi >= g.c0 && clo < g.c0 + g.nc;
+            }
+            const uint64_t m = __ballot(act);
+            if (act) hpL[nact + (uint32_t)__popcll(m & lt)] = (uint16_t)hp;
+            nact += (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        const uint32_t total = nact * g.pva2;
+        const uint32_t q64 = 64u / g.pva2, r64 = 64u % g.pva2;
+        uint32_t k = (uint32_t)lane / g.pva2, pp = (uint32_t)lane % g.pva2;  // t = k * pva2 + pp
         for (uint32_t t0 = 0; t0 < total; t0 += 64) {
-            const uint32_t t = t0 + lane;  // = hp * pva2 + pp
+            const uint32_t t = t0 + lane;
             uint64_t holes = 0ull, parts = 0ull, a2 = a;
             uint32_t c = ~0u;
             if (t < total) {
-                const uint32_t po = pOA[hp], pv = pVA[pp];
+                const uint32_t po = pOA[hpL[k]], pv = pVA[pp];
                 holes = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
                 parts = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
                 a2 = (a & ~holes) | parts;
                 c = class_of(a2, g.cmap);
             }
             pp += r64;
-            hp += q64;
+            k += q64;
             if (pp >= g.pva2) {
                 pp -= g.pva2;
-                ++hp;
+                ++k;
             }
             const bool act = c >= g.c0 && c < g.c0 + g.nc;
             if (__ballot(act) == 0ull) continue;  // no double of this round is in the batch
@@ -1296,7 +1319,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.cap = Pb;
             ga.force_fault = ctx->fault_test;
             const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 +
-                               2 * ((size_t)ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
+                               2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
             k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
             ASCI_LAUNCH_CHECK();
         }
@@ -1681,7 +1704,7 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
         ga.cap = Pb;
         ga.force_fault = ctx->fault_test;
         const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)ga.nc * 4 + 256 +
-                           2 * ((size_t)ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
+                           2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
         k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
         ASCI_LAUNCH_CHECK();
     }
