@@ -183,7 +183,7 @@ def _requests(asci, syn, torch, specs, dev):
     return reqs, pairs
 
 
-def _batch_compare(asci, syn, torch, specs, label):
+def _batch_compare(asci, syn, torch, specs, label, solo_pairs=None):
     """The searches of `specs` one by one on one context (each bracketed by
     device synchronisations; the total is the sum of those times), then as
     batches: every request on the worker streams, and the requests inside the
@@ -196,6 +196,8 @@ def _batch_compare(asci, syn, torch, specs, label):
     print("%s batch inputs ready: %d searches, %.3g pairs" % (label, len(reqs), P), file=sys.stderr, flush=True)
     ctx = asci.Context.get(0)
     gctx = asci.Context(0)
+    if solo_pairs is not None:
+        gctx.set_param("batch_solo_pairs", int(solo_pairs))
 
     def snapshot():
         return [(r.out_dets.view(torch.int64).cpu().numpy().copy(), r.out_scores.cpu().numpy().copy()) for r in reqs]
@@ -244,7 +246,8 @@ def _batch_compare(asci, syn, torch, specs, label):
            "batch_s": round(batch_workers, 4), "batch_graph_s": round(batch_graph, 4),
            "single_contributions_per_s": P / single, "batch_contributions_per_s": P / batch_workers,
            "speedup": single / batch_workers, "speedup_graph": single / batch_graph,
-           "identical_to_single": bool(same_g and same_w), "batch_slots": gctx.get_param("batch_slots")}
+           "identical_to_single": bool(same_g and same_w), "batch_slots": gctx.get_param("batch_slots"),
+           "batch_solo_pairs": gctx.get_param("batch_solo_pairs")}
     if sub and len(sub) < len(reqs):
         sub_single = sum(per[i]["single_ms"] for i in sub) * 1e-3
         sub_graph, _ = timed_batch(True, sub)
@@ -262,9 +265,11 @@ def mode_batch(args, asci, syn, torch):
     """Batched vs one-by-one searches on two batches: 64 searches of uneven
     active spaces and core counts (most fill the GPU alone), and 256 small
     searches (each far from filling it)."""
+    solo = args.batch_solo_pairs if args.batch_solo_pairs >= 0 else None
     return {"metric": "batched vs single searches",
-            "uneven": _batch_compare(asci, syn, torch, syn.batch_specs(args.batch_count, seed=64), "uneven"),
-            "small": _batch_compare(asci, syn, torch, syn.small_batch_specs(4 * args.batch_count, seed=65), "small")}
+            "uneven": _batch_compare(asci, syn, torch, syn.batch_specs(args.batch_count, seed=64), "uneven", solo),
+            "small": _batch_compare(asci, syn, torch, syn.small_batch_specs(4 * args.batch_count, seed=65), "small",
+                                    solo)}
 
 
 SERVE_MIX = [(0.70, dict(n=20, na=8, nb=8, ndets=1_000)), (0.25, dict(n=26, na=10, nb=10, ndets=10_000)),
@@ -304,6 +309,8 @@ def mode_serve(args, asci, syn, torch):
         return out
 
     srv = asci.Server(device=0, slots=args.slots)
+    if args.serve_solo_pairs > 0:
+        srv.set_param("solo_pairs", args.serve_solo_pairs)
     # each class alone on the server (after one untimed run)
     solo = []
     for _, reqs, _, name in pools:
@@ -319,12 +326,16 @@ def mode_serve(args, asci, syn, torch):
     # saturated: everything queued at once, timed after an untimed pass of the
     # same requests that sizes the workers' workspaces
     batch = draw(args.requests)
-    for t in [srv.submit(r) for r, _, _ in batch]:
+    for i, t in enumerate([srv.submit(r) for r, _, _ in batch]):
         srv.wait(t)
+        if (i + 1) % 250 == 0:
+            print("saturated warm-up: %d done" % (i + 1), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     tickets = [srv.submit(r) for r, _, _ in batch]
-    for t in tickets:
+    for i, t in enumerate(tickets):
         srv.wait(t)
+        if (i + 1) % 250 == 0:
+            print("saturated: %d done" % (i + 1), file=sys.stderr, flush=True)
     sat_s = time.perf_counter() - t0
     sat_qps = len(batch) / sat_s
     sat_cps = sum(per for _, per, _ in batch) / sat_s
@@ -363,7 +374,8 @@ def mode_serve(args, asci, syn, torch):
     srv.close()
     return {"metric": "served searches: saturated throughput and latency under Poisson load",
             "mix": "70% (16e,20o)/1e3, 25% (20e,26o)/1e4, 5% (24e,30o)/1e5; k = 10 x cores",
-            "requests_per_point": args.requests, "slots": args.slots, "alone_ms": [round(x, 2) for x in solo],
+            "requests_per_point": args.requests, "slots": args.slots, "solo_pairs": args.serve_solo_pairs,
+            "alone_ms": [round(x, 2) for x in solo],
             "p99_bar_ms": bar_ms, "saturated_qps": sat_qps, "saturated_contributions_per_s": sat_cps,
             "points": points}
 
@@ -416,8 +428,12 @@ def main():
     ap.add_argument("--ncore", type=int, default=0, help="loop mode: N_cdets (0 = all)")
     ap.add_argument("--iters", type=int, default=4, help="loop mode: outer iterations")
     ap.add_argument("--batch-count", type=int, default=64, help="batch mode: searches")
+    ap.add_argument("--batch-solo-pairs", type=int, default=-1,
+                    help="batch mode: pairs at which a request runs alone (-1: the library default)")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
     ap.add_argument("--slots", type=int, default=4, help="serve mode: server worker slots")
+    ap.add_argument("--serve-solo-pairs", type=int, default=0,
+                    help="serve mode: requests of at least this many pairs run alone (0: off)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the search shards by "
