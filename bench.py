@@ -309,8 +309,6 @@ def mode_serve(args, asci, syn, torch):
         return out
 
     srv = asci.Server(device=0, slots=args.slots)
-    if args.serve_solo_pairs > 0:
-        srv.set_param("solo_pairs", args.serve_solo_pairs)
     # each class alone on the server (after one untimed run)
     solo = []
     for _, reqs, _, name in pools:
@@ -374,7 +372,7 @@ def mode_serve(args, asci, syn, torch):
     srv.close()
     return {"metric": "served searches: saturated throughput and latency under Poisson load",
             "mix": "70% (16e,20o)/1e3, 25% (20e,26o)/1e4, 5% (24e,30o)/1e5; k = 10 x cores",
-            "requests_per_point": args.requests, "slots": args.slots, "solo_pairs": args.serve_solo_pairs,
+            "requests_per_point": args.requests, "slots": args.slots,
             "alone_ms": [round(x, 2) for x in solo],
             "p99_bar_ms": bar_ms, "saturated_qps": sat_qps, "saturated_contributions_per_s": sat_cps,
             "points": points}
@@ -432,8 +430,6 @@ def main():
                     help="batch mode: pairs at which a request runs alone (-1: the library default)")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")
     ap.add_argument("--slots", type=int, default=4, help="serve mode: server worker slots")
-    ap.add_argument("--serve-solo-pairs", type=int, default=0,
-                    help="serve mode: requests of at least this many pairs run alone (0: off)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the search shards by "

@@ -515,11 +515,7 @@ int asci_server_create(int device, int64_t hbm_budget, int slots, asci_server **
 int asci_server_create_fake(int64_t hbm_budget, int slots, double ns_per_byte, asci_server **out);
 int asci_server_submit(asci_server *srv, const asci_request *req, uint64_t *ticket);
 /* Scheduler parameters: "age_ms" (>= 0), the wait after which the oldest
- * request can no longer be passed; "solo_pairs" (>= 0; 0, the default, turns
- * it off): a request of at least that many (core, target) pairs runs alone,
- * with a pair buffer sized for the whole budget: it starts once nothing else
- * runs, nothing starts beside it, and later requests wait behind it (none
- * passes it).  Unknown names or values: ASCI_EINVAL. */
+ * request can no longer be passed.  Unknown names or values: ASCI_EINVAL. */
 int asci_server_set_param(asci_server *srv, const char *name, double value);
 /* Bytes this server budgets for a request: the server caps each request's
  * pair buffer at hbm_budget / (slots * 160) records, so large requests run in

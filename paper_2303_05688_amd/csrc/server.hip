@@ -89,7 +89,6 @@ struct Job {
     double t_submit;
     int64_t footprint;
     int64_t pairs;
-    bool solo;  // runs alone: nothing starts beside it, later jobs wait behind it
 };
 
 struct WorkerState {
@@ -162,34 +161,21 @@ class Pool {
     // records, then halved while the whole workspace exceeds the budget (its
     // other parts, such as the class x core matrix and the spin tables, do
     // not shrink with the pair buffer), down to 2^20 records
-    // (a job that runs alone starts from a pair buffer sized for the whole budget)
     asci_request shaped(const asci_request &r) const
     {
         asci_request q = r;
         const int64_t rec = r.norb <= 32 ? 32 : 48;  // ping-pong keys + values per record
-        int64_t cap = is_solo(r) ? solo_cap() : (int64_t)cap_records_;
+        int64_t cap = (int64_t)cap_records_;
         if (q.opt.pair_buffer_bytes > 0) cap = std::max<int64_t>(1, std::min<int64_t>(cap, q.opt.pair_buffer_bytes / rec));
         q.opt.pair_buffer_bytes = cap * rec;
-        while (cap > (1 << 20) && request_footprint(q, (uint64_t)cap, finish_cap_) > budget_) {
+        while (cap > (1 << 20) && request_footprint(q, cap_records_, finish_cap_) > budget_) {
             cap = std::max<int64_t>(cap / 2, 1 << 20);
             q.opt.pair_buffer_bytes = cap * rec;
         }
         return q;
     }
 
-    bool is_solo(const asci_request &r) const { return solo_pairs_ > 0 && request_pairs(r) >= solo_pairs_; }
-    int64_t solo_cap() const { return std::max<int64_t>(1 << 20, std::min<int64_t>(1ll << 30, budget_ / 160)); }
-    uint64_t cap_of(const asci_request &r) const { return is_solo(r) ? (uint64_t)solo_cap() : cap_records_; }
-
-    int64_t footprint(const asci_request &r) const { return request_footprint(shaped(r), cap_of(r), finish_cap_); }
-
-    // requests of at least `pairs` pairs run alone (0: none)
-    void set_solo_pairs(int64_t pairs)
-    {
-        std::unique_lock<std::mutex> lk(mu_);
-        solo_pairs_ = pairs;
-        cv_work_.notify_all();
-    }
+    int64_t footprint(const asci_request &r) const { return request_footprint(shaped(r), cap_records_, finish_cap_); }
 
     int submit(const asci_request &r, uint64_t *ticket)
     {
@@ -197,8 +183,7 @@ class Pool {
         Job j;
         j.req = shaped(r);
         j.pairs = request_pairs(r);
-        j.solo = is_solo(r);
-        j.footprint = request_footprint(j.req, cap_of(r), finish_cap_);
+        j.footprint = request_footprint(j.req, cap_records_, finish_cap_);
         std::unique_lock<std::mutex> lk(mu_);
         j.ticket = next_ticket_++;
         *ticket = j.ticket;
@@ -341,22 +326,17 @@ class Pool {
     // fits; only the oldest once it has waited longer than the age bound
     static constexpr size_t npos = ~size_t(0);
     static constexpr size_t kScan = 64;  // jobs looked at past the head
-    // A job that runs alone starts once nothing runs, and the jobs behind it
-    // wait for it (none passes it).
     size_t choose_locked(int wi)
     {
-        if (queue_.empty() || solo_running_ > 0) return npos;
+        if (queue_.empty()) return npos;
         WorkerState &me = *ws_[(size_t)wi];
         const bool head_old = now_ms() - queue_.front().t_submit > age_ms_;
         const size_t lim = head_old ? 1 : std::min(queue_.size(), kScan);
-        for (size_t q = 0; q < lim; ++q) {
-            const Job &j = queue_[q];
-            if (j.solo && running_ > 0) return npos;
-            if (fits_locked(me, j.footprint)) {
+        for (size_t q = 0; q < lim; ++q)
+            if (fits_locked(me, queue_[q].footprint)) {
                 if (q > 0) ++bypassed_;
                 return q;
             }
-        }
         return npos;
     }
 
@@ -379,7 +359,6 @@ class Pool {
                 me.busy = true;
                 me.reserved = need_for(me, j.footprint);
                 ++running_;
-                if (j.solo) ++solo_running_;
                 max_running_ = std::max<int64_t>(max_running_, running_);
                 peak_bytes_ = std::max(peak_bytes_, committed_locked());
             }
@@ -419,7 +398,6 @@ class Pool {
                 std::unique_lock<std::mutex> lk(mu_);
                 me.busy = false;
                 me.reserved = 0;
-                if (j.solo) --solo_running_;
                 me.resident = fake_ ? std::max(me.resident, j.footprint)
                                     : (int64_t)(me.ctx->setup.capacity() + me.ctx->main.capacity() +
                                                 me.ctx->tables.capacity());
@@ -452,8 +430,6 @@ class Pool {
     std::unordered_map<uint64_t, asci_result> done_;  // finished, not yet handed over
     std::unordered_set<uint64_t> live_;               // submitted, not yet handed over
     double age_ms_ = 250.0;
-    int64_t solo_pairs_ = 0;
-    int solo_running_ = 0;
     int64_t bypassed_ = 0;
     uint64_t next_ticket_ = 1;
     bool stop_ = false;
@@ -551,11 +527,6 @@ int asci_server_set_param(asci_server *srv, const char *name, double value)
     if (std::string(name) == "age_ms") {
         if (!(value >= 0.0)) return ASCI_EINVAL;
         srv->pool->set_age_bound(value);
-        return ASCI_OK;
-    }
-    if (std::string(name) == "solo_pairs") {
-        if (!(value >= 0.0) || value > 9.2e18) return ASCI_EINVAL;
-        srv->pool->set_solo_pairs((int64_t)value);
         return ASCI_OK;
     }
     return ASCI_EINVAL;

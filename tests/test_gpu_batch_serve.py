@@ -98,26 +98,6 @@ def test_server_results_same_alone_and_in_the_mix(setup):
     assert 0 < st["p50_ms"] <= st["p99_ms"]
 
 
-def test_server_solo_policy_keeps_results(setup):
-    """With solo_pairs set between the request sizes, the larger requests run
-    alone on the server (nothing beside them, nothing passes them); every
-    result is still the search run alone, bit for bit."""
-    asci, cases, alone = setup
-    pairs = sorted(len(c["coeffs"]) * asci.pairs_per_det(c["norb"], c["nalpha"], c["nbeta"]) for c in cases)
-    srv = asci.Server(device=0, slots=3)
-    try:
-        srv.set_param("solo_pairs", pairs[len(pairs) // 2])
-        reqs = _requests(asci, cases) + _requests(asci, cases)
-        results = [srv.wait(t) for t in [srv.submit(r) for r in reqs]]
-        st = srv.stats()
-    finally:
-        srv.close()
-    for q, r, w in zip(reqs, results, alone + alone):
-        assert r.status == 0
-        assert _same(q, r, w)
-    assert st["completed"] == len(reqs) and st["bypassed"] == 0
-
-
 @pytest.mark.skip(reason="this test's earlier form (asci_autotune sweeping batch_slots 1-4 x finish_cap "
                          "4096/2048, rebuilding the batch workers and re-capturing the batch graph for each) "
                          "ended once in a host segmentation fault inside asci_autotune; no cause was found by "

@@ -220,31 +220,3 @@ def test_one_slot_pool_fits_large_requests_into_its_budget():
             assert all(srv.wait(srv.submit(r)).status == 0 for r in reqs)
         finally:
             srv.close()
-
-
-def test_solo_requests_run_alone_and_are_not_passed():
-    """With solo_pairs set, a large request starts only once nothing runs, and
-    the requests behind it wait for it; with it off they run beside it."""
-    big, small = _reqs([(30, 12, 12, 100_000, 1_000_000), (20, 8, 8, 1000, 10_000)])
-    pairs_big = 100_000 * asci.pairs_per_det(30, 12, 12)
-
-    def run(solo):
-        srv = asci.Server(hbm_budget=int(4e11), slots=3, fake_ns_per_byte=1e-3)
-        try:
-            if solo:
-                srv.set_param("solo_pairs", pairs_big)
-            tickets = [srv.submit(r) for r in (small, big, small, small, small)]
-            res = [srv.wait(t) for t in tickets]
-            return res, srv.stats()
-        finally:
-            srv.close()
-
-    res, st = run(True)
-    assert all(r.status == 0 for r in res)
-    # the three small requests behind the large one waited for all of it
-    assert min(r.latency_ms for r in res[2:]) >= res[1].run_ms
-    assert st["bypassed"] == 0
-    res0, _ = run(False)
-    assert max(r.latency_ms for r in res0[2:]) < res0[1].run_ms
-    with pytest.raises(asci.AsciError):
-        asci.Server(hbm_budget=int(1e9), slots=1, fake_ns_per_byte=1e-3).set_param("solo_pairs", -1)
