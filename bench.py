@@ -236,6 +236,8 @@ def _batch_compare(asci, syn, torch, specs, label, solo_pairs=None):
 
     batch_workers, res_w = timed_batch(False)
     same_w = identical(res_w)
+    for p, rr in zip(per, res_w):  # each request's own time inside the batch
+        p["batch_run_ms"] = round(rr.run_ms, 3)
     print("%s: one by one %.3f s, worker batch %.3f s (identical %s)" % (label, single, batch_workers, same_w),
           file=sys.stderr, flush=True)
     batch_graph, res_g = timed_batch(True)

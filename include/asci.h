@@ -113,9 +113,9 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *                 the context's "finish_cap".
  *   "batch_solo_pairs": requests of asci_search_batch with at least this
  *                 many (core, target) pairs run one at a time on ctx itself
- *                 (default 2^30: those needing more than one class batch,
- *                 which fill the GPU alone); 0 sends every request to the
- *                 workers.
+ *                 (default 2^26: searches of that size fill the GPU alone,
+ *                 and two of them at once run slower than one after the
+ *                 other); 0 sends every request to the workers.
  *   "batch_graph": 1 runs the requests of asci_search_batch that fit
  *                 asci_search_async's scope as one captured graph; 0
  *                 (default) sends them to the worker streams.

@@ -144,7 +144,7 @@ struct asci_ctx {
     int spin_tables = 1;    // tunable: 1 = spin-string energy tables when they pay, 0 = never
     int fault_test = 0;     // 1: the next search raises a forced fault (tests of the error path)
     int batch_graph = 0;    // 1: batch requests within the asynchronous search's scope run as one graph
-    int64_t batch_solo_pairs = (int64_t)1 << 30;  // batch requests with this many pairs run alone (0: none)
+    int64_t batch_solo_pairs = (int64_t)1 << 26;  // batch requests with this many pairs run alone (0: none)
     int use_tuned = 1;      // 1: a search takes the tuned finish_cap of its shape when one is recorded
     // diagnostics of the last search
     int64_t last_batches = 0, last_finals = 0, last_levels = 0, last_candidates = 0;

@@ -35,11 +35,10 @@ struct NoAllocDevice {
 
 NoAllocDevice g_dev[kMaxDevices];
 
-// set-up on the device's first call (that device current): the region's address
-NoAllocDevice &device_state(int dev)
+// set-up on the device's first call (that device current, d.mu held): the
+// region's address
+void setup_locked(NoAllocDevice &d, int dev)
 {
-    require(dev >= 0 && dev < kMaxDevices, ASCI_EINVAL, "device index out of range");
-    NoAllocDevice &d = g_dev[dev];
     if (!d.ptr) {
         void *p = nullptr;
         ASCI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
@@ -52,7 +51,6 @@ NoAllocDevice &device_state(int dev)
         d.ctx->stage.attach(d.host, kHostStageBytes);
         d.ptr = (char *)p;
     }
-    return d;
 }
 
 }  // namespace
@@ -74,8 +72,10 @@ extern "C" int asci_search_device_noalloc(const double *d_h, const double *d_eri
         asci_options o = resolve(opt);
         int dev = 0;
         ASCI_HIP(hipGetDevice(&dev));
-        NoAllocDevice &d = device_state(dev);
+        require(dev >= 0 && dev < kMaxDevices, ASCI_EINVAL, "device index out of range");
+        NoAllocDevice &d = g_dev[dev];
         std::lock_guard<std::mutex> lk(d.mu);
+        setup_locked(d, dev);
         // one class batch holds every pair: the pair buffer is sized from the
         // closed-form count, so no free-memory query or extra batch is needed
         SearchArgs in{d_h, d_eri, norb, nalpha, nbeta, d_dets, d_coeffs, ndets, E0, o};

@@ -28,21 +28,30 @@ using Key = std::tuple<std::string, int, int, int>;
 std::mutex g_tune_mu;
 std::map<Key, int> g_tune;
 
-std::string arch_of(int device)
+std::map<int, std::string> g_arch;  // per device, read once (guarded by g_tune_mu)
+
+std::string arch_of_locked(int device)
 {
+    auto it = g_arch.find(device);
+    if (it != g_arch.end()) return it->second;
     hipDeviceProp_t p;
     if (hipGetDeviceProperties(&p, device) != hipSuccess) {
         (void)hipGetLastError();
-        return "unknown";
+        return "unknown";  // not kept: a device may appear later
     }
     std::string a(p.gcnArchName);
     const size_t c = a.find(':');  // drop feature suffixes (":sramecc+:xnack-")
-    return c == std::string::npos ? a : a.substr(0, c);
+    a = c == std::string::npos ? a : a.substr(0, c);
+    g_arch[device] = a;
+    return a;
 }
 
 int bucket_of(uint64_t pairs) { return pairs ? 63 - __builtin_clzll(pairs) : 0; }
 
-Key key_of(int device, int norb, int na, uint64_t pairs) { return Key{arch_of(device), norb, na, bucket_of(pairs)}; }
+Key key_of_locked(int device, int norb, int na, uint64_t pairs)
+{
+    return Key{arch_of_locked(device), norb, na, bucket_of(pairs)};
+}
 
 }  // namespace
 
@@ -51,7 +60,7 @@ int effective_finish_cap(const asci_ctx *ctx, int norb, int na, uint64_t pairs)
     if (!ctx->use_tuned) return ctx->finish_cap;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (g_tune.empty()) return ctx->finish_cap;
-    auto it = g_tune.find(key_of(ctx->device, norb, na, pairs));
+    auto it = g_tune.find(key_of_locked(ctx->device, norb, na, pairs));
     return it == g_tune.end() ? ctx->finish_cap : it->second;
 }
 
@@ -68,7 +77,17 @@ int asci_tune_shapes(asci_ctx *ctx, const asci_request *reqs, int nreq, int *out
         ASCI_HIP(hipSetDevice(ctx->device));
         int tuned = 0;
         std::map<Key, bool> seen;
-        const int saved_cap = ctx->finish_cap, saved_use = ctx->use_tuned;
+        // the context's own settings come back however the timing ends
+        struct Restore {
+            asci_ctx *c;
+            int cap, use;
+            ~Restore()
+            {
+                c->finish_cap = cap;
+                c->use_tuned = use;
+            }
+        } restore{ctx, ctx->finish_cap, ctx->use_tuned};
+        const int saved_cap = ctx->finish_cap;
         ctx->use_tuned = 0;
         for (int i = 0; i < nreq; ++i) {
             const asci_request &r = reqs[i];
@@ -76,7 +95,11 @@ int asci_tune_shapes(asci_ctx *ctx, const asci_request *reqs, int nreq, int *out
             require(r.k >= 1 && r.h && r.eri && r.dets && r.coeffs && r.out_dets && r.out_scores, ASCI_EINVAL,
                     "bad request");
             SearchArgs in{r.h, r.eri, r.norb, r.nalpha, r.nbeta, r.dets, r.coeffs, r.ndets, r.E0, resolve(&r.opt)};
-            const Key key = key_of(ctx->device, r.norb, r.nalpha, search_pairs(in));
+            Key key;
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                key = key_of_locked(ctx->device, r.norb, r.nalpha, search_pairs(in));
+            }
             if (seen.count(key)) continue;
             seen[key] = true;
             double best = 1e300;
@@ -105,8 +128,6 @@ int asci_tune_shapes(asci_ctx *ctx, const asci_request *reqs, int nreq, int *out
             }
             ++tuned;
         }
-        ctx->finish_cap = saved_cap;
-        ctx->use_tuned = saved_use;
         if (out_tuned) *out_tuned = tuned;
         return ASCI_OK;
     } catch (const Error &e) {
@@ -132,7 +153,7 @@ int asci_tune_lookup(int device, int norb, int nalpha, int64_t pairs, int *finis
 {
     if (!finish_cap || pairs < 0) return ASCI_EINVAL;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(key_of(device, norb, nalpha, (uint64_t)pairs));
+    auto it = g_tune.find(key_of_locked(device, norb, nalpha, (uint64_t)pairs));
     *finish_cap = it == g_tune.end() ? 0 : it->second;
     return ASCI_OK;
 }
@@ -140,7 +161,11 @@ int asci_tune_lookup(int device, int norb, int nalpha, int64_t pairs, int *finis
 int asci_tune_arch(int device, char *buf, int cap)
 {
     if (!buf || cap < 1) return ASCI_EINVAL;
-    const std::string a = arch_of(device);
+    std::string a;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        a = arch_of_locked(device);
+    }
     if ((int)a.size() + 1 > cap) return ASCI_EINVAL;
     std::memcpy(buf, a.c_str(), a.size() + 1);
     return ASCI_OK;

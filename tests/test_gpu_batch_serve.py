@@ -235,3 +235,28 @@ def test_per_shape_tuning_keeps_results(setup):
             assert (host(k) == want[0]).all() and (host(s) == want[1]).all()
     finally:
         asci.tune_clear()
+
+
+def test_tuning_failure_leaves_the_context_as_it_was(setup):
+    """A request that fails inside asci_tune_shapes (here k = 0, after a valid
+    one has been timed) fails the call; the context's finish_cap and
+    use_tuned are what they were before."""
+    asci, cases, alone = setup
+    ctx = asci.Context(0)
+    try:
+        ctx.set_param("finish_cap", 2048)
+        ctx.set_param("use_tuned", 0)
+        c = cases[0]
+        d = c["dev"]
+        good = asci.SearchRequest(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], c["E0"],
+                                  c["kk"])
+        bad = asci.SearchRequest(d["h"], d["eri"], c["norb"], c["nalpha"], c["nbeta"], d["dets"], d["coeffs"], c["E0"],
+                                 c["kk"])
+        bad.c.k = 0
+        asci.tune_clear()
+        with pytest.raises(asci.AsciError):
+            asci.tune_shapes([good, bad], ctx=ctx)
+        assert ctx.get_param("finish_cap") == 2048 and ctx.get_param("use_tuned") == 0
+    finally:
+        asci.tune_clear()
+        ctx.close()
