@@ -472,7 +472,7 @@ def main():
 
 def measure_search(args, asci, syn, torch, np, ctx, workload, steps, warmup, full):
     """Time `steps` whole searches of `workload` after `warmup` untimed ones.
-    full: the default line (roofline of the dominant kernel, per-phase
+    full: the headline line (roofline of the dominant kernel, per-phase
     breakdown); otherwise the rate and wall time only."""
     case = syn.workload(workload)
     n, na, nb = case["norb"], case["nalpha"], case["nbeta"]

@@ -1096,16 +1096,30 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
                 const uint64_t a = W == 1 ? (lo >> n) : hi, b = W == 1 ? (lo & nmask) : lo;
                 double haa;
                 const uint32_t ai = S.aidx[u];
+                // E(beta) first: a table entry read at random from HBM, whose
+                // latency then overlaps the LDS work below (the sums keep their order)
+                const double eb = cached ? spin_e(st, 1, X, hd, n, b) : 0.0;
+                double cross = 0.0;
                 if (cached) {
                     const double *cs = colsum + (size_t)ai * n;
-                    const double cross = n <= 32 ? bit_sum<uint32_t>((uint32_t)b, [&](int q) { return cs[q]; })
-                                                 : bit_sum<uint64_t>(b, [&](int q) { return cs[q]; });
-                    haa = ((f.ecore + ealpha[ai]) + spin_e(st, 1, X, hd, n, b)) + cross;
-                } else {
-                    haa = diag_tab(st, J, X, hd, n, f.ecore, a, b);
+                    cross = n <= 32 ? bit_sum<uint32_t>((uint32_t)b, [&](int q) { return cs[q]; })
+                                    : bit_sum<uint64_t>(b, [&](int q) { return cs[q]; });
                 }
+                if (f.eps <= 0.0) {
+                    // the run's values, in sorted (= record, ascending core)
+                    // order, four in flight at a time, added in order
+                    for (uint32_t j = j0; j < j1; j += 4) {
+                        double v[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) v[k] = S.val[min(j + (uint32_t)k, j1 - 1u)];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) sum = j + (uint32_t)k < j1 ? sum + v[k] : sum;
+                    }
+                    keep = true;
+                }
+                if (cached) haa = ((f.ecore + ealpha[ai]) + eb) + cross;
+                else haa = diag_tab(st, J, X, hd, n, f.ecore, a, b);
                 const double den = f.E0 - haa;
-                // the run's values, in sorted (= record, ascending core) order
                 if (f.eps > 0.0) {
                     // Alg. 2's threshold, per pair
                     for (uint32_t j = j0; j < j1; ++j) {
@@ -1115,16 +1129,6 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
                             keep = true;
                         }
                     }
-                } else {
-                    // four values in flight at a time, added in order
-                    for (uint32_t j = j0; j < j1; j += 4) {
-                        double v[4];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) v[k] = S.val[min(j + (uint32_t)k, j1 - 1u)];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) sum = j + (uint32_t)k < j1 ? sum + v[k] : sum;
-                    }
-                    keep = true;
                 }
                 score = sum / den;
                 keep = keep && abs_order(score) >= thr;
