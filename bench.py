@@ -183,7 +183,7 @@ def _requests(asci, syn, torch, specs, dev):
     return reqs, pairs
 
 
-def _batch_compare(asci, syn, torch, specs, label, solo_pairs=None):
+def _batch_compare(asci, syn, torch, specs, label, solo_pairs=None, slots=None):
     """The searches of `specs` one by one on one context (each bracketed by
     device synchronisations; the total is the sum of those times), then as
     batches: every request on the worker streams, and the requests inside the
@@ -198,6 +198,8 @@ def _batch_compare(asci, syn, torch, specs, label, solo_pairs=None):
     gctx = asci.Context(0)
     if solo_pairs is not None:
         gctx.set_param("batch_solo_pairs", int(solo_pairs))
+    if slots is not None:
+        gctx.set_param("batch_slots", int(slots))
 
     def snapshot():
         return [(r.out_dets.view(torch.int64).cpu().numpy().copy(), r.out_scores.cpu().numpy().copy()) for r in reqs]
@@ -268,10 +270,12 @@ def mode_batch(args, asci, syn, torch):
     active spaces and core counts (most fill the GPU alone), and 256 small
     searches (each far from filling it)."""
     solo = args.batch_solo_pairs if args.batch_solo_pairs >= 0 else None
+    slots = args.batch_slots if args.batch_slots > 0 else None
     return {"metric": "batched vs single searches",
-            "uneven": _batch_compare(asci, syn, torch, syn.batch_specs(args.batch_count, seed=64), "uneven", solo),
+            "uneven": _batch_compare(asci, syn, torch, syn.batch_specs(args.batch_count, seed=64), "uneven", solo,
+                                     slots),
             "small": _batch_compare(asci, syn, torch, syn.small_batch_specs(4 * args.batch_count, seed=65), "small",
-                                    solo)}
+                                    solo, slots)}
 
 
 SERVE_MIX = [(0.70, dict(n=20, na=8, nb=8, ndets=1_000)), (0.25, dict(n=26, na=10, nb=10, ndets=10_000)),
@@ -428,6 +432,7 @@ def main():
     ap.add_argument("--ncore", type=int, default=0, help="loop mode: N_cdets (0 = all)")
     ap.add_argument("--iters", type=int, default=4, help="loop mode: outer iterations")
     ap.add_argument("--batch-count", type=int, default=64, help="batch mode: searches")
+    ap.add_argument("--batch-slots", type=int, default=0, help="batch mode: worker slots (0: the library default)")
     ap.add_argument("--batch-solo-pairs", type=int, default=-1,
                     help="batch mode: pairs at which a request runs alone (-1: the library default)")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per load point")

@@ -100,7 +100,7 @@ int asci_ctx_destroy(asci_ctx *ctx);
  *                 workgroup of cap / 8 threads takes a bucket; smaller
  *                 buckets let more workgroups share a CU but need more split
  *                 passes.
- *   "batch_slots": concurrent searches of asci_search_batch, 1..8 (default 2).
+ *   "batch_slots": concurrent searches of asci_search_batch, 1..8 (default 4).
  *   "spin_tables": 1 (default) tabulates E(s) of every alpha and beta string
  *                 (at most 2^27 strings per spin, and only when the search
  *                 has at least four pairs per string) so the diagonal element

@@ -140,7 +140,7 @@ struct ProfScope {
 struct asci_ctx {
     int device = 0;
     int finish_cap = 4096;  // tunable: records per LDS bucket (see asci_ctx_set_param)
-    int batch_slots = 2;    // tunable: concurrent searches of a batch
+    int batch_slots = 4;    // tunable: concurrent searches of a batch
     int spin_tables = 1;    // tunable: 1 = spin-string energy tables when they pay, 0 = never
     int fault_test = 0;     // 1: the next search raises a forced fault (tests of the error path)
     int batch_graph = 0;    // 1: batch requests within the asynchronous search's scope run as one graph
