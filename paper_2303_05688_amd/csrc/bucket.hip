@@ -79,6 +79,14 @@ __device__ __forceinline__ bool key_less(uint64_t alo, uint64_t ahi, uint64_t bl
     return W == 1 ? alo < blo : (ahi < bhi || (ahi == bhi && alo < blo));
 }
 
+// a value every lane of the wavefront holds, moved to a scalar register
+__device__ __forceinline__ uint64_t uniform64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
     const int lane = threadIdx.x & 63;
@@ -698,15 +706,17 @@ __device__ __forceinline__ int key_top(uint64_t vlo, uint64_t vhi, int n)
 // rebuilt from its window and the segment's constant bits); the values are
 // then gathered from the segment in sorted order.  After the sort ix[cur ^ 1] holds the run
 // heads, `aidx` (over the digit counters) each run's alpha slot, and `acache`
-// the strings, E(alpha) and c_q(alpha) of up to a few dozen alpha strings.
+// E(alpha) and c_q(alpha) of the segment's alpha strings when they fit: a
+// segment whose keys need two or more windows reads its keys from memory
+// after the sort, so the window array `ck` just before `acache` extends it.
 template <int W, int CAP, int NT>
 struct FinishLds {
     static constexpr int NW = NT / 64;
     static constexpr uint32_t kAcacheBytes = CAP;
     uint32_t ck[CAP];
+    uint64_t acache[kAcacheBytes / 8];
     uint16_t ix[2][CAP + 8];
     double val[CAP];
-    uint64_t acache[kAcacheBytes / 8];
     union {
         uint16_t wcnt[NW][256];
         uint8_t aidx[CAP];
@@ -714,7 +724,7 @@ struct FinishLds {
     uint32_t dbase[256];
     uint32_t tmp[2 * NW];
     uint32_t nruns, nalpha;
-    uint64_t red[4][NW];  // per-wave OR / AND of the key words
+    uint64_t red[2][NW];  // per wave: OR of the key words' differences from the first key
 };
 
 // one final segment, processed by the whole workgroup
@@ -777,8 +787,11 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
     // stay in registers for their windows; two-word keys are read again, from
     // cache.
     uint64_t rk[IT];
+    // the bits that vary inside the segment: those in which some key differs
+    // from the first (one OR reduction; the constant bits are the first key's)
+    const uint64_t k0lo = size ? gk[0] : 0ull, k0hi = (W == 2 && size) ? gh[0] : 0ull;
     {
-        uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
+        uint64_t d0 = 0ull, d1 = 0ull;
         double rv[IT];
         // record r = wv * 64 * IT + k * 64 + lane: the layout of the radix
         // passes' items, so the first pass ranks straight from these registers
@@ -792,43 +805,31 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
         for (int k = 0; k < IT; ++k) {
             const uint32_t r = (uint32_t)wv * 64 * IT + (uint32_t)k * 64 + (uint32_t)lane;
             if (r < size) {
-                const uint64_t lo = rk[k], hi = W == 2 ? gh[r] : 0ull;
                 S.val[r] = rv[k];
-                o0 |= lo;
-                a0 &= lo;
-                o1 |= hi;
-                a1 &= hi;
+                d0 |= rk[k] ^ k0lo;
+                if (W == 2) d1 |= gh[r] ^ k0hi;
             }
         }
         for (int d = 32; d >= 1; d >>= 1) {
-            o0 |= __shfl_xor(o0, d, 64);
-            a0 &= __shfl_xor(a0, d, 64);
-            o1 |= __shfl_xor(o1, d, 64);
-            a1 &= __shfl_xor(a1, d, 64);
+            d0 |= __shfl_xor(d0, d, 64);
+            if (W == 2) d1 |= __shfl_xor(d1, d, 64);
         }
         if (lane == 0) {
-            S.red[0][wv] = o0;
-            S.red[1][wv] = a0;
-            S.red[2][wv] = o1;
-            S.red[3][wv] = a1;
+            S.red[0][wv] = d0;
+            S.red[1][wv] = d1;
         }
     }
     __syncthreads();
-    uint64_t var_lo, var_hi, and_lo, and_hi;
-    {
-        uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
+    uint64_t var_lo = 0ull, var_hi = 0ull;
 #pragma unroll
-        for (int i = 0; i < NW; ++i) {
-            o0 |= S.red[0][i];
-            a0 &= S.red[1][i];
-            o1 |= S.red[2][i];
-            a1 &= S.red[3][i];
-        }
-        var_lo = o0 ^ a0;
-        var_hi = W == 2 ? (o1 ^ a1) : 0ull;
-        and_lo = a0;
-        and_hi = W == 2 ? a1 : 0ull;
+    for (int i = 0; i < NW; ++i) {
+        var_lo |= S.red[0][i];
+        if (W == 2) var_hi |= S.red[1][i];
     }
+    // the same for every lane: kept in scalar registers
+    var_lo = uniform64(var_lo);
+    var_hi = uniform64(var_hi);
+    const uint64_t and_lo = k0lo & ~var_lo, and_hi = k0hi & ~var_hi;
     const int low = key_low<W>(var_lo, var_hi, n);
     const int span = low < 0 ? 0 : key_top<W>(var_lo, var_hi, n) - low;
     const int nwin = (span + 31) / 32;  // 32-bit windows holding the varying bits
@@ -970,8 +971,10 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
         for (int i = 0; i < IT; ++i) gval[i] = j0 + i < size ? S.val[perm[j0 + i]] : 0.0;
     }
     const int aw = n - low;  // window bits at or above this one are alpha bits (one-word keys: also two-word)
-    const uint32_t amax = min(255u, L::kAcacheBytes / (8u * (uint32_t)(n + 2)));
-    double *ealpha = reinterpret_cast<double *>(&S.acache[0]);
+    const uint32_t cache_bytes = L::kAcacheBytes + (nwin >= 2 ? (uint32_t)sizeof(S.ck) : 0u);
+    const uint32_t amax = min(255u, cache_bytes / (8u * (uint32_t)(n + 2)));
+    static_assert(offsetof(L, acache) == sizeof(S.ck), "the window array must end where the cache starts");
+    double *ealpha = reinterpret_cast<double *>(nwin >= 2 ? (void *)&S.ck[0] : (void *)&S.acache[0]);
     double *colsum = ealpha + amax;
     uint32_t nalpha, nruns;
     {

@@ -118,6 +118,20 @@ struct EriPacked {
         }
         return e[tri(tri(up, uq), tri(ur, us))];
     }
+    // the entry at pair indices pq = tri(p, q), rs = tri(r, s), for callers
+    // whose orbitals come from the lists a kernel builds out of a validated
+    // string's bits (every index below n by construction, so no range test)
+    __device__ __forceinline__ double pairs(uint32_t pq, uint32_t rs) const { return e[tri(pq, rs)]; }
+    __device__ __forceinline__ double listed(int p, int q, int r, int s) const
+    {
+        return pairs(tri((uint32_t)p, (uint32_t)q), tri((uint32_t)r, (uint32_t)s));
+    }
+};
+
+// the packed integrals read through `listed` (orbitals from validated lists)
+struct EriListed {
+    EriPacked e;
+    __device__ __forceinline__ double operator()(int p, int q, int r, int s) const { return e.listed(p, q, r, s); }
 };
 
 // entries of the packed form of n orbitals
@@ -170,6 +184,19 @@ __device__ __forceinline__ double double_same_value(const double *__restrict__ e
                                                     uint64_t holes, uint64_t parts)
 {
     return double_same_value_e(EriFull{eri, n}, n, si, holes, parts);
+}
+
+// The same element times c, for holes p < r and particles q < s taken from
+// validated orbital lists: the sign (+-1) is applied to [(qp|sr) - (qr|sp)] * c
+// instead of before the product, which rounds to the same bits (negation is
+// exact and rounding is symmetric in sign).
+__device__ __forceinline__ double double_same_times(const EriPacked &eri, uint64_t si, int p, int r, int q, int s,
+                                                    double c)
+{
+    const uint64_t mid = (si & ~(1ull << p)) | (1ull << q);
+    const bool neg = between_sign(si, p, q) != between_sign(mid, r, s);
+    const double v = (eri.listed(q, p, s, r) - eri.listed(q, r, s, p)) * c;
+    return neg ? -v : v;
 }
 
 // opposite-spin double: alpha p -> q, beta r -> s: sign_a * sign_b * (qp|sr)

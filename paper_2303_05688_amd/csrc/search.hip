@@ -216,15 +216,19 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     const uint64_t lt = (1ull << lane) - 1ull;
     const int n = g.n;
     const uint32_t va = (uint32_t)(n - g.na), vb = (uint32_t)(n - g.nb);
+    // Every orbital below comes from the lists built here out of the core's
+    // bits below n (the input strings are validated), so the integrals are
+    // read without a range test (EriListed, EriPacked::pairs).
     const EriPacked E{g.eri8, n};
+    const EriListed L{E};
 
     double *asV = (double *)smem;                     // nas
     uint64_t *asA = (uint64_t *)(asV + g.nas);        // nas
     uint64_t *bsB = asA + g.nas;                      // nbs
     uint32_t *asP = (uint32_t *)(bsB + g.nbs);        // nas: slot, or ~0 outside the batch
-    uint32_t *asX = asP + g.nas;                      // nas: p | q << 8 | (sign < 0) << 16
+    uint32_t *asX = asP + g.nas;                      // nas: p | q << 8 | (sign < 0) << 16 | tri(p, q) << 20
     uint32_t *asL = asX + g.nas;                      // nas: compacted in-batch alpha singles
-    uint32_t *bsX = asL + g.nas;                      // nbs: r | s << 8 | (sign < 0) << 16
+    uint32_t *bsX = asL + g.nas;                      // nbs: r | s << 8 | (sign < 0) << 16 | tri(r, s) << 20
     uint32_t *cur = bsX + g.nbs;                      // nc cursors
     uint8_t *occA = (uint8_t *)(cur + g.nc), *virA = occA + 64, *occB = occA + 128, *virB = occA + 192;
     // orbital pairs in the order unrank_pair enumerates them: lo | hi << 8
@@ -256,8 +260,9 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const bool in = c >= g.c0 && c < g.c0 + g.nc;
         asA[u] = a2;
         // the element (an O(n) sum) only for singles whose class is in the batch
-        asV[u] = in ? single_value_e(g.h, E, n, a, b, p, q) : 0.0;
-        asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u);
+        asV[u] = in ? single_value_e(g.h, L, n, a, b, p, q) : 0.0;
+        asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u) |
+                 (tri((uint32_t)p, (uint32_t)q) << 20);
         asP[u] = in ? c - g.c0 : ~0u;
     }
     // occupied and virtual orbital pairs of both spins (hole and particle pairs
@@ -279,7 +284,8 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     for (uint32_t t = lane; t < g.nbs; t += 64) {
         const int r = occB[t / vb], s = virB[t % vb];
         bsB[t] = (b & ~(1ull << r)) | (1ull << s);
-        bsX[t] = (uint32_t)r | ((uint32_t)s << 8) | (between_sign(b, r, s) < 0 ? (1u << 16) : 0u);
+        bsX[t] = (uint32_t)r | ((uint32_t)s << 8) | (between_sign(b, r, s) < 0 ? (1u << 16) : 0u) |
+                 (tri((uint32_t)r, (uint32_t)s) << 20);
     }
     const uint32_t cs = class_of(a, g.cmap);
     const bool self_in = cs >= g.c0 && cs < g.c0 + g.nc;
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const uint32_t ns1 = min(g.nbs, g.f0);
         for (uint32_t t = lane; t < ns1; t += 64) {
             const uint32_t x = bsX[t];
-            const double hv = single_value_e(g.h, E, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
+            const double hv = single_value_e(g.h, L, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
             emit<W>(g, base + t, a, bsB[t], hv * ci);
         }
         // beta-beta doubles y = hole pair * pvb2 + particle pair, the pair
@@ -306,7 +312,8 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
                 const uint64_t hb = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
                 const uint64_t pb = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
                 const uint64_t b2 = (b & ~hb) | pb;
-                emit<W>(g, base + ns1 + y, a, b2, double_same_value_e(E, n, b, hb, pb) * ci);
+                emit<W>(g, base + ns1 + y, a, b2,
+                        double_same_times(E, b, (int)(po & 0xFFu), (int)(po >> 8), (int)(pv & 0xFFu), (int)(pv >> 8), ci));
                 pp += r64;
                 hp += q64;
                 if (pp >= g.pvb2) {
@@ -336,28 +343,27 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         if (lane == 0) s_nsel = nsel0 + (uint32_t)__popcll(sel);
         __syncthreads();
     }
-    // alpha-single blocks, flattened over (selected single, record)
-    {
-        const uint32_t total = s_nsel * g.f1;
-        const uint32_t q64 = 64u / g.f1, r64 = 64u % g.f1;
-        uint32_t k = (uint32_t)lane / g.f1, j = (uint32_t)lane % g.f1;  // t = k * f1 + j
+    // alpha-single blocks: the single at the block's first slot, then its
+    // alpha-beta doubles with every beta single, flattened over (selected
+    // single, beta single).  The double's integral (qp|sr) is read at the pair
+    // indices kept in the tables; its sign is applied to the product with c_i.
+    for (uint32_t k = lane; k < s_nsel; k += 64) {
+        const uint32_t u = asL[k];
+        emit<W>(g, (size_t)asP[u], asA[u], b, asV[u] * ci);
+    }
+    if (g.nbs) {
+        const uint32_t nbs = g.nbs, total = s_nsel * nbs;
+        const uint32_t q64 = 64u / nbs, r64 = 64u % nbs;
+        uint32_t k = (uint32_t)lane / nbs, j = (uint32_t)lane % nbs;  // t = k * nbs + j
         for (uint32_t t = lane; t < total; t += 64, j += r64, k += q64) {
-            if (j >= g.f1) {
-                j -= g.f1;
+            if (j >= nbs) {
+                j -= nbs;
                 ++k;
             }
             const uint32_t u = asL[k];
-            const uint64_t a2 = asA[u];
-            const size_t dst = (size_t)asP[u] + j;
-            if (j == 0) {
-                emit<W>(g, dst, a2, b, asV[u] * ci);
-            } else {
-                const uint32_t x = bsX[j - 1], xa = asX[u];
-                const int p = (int)(xa & 0xFFu), q = (int)((xa >> 8) & 0xFFu);
-                const int r = (int)(x & 0xFFu), s = (int)((x >> 8) & 0xFFu);
-                const int sg = (((xa ^ x) >> 16) & 1u) ? -1 : 1;
-                emit<W>(g, dst, a2, bsB[j - 1], (sg * E(q, p, s, r)) * ci);
-            }
+            const uint32_t x = bsX[j], xa = asX[u];
+            const double v = E.pairs(xa >> 20, x >> 20) * ci;
+            emit<W>(g, (size_t)asP[u] + 1u + j, asA[u], bsB[j], (((xa ^ x) >> 16) & 1u) ? -v : v);
         }
     }
     // alpha-alpha doubles, one record each.  The class index grows with the
@@ -390,9 +396,10 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         for (uint32_t t0 = 0; t0 < total; t0 += 64) {
             const uint32_t t = t0 + lane;
             uint64_t holes = 0ull, parts = 0ull, a2 = a;
-            uint32_t c = ~0u;
+            uint32_t c = ~0u, po = 0u, pv = 0u;
             if (t < total) {
-                const uint32_t po = pOA[hpL[k]], pv = pVA[pp];
+                po = pOA[hpL[k]];
+                pv = pVA[pp];
                 holes = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
                 parts = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
                 a2 = (a & ~holes) | parts;
@@ -412,7 +419,8 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             if (act) {
                 const size_t dst = (size_t)before + (uint32_t)__popcll(peers & lt);
                 if ((peers & lt) == 0ull) cur[key] = before + (uint32_t)__popcll(peers);
-                emit<W>(g, dst, a2, b, double_same_value_e(E, n, a, holes, parts) * ci);
+                emit<W>(g, dst, a2, b,
+                        double_same_times(E, a, (int)(po & 0xFFu), (int)(po >> 8), (int)(pv & 0xFFu), (int)(pv >> 8), ci));
             }
         }
     }
