@@ -113,12 +113,15 @@ __device__ __forceinline__ void put_key(uint64_t *klo, uint64_t *khi, size_t j, 
     }
 }
 
-// C(x, k) for k <= 6 and x < 64 (exact: every partial product is a binomial)
+// C(x, k) for k <= 6 and x < 64 (exact: every partial product is a binomial).
+// Unrolled, so that every division is by a constant (a multiply and a shift).
 __device__ __forceinline__ uint32_t choose_le6(uint32_t x, int k)
 {
     if ((int)x < k) return 0u;
     uint32_t r = 1u;
-    for (int i = 0; i < k; ++i) r = r * (x - (uint32_t)i) / (uint32_t)(i + 1);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        if (i < k) r = r * (x - (uint32_t)i) / (uint32_t)(i + 1);
     return r;
 }
 
@@ -233,7 +236,10 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     uint8_t *occA = (uint8_t *)(cur + g.nc), *virA = occA + 64, *occB = occA + 128, *virB = occA + 192;
     // orbital pairs in the order unrank_pair enumerates them: lo | hi << 8
     uint16_t *pOA = (uint16_t *)(occA + 256), *pVA = pOA + g.npa2, *pOB = pVA + g.pva2, *pVB = pOB + g.npb2;
-    uint16_t *hpL = pVB + g.pvb2;  // npa2: alpha hole pairs whose doubles can reach the batch
+    uint16_t *hpL = pVB + g.pvb2;  // npa2: alpha hole pairs whose doubles reach the batch
+    // npa2 each: their particle-pair ranges (first | end << 16), and the ranges' starts when flattened
+    uint32_t *hpR = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(hpL + g.npa2) + 3u) & ~(uintptr_t)3u);
+    uint32_t *hpS = hpR + g.npa2;
     __shared__ uint32_t s_nsel;
 
     const uint64_t a = g.core_a[i], b = g.core_b[i];
@@ -367,53 +373,102 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         }
     }
     // alpha-alpha doubles, one record each.  The class index grows with the
-    // alpha string, so the doubles of one hole pair lie between the classes of
-    // its smallest and largest targets (the two lowest and the two highest
-    // virtual orbitals added): hole pairs whose range misses the batch are
-    // left out, and the doubles of the others are enumerated flattened over
-    // (listed hole pair, particle pair), in the order of the full enumeration.
+    // alpha string, and for one hole pair the target grows with the particle
+    // pair's index (pairs are listed by their higher, then their lower
+    // orbital), so the doubles of a hole pair whose class lies in the batch
+    // are one range of particle pairs: bounded by the classes of its lowest
+    // and highest targets when those fall inside the batch, else found by a
+    // binary search.  The listed ranges are enumerated flattened, in the order
+    // of the full enumeration.
     if (g.npa2 && g.pva2) {
+        const uint32_t cend = g.c0 + g.nc;
         const uint64_t vlo = (1ull << virA[0]) | (1ull << virA[1]);
         const uint64_t vhi = (1ull << virA[va - 1]) | (1ull << virA[va - 2]);
+        // first particle pair whose target's class is at least cb (pva2: none)
+        auto first_at = [&](uint64_t rest, uint32_t cb) {
+            uint32_t l = 0u, r = g.pva2;
+            while (l < r) {
+                const uint32_t m = (l + r) >> 1;
+                const uint32_t pv = pVA[m];
+                const uint64_t a2 = rest | (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
+                if (class_of(a2, g.cmap) >= cb) r = m;
+                else l = m + 1u;
+            }
+            return l;
+        };
         uint32_t nact = 0;
         for (uint32_t h0 = 0; h0 < g.npa2; h0 += 64) {
             const uint32_t hp = h0 + (uint32_t)lane;
-            bool act = false;
+            uint32_t lo = 0u, hi = 0u;
             if (hp < g.npa2) {
                 const uint32_t po = pOA[hp];
                 const uint64_t rest = a & ~((1ull << (po & 0xFFu)) | (1ull << (po >> 8)));
                 const uint32_t clo = class_of(rest | vlo, g.cmap), chi = class_of(rest | vhi, g.cmap);
-                act = chi >= g.c0 && clo < g.c0 + g.nc;
+                if (chi >= g.c0 && clo < cend) {
+                    lo = clo >= g.c0 ? 0u : first_at(rest, g.c0);
+                    hi = chi < cend ? g.pva2 : first_at(rest, cend);
+                }
             }
+            const bool act = hi > lo;
             const uint64_t m = __ballot(act);
-            if (act) hpL[nact + (uint32_t)__popcll(m & lt)] = (uint16_t)hp;
+            if (act) {
+                const uint32_t slot = nact + (uint32_t)__popcll(m & lt);
+                hpL[slot] = (uint16_t)hp;
+                hpR[slot] = lo | (hi << 16);
+            }
             nact += (uint32_t)__popcll(m);
         }
         __syncthreads();
-        const uint32_t total = nact * g.pva2;
-        const uint32_t q64 = 64u / g.pva2, r64 = 64u % g.pva2;
-        uint32_t k = (uint32_t)lane / g.pva2, pp = (uint32_t)lane % g.pva2;  // t = k * pva2 + pp
-        for (uint32_t t0 = 0; t0 < total; t0 += 64) {
-            const uint32_t t = t0 + lane;
-            uint64_t holes = 0ull, parts = 0ull, a2 = a;
-            uint32_t c = ~0u, po = 0u, pv = 0u;
-            if (t < total) {
-                po = pOA[hpL[k]];
-                pv = pVA[pp];
-                holes = (1ull << (po & 0xFFu)) | (1ull << (po >> 8));
-                parts = (1ull << (pv & 0xFFu)) | (1ull << (pv >> 8));
-                a2 = (a & ~holes) | parts;
-                c = class_of(a2, g.cmap);
+        // starts of the listed ranges in the flattened order
+        uint32_t total = 0;
+        for (uint32_t k0 = 0; k0 < nact; k0 += 64) {
+            const uint32_t kk = k0 + (uint32_t)lane;
+            const uint32_t len = kk < nact ? (hpR[kk] >> 16) - (hpR[kk] & 0xFFFFu) : 0u;
+            uint32_t inc = len;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += y;
             }
-            pp += r64;
-            k += q64;
-            if (pp >= g.pva2) {
-                pp -= g.pva2;
+            if (kk < nact) hpS[kk] = total + inc - len;
+            total += __shfl(inc, 63, 64);
+        }
+        __syncthreads();
+        // the listed range of this lane's first item t = lane, and the offset in it
+        uint32_t k = 0, off = (uint32_t)lane;
+        if (nact) {
+            uint32_t l = 0, r = nact;  // the last range starting at or before lane
+            while (r - l > 1u) {
+                const uint32_t m = (l + r) >> 1;
+                if (hpS[m] <= (uint32_t)lane) l = m;
+                else r = m;
+            }
+            k = l;
+            off = (uint32_t)lane - hpS[k];
+        }
+        for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+            const bool act = t0 + (uint32_t)lane < total;
+            uint64_t a2 = a;
+            uint32_t c = g.c0, po = 0u, pv = 0u;
+            if (act) {
+                po = pOA[hpL[k]];
+                pv = pVA[(hpR[k] & 0xFFFFu) + off];
+                a2 = (a & ~((1ull << (po & 0xFFu)) | (1ull << (po >> 8)))) | (1ull << (pv & 0xFFu)) |
+                     (1ull << (pv >> 8));
+                c = class_of(a2, g.cmap);
+                // in the batch by construction; a class outside it is a logic error
+                if (c < g.c0 || c >= cend) {
+                    raise_fault(kFaultSlot);
+                    c = g.c0;
+                }
+            }
+            // the item 64 further on
+            off += 64u;
+            while (k + 1u < nact && off >= hpS[k + 1u] - hpS[k]) {
+                off -= hpS[k + 1u] - hpS[k];
                 ++k;
             }
-            const bool act = c >= g.c0 && c < g.c0 + g.nc;
-            if (__ballot(act) == 0ull) continue;  // no double of this round is in the batch
-            const uint32_t key = act ? c - g.c0 : 0u;
+            const uint32_t key = c - g.c0;
             const uint64_t peers = wave_match(key, act, g.nbits);
             const uint32_t before = cur[key];
             if (act) {
@@ -1327,7 +1382,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.cap = Pb;
             ga.force_fault = ctx->fault_test;
             const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 +
-                               2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
+                               2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 8 * (size_t)ga.npa2 + 68;
             k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
             ASCI_LAUNCH_CHECK();
         }
@@ -1712,7 +1767,7 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
         ga.cap = Pb;
         ga.force_fault = ctx->fault_test;
         const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)ga.nc * 4 + 256 +
-                           2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 64;
+                           2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 8 * (size_t)ga.npa2 + 68;
         k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
         ASCI_LAUNCH_CHECK();
     }
