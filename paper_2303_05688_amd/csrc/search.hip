@@ -180,6 +180,12 @@ struct GenArgs {
     int force_fault;  // raise kFaultForced once (tests of the error path)
 };
 
+// a spin string with the two orbitals of a single's table entry (p | q << 8) flipped
+__device__ __forceinline__ uint64_t flip2(uint64_t s, uint32_t x)
+{
+    return s ^ (1ull << (x & 0xFFu)) ^ (1ull << ((x >> 8) & 0xFFu));
+}
+
 template <int W>
 __device__ __forceinline__ void emit(const GenArgs &g, size_t dst, uint64_t a2, uint64_t b2, double v)
 {
@@ -225,10 +231,10 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     const EriPacked E{g.eri8, n};
     const EriListed L{E};
 
+    // (a single's target string is the core's string with the two orbital
+    // bits of its table entry flipped: flip2)
     double *asV = (double *)smem;                     // nas
-    uint64_t *asA = (uint64_t *)(asV + g.nas);        // nas
-    uint64_t *bsB = asA + g.nas;                      // nbs
-    uint32_t *asP = (uint32_t *)(bsB + g.nbs);        // nas: slot, or ~0 outside the batch
+    uint32_t *asP = (uint32_t *)(asV + g.nas);        // nas: slot, or ~0 outside the batch
     uint32_t *asX = asP + g.nas;                      // nas: p | q << 8 | (sign < 0) << 16 | tri(p, q) << 20
     uint32_t *asL = asX + g.nas;                      // nas: compacted in-batch alpha singles
     uint32_t *bsX = asL + g.nas;                      // nbs: r | s << 8 | (sign < 0) << 16 | tri(r, s) << 20
@@ -264,7 +270,6 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         const uint64_t a2 = (a & ~(1ull << p)) | (1ull << q);
         const uint32_t c = class_of(a2, g.cmap);
         const bool in = c >= g.c0 && c < g.c0 + g.nc;
-        asA[u] = a2;
         // the element (an O(n) sum) only for singles whose class is in the batch
         asV[u] = in ? single_value_e(g.h, L, n, a, b, p, q) : 0.0;
         asX[u] = (uint32_t)p | ((uint32_t)q << 8) | (between_sign(a, p, q) < 0 ? (1u << 16) : 0u) |
@@ -289,7 +294,6 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // beta singles: target, orbitals, sign
     for (uint32_t t = lane; t < g.nbs; t += 64) {
         const int r = occB[t / vb], s = virB[t % vb];
-        bsB[t] = (b & ~(1ull << r)) | (1ull << s);
         bsX[t] = (uint32_t)r | ((uint32_t)s << 8) | (between_sign(b, r, s) < 0 ? (1u << 16) : 0u) |
                  (tri((uint32_t)r, (uint32_t)s) << 20);
     }
@@ -305,7 +309,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
         for (uint32_t t = lane; t < ns1; t += 64) {
             const uint32_t x = bsX[t];
             const double hv = single_value_e(g.h, L, n, b, a, (int)(x & 0xFFu), (int)((x >> 8) & 0xFFu));
-            emit<W>(g, base + t, a, bsB[t], hv * ci);
+            emit<W>(g, base + t, a, flip2(b, x), hv * ci);
         }
         // beta-beta doubles y = hole pair * pvb2 + particle pair, the pair
         // indices advanced by the 64 records a lane strides over
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // indices kept in the tables; its sign is applied to the product with c_i.
     for (uint32_t k = lane; k < s_nsel; k += 64) {
         const uint32_t u = asL[k];
-        emit<W>(g, (size_t)asP[u], asA[u], b, asV[u] * ci);
+        emit<W>(g, (size_t)asP[u], flip2(a, asX[u]), b, asV[u] * ci);
     }
     if (g.nbs) {
         const uint32_t nbs = g.nbs, total = s_nsel * nbs;
@@ -369,7 +373,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             const uint32_t u = asL[k];
             const uint32_t x = bsX[j], xa = asX[u];
             const double v = E.pairs(xa >> 20, x >> 20) * ci;
-            emit<W>(g, (size_t)asP[u] + 1u + j, asA[u], bsB[j], (((xa ^ x) >> 16) & 1u) ? -v : v);
+            emit<W>(g, (size_t)asP[u] + 1u + j, flip2(a, xa), flip2(b, x), (((xa ^ x) >> 16) & 1u) ? -v : v);
         }
     }
     // alpha-alpha doubles, one record each.  The class index grows with the
@@ -1381,7 +1385,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.vals = v[0];
             ga.cap = Pb;
             ga.force_fault = ctx->fault_test;
-            const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)nc * 4 + 256 +
+            const size_t lds = (size_t)ga.nas * (8 + 4 + 4 + 4) + (size_t)ga.nbs * 4 + (size_t)nc * 4 + 256 +
                                2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 8 * (size_t)ga.npa2 + 68;
             k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
             ASCI_LAUNCH_CHECK();
@@ -1766,7 +1770,7 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
         ga.vals = v[0];
         ga.cap = Pb;
         ga.force_fault = ctx->fault_test;
-        const size_t lds = (size_t)ga.nas * (8 + 8 + 4 + 4 + 4) + (size_t)ga.nbs * (8 + 4) + (size_t)ga.nc * 4 + 256 +
+        const size_t lds = (size_t)ga.nas * (8 + 4 + 4 + 4) + (size_t)ga.nbs * 4 + (size_t)ga.nc * 4 + 256 +
                            2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 8 * (size_t)ga.npa2 + 68;
         k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
         ASCI_LAUNCH_CHECK();
