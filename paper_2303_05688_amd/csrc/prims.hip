@@ -56,9 +56,19 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t *__rest
     n = dev_n(n, dn);
     const size_t base = (size_t)blockIdx.x * kTile;
     uint32_t s = 0;
-    for (int i = threadIdx.x; i < kTile; i += kThreads) {
-        size_t j = base + i;
-        if (j < n) s += in[j];
+    if (base + kTile <= n && (reinterpret_cast<uintptr_t>(in) & 15u) == 0) {
+        // a whole tile: 16-byte loads, coalesced across the block
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
+#pragma unroll
+        for (int i = 0; i < kTile / 4 / kThreads; ++i) {
+            const uint4 q = p[i * kThreads + threadIdx.x];
+            s += (q.x + q.y) + (q.z + q.w);
+        }
+    } else {
+        for (int i = threadIdx.x; i < kTile; i += kThreads) {
+            size_t j = base + i;
+            if (j < n) s += in[j];
+        }
     }
     uint32_t tot;
     block_excl_scan<kWaves>(s, s_tmp, tot);
@@ -116,21 +126,56 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t *in, uint
     __shared__ uint32_t s_tmp[kWaves];
     n = dev_n(n, dn);
     const size_t base = (size_t)blockIdx.x * kTile + (size_t)threadIdx.x * kItems;
+    // a whole tile with aligned ends moves each thread's 16 items as four
+    // 16-byte words (the scan may run in place: every word is read before the
+    // block's barrier and written after it)
+    const bool full = (size_t)blockIdx.x * kTile + kTile <= n &&
+                      ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
     uint32_t v[kItems];
     uint32_t s = 0;
+    if (full) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-        size_t j = base + i;
-        v[i] = j < n ? in[j] : 0u;
-        s += v[i];
+        for (int i = 0; i < kItems / 4; ++i) {
+            const uint4 q = p[i];
+            v[4 * i] = q.x;
+            v[4 * i + 1] = q.y;
+            v[4 * i + 2] = q.z;
+            v[4 * i + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            size_t j = base + i;
+            v[i] = j < n ? in[j] : 0u;
+        }
     }
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) s += v[i];
     uint32_t tot;
     uint32_t e = block_excl_scan<kWaves>(s, s_tmp, tot) + partial[blockIdx.x];
+    if (full) {
+        uint4 *p = reinterpret_cast<uint4 *>(out + base);
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-        size_t j = base + i;
-        if (j < n) out[j] = e;
-        e += v[i];
+        for (int i = 0; i < kItems / 4; ++i) {
+            uint4 q;
+            q.x = e;
+            e += v[4 * i];
+            q.y = e;
+            e += v[4 * i + 1];
+            q.z = e;
+            e += v[4 * i + 2];
+            q.w = e;
+            e += v[4 * i + 3];
+            p[i] = q;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            size_t j = base + i;
+            if (j < n) out[j] = e;
+            e += v[i];
+        }
     }
 }
 
