@@ -35,8 +35,8 @@ namespace asci {
 
 namespace {
 
-constexpr int kTileT = 512;           // threads of the scatter (two workgroups per CU)
-constexpr int kTileItems = 8;
+constexpr int kTileT = 1024;          // threads of the scatter: two workgroups of 16 waves per CU
+constexpr int kTileItems = 4;
 constexpr int kHistT = 256;           // threads of the histogram pass
 constexpr int kTileN = kTileT * kTileItems;  // 4096 records per tile
 
@@ -530,14 +530,16 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
 }
 
 template <int W>
-__global__ __launch_bounds__(kTileT) void k_split_scatter(SplitArgs a, const uint32_t *__restrict__ scan,
+// eight waves per SIMD (64 VGPRs): the load, rank and write phases of four
+// workgroups' worth of waves overlap on each CU
+__global__ __launch_bounds__(kTileT) __attribute__((amdgpu_waves_per_eu(8))) void k_split_scatter(SplitArgs a, const uint32_t *__restrict__ scan,
                                                           const uint32_t *__restrict__ skip)
 {
     constexpr int NW = kTileT / 64;
     __shared__ uint64_t s_lo[kTileN];
     __shared__ uint64_t s_hi[W == 2 ? kTileN : 1];
     __shared__ double s_val[kTileN];
-    __shared__ uint32_t s_wcnt[NW][256];
+    __shared__ uint16_t s_wcnt[NW][256];  // counts and prefixes below kTileN
     __shared__ uint32_t s_dbase[256];
     __shared__ uint32_t s_gbase[256];
     __shared__ uint32_t s_tmp[NW];
