@@ -155,7 +155,7 @@ struct SplitArgs {
     int n;
     uint32_t cap;
     const uint64_t *spl_lo, *spl_hi;  // splitters: kMaxSplit - 1 per segment
-    unsigned long long *kor, *kand;   // per segment: OR and AND of its keys (2 words each)
+    unsigned long long *kvar;         // per segment: the key bits that vary in it (2 words each)
     uint8_t *dig;                     // per record: its digit, from the histogram pass
     const uint32_t *dn_seg = nullptr;    // device: segments of the level (nseg is then a bound)
     const uint32_t *dn_tiles = nullptr;  // device: tiles of the level (ntiles is then a bound)
@@ -311,18 +311,16 @@ __global__ __launch_bounds__(256) void k_seg_tiles(const Seg *__restrict__ segs,
     if (blockIdx.x == 0 && threadIdx.x == 0) *nnext = 0u;
 }
 
-// the segment of every tile; also starts the OR / AND of every segment's keys
+// the segment of every tile; also clears the varying-bit words of every segment
 __global__ __launch_bounds__(256) void k_seg_expand(const Seg *__restrict__ segs, uint32_t nseg,
                                                     const uint32_t *__restrict__ tile_base,
-                                                    uint32_t *__restrict__ tile_seg, unsigned long long *__restrict__ kor,
-                                                    unsigned long long *__restrict__ kand, const uint32_t *dn_seg)
+                                                    uint32_t *__restrict__ tile_seg, unsigned long long *__restrict__ kvar,
+                                                    const uint32_t *dn_seg)
 {
     const uint32_t ns = dev_count(nseg, dn_seg);
     for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < ns; s += gridDim.x * 256) {
-        kor[2 * s] = 0ull;
-        kor[2 * s + 1] = 0ull;
-        kand[2 * s] = ~0ull;
-        kand[2 * s + 1] = ~0ull;
+        kvar[2 * s] = 0ull;
+        kvar[2 * s + 1] = 0ull;
         const uint32_t nt = (segs[s].size + kTileN - 1) / kTileN, tb = tile_base[s];
         for (uint32_t t = 0; t < nt; ++t) tile_seg[tb + t] = s;
     }
@@ -354,7 +352,10 @@ __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
     load_splitters<W>(rule, a.spl_lo, a.spl_hi, s, spl_lo, spl_hi);
     const uint32_t r0 = tl * kTileN, r1 = min(sg.size, r0 + kTileN);
     const int wv = threadIdx.x >> 6;
-    uint64_t o0 = 0ull, a0 = ~0ull, o1 = 0ull, a1 = ~0ull;
+    // the bits in which some key differs from the segment's first key vary in
+    // the segment (one OR per word instead of an OR and an AND)
+    const uint64_t ref_lo = a.klo[buf][sg.start], ref_hi = W == 2 ? a.khi[buf][sg.start] : 0ull;
+    uint64_t d0 = 0ull, d1 = 0ull;
     // four records per step, their searches interleaved
     for (uint32_t rb = r0 + threadIdx.x; rb < r1; rb += 4 * kHistT) {
         uint64_t lo[4], hi[4];
@@ -372,10 +373,8 @@ __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
         for (int k = 0; k < 4; ++k) {
             const uint32_t r = rb + (uint32_t)k * kHistT;
             if (r < r1) {
-                o0 |= lo[k];
-                a0 &= lo[k];
-                o1 |= hi[k];
-                a1 &= hi[k];
+                d0 |= lo[k] ^ ref_lo;
+                d1 |= hi[k] ^ ref_hi;
                 a.dig[(size_t)sg.start + r] = (uint8_t)dg[k];
                 atomicAdd(&h[wv][dg[k]], 1u);
             }
@@ -383,18 +382,12 @@ __global__ __launch_bounds__(kHistT) void k_split_hist(SplitArgs a)
     }
     // which key bits vary inside the segment (for segments the split cannot divide)
     for (int dd = 32; dd >= 1; dd >>= 1) {
-        o0 |= __shfl_xor(o0, dd, 64);
-        a0 &= __shfl_xor(a0, dd, 64);
-        o1 |= __shfl_xor(o1, dd, 64);
-        a1 &= __shfl_xor(a1, dd, 64);
+        d0 |= __shfl_xor(d0, dd, 64);
+        if (W == 2) d1 |= __shfl_xor(d1, dd, 64);
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicOr(&a.kor[2 * s], (unsigned long long)o0);
-        atomicAnd(&a.kand[2 * s], (unsigned long long)a0);
-        if (W == 2) {
-            atomicOr(&a.kor[2 * s + 1], (unsigned long long)o1);
-            atomicAnd(&a.kand[2 * s + 1], (unsigned long long)a1);
-        }
+        atomicOr(&a.kvar[2 * s], (unsigned long long)d0);
+        if (W == 2) atomicOr(&a.kvar[2 * s + 1], (unsigned long long)d1);
     }
     __syncthreads();
     const int d = threadIdx.x;
@@ -421,8 +414,7 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
                                                         uint32_t *__restrict__ nfinal, uint32_t finals_cap,
                                                         Seg *__restrict__ next, uint32_t *__restrict__ nnext,
                                                         uint32_t next_cap, uint32_t *__restrict__ overflow,
-                                                        const unsigned long long *__restrict__ kor,
-                                                        const unsigned long long *__restrict__ kand, int n,
+                                                        const unsigned long long *__restrict__ kvar, int n,
                                                         const uint32_t *dn_seg)
 {
     __shared__ uint32_t s_cnt[256], s_off[256];
@@ -457,7 +449,7 @@ __global__ __launch_bounds__(256) void k_split_children(const Seg *__restrict__ 
             skip[s] = 1u;
             Seg c{sg.start, sg.size, 0u};
             // highest key bit that varies inside the segment, + 1 (0: one key)
-            const uint64_t v0 = kor[2 * s] ^ kand[2 * s], v1 = W == 2 ? (kor[2 * s + 1] ^ kand[2 * s + 1]) : 0ull;
+            const uint64_t v0 = kvar[2 * s], v1 = W == 2 ? kvar[2 * s + 1] : 0ull;
             const uint32_t vtop = W == 1 ? (v0 ? 64u - (uint32_t)__clzll((long long)v0) : 0u)
                                          : (v1 ? (uint32_t)n + 64u - (uint32_t)__clzll((long long)v1)
                                                : (v0 ? 64u - (uint32_t)__clzll((long long)v0) : 0u));
@@ -784,10 +776,9 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
 
     const uint32_t size = sg.size;
     // identity order; the values in record order (permuted in LDS once the
-    // sort is done, instead of gathered from memory in sorted order); OR / AND
-    // of the keys give the bits that vary inside the segment.  One-word keys
-    // stay in registers for their windows; two-word keys are read again, from
-    // cache.
+    // sort is done, instead of gathered from memory in sorted order).  One-word
+    // keys stay in registers for their windows; two-word keys are read again,
+    // from cache.
     uint64_t rk[IT];
     // the bits that vary inside the segment: those in which some key differs
     // from the first (one OR reduction; the constant bits are the first key's)
@@ -1442,9 +1433,8 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         uint32_t *hscan = ar.take<uint32_t>((size_t)ntiles * 256 + 1);
         uint64_t *spl_lo = ar.take<uint64_t>((size_t)nlarge * (kMaxSplit - 1));
         uint64_t *spl_hi = W == 2 ? ar.take<uint64_t>((size_t)nlarge * (kMaxSplit - 1)) : nullptr;
-        unsigned long long *kor = ar.take<unsigned long long>(2 * (size_t)nlarge);
-        unsigned long long *kand = ar.take<unsigned long long>(2 * (size_t)nlarge);
-        k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg, kor, kand, nullptr);
+        unsigned long long *kvar = ar.take<unsigned long long>(2 * (size_t)nlarge);
+        k_seg_expand<<<(nlarge + 255) / 256, 256, 0, s>>>(segs, nlarge, tbase, tseg, kvar, nullptr);
         ASCI_LAUNCH_CHECK();
         {
             ProfScope ps(prof, "split_sample", 0.0, s);
@@ -1472,8 +1462,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         sa.cap = (uint32_t)CAP;
         sa.spl_lo = spl_lo;
         sa.spl_hi = spl_hi;
-        sa.kor = kor;
-        sa.kand = kand;
+        sa.kvar = kvar;
         sa.dig = dig;
         {
             ProfScope ps(prof, "split_hist", (8.0 * W) * (double)ntiles * kTileN, s);
@@ -1482,7 +1471,7 @@ void bucket_accumulate(BucketArgs &b, Arena &ar, hipStream_t s, Profiler *prof, 
         }
         scan_u32(hist, hscan, (size_t)ntiles * 256, nullptr, ar, s, prof);
         k_split_children<W><<<nlarge, 256, 0, s>>>(segs, nlarge, tbase, hscan, (uint32_t)CAP, skip, finals, ctr,
-                                                   finals_cap, next, nnext, level_cap, ctr + 3, kor, kand, b.n, nullptr);
+                                                   finals_cap, next, nnext, level_cap, ctr + 3, kvar, b.n, nullptr);
         ASCI_LAUNCH_CHECK();
         sa.hist = hscan;
         {
@@ -1677,8 +1666,7 @@ void bucket_accumulate_dev(BucketArgs &b, Arena &ar, hipStream_t s, uint32_t *d_
     uint32_t *hscan = ar.take<uint32_t>((size_t)max_tiles * 256 + 1);
     uint64_t *spl_lo = ar.take<uint64_t>((size_t)level_cap * (kMaxSplit - 1));
     uint64_t *spl_hi = W == 2 ? ar.take<uint64_t>((size_t)level_cap * (kMaxSplit - 1)) : nullptr;
-    unsigned long long *kor = ar.take<unsigned long long>(2 * (size_t)level_cap);
-    unsigned long long *kand = ar.take<unsigned long long>(2 * (size_t)level_cap);
+    unsigned long long *kvar = ar.take<unsigned long long>(2 * (size_t)level_cap);
     // launch shapes: per-segment kernels stride over the level's segments, tile
     // kernels over its tiles (eight XCD groups of workgroups)
     const unsigned g_seg = std::min<uint32_t>(level_cap, 2048u);
@@ -1695,7 +1683,7 @@ void bucket_accumulate_dev(BucketArgs &b, Arena &ar, hipStream_t s, uint32_t *d_
         k_seg_tiles<<<g_seg256, 256, 0, s>>>(segs, level_cap, ntile, skip, nnext, dn_seg);
         ASCI_LAUNCH_CHECK();
         scan_u32(ntile, tbase, level_cap, d_ntiles, ar, s, nullptr, dn_seg);
-        k_seg_expand<<<g_seg256, 256, 0, s>>>(segs, level_cap, tbase, tseg, kor, kand, dn_seg);
+        k_seg_expand<<<g_seg256, 256, 0, s>>>(segs, level_cap, tbase, tseg, kvar, dn_seg);
         ASCI_LAUNCH_CHECK();
         if (lev == 0) k_seg_splitters<W, 1024><<<g_seg, 1024, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi, level_cap, dn_seg);
         else k_seg_splitters<W, 256><<<g_seg, 256, 0, s>>>(segs, (uint32_t)CAP, kb, spl_lo, spl_hi, level_cap, dn_seg);
@@ -1717,8 +1705,7 @@ void bucket_accumulate_dev(BucketArgs &b, Arena &ar, hipStream_t s, uint32_t *d_
         sa.cap = (uint32_t)CAP;
         sa.spl_lo = spl_lo;
         sa.spl_hi = spl_hi;
-        sa.kor = kor;
-        sa.kand = kand;
+        sa.kvar = kvar;
         sa.dig = dig;
         sa.dn_seg = dn_seg;
         sa.dn_tiles = d_ntiles;
@@ -1728,7 +1715,7 @@ void bucket_accumulate_dev(BucketArgs &b, Arena &ar, hipStream_t s, uint32_t *d_
         ASCI_LAUNCH_CHECK();
         scan_u32(hist, hscan, (size_t)max_tiles * 256, nullptr, ar, s, nullptr, d_ntiles + 1);
         k_split_children<W><<<g_seg, 256, 0, s>>>(segs, level_cap, tbase, hscan, (uint32_t)CAP, skip, finals, ctr,
-                                                  finals_cap, next, nnext, level_cap, ctr + 3, kor, kand, b.n, dn_seg);
+                                                  finals_cap, next, nnext, level_cap, ctr + 3, kvar, b.n, dn_seg);
         ASCI_LAUNCH_CHECK();
         sa.hist = hscan;
         k_split_scatter<W><<<g_tiles, kTileT, 0, s>>>(sa, hscan, skip);
