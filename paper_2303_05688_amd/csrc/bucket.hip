@@ -839,16 +839,20 @@ __device__ __forceinline__ void finish_segment(const FinishArgs &f, const SpinTa
     for (int win = 0; win < nwin; ++win) {
         const int o = low + 32 * win;
         const uint32_t vwin = key_window<W>(var_lo, var_hi, n, o);
-        const bool regs = W == 1 && win == 0;
+        // the first window comes from the low key words held in registers when
+        // it lies inside them (always for one-word keys; for two-word keys when
+        // it ends at or below bit n, i.e. inside the beta word)
+        const bool regs = win == 0 && (W == 1 || low + 32 <= n);
         if (W == 1 && !regs) {
 #pragma unroll
             for (int k = 0; k < IT; ++k) {
                 const uint32_t r = (uint32_t)wv * 64 * IT + (uint32_t)k * 64 + (uint32_t)lane;
                 if (r < size) S.ck[r] = key_window<W>(rk[k], 0ull, n, o);
             }
-        } else if (W == 2) {
+        } else if (W == 2 && !regs) {
             for (uint32_t r = tid; r < size; r += NT) S.ck[r] = key_window<W>(gk[r], gh[r], n, o);
-            // the first pass of two-word keys reads the identity order from LDS
+            // a first pass of two-word keys not taken from registers reads the
+            // identity order from LDS
             if (win == 0)
                 for (uint32_t r = tid; r < size; r += NT) S.ix[0][r] = (uint16_t)r;
         }
