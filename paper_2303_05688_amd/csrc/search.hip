@@ -243,9 +243,8 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // orbital pairs in the order unrank_pair enumerates them: lo | hi << 8
     uint16_t *pOA = (uint16_t *)(occA + 256), *pVA = pOA + g.npa2, *pOB = pVA + g.pva2, *pVB = pOB + g.npb2;
     uint16_t *hpL = pVB + g.pvb2;  // npa2: alpha hole pairs whose doubles reach the batch
-    // npa2 each: their particle-pair ranges (first | end << 16), and the ranges' starts when flattened
+    // npa2: their particle-pair ranges (first | end << 16)
     uint32_t *hpR = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(hpL + g.npa2) + 3u) & ~(uintptr_t)3u);
-    uint32_t *hpS = hpR + g.npa2;
     __shared__ uint32_t s_nsel;
 
     const uint64_t a = g.core_a[i], b = g.core_b[i];
@@ -382,8 +381,7 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
     // orbital), so the doubles of a hole pair whose class lies in the batch
     // are one range of particle pairs: bounded by the classes of its lowest
     // and highest targets when those fall inside the batch, else found by a
-    // binary search.  The listed ranges are enumerated flattened, in the order
-    // of the full enumeration.
+    // binary search.
     if (g.npa2 && g.pva2) {
         const uint32_t cend = g.c0 + g.nc;
         const uint64_t vlo = (1ull << virA[0]) | (1ull << virA[1]);
@@ -423,55 +421,53 @@ __global__ __launch_bounds__(64) void k_generate(GenArgs g)
             nact += (uint32_t)__popcll(m);
         }
         __syncthreads();
-        // starts of the listed ranges in the flattened order
-        uint32_t total = 0;
-        for (uint32_t k0 = 0; k0 < nact; k0 += 64) {
-            const uint32_t kk = k0 + (uint32_t)lane;
-            const uint32_t len = kk < nact ? (hpR[kk] >> 16) - (hpR[kk] & 0xFFFFu) : 0u;
-            uint32_t inc = len;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t y = __shfl_up(inc, d, 64);
-                if (lane >= d) inc += y;
-            }
-            if (kk < nact) hpS[kk] = total + inc - len;
-            total += __shfl(inc, 63, 64);
+        // The doubles are enumerated particle-pair major: for one particle
+        // pair, the targets of most hole pairs share their highest orbitals
+        // and hence their class, so the records of one (class, core) item are
+        // written in a few contiguous bursts instead of one at a time (stores
+        // of single records to many items leave partial cache lines).  Items
+        // run over the rectangle [x0, x1) x listed hole pairs, hole pair
+        // minor; an item outside its hole pair's range is skipped.
+        uint32_t x0 = g.pva2, x1 = 0u;
+        for (uint32_t kk = lane; kk < nact; kk += 64) {
+            x0 = min(x0, hpR[kk] & 0xFFFFu);
+            x1 = max(x1, hpR[kk] >> 16);
         }
-        __syncthreads();
-        // the listed range of this lane's first item t = lane, and the offset in it
-        uint32_t k = 0, off = (uint32_t)lane;
-        if (nact) {
-            uint32_t l = 0, r = nact;  // the last range starting at or before lane
-            while (r - l > 1u) {
-                const uint32_t m = (l + r) >> 1;
-                if (hpS[m] <= (uint32_t)lane) l = m;
-                else r = m;
-            }
-            k = l;
-            off = (uint32_t)lane - hpS[k];
+        for (int d = 32; d >= 1; d >>= 1) {
+            x0 = min(x0, (uint32_t)__shfl_xor((int)x0, d, 64));
+            x1 = max(x1, (uint32_t)__shfl_xor((int)x1, d, 64));
         }
+        const uint32_t total = (nact && x1 > x0) ? (x1 - x0) * nact : 0u;
+        const uint32_t q64 = nact ? 64u / nact : 0u, r64 = nact ? 64u % nact : 0u;
+        // t = (x - x0) * nact + k, advanced by the 64 items a lane strides over
+        uint32_t k = nact ? (uint32_t)lane % nact : 0u, x = x0 + (nact ? (uint32_t)lane / nact : 0u);
         for (uint32_t t0 = 0; t0 < total; t0 += 64) {
-            const bool act = t0 + (uint32_t)lane < total;
+            bool act = false;
             uint64_t a2 = a;
             uint32_t c = g.c0, po = 0u, pv = 0u;
-            if (act) {
-                po = pOA[hpL[k]];
-                pv = pVA[(hpR[k] & 0xFFFFu) + off];
-                a2 = (a & ~((1ull << (po & 0xFFu)) | (1ull << (po >> 8)))) | (1ull << (pv & 0xFFu)) |
-                     (1ull << (pv >> 8));
-                c = class_of(a2, g.cmap);
-                // in the batch by construction; a class outside it is a logic error
-                if (c < g.c0 || c >= cend) {
-                    raise_fault(kFaultSlot);
-                    c = g.c0;
+            if (t0 + (uint32_t)lane < total) {
+                const uint32_t rg = hpR[k];
+                if (x >= (rg & 0xFFFFu) && x < (rg >> 16)) {
+                    act = true;
+                    po = pOA[hpL[k]];
+                    pv = pVA[x];
+                    a2 = (a & ~((1ull << (po & 0xFFu)) | (1ull << (po >> 8)))) | (1ull << (pv & 0xFFu)) |
+                         (1ull << (pv >> 8));
+                    c = class_of(a2, g.cmap);
+                    // in the batch by construction; a class outside it is a logic error
+                    if (c < g.c0 || c >= cend) {
+                        raise_fault(kFaultSlot);
+                        c = g.c0;
+                    }
                 }
             }
-            // the item 64 further on
-            off += 64u;
-            while (k + 1u < nact && off >= hpS[k + 1u] - hpS[k]) {
-                off -= hpS[k + 1u] - hpS[k];
-                ++k;
+            k += r64;
+            x += q64;
+            if (k >= nact) {
+                k -= nact;
+                ++x;
             }
+            if (__ballot(act) == 0ull) continue;  // no item of this round in a range
             const uint32_t key = c - g.c0;
             const uint64_t peers = wave_match(key, act, g.nbits);
             const uint32_t before = cur[key];
@@ -1386,7 +1382,7 @@ static void run_search(asci_ctx *ctx, const SearchArgs &in, SearchOut &out, hipS
             ga.cap = Pb;
             ga.force_fault = ctx->fault_test;
             const size_t lds = (size_t)ga.nas * (8 + 4 + 4 + 4) + (size_t)ga.nbs * 4 + (size_t)nc * 4 + 256 +
-                               2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 8 * (size_t)ga.npa2 + 68;
+                               2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 4 * (size_t)ga.npa2 + 68;
             k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
             ASCI_LAUNCH_CHECK();
         }
@@ -1771,7 +1767,7 @@ static void run_search_async(asci_ctx *ctx, const SearchArgs &in, int64_t k, uin
         ga.cap = Pb;
         ga.force_fault = ctx->fault_test;
         const size_t lds = (size_t)ga.nas * (8 + 4 + 4 + 4) + (size_t)ga.nbs * 4 + (size_t)ga.nc * 4 + 256 +
-                           2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 8 * (size_t)ga.npa2 + 68;
+                           2 * ((size_t)2 * ga.npa2 + ga.pva2 + ga.npb2 + ga.pvb2) + 4 * (size_t)ga.npa2 + 68;
         k_generate<W><<<(unsigned)(8 * ((nq + 7) / 8)), 64, lds, s>>>(ga);
         ASCI_LAUNCH_CHECK();
     }
