@@ -84,6 +84,20 @@ def test_candidates_two_word_keys(asci, oracle_lib, n, na, nb, ndets):
     _all_parity(asci, oracle_lib, c, E0)
 
 
+@pytest.mark.parametrize("n,na,nb,ndets,buf", [(20, 12, 6, 40, 1 << 18), (34, 12, 4, 12, 1 << 19)])
+def test_many_hole_pairs_in_small_batches(asci, oracle_lib, n, na, nb, ndets, buf):
+    """More alpha hole pairs than a wavefront has lanes (66), the alpha-alpha
+    doubles of each core spread over many class batches: the in-batch
+    particle-pair ranges and their enumeration order, one- and two-word keys."""
+    c = _case(n, na, nb, ndets, seed=4100 + n)
+    E0 = oracle_lib.energy(c["h"], c["eri"], c["dets"], c["coeffs"])
+    _all_parity(asci, oracle_lib, c, E0, pair_buffer_bytes=buf)
+    d = to_dev(c)
+    k1, s1 = asci.search(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, 500, pair_buffer_bytes=buf)
+    k2, s2 = asci.search(d["h"], d["eri"], n, na, nb, d["dets"], d["coeffs"], E0, 500)
+    assert (host(k1) == host(k2)).all() and (host(s1) == host(s2)).all()
+
+
 def test_candidates_8e12o(asci, oracle_lib):
     c = syn.workload("8e12o")
     g = _golden("8e12o")
